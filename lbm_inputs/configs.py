@@ -1,0 +1,154 @@
+"""The workloads, as seeded synthetic ``Case`` objects.
+
+Lattice parameters follow the recipes written out in the design notes; the
+dimensionless groups are Re = U L / nu, Pe = U L / D, Da = k_r / U and
+PeDa = k_r L / D (paper, definitions of the dimensionless numbers), with
+D = c_s^2 (tau_AD - 1/2) and the rest fraction J0 chosen so that c_s^2 gives the
+wanted D at fixed tau_AD (paper, rest fraction method; generalised to D2Q9 and
+D3Q19 as c_s^2 = (1/3)(1 - J0)/(1 - w0_std)).
+"""
+from __future__ import annotations
+
+import math
+from typing import List
+
+import numpy as np
+
+from .case import Case, MECH_PRE, SCHEME_SNEW
+from . import geometry
+
+
+def j0_for_cs2(q: int, cs2: float) -> float:
+    """Rest fraction giving squared sound speed cs2 on the generalised lattice."""
+    w0 = 4.0 / 9.0 if q == 9 else 1.0 / 3.0
+    return 1.0 - cs2 * 3.0 * (1.0 - w0)
+
+
+# --------------------------------------------------------------------------
+# workload 0: 64 x 32 reactive channel, pure diffusion, FP64
+# --------------------------------------------------------------------------
+def robin_channel(nx=64, ny=32, tau_ad=0.8, k_r=1e-3, c_eq=1.0, steps=2000,
+                  mechanics=MECH_PRE, scheme=SCHEME_SNEW) -> Case:
+    solid, normals = geometry.plane_channel(nx, ny, (0, ny - 1))
+    return Case(name=f"robin_channel_{nx}x{ny}", dim=2, nx=nx, ny=ny, nz=1, q=9,
+                solid=solid, normals=normals, tau_ns=1.0, tau_ad=tau_ad, j0=-1.0,
+                c_eq=c_eq, k_r=k_r, v_m=1.0, periodic=(1, 1, 1), c0=0.0, c_ref=0.0,
+                mechanics=mechanics, scheme=scheme, steps=steps)
+
+
+def robin_1d(ny_fluid=24, nx=3, tau_ad=0.8, k_r=2e-2, c_eq=1.0, c_in=0.25,
+             mechanics=MECH_PRE, scheme=SCHEME_SNEW) -> Case:
+    """Column with a fixed-concentration inlet plane below row 0 and a reactive
+    solid row on top; periodic in x.  Used for the exact linear steady state."""
+    ny = ny_fluid + 1
+    solid = np.zeros((1, ny, nx), np.uint8)
+    solid[0, ny - 1, :] = 1
+    normals = np.zeros((1, ny, nx, 3))
+    normals[0, ny - 1, :, 1] = -1.0
+    return Case(name="robin_1d", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid,
+                normals=normals, tau_ns=1.0, tau_ad=tau_ad, c_eq=c_eq, k_r=k_r,
+                v_m=0.0, periodic=(1, 0, 1), inlet_axis=1, c_in=c_in, c0=c_in,
+                mechanics=mechanics, scheme=scheme)
+
+
+# --------------------------------------------------------------------------
+# workload 1: 512 x 512 tilted channel, Poiseuille flow + solute, Pe x Da sweep
+# --------------------------------------------------------------------------
+def channel_flow_params(pe: float, da: float, L: float, tau_ns: float, q: int = 9,
+                        tau_ad: float = 1.0):
+    nu = (tau_ns - 0.5) / 3.0
+    U = min(0.01, pe * 0.3 / L)
+    D = U * L / pe
+    cs2 = D / (tau_ad - 0.5)
+    return dict(U=U, D=D, nu=nu, F=12.0 * nu * U / (L * L), k_r=da * U,
+                j0=j0_for_cs2(q, cs2), cs2=cs2, tau_ad=tau_ad)
+
+
+def tilted_channel(pe=10.0, da=1.0, n=512, shift=296, width=256, aligned=False,
+                   tau_ns=0.6, steps=20000, c_ref=0.5) -> Case:
+    if aligned:
+        L = math.hypot(n, shift)
+        ny = int(round(n * n / L))
+        solid, normals, info = geometry.tilted_band(n, ny, 0, width)
+        nx = n
+    else:
+        solid, normals, info = geometry.tilted_band(n, n, shift, width)
+        nx, ny = n, n
+    p = channel_flow_params(pe, da, width, tau_ns)
+    t = info["t"]
+    d = info["d"][0]
+    fluid = solid[0] == 0
+    prof = np.where(fluid, p["F"] / (2 * p["nu"]) * d * (width - d), 0.0)
+    u = np.zeros((1, ny, nx, 3))
+    u[0, :, :, 0] = prof * t[0]
+    u[0, :, :, 1] = prof * t[1]
+    F = (p["F"] * t[0], p["F"] * t[1], 0.0)
+    info.update(p)
+    return Case(name=f"tilted_{'0' if aligned else '30'}deg_pe{pe:g}_da{da:g}", dim=2,
+                nx=nx, ny=ny, nz=1, q=9, solid=solid, normals=normals, tau_ns=tau_ns,
+                tau_ad=p["tau_ad"], j0=p["j0"], force=F, c_eq=1.0, k_r=p["k_r"],
+                v_m=1.0, periodic=(1, 1, 1), xwrap_shift_y=0 if aligned else shift,
+                u_init=u, c0=0.0, c_ref=c_ref, steps=steps, info=info)
+
+
+def tilted_sweep(aligned=False, n=512, shift=296, width=256, steps=20000) -> List[Case]:
+    return [tilted_channel(pe, da, n, shift, width, aligned, steps=steps)
+            for pe in (1.0, 10.0, 100.0) for da in (0.1, 1.0, 10.0)]
+
+
+# --------------------------------------------------------------------------
+# workload 2: 256^3 sphere packing, pressure-driven flow, precipitation
+# --------------------------------------------------------------------------
+def sphere_precipitation(n=256, seed=3, porosity=0.40, r_min=8.0, r_max=16.0,
+                         steps=10000, phase_change=1) -> Case:
+    solid, normals, info = geometry.sphere_packing(n, r_min, r_max, porosity, seed)
+    nu = 1.0 / 6.0
+    D = nu / 1000.0
+    cs2 = D / 0.5
+    return Case(name=f"spheres_{n}^3_precip", dim=3, nx=n, ny=n, nz=n, q=19,
+                solid=solid, normals=normals, tau_ns=1.0, tau_ad=1.0,
+                j0=j0_for_cs2(19, cs2), force=(0.0, 0.0, 1e-5), c_eq=1.0, k_r=1e-2,
+                v_m=0.1, periodic=(1, 1, 1), inlet_axis=2, c_in=2.0, c0=1.0,
+                c_ref=1.0, phase_change=phase_change, steps=steps, info=info)
+
+
+# --------------------------------------------------------------------------
+# workload 3: 1024 uneven 2D flow + solute domains (batched sweep)
+# --------------------------------------------------------------------------
+def batch_domains(count=1024, seed=4, steps=5000, w_range=(32, 256), h_range=(32, 128),
+                  tau_ns=0.8) -> List[Case]:
+    rng = np.random.default_rng(seed)
+    cases = []
+    for k in range(count):
+        W = int(rng.integers(w_range[0], w_range[1] + 1))
+        H = int(rng.integers(h_range[0], h_range[1] + 1))
+        por = float(rng.uniform(0.5, 0.8))
+        pe = 10.0 ** rng.uniform(-1.0, 2.0)
+        da = 10.0 ** rng.uniform(-2.0, 2.0)
+        gseed = int(rng.integers(0, 2 ** 31 - 1))
+        solid, normals, info = geometry.disk_medium(W, H, por, 3.0, 12.0, gseed)
+        p = channel_flow_params(pe, da, H, tau_ns)
+        info.update(p, pe=pe, da=da)
+        cases.append(Case(name=f"batch_{k}", dim=2, nx=W, ny=H, nz=1, q=9, solid=solid,
+                          normals=normals, tau_ns=tau_ns, tau_ad=p["tau_ad"], j0=p["j0"],
+                          force=(p["F"], 0.0, 0.0), c_eq=1.0, k_r=p["k_r"], v_m=1.0,
+                          periodic=(1, 1, 1), c0=0.0, c_ref=0.5, steps=steps, info=info))
+    return cases
+
+
+# --------------------------------------------------------------------------
+# workload 4: rate-field recovery by the adjoint (128^3 sphere packing)
+# --------------------------------------------------------------------------
+def lognormal_rate_field(solid: np.ndarray, seed: int, mu=math.log(1e-3), sigma=0.5):
+    rng = np.random.default_rng(seed)
+    return np.exp(rng.normal(mu, sigma, size=solid.size)) * solid.reshape(-1)
+
+
+def rate_recovery(n=128, seed=5, porosity=0.45, r_min=8.0, r_max=16.0, steps=2000,
+                  k_seed=51) -> Case:
+    solid, normals, info = geometry.sphere_packing(n, r_min, r_max, porosity, seed)
+    k = lognormal_rate_field(solid, k_seed)
+    return Case(name=f"rate_recovery_{n}^3", dim=3, nx=n, ny=n, nz=n, q=19, solid=solid,
+                normals=normals, tau_ns=1.0, tau_ad=0.8, j0=-1.0, c_eq=1.0, k_r=1e-3,
+                k_r_field=k, v_m=0.0, periodic=(1, 1, 1), c0=0.0, c_ref=0.0,
+                steps=steps, info=info)

@@ -1,0 +1,389 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every test here runs on the CPU.  None of them compares the oracle with a
+second copy of its own formulas: each uses a closed form, an invariant, a
+limit stated in the paper, a value printed in the paper, or a different
+computation (a Fourier matrix power) of the same linear dynamics.
+"""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from lbm_inputs import (Case, configs, geometry, MECH_PRE, MECH_POST, SCHEME_SNEW, SCHEME_SV,
+                        SCHEME_SPJ, SCHEME_ABB)
+from oracle import Oracle
+
+from analytic import linear_robin_steady, plane_wall_robin
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def _small_case(**kw):
+    solid, normals = geometry.plane_channel(8, 6, (0, 5))
+    base = dict(name="t", dim=2, nx=8, ny=6, nz=1, q=9, solid=solid, normals=normals)
+    base.update(kw)
+    return Case(**base)
+
+
+# --------------------------------------------------------------------------
+# lattices
+# --------------------------------------------------------------------------
+def test_d2q9_matches_paper_table():
+    """Velocity set and weights equal the paper's appendix table (golden file)."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "d2q9_velocity_set.txt"))
+    lat = Oracle(_small_case()).lattice()
+    assert np.array_equal(lat["e"][:, :2], rows[:, 1:3].astype(int))
+    assert np.allclose(lat["wf"], rows[:, 3] / rows[:, 4], rtol=0, atol=1e-16)
+    assert lat["cs2f"] == pytest.approx(1 / 3, abs=1e-16)
+
+
+@pytest.mark.parametrize("q", [9, 19])
+@pytest.mark.parametrize("j0", [-1.0, 0.0, 0.2, 0.6, 0.99933])
+def test_lattice_moments_and_rest_fraction(q, j0):
+    """Isotropy that fixes the weights: sum w = 1, sum w e = 0,
+    sum w e e = c_s^2 I on both lattices, the fourth moment of the fluid
+    lattice is c_s^4 (d_ab d_cd + d_ac d_bd + d_ad d_bc), and w_0 = J0 on the
+    rest-fraction solute lattice (paper, eq. RestFraction)."""
+    dim = 2 if q == 9 else 3
+    if q == 9:
+        case = _small_case(j0=j0)
+    else:
+        solid = np.zeros((3, 3, 3), np.uint8)
+        case = Case(name="t", dim=3, nx=3, ny=3, nz=3, q=19, solid=solid, j0=j0)
+    lat = Oracle(case).lattice()
+    e = lat["e"][:, :dim].astype(float)
+    I = np.eye(dim)
+    for w, cs2 in ((lat["wf"], lat["cs2f"]), (lat["ws"], lat["cs2s"])):
+        assert w.sum() == pytest.approx(1.0, abs=1e-15)
+        assert np.abs(w @ e).max() < 1e-16
+        assert np.allclose(np.einsum("i,ia,ib->ab", w, e, e), cs2 * I, atol=1e-15)
+        assert (w >= 0).all()
+    w4 = np.einsum("i,ia,ib,ic,id->abcd", lat["wf"], e, e, e, e)
+    iso = (np.einsum("ab,cd->abcd", I, I) + np.einsum("ac,bd->abcd", I, I) +
+           np.einsum("ad,bc->abcd", I, I)) / 9.0
+    assert np.allclose(w4, iso, atol=1e-15)
+    if j0 >= 0:
+        assert lat["ws"][0] == j0
+
+
+@pytest.mark.parametrize("q", [9, 19])
+def test_rest_fraction_at_standard_weight_is_standard_lattice(q):
+    """J0 equal to the standard rest weight reproduces the standard lattice
+    (paper, rest fraction section: J0 = 1/3 on D2Q5 gives the usual values)."""
+    w0 = 4 / 9 if q == 9 else 1 / 3
+    if q == 9:
+        a, b = _small_case(j0=-1.0), _small_case(j0=w0)
+    else:
+        solid = np.zeros((3, 3, 3), np.uint8)
+        a = Case(name="t", dim=3, nx=3, ny=3, nz=3, q=19, solid=solid, j0=-1.0)
+        b = a.replace(j0=w0)
+    la, lb = Oracle(a).lattice(), Oracle(b).lattice()
+    assert np.allclose(la["ws"], lb["ws"], rtol=0, atol=1e-16)
+    assert lb["cs2s"] == pytest.approx(la["cs2s"], abs=1e-16)
+
+
+# --------------------------------------------------------------------------
+# bulk dynamics
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("q,j0,tau,u", [
+    (9, -1.0, 0.8, (0.0, 0.0, 0.0)),
+    (9, 0.3, 1.3, (0.02, -0.01, 0.0)),
+    (19, 0.6, 0.7, (0.01, 0.015, -0.02)),
+])
+def test_fourier_mode_matches_matrix_power(q, j0, tau, u):
+    """One periodic Fourier mode of C under uniform flow evolves by the power of
+    the Q x Q step matrix M(k) = (I - (I - E)/tau) diag(exp(-i k.e_i)) with
+    E_ij = w_i (1 + e_i.u/c_s^2) (von Neumann analysis of the solute
+    eqs. solute_BGK and solute_equilibrium_function).  The fluid stays exactly
+    uniform, so u is the same at every node."""
+    dim = 2 if q == 9 else 3
+    n = (16, 12, 1) if dim == 2 else (8, 6, 10)
+    solid = np.zeros((n[2], n[1], n[0]), np.uint8)
+    N = solid.size
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    kv = np.array([2 * np.pi * 2 / n[0], 2 * np.pi * 1 / n[1], (2 * np.pi / n[2]) if dim == 3 else 0.0])
+    phase = (kv[0] * x + kv[1] * y + kv[2] * z).reshape(-1)
+    A, C0 = 0.3, 1.1
+    c = C0 + A * np.cos(phase + 0.4)
+    uu = np.tile(np.array(u, float), (N, 1))
+    case = Case(name="f", dim=dim, nx=n[0], ny=n[1], nz=n[2], q=q, solid=solid, tau_ns=0.9,
+                tau_ad=tau, j0=j0, c_init=c, u_init=uu)
+    o = Oracle(case)
+    lat = o.lattice()
+    e, ws, cs2 = lat["e"].astype(float), lat["ws"], lat["cs2s"]
+    steps = 25
+    o.step(steps)
+    _, g = o.pops()
+    E = np.outer(ws * (1 + e @ np.array(u) / cs2), np.ones(q))
+    S = np.diag(np.exp(-1j * (e @ kv)))
+    M = (np.eye(q) - (np.eye(q) - E) / tau) @ S
+    v0 = A * np.exp(0.4j) * ws * (1 + e @ np.array(u) / cs2)
+    vn = np.linalg.matrix_power(M, steps) @ v0
+    pred = C0 * ws[:, None] * (1 + e @ np.array(u) / cs2)[:, None] + \
+        np.real(vn[:, None] * np.exp(1j * phase)[None, :])
+    assert np.abs(g - pred).max() < 1e-12
+
+
+@pytest.mark.parametrize("j0", [-1.0, 0.1, 0.7])
+def test_diffusion_coefficient_from_mode_decay(j0):
+    """A long-wavelength mode decays as exp(-D k^2 t) with
+    D = c_s^2 (tau_AD - 1/2) (paper, eq. solute_BGK and the rest fraction
+    relation D = (1 - J0)/dim (tau - 1/2), generalised to D2Q9 as
+    c_s^2 = 3 (1 - J0)/5).  Accuracy O(k^2)."""
+    nx, tau = 128, 0.9
+    solid = np.zeros((1, 1, nx), np.uint8)
+    x = np.arange(nx)
+    k = 2 * np.pi / nx
+    case = Case(name="d", dim=2, nx=nx, ny=1, nz=1, q=9, solid=solid, tau_ad=tau, j0=j0,
+                c_init=1.0 + 0.1 * np.cos(k * x))
+    o = Oracle(case)
+    steps = 400
+    o.step(steps)
+    c = o.fields()["c"]
+    amp = 2 * np.abs(np.fft.rfft(c - c.mean())[1]) / nx
+    cs2 = 1 / 3 if j0 < 0 else 3 * (1 - j0) / 5
+    D = cs2 * (tau - 0.5)
+    assert amp / 0.1 == pytest.approx(math.exp(-D * k * k * steps), rel=2e-3)
+
+
+@pytest.mark.parametrize("tau", [0.6, 0.5 + math.sqrt(3 / 16), 1.0])
+def test_poiseuille_body_force(tau):
+    """Force-driven channel flow between bounce-back walls: the bulk profile is
+    exactly parabolic with curvature -F/nu, nu = c_s^2 (tau - 1/2)
+    (eq. fluid_BGK_visc).  At (tau - 1/2)^2 = 3/16 the walls lie exactly
+    halfway (the paper's statement on the magic parameter for BGK = TRT with
+    equal rates), so the whole profile equals the parabola."""
+    ny, nx, F = 18, 2, 1e-5
+    solid, normals = geometry.plane_channel(nx, ny, (0, ny - 1))
+    case = Case(name="p", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=tau, force=(F, 0, 0))
+    o = Oracle(case)
+    o.step(30000)
+    u = o.fields()["u"].reshape(ny, nx, 3)[1:-1, 0, 0]
+    nu = (tau - 0.5) / 3
+    d2 = u[2:] - 2 * u[1:-1] + u[:-2]
+    assert np.allclose(d2, -F / nu, rtol=1e-9)
+    if abs((tau - 0.5) ** 2 - 3 / 16) < 1e-12:
+        y = np.arange(1, ny - 1)
+        exact = F / (2 * nu) * (y - 0.5) * (ny - 1.5 - y)
+        assert np.abs(u - exact).max() < 1e-10 * exact.max()
+
+
+# --------------------------------------------------------------------------
+# reactive boundary condition
+# --------------------------------------------------------------------------
+READINGS = [  # (mechanics, scheme, wall offset, factor on k_r that is realised)
+    (MECH_PRE, SCHEME_SNEW, 0.0, "1"),
+    (MECH_POST, SCHEME_SV, 0.5, "1"),
+    (MECH_PRE, SCHEME_SV, 0.0, "1/gamma"),
+    (MECH_POST, SCHEME_SNEW, 0.5, "gamma"),
+]
+
+
+@pytest.mark.parametrize("mech,scheme,offset,factor", READINGS)
+@pytest.mark.parametrize("tau,k_r", [(0.8, 2e-2), (1.4, 5e-3)])
+def test_linear_steady_robin(mech, scheme, offset, factor, tau, k_r):
+    """1D steady diffusion between an equilibrium inlet and a reactive wall:
+    the exact discrete solution is linear (see ``analytic.linear_robin_steady``).
+    With the pre-collision source the new scheme (gamma included, eq.
+    k_i_S_New) realises k_r exactly with the wall on the boundary node, and the
+    scheme without gamma (eq. k_i_S_Ve) realises k_r/gamma -- the shift of the
+    effective PeDa by 1/gamma that the paper reports for Verhaeghe's scheme.
+    With the post-collision source the roles swap (wall halfway)."""
+    case = configs.robin_1d(ny_fluid=20, tau_ad=tau, k_r=k_r, mechanics=mech, scheme=scheme)
+    o = Oracle(case)
+    o.step(40000)
+    c = o.fields()["c"].reshape(case.ny, case.nx)[:-1]
+    gamma = tau / (tau - 0.5)
+    keff = {"1": k_r, "gamma": gamma * k_r, "1/gamma": k_r / gamma}[factor]
+    exact = linear_robin_steady(case.ny - 1, tau, 1 / 3, keff, case.c_in, case.c_eq, offset)
+    for col in range(case.nx):
+        assert np.abs(c[:, col] - exact).max() < 1e-11
+
+
+@pytest.mark.parametrize("mech,scheme,H", [(MECH_PRE, SCHEME_SNEW, 29.0),
+                                           (MECH_POST, SCHEME_SV, 30.0)])
+def test_reactive_channel_against_series(mech, scheme, H):
+    """The 64x32 reactive channel (C = 0 at t = 0, C_eq = 1, tau = 0.8,
+    k_r = 1e-3) at t = 2000 against the plane-wall Robin eigen-series (the
+    classical solution family the paper cites for its analytic case).  Walls
+    on rows 1 and 30 (pre-collision source) or halfway (post-collision)."""
+    case = configs.robin_channel(mechanics=mech, scheme=scheme)
+    o = Oracle(case)
+    o.step(2000)
+    c = o.fields()["c"].reshape(32, 64)
+    D = (case.tau_ad - 0.5) / 3
+    L = H / 2
+    y = np.arange(1, 31)
+    exact = plane_wall_robin((y - 15.5) / L, 2000, D, L, case.k_r, 1.0)
+    assert np.abs(c[1:31] - exact[:, None]).max() < 1e-4
+    # x-invariance of a periodic channel
+    assert np.abs(c - c[:, :1]).max() < 1e-13
+
+
+def test_zero_rate_is_bounce_back():
+    """k_r = 0 reduces the scheme to bounce-back (paper, RBC limits): with the
+    post-collision source a channel with solid rows is bitwise the channel
+    with non-periodic box walls, and the solute mass is conserved."""
+    ny, nx = 12, 10
+    rng = np.random.default_rng(0)
+    c0 = rng.uniform(0.2, 1.0, size=(1, ny, nx))
+    u0 = np.zeros((1, ny, nx, 3))
+    u0[..., 0] = rng.uniform(-0.02, 0.02, size=(1, ny, nx))
+    solid, normals = geometry.plane_channel(nx, ny, (0, ny - 1))
+    a = Case(name="a", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid, normals=normals,
+             tau_ns=0.8, tau_ad=0.9, j0=0.3, k_r=0.0, c_eq=1.0, mechanics=MECH_POST,
+             c_init=c0, u_init=u0, force=(1e-5, 0, 0))
+    b = Case(name="b", dim=2, nx=nx, ny=ny - 2, nz=1, q=9, solid=solid[:, 1:-1].copy(),
+             tau_ns=0.8, tau_ad=0.9, j0=0.3, c_eq=1.0, periodic=(1, 0, 1), mechanics=MECH_POST,
+             c_init=c0[:, 1:-1].copy(), u_init=u0[:, 1:-1].copy(), force=(1e-5, 0, 0))
+    oa, ob = Oracle(a), Oracle(b)
+    m0 = oa.diag()["mass_c"]
+    oa.step(300)
+    ob.step(300)
+    fa, ga = oa.pops()
+    fb, gb = ob.pops()
+    sl = fa.reshape(9, ny, nx)[:, 1:-1].reshape(9, -1)
+    assert np.array_equal(sl, fb)
+    assert np.array_equal(ga.reshape(9, ny, nx)[:, 1:-1].reshape(9, -1), gb)
+    assert abs(oa.diag()["mass_c"] - m0) < 1e-12 * m0
+
+
+def test_zero_rate_pre_collision_wall_flux_vanishes():
+    """k_r = 0 with the pre-collision source: alpha = 0 and beta = 1, so the
+    wall carries no net flux once the profile is steady."""
+    case = configs.robin_channel(k_r=0.0)
+    rng = np.random.default_rng(1)
+    case = case.replace(c_init=rng.uniform(0.0, 1.0, size=case.n))
+    o = Oracle(case)
+    o.step(20000)
+    q, kind = o.exchange()
+    assert np.abs(q[kind == 1]).max() < 1e-12
+
+
+def test_infinite_rate_is_anti_bounce_back():
+    """k_r -> infinity gives anti-bounce-back with C_eq (paper, RBC limits and
+    SI on the PeDa -> infinity limit): k_r = 1e15 matches the ABB scheme."""
+    case = configs.robin_channel(k_r=1e15, steps=500)
+    a = Oracle(case)
+    b = Oracle(case.replace(scheme=SCHEME_ABB))
+    a.step(500)
+    b.step(500)
+    assert np.abs(a.pops()[1] - b.pops()[1]).max() < 1e-12
+
+
+@pytest.mark.parametrize("nx,shift", [(512, 0), (512, 256), (512, 296), (512, 512), (300, 97)])
+def test_orientation_identity(nx, shift):
+    """Sum over the reactive links of w_i max(0, e_i.n), per unit wall length,
+    is c_s^2/2 for any wall angle on D2Q9 (half the second moment of the
+    weights; lattice links of direction e_i cross a straight wall with density
+    |e_i.n|).  The new scheme's k_i (eq. k_i_S_New) is proportional to that
+    projection, so the wall flux is orientation-invariant (paper, config. B).
+    Patel/Ju's k_i (eq. k_i_S2) divides instead, and its sum depends on the
+    angle -- the grid dependence the paper reports."""
+    ny = nx
+    solid, normals, info = geometry.tilted_band(nx, ny, shift, width=nx * 0.3)
+    tau, k_r = 0.8, 1e-3
+    gamma = tau / (tau - 0.5)
+    case = Case(name="o", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid, normals=normals,
+                tau_ad=tau, k_r=k_r, xwrap_shift_y=shift)
+    o = Oracle(case, init=False)
+    k = o.link_k()
+    w = np.array([4 / 9, 1 / 36, 1 / 9, 1 / 36, 1 / 9, 1 / 36, 1 / 9, 1 / 36, 1 / 9])
+    wall_length = 2 * math.hypot(nx, shift)
+    proj = np.where(k >= 0, k, 0.0) / (3 * gamma * k_r)       # c_s^-2 = 3
+    total = (proj * w[None, :]).sum() / wall_length
+    assert total == pytest.approx(1 / 6, abs=1e-12)
+    spj = Oracle(case.replace(scheme=SCHEME_SPJ), init=False).link_k()
+    inv = np.where(spj > 0, 3 * gamma * k_r / np.where(spj > 0, spj, 1.0), 0.0)
+    assert np.allclose(inv[spj > 0], proj[spj > 0], rtol=1e-12)
+
+
+def test_orientation_simulated_flux():
+    """Pure diffusion from reactive walls: the total wall exchange per unit
+    wall length of a 30.03 deg band equals that of the 0 deg twin to O(dx/W)
+    (the orientation invariance the paper demonstrates with config. B)."""
+    out = []
+    for aligned in (False, True):
+        n, shift, width = 128, 74, 40.0
+        if aligned:
+            L = math.hypot(n, shift)
+            ny = int(round(n * n / L))
+            solid, normals, info = geometry.tilted_band(n, ny, 0, width)
+            nx, sh = n, 0
+        else:
+            solid, normals, info = geometry.tilted_band(n, n, shift, width)
+            nx, ny, sh = n, n, shift
+        case = Case(name="fl", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid, normals=normals,
+                    tau_ad=0.8, k_r=5e-3, c_eq=1.0, v_m=1.0, xwrap_shift_y=sh)
+        o = Oracle(case)
+        o.step(1500)
+        out.append(o.diag()["wall_exchange"] / (2 * math.hypot(nx, sh)))
+    assert out[0] == pytest.approx(out[1], rel=0.02)
+
+
+# --------------------------------------------------------------------------
+# mass accounting with the solid fraction
+# --------------------------------------------------------------------------
+@pytest.mark.parametrize("mech", [MECH_PRE, MECH_POST])
+@pytest.mark.parametrize("scheme", [SCHEME_SNEW, SCHEME_SPJ, SCHEME_ABB])
+def test_solute_plus_solid_mass_invariant(mech, scheme):
+    """Closed periodic domain: every change of solute mass crosses a reactive
+    link, and eq. solidFractionUpdate books the same amount into phi, so
+    sum C + sum phi / V_m is invariant."""
+    solid, normals, _ = geometry.disk_medium(48, 40, 0.65, 3.0, 7.0, seed=11)
+    rng = np.random.default_rng(2)
+    case = Case(name="m", dim=2, nx=48, ny=40, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=0.8, tau_ad=0.75, j0=0.2, force=(2e-5, 0, 0), c_eq=1.0,
+                k_r_field=rng.uniform(0, 0.05, solid.size), v_m=0.3, mechanics=mech,
+                scheme=scheme, c_init=rng.uniform(0.0, 2.0, solid.size))
+    o = Oracle(case)
+    d0 = o.diag()
+    tot0 = d0["mass_c"] + d0["phi_sum"] / case.v_m
+    o.step(400)
+    d = o.diag()
+    assert d["mass_c"] + d["phi_sum"] / case.v_m == pytest.approx(tot0, rel=1e-12)
+    assert d["mass_c"] - d0["mass_c"] == pytest.approx(d["wall_exchange"], rel=1e-9, abs=1e-12)
+
+
+def test_mass_budget_with_inlet_and_outlet():
+    """With an inlet and an outlet plane the change of sum C + sum phi / V_m is
+    the exchange through the two planes."""
+    rng = np.random.default_rng(3)
+    n = 12
+    solid = np.zeros((n, n, n), np.uint8)
+    solid[3:7, 4:9, 5:8] = 1
+    normals = np.zeros((n, n, n, 3))
+    normals[..., 2] = 1.0
+    case = Case(name="b", dim=3, nx=n, ny=n, nz=n, q=19, solid=solid, normals=normals,
+                tau_ns=0.9, tau_ad=0.8, j0=0.5, force=(0, 0, 1e-4), c_eq=1.0, k_r=0.02,
+                v_m=0.2, inlet_axis=2, c_in=2.0, c_init=rng.uniform(0.5, 1.5, solid.size))
+    o = Oracle(case)
+    d0 = o.diag()
+    o.step(200)
+    d = o.diag()
+    tot0 = d0["mass_c"] + d0["phi_sum"] / case.v_m
+    tot = d["mass_c"] + d["phi_sum"] / case.v_m
+    assert tot - tot0 == pytest.approx(d["inlet_exchange"] + d["outlet_exchange"], rel=1e-10)
+    assert abs(d["inlet_exchange"]) > 1e-3
+
+
+def test_phase_change_conserves_mass():
+    """Dissolution and precipitation events (thresholds phi = 0 and 1, paper
+    Sec. 2.4) move mass between the two phases without creating any."""
+    solid, normals = geometry.plane_channel(24, 16, (0, 15))
+    solid[0, 1:4, 10:13] = 1
+    normals[0, 1:4, 10:13, 1] = 1.0
+    rng = np.random.default_rng(4)
+    phi0 = np.where(solid.reshape(-1) == 1, 0.02, 0.0)
+    case = Case(name="e", dim=2, nx=24, ny=16, nz=1, q=9, solid=solid, normals=normals,
+                tau_ad=0.8, c_eq=0.0, k_r=0.05, v_m=1.0, phase_change=1, phi0=phi0,
+                c_init=rng.uniform(0.5, 1.5, solid.size))
+    o = Oracle(case)
+    d0 = o.diag()
+    o.step(300)
+    d = o.diag()
+    assert d["n_events"] > 0
+    assert d["mass_c"] + d["phi_sum"] == pytest.approx(d0["mass_c"] + d0["phi_sum"], rel=1e-12)
