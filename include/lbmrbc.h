@@ -1,0 +1,192 @@
+/*
+ * lbmrbc.h -- C ABI of the MI355X (gfx950) reactive lattice Boltzmann library.
+ *
+ * One fused time step advances two coupled lattices on one GPU:
+ *   - a fluid population f_i: BGK collision with the second-order equilibrium
+ *     (Weinmiller et al., Sec. 2.1, eqs. fluid_BGK, fluid_Equilib,
+ *     fluid_BGK_visc), halfway bounce-back at solid neighbours, Guo body force;
+ *   - a solute population g_i: advection-diffusion BGK with the linear
+ *     equilibrium g_eq = C w_i (1 + u.e_i / c_s^2), u taken from the fluid at
+ *     the same node and step (Sec. 2.1, eqs. solute_BGK,
+ *     solute_equilibrium_function, solute_diffu), with the rest-fraction
+ *     weights (Sec. 2.2, eqs. RestFraction, RestFractionCs2);
+ *   - the general reactive boundary condition on every link that enters a
+ *     fluid node from a solid node (Sec. 2.3, eq. general_RBC with the k_i of
+ *     eqs. k_i_S_Ve, k_i_S2, k_i_S_New and gamma of eq. gammaAppendix);
+ *   - the solid-fraction update of each interface node from the mass that
+ *     crossed its reactive links (Sec. 2.4, eq. solidFractionUpdate), in FP64,
+ *     and the phase-change thresholds phi = 0 / phi = 1 (Sec. 2.4).
+ *
+ * Conventions
+ *   - Nodes are indexed n = x + nx*(y + ny*z) (x fastest).  2D uses nz = 1.
+ *   - All array arguments are DEVICE pointers unless stated otherwise, and are
+ *     owned by the caller.  The library never frees them.  The only device
+ *     memory the library uses is the caller's workspace given to lbm_create.
+ *   - All device work is enqueued, in order, on the HIP stream given to
+ *     lbm_create (NULL = the legacy default stream).  Only lbm_get_diag,
+ *     lbm_set_geometry and lbm_create synchronise that stream.
+ *   - Every function returns an lbm_status.  Errors never cross the ABI as
+ *     exceptions.  An argument error leaves the context unchanged; the text of
+ *     the last error is available from lbm_last_error.
+ *   - Not thread-safe per context.  Distinct contexts are independent.
+ */
+#ifndef LBMRBC_H
+#define LBMRBC_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct lbm_ctx lbm_ctx;
+
+typedef enum {
+    LBM_OK = 0,
+    LBM_EINVAL = -1,     /* invalid argument or parameter                      */
+    LBM_ENOMEM = -2,     /* workspace too small                                */
+    LBM_EDEVICE = -3,    /* HIP runtime error (message names the call)         */
+    LBM_ESTATE = -4,     /* call out of order (e.g. step before set_geometry)  */
+    LBM_ENUMERIC = -5,   /* non-finite population detected                     */
+    LBM_ECAPACITY = -6   /* reactive links exceed params.max_links             */
+} lbm_status;
+
+/* precision: storage and arithmetic of the populations */
+#define LBM_FP64 0       /* FP64 populations                                    */
+#define LBM_FP32_DEV 1   /* FP32 deviations f - w_i rho0, g - w_i C_ref; the
+                            solid fraction and the mass sums stay FP64        */
+
+/* source population of the reactive boundary condition (the paper's g~_i) */
+#define LBM_PRECOLL 0    /* pre-collision population at the fluid boundary node,
+                            streamed toward the wall this step (default)      */
+#define LBM_POSTCOLL 1   /* the node's own post-collision population that
+                            streamed into the wall (halfway, link-wise)       */
+
+/* k_i of the reactive boundary condition */
+#define LBM_SNEW 0       /* c_s^-2 gamma k_r (e.n)   -- the paper's new scheme  */
+#define LBM_SV 1         /* c_s^-2 k_r (e.n)         -- Verhaeghe              */
+#define LBM_SPJ 2        /* c_s^-2 gamma k_r / (e.n) -- Patel / Ju             */
+#define LBM_ABB 3        /* k_i = infinity: anti-bounce-back with C_eq         */
+
+typedef struct {
+    int32_t dim;              /* 2 or 3                                            */
+    int32_t nx, ny, nz;       /* lattice size; nz = 1 when dim = 2                 */
+    int32_t fluid_q;          /* 9 (D2Q9) or 19 (D3Q19)                            */
+    int32_t solute_q;         /* must equal fluid_q                                */
+    int32_t precision;        /* LBM_FP64 | LBM_FP32_DEV                           */
+    int32_t rbc_mechanics;    /* LBM_PRECOLL | LBM_POSTCOLL                        */
+    int32_t rbc_scheme;       /* LBM_SNEW | LBM_SV | LBM_SPJ | LBM_ABB             */
+    double tau_ns;            /* fluid relaxation time, > 1/2                      */
+    double tau_ad;            /* solute relaxation time, > 1/2                     */
+    double j0;                /* rest fraction in [0,1); < 0: standard weights     */
+    double force[3];          /* body force on the fluid (lattice units)           */
+    double rho0;              /* FP32_DEV reference density (ignored in FP64)      */
+    double c_ref;             /* FP32_DEV reference concentration (ignored in FP64)*/
+    double c_eq;              /* equilibrium concentration of the reaction         */
+    double k_r;               /* uniform rate constant (when no per-node field)    */
+    double v_m;               /* dimensionless molar volume                         */
+    double a_m;               /* specific surface area (the paper uses 1)          */
+    int32_t periodic[3];      /* fluid periodicity per axis                        */
+    int32_t xwrap_shift_y;    /* site (x+nx, y) is site (x, y+shift); needs
+                                 periodic[0] and periodic[1]                        */
+    int32_t inlet_axis;       /* -1: none; else the solute sees this axis as
+                                 non-periodic with a fixed-concentration inlet at
+                                 coordinate 0 and a zero-gradient outlet at n-1    */
+    double c_in;              /* inlet concentration                                */
+    int32_t phase_change;     /* 1: apply the phi thresholds after each step       */
+    int32_t reserved0;
+    int64_t max_links;        /* capacity for reactive links; <= 0 selects
+                                 max(4096, N*(Q-1)/8)                              */
+} lbm_params;
+
+typedef struct {
+    int64_t step;             /* steps taken since lbm_init_fields                 */
+    int64_t n_events;         /* phase-change events applied                       */
+    int64_t n_links;          /* reactive links of the current geometry            */
+    int64_t n_solid_iface;    /* solid nodes with at least one reactive link       */
+    int64_t n_fluid;          /* fluid nodes                                       */
+    int64_t n_fluid_iface;    /* fluid nodes with at least one reactive link       */
+    double mass_c;            /* sum of C over fluid nodes (FP64)                  */
+    double phi_sum;           /* sum of phi over all nodes (FP64)                  */
+    double wall_exchange;     /* cumulative mass entering the fluid over reactive
+                                 links since lbm_init_fields (FP64)               */
+    int32_t nan_flag;         /* 1 if any population is non-finite                 */
+    int32_t reserved0;
+} lbm_diag;
+
+/* Workspace size in bytes for these parameters (host call, no device work).
+ * EINVAL on invalid parameters. */
+lbm_status lbm_workspace_bytes(const lbm_params *params, size_t *bytes);
+
+/* Create a context on the current HIP device.  dev_workspace: device memory of
+ * at least lbm_workspace_bytes, 256-byte aligned, owned by the caller and kept
+ * alive until lbm_destroy.  hip_stream: a hipStream_t (NULL = default).
+ * EINVAL: bad parameters; ENOMEM: workspace too small. */
+lbm_status lbm_create(const lbm_params *params, void *dev_workspace, size_t bytes,
+                      void *hip_stream, lbm_ctx **out);
+
+/* Geometry prep (per geometry, not per step): node classes, reactive link
+ * list with k_i per link (Sec. 2.3), solid-side link lists.
+ *   solid   [N]    uint8, nonzero = solid (required)
+ *   normals [N][3] FP64 unit normals pointing from solid into fluid, read at
+ *                  solid nodes (NULL: lattice-gradient normals of the solid
+ *                  indicator)
+ *   k_r     [N]    FP64 rate constant per solid node (NULL: params.k_r)
+ *   phi0    [N]    FP64 initial solid fraction (NULL: 1 at solid, 0 at fluid)
+ * Synchronises the stream.  ECAPACITY if the links exceed max_links (the
+ * message gives the count needed). */
+lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *normals,
+                            const double *k_r, const double *phi0);
+
+/* Equilibrium initial state of (rho, u, C) at every fluid node, written as the
+ * post-collision populations.  rho [N], u [N][3], c [N] FP64; NULL = 1, 0, 0.
+ * Resets the step counter and the cumulative exchange. */
+lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u,
+                           const double *c);
+
+/* Advance nsteps fused time steps (asynchronous). */
+lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
+
+/* lbm_step with per-kernel timing, for measurement: runs nsteps exactly like
+ * lbm_step, records a HIP event pair around every kernel launch on the
+ * context stream, synchronises, and writes the summed kernel durations in
+ * milliseconds: ms[0] the fused step kernel, ms[1] the solid-fraction kernel
+ * (host array of 2).  Results are identical to lbm_step. */
+lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms);
+
+/* Macroscopic fields of the current state (asynchronous; NULL skips a field):
+ * rho = sum f, u = (sum e f - F/2)/rho, C = sum g (the values that entered
+ * the last collision), phi, type (1 = solid).  rho/c/phi [N], u [N][3] FP64,
+ * type [N] uint8.  Solid nodes read rho = u = C = 0. */
+lbm_status lbm_get_fields(lbm_ctx *ctx, double *rho, double *u, double *c, double *phi,
+                          uint8_t *type);
+
+/* Post-collision populations as absolute FP64 values, [Q][N] (NULL skips). */
+lbm_status lbm_get_pops(lbm_ctx *ctx, double *f, double *g);
+
+/* Mass that crossed each reactive link in the last step, scattered to a dense
+ * [N][Q] FP64 array (zero where there is no link). */
+lbm_status lbm_get_exchange(lbm_ctx *ctx, double *q);
+
+/* FP64 reductions of the current state (host struct; synchronises).
+ * Returns ENUMERIC when a non-finite population is present. */
+lbm_status lbm_get_diag(lbm_ctx *ctx, lbm_diag *out);
+
+/* Full state (populations, phi, geometry arrays, counters) to/from a caller
+ * device buffer of lbm_state_bytes. */
+lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes);
+lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes);
+lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes);
+
+/* Text of the last error on this context (valid until the next call on it);
+ * with ctx = NULL, the last error of a failed lbm_create. */
+const char *lbm_last_error(const lbm_ctx *ctx);
+
+/* Release host state.  The caller's workspace is not touched. */
+void lbm_destroy(lbm_ctx *ctx);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* LBMRBC_H */

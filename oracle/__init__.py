@@ -58,6 +58,7 @@ def _load():
         lib.orc_get_exchange.argtypes = [P, P, P]
         lib.orc_get_link_k.argtypes = [P, P]
         lib.orc_get_lattice.argtypes = [P, P, P, P, P]
+        lib.orc_get_normals.argtypes = [P, P]
         lib.orc_diag.argtypes = [P, dp]
         lib.orc_threads.restype = C.c_int
         _lib = lib
@@ -141,6 +142,11 @@ class Oracle:
         k = np.empty((self.N, self.Q))
         _load().orc_get_link_k(self._h, _ptr(k))
         return k
+
+    def normals(self):
+        n = np.empty((self.N, 3))
+        _load().orc_get_normals(self._h, _ptr(n))
+        return n
 
     def lattice(self):
         e = np.empty((self.Q, 3), np.int32)

@@ -179,6 +179,8 @@ static long site(const orc *o, int x, int y, int z, int dx, int dy, int dz, int 
 
 /* ------------------------------------------------------------------------- */
 
+static void fd_normal(orc *o, long s);
+
 orc *orc_create(const orc_params *p, const uint8_t *solid, const double *normals,
                 const double *k_r, const double *phi0)
 {
@@ -190,7 +192,15 @@ orc *orc_create(const orc_params *p, const uint8_t *solid, const double *normals
     o->solid = (uint8_t *)malloc(N);
     memcpy(o->solid, solid, N);
     o->nrm = (double *)calloc(N * 3, sizeof(double));
-    if (normals) memcpy(o->nrm, normals, sizeof(double) * N * 3);
+    if (normals) {
+        memcpy(o->nrm, normals, sizeof(double) * N * 3);
+    } else {
+        /* no normals given: isotropic lattice gradient of the solid indicator
+         * (the paper computes wall normals with an isotropic finite difference,
+         * Sec. 3.2) */
+        for (long n = 0; n < N; n++)
+            if (o->solid[n]) fd_normal(o, n);
+    }
     o->kr = (double *)malloc(sizeof(double) * N);
     for (long n = 0; n < N; n++) o->kr[n] = k_r ? k_r[n] : p->k_r;
     o->phi = (double *)malloc(sizeof(double) * N);
@@ -619,6 +629,11 @@ void orc_get_link_k(const orc *o, double *k)
             if (y >= 0 && o->solid[y]) k[n * Q + i] = link_k(o, y, i);
         }
     }
+}
+
+void orc_get_normals(const orc *o, double *nrm)
+{
+    memcpy(nrm, o->nrm, sizeof(double) * 3 * o->N);
 }
 
 void orc_get_lattice(const orc *o, int *e, double *wf, double *ws, double *cs2)

@@ -1,0 +1,516 @@
+// lbm_api.hip -- the C ABI: parameter validation, workspace carving, context
+// life cycle, and the ordering of the kernel launches on the caller's stream.
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+#include <string>
+
+#include "lbm_internal.hpp"
+
+using namespace lbm;
+
+namespace {
+
+thread_local std::string g_create_err;
+
+constexpr size_t ALIGN = 256;
+
+size_t up(size_t x) { return (x + ALIGN - 1) / ALIGN * ALIGN; }
+
+std::string check_params(const lbm_params &p) {
+    char b[256];
+    if (p.dim != 2 && p.dim != 3) return "dim must be 2 or 3";
+    if (p.nx < 1 || p.ny < 1 || p.nz < 1) return "nx, ny, nz must be >= 1";
+    if (p.dim == 2 && (p.nz != 1 || p.fluid_q != 9)) return "dim = 2 requires nz = 1 and fluid_q = 9";
+    if (p.dim == 3 && p.fluid_q != 19) return "dim = 3 requires fluid_q = 19";
+    if (p.dim == 3 && p.nz < 2) return "dim = 3 requires nz >= 2";
+    if (p.solute_q != p.fluid_q) return "solute_q must equal fluid_q";
+    if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV) return "unknown precision";
+    if (p.rbc_mechanics != LBM_PRECOLL && p.rbc_mechanics != LBM_POSTCOLL) return "unknown rbc_mechanics";
+    if (p.rbc_scheme < LBM_SNEW || p.rbc_scheme > LBM_ABB) return "unknown rbc_scheme";
+    if (!(p.tau_ns > 0.5) || !(p.tau_ad > 0.5)) return "tau_ns and tau_ad must be > 1/2";
+    if (!(p.j0 < 1.0)) return "j0 must be < 1 (negative selects the standard weights)";
+    if (!(p.v_m >= 0.0) || !(p.a_m >= 0.0)) return "v_m and a_m must be >= 0";
+    if (!(p.k_r >= 0.0)) return "k_r must be >= 0";
+    for (int d = 0; d < 3; d++)
+        if (p.periodic[d] != 0 && p.periodic[d] != 1) return "periodic[] entries must be 0 or 1";
+    if (p.xwrap_shift_y != 0) {
+        if (!p.periodic[0] || !p.periodic[1]) return "xwrap_shift_y needs periodic x and y";
+        if (p.xwrap_shift_y <= -p.ny || p.xwrap_shift_y >= p.ny) return "|xwrap_shift_y| must be < ny";
+    }
+    if (p.inlet_axis < -1 || p.inlet_axis >= p.dim) return "inlet_axis must be -1 or an axis of the lattice";
+    if (p.inlet_axis == 0 && p.xwrap_shift_y != 0) return "inlet_axis 0 is incompatible with xwrap_shift_y";
+    const double N = (double)p.nx * p.ny * p.nz;
+    if (N >= 2147483647.0) {
+        snprintf(b, sizeof b, "lattice of %.0f nodes exceeds 2^31 - 1", N);
+        return b;
+    }
+    if (p.phase_change != 0 && p.phase_change != 1) return "phase_change must be 0 or 1";
+    return "";
+}
+
+int64_t default_links(const lbm_params &p) {
+    const int64_t N = (int64_t)p.nx * p.ny * p.nz;
+    int64_t m = p.max_links > 0 ? p.max_links : N * (p.fluid_q - 1) / 8;
+    if (m < 4096) m = 4096;
+    if (m > 2147483000LL) m = 2147483000LL;
+    return m;
+}
+
+}  // namespace
+
+namespace lbm {
+
+// Carve the workspace.  With base == nullptr only the size is computed.
+size_t workspace_layout(const lbm_params &p, Ctx *c, char *base) {
+    const long N = (long)p.nx * p.ny * p.nz;
+    const long S = (N + 63) / 64 * 64;
+    const int Q = p.fluid_q;
+    const size_t ts = p.precision == LBM_FP64 ? 8 : 4;
+    const int64_t L = default_links(p);
+    size_t off = 0;
+    auto take = [&](size_t bytes) -> char * {
+        char *r = base ? base + off : nullptr;
+        off += up(bytes);
+        return r;
+    };
+    char *f0 = take(ts * Q * S), *f1 = take(ts * Q * S), *g0 = take(ts * Q * S), *g1 = take(ts * Q * S);
+    char *flags = take(4 * S), *rmask = take(4 * S), *lbase = take(4 * S), *cnt = take(4 * S),
+         *sidx = take(4 * S);
+    char *phi = take(8 * S), *kr = take(8 * S), *nrm = take(24 * S), *solid = take(S);
+    char *lbeta = take(ts * L), *lq = take(ts * L), *lnode = take(4 * L), *lsolid = take(4 * L),
+         *ldir = take(L);
+    char *sif = take(4 * L), *soff = take(4 * (L + 1)), *slinks = take(4 * L);
+    char *bsum = take(4 * ((S + 4095) / 4096 + 64));
+    char *dacc = take(8 * 64), *iacc = take(4 * 64);
+    if (c && base) {
+        c->N = N;
+        c->S = S;
+        c->Q = Q;
+        c->max_links = L;
+        c->f[0] = f0; c->f[1] = f1; c->g[0] = g0; c->g[1] = g1;
+        c->flags = (uint32_t *)flags; c->rmask = (uint32_t *)rmask;
+        c->lbase = (int32_t *)lbase; c->cnt = (int32_t *)cnt; c->sidx = (int32_t *)sidx;
+        c->phi = (double *)phi; c->kr = (double *)kr; c->nrm = (double *)nrm;
+        c->solid = (uint8_t *)solid;
+        c->lbeta = lbeta; c->lq = lq; c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
+        c->ldir = (uint8_t *)ldir;
+        c->sif = (int32_t *)sif; c->soff = (int32_t *)soff; c->slinks = (int32_t *)slinks;
+        c->bsum = (int32_t *)bsum;
+        c->dacc = (double *)dacc; c->iacc = (int32_t *)iacc;
+    }
+    return off;
+}
+
+}  // namespace lbm
+
+// true when p is device memory the GPU can address (NULL counts as valid for
+// optional arguments and is checked separately where required)
+static bool dev_ptr_ok(const void *p) {
+    if (!p) return true;
+    hipPointerAttribute_t a;
+    hipError_t e = hipPointerGetAttributes(&a, p);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return false;
+    }
+    return a.type == hipMemoryTypeDevice || a.type == hipMemoryTypeManaged;
+}
+
+static lbm_status bad_ptr(Ctx *c, const char *what) {
+    c->err = std::string(what) + " is not a device pointer";
+    return LBM_EINVAL;
+}
+
+static lbm_status dev_err(Ctx *c, hipError_t e, const char *what) {
+    c->err = std::string(what) + ": " + hipGetErrorString(e);
+    return LBM_EDEVICE;
+}
+
+static void setup_lattice(Ctx *c) {
+    const lbm_params &p = c->p;
+    c->dim = p.dim;
+    c->fp64 = p.precision == LBM_FP64;
+    c->box.nx = p.nx;
+    c->box.ny = p.ny;
+    c->box.nz = p.nz;
+    for (int d = 0; d < 3; d++) c->box.per[d] = p.periodic[d];
+    c->box.shift = p.xwrap_shift_y;
+    c->box.inlet_axis = p.inlet_axis;
+    const double *w = p.fluid_q == 9 ? D2Q9::w : D3Q19::w;
+    const double w0 = w[0];
+    for (int i = 0; i < 19; i++) c->ws[i] = 0.0;
+    if (p.j0 < 0) {
+        for (int i = 0; i < p.fluid_q; i++) c->ws[i] = w[i];
+        c->cs2s = 1.0 / 3.0;
+    } else {
+        // rest fraction: w_0 = J0, moving weights and c_s^2 scaled by (1-J0)/(1-w0)
+        const double sc = (1.0 - p.j0) / (1.0 - w0);
+        c->ws[0] = p.j0;
+        for (int i = 1; i < p.fluid_q; i++) c->ws[i] = w[i] * sc;
+        c->cs2s = sc / 3.0;
+    }
+    c->gamma = p.tau_ad / (p.tau_ad - 0.5);
+}
+
+extern "C" {
+
+lbm_status lbm_workspace_bytes(const lbm_params *params, size_t *bytes) {
+    if (!params || !bytes) return LBM_EINVAL;
+    std::string m = check_params(*params);
+    if (!m.empty()) {
+        g_create_err = m;
+        return LBM_EINVAL;
+    }
+    *bytes = workspace_layout(*params, nullptr, nullptr);
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params *params, void *dev_workspace, size_t bytes, void *hip_stream,
+                      lbm_ctx **out) {
+    if (!params || !out) {
+        g_create_err = "null argument";
+        return LBM_EINVAL;
+    }
+    *out = nullptr;
+    std::string m = check_params(*params);
+    if (!m.empty()) {
+        g_create_err = m;
+        return LBM_EINVAL;
+    }
+    const size_t need = workspace_layout(*params, nullptr, nullptr);
+    if (!dev_workspace || bytes < need) {
+        g_create_err = "workspace of " + std::to_string(bytes) + " bytes is smaller than the " +
+                       std::to_string(need) + " needed";
+        return LBM_ENOMEM;
+    }
+    if (((uintptr_t)dev_workspace) % ALIGN != 0) {
+        g_create_err = "workspace must be 256-byte aligned";
+        return LBM_EINVAL;
+    }
+    if (!dev_ptr_ok(dev_workspace)) {
+        g_create_err = "workspace is not device memory";
+        return LBM_EINVAL;
+    }
+    Ctx *c = new (std::nothrow) Ctx();
+    if (!c) {
+        g_create_err = "host allocation failed";
+        return LBM_ENOMEM;
+    }
+    c->p = *params;
+    c->stream = (hipStream_t)hip_stream;
+    setup_lattice(c);
+    c->ws_bytes = bytes;
+    workspace_layout(c->p, c, (char *)dev_workspace);
+    c->cur = 0;
+    c->n_links = c->n_sif = 0;
+    c->step = c->n_events = 0;
+    c->have_geom = c->have_state = false;
+    c->have_events = false;
+    *out = (lbm_ctx *)c;
+    return LBM_OK;
+}
+
+void lbm_destroy(lbm_ctx *ctx) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return;
+    if (c->have_events)
+        for (int k = 0; k < 4; k++) (void)hipEventDestroy(c->ev[k]);
+    delete c;
+}
+
+const char *lbm_last_error(const lbm_ctx *ctx) {
+    if (!ctx) return g_create_err.c_str();
+    return ((const Ctx *)ctx)->err.c_str();
+}
+
+lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *normals,
+                            const double *k_r, const double *phi0) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (!solid) {
+        c->err = "solid mask is required";
+        return LBM_EINVAL;
+    }
+    if (c->p.phase_change) {
+        c->err = "phase_change is not supported by this build";
+        return LBM_EINVAL;
+    }
+    if (!dev_ptr_ok(solid)) return bad_ptr(c, "solid");
+    if (!dev_ptr_ok(normals)) return bad_ptr(c, "normals");
+    if (!dev_ptr_ok(k_r)) return bad_ptr(c, "k_r");
+    if (!dev_ptr_ok(phi0)) return bad_ptr(c, "phi0");
+    int64_t nl = 0, ns = 0;
+    hipError_t e = launch_geometry(*c, solid, normals, k_r, phi0, &nl, &ns);
+    if (e != hipSuccess) return dev_err(c, e, "geometry preparation");
+    if (nl > c->max_links) {
+        c->err = "geometry has " + std::to_string(nl) + " reactive links; params.max_links allows " +
+                 std::to_string(c->max_links);
+        c->have_geom = false;
+        return LBM_ECAPACITY;
+    }
+    c->n_links = nl;
+    c->n_sif = ns;
+    c->have_geom = true;
+    c->have_state = false;
+    return LBM_OK;
+}
+
+lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u, const double *cc) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (!c->have_geom) {
+        c->err = "lbm_init_fields before lbm_set_geometry";
+        return LBM_ESTATE;
+    }
+    if (!dev_ptr_ok(rho)) return bad_ptr(c, "rho");
+    if (!dev_ptr_ok(u)) return bad_ptr(c, "u");
+    if (!dev_ptr_ok(cc)) return bad_ptr(c, "c");
+    hipError_t e = launch_init(*c, rho, u, cc);
+    if (e != hipSuccess) return dev_err(c, e, "init");
+    c->step = 0;
+    c->have_state = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (nsteps < 0) {
+        c->err = "nsteps must be >= 0";
+        return LBM_EINVAL;
+    }
+    if (!c->have_state) {
+        c->err = "lbm_step before lbm_init_fields";
+        return LBM_ESTATE;
+    }
+    for (int32_t t = 0; t < nsteps; t++) {
+        hipError_t e = launch_step(*c);
+        if (e != hipSuccess) return dev_err(c, e, "step launch");
+        c->step++;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c || !ms || nsteps < 0) return LBM_EINVAL;
+    if (!c->have_state) {
+        c->err = "lbm_step_timed before lbm_init_fields";
+        return LBM_ESTATE;
+    }
+    if (!c->have_events) {
+        for (int k = 0; k < 4; k++) {
+            hipError_t e = hipEventCreate(&c->ev[k]);
+            if (e != hipSuccess) return dev_err(c, e, "hipEventCreate");
+        }
+        c->have_events = true;
+    }
+    ms[0] = ms[1] = 0.0;
+    for (int32_t t = 0; t < nsteps; t++) {
+        hipError_t e = launch_step(*c, c->ev);
+        if (e != hipSuccess) return dev_err(c, e, "step launch");
+        c->step++;
+        e = hipEventSynchronize(c->ev[3]);
+        if (e != hipSuccess) return dev_err(c, e, "event sync");
+        float a = 0.f, b = 0.f;
+        e = hipEventElapsedTime(&a, c->ev[0], c->ev[1]);
+        if (e == hipSuccess) e = hipEventElapsedTime(&b, c->ev[2], c->ev[3]);
+        if (e != hipSuccess) return dev_err(c, e, "event timing");
+        ms[0] += a;
+        ms[1] += b;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_get_fields(lbm_ctx *ctx, double *rho, double *u, double *cc, double *phi,
+                          uint8_t *type) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (!c->have_state) {
+        c->err = "no state: call lbm_init_fields first";
+        return LBM_ESTATE;
+    }
+    if (!dev_ptr_ok(rho)) return bad_ptr(c, "rho");
+    if (!dev_ptr_ok(u)) return bad_ptr(c, "u");
+    if (!dev_ptr_ok(cc)) return bad_ptr(c, "c");
+    if (!dev_ptr_ok(phi)) return bad_ptr(c, "phi");
+    if (!dev_ptr_ok(type)) return bad_ptr(c, "type");
+    hipError_t e = launch_fields(*c, rho, u, cc, phi, type);
+    if (e != hipSuccess) return dev_err(c, e, "get_fields");
+    return LBM_OK;
+}
+
+lbm_status lbm_get_pops(lbm_ctx *ctx, double *f, double *g) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (!c->have_state) {
+        c->err = "no state: call lbm_init_fields first";
+        return LBM_ESTATE;
+    }
+    if (!dev_ptr_ok(f)) return bad_ptr(c, "f");
+    if (!dev_ptr_ok(g)) return bad_ptr(c, "g");
+    hipError_t e = launch_pops(*c, f, g);
+    if (e != hipSuccess) return dev_err(c, e, "get_pops");
+    return LBM_OK;
+}
+
+lbm_status lbm_get_exchange(lbm_ctx *ctx, double *q) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c || !q) return LBM_EINVAL;
+    if (!c->have_geom) {
+        c->err = "no geometry";
+        return LBM_ESTATE;
+    }
+    if (!dev_ptr_ok(q)) return bad_ptr(c, "q");
+    hipError_t e = launch_exchange(*c, q);
+    if (e != hipSuccess) return dev_err(c, e, "get_exchange");
+    return LBM_OK;
+}
+
+lbm_status lbm_get_diag(lbm_ctx *ctx, lbm_diag *out) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c || !out) return LBM_EINVAL;
+    if (!c->have_state) {
+        c->err = "no state: call lbm_init_fields first";
+        return LBM_ESTATE;
+    }
+    double sums[3] = {0, 0, 0};
+    int32_t nan_flag = 0;
+    hipError_t e = launch_diag(*c, sums, &nan_flag);
+    if (e != hipSuccess) return dev_err(c, e, "diag");
+    memset(out, 0, sizeof *out);
+    out->step = c->step;
+    out->n_events = c->n_events;
+    out->n_links = c->n_links;
+    out->n_solid_iface = c->n_sif;
+    out->n_fluid = c->n_fluid;
+    out->n_fluid_iface = c->n_fluid_iface;
+    out->wall_exchange = sums[0];
+    out->mass_c = sums[1];
+    out->phi_sum = sums[2];
+    out->nan_flag = nan_flag;
+    if (nan_flag) {
+        c->err = "non-finite population";
+        return LBM_ENUMERIC;
+    }
+    return LBM_OK;
+}
+
+// state layout: header (64 B) | f | g (Q*N of T each) | phi | kr (N doubles) |
+// nrm (3N doubles) | solid (N bytes)
+struct StateHeader {
+    uint64_t magic;
+    int64_t N, Q, precision, step, n_events;
+    double wall_ex;
+    int64_t pad;
+};
+
+lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes) {
+    const Ctx *c = (const Ctx *)ctx;
+    if (!c || !bytes) return LBM_EINVAL;
+    const size_t ts = c->fp64 ? 8 : 4;
+    *bytes = sizeof(StateHeader) + 2 * ts * c->Q * c->N + 8 * 5 * c->N + c->N;
+    return LBM_OK;
+}
+
+lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c || !dev_buf) return LBM_EINVAL;
+    size_t need = 0;
+    lbm_state_bytes(ctx, &need);
+    if (bytes < need) {
+        c->err = "state buffer too small";
+        return LBM_ENOMEM;
+    }
+    if (!c->have_state) {
+        c->err = "no state to save";
+        return LBM_ESTATE;
+    }
+    if (!dev_ptr_ok(dev_buf)) return bad_ptr(c, "state buffer");
+    const size_t ts = c->fp64 ? 8 : 4;
+    const size_t pb = ts * c->N;
+    StateHeader h;
+    memset(&h, 0, sizeof h);
+    h.magic = 0x4c424d5242433031ULL;
+    h.N = c->N; h.Q = c->Q; h.precision = c->p.precision; h.step = c->step; h.n_events = c->n_events;
+    double wex = 0;
+    hipError_t e = hipMemcpyAsync(&wex, c->dacc, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_err(c, e, "save_state");
+    h.wall_ex = wex;
+    char *b = (char *)dev_buf;
+    e = hipMemcpyAsync(b, &h, sizeof h, hipMemcpyHostToDevice, c->stream);
+    size_t off = sizeof h;
+    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
+        e = hipMemcpyAsync(b + off, (char *)c->f[c->cur] + i * ts * c->S, pb, hipMemcpyDeviceToDevice, c->stream);
+    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
+        e = hipMemcpyAsync(b + off, (char *)c->g[c->cur] + i * ts * c->S, pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->phi, 8 * c->N, hipMemcpyDeviceToDevice, c->stream);
+    off += 8 * c->N;
+    if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->kr, 8 * c->N, hipMemcpyDeviceToDevice, c->stream);
+    off += 8 * c->N;
+    if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->nrm, 24 * c->N, hipMemcpyDeviceToDevice, c->stream);
+    off += 24 * c->N;
+    if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->solid, c->N, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_err(c, e, "save_state");
+    return LBM_OK;
+}
+
+lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c || !dev_buf) return LBM_EINVAL;
+    size_t need = 0;
+    lbm_state_bytes(ctx, &need);
+    if (bytes < need) {
+        c->err = "state buffer too small";
+        return LBM_ENOMEM;
+    }
+    if (!dev_ptr_ok(dev_buf)) return bad_ptr(c, "state buffer");
+    StateHeader h;
+    const char *b = (const char *)dev_buf;
+    hipError_t e = hipMemcpyAsync(&h, b, sizeof h, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_err(c, e, "load_state");
+    if (h.magic != 0x4c424d5242433031ULL || h.N != c->N || h.Q != c->Q ||
+        h.precision != c->p.precision) {
+        c->err = "state buffer does not match this context";
+        return LBM_EINVAL;
+    }
+    const size_t ts = c->fp64 ? 8 : 4;
+    const size_t pb = ts * c->N;
+    const size_t pops = sizeof h, phio = pops + 2 * c->Q * pb;
+    // geometry first (rebuilds links from solid, normals and k_r), then state
+    const double *phi_src = (const double *)(b + phio);
+    const double *kr_src = (const double *)(b + phio + 8 * c->N);
+    const double *nrm_src = (const double *)(b + phio + 16 * c->N);
+    const uint8_t *sol_src = (const uint8_t *)(b + phio + 40 * c->N);
+    int64_t nl = 0, ns = 0;
+    e = launch_geometry(*c, sol_src, nrm_src, kr_src, phi_src, &nl, &ns);
+    if (e != hipSuccess) return dev_err(c, e, "load_state geometry");
+    if (nl > c->max_links) {
+        c->err = "saved geometry exceeds max_links";
+        return LBM_ECAPACITY;
+    }
+    c->n_links = nl;
+    c->n_sif = ns;
+    c->have_geom = true;
+    c->cur = 0;
+    size_t off = pops;
+    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
+        e = hipMemcpyAsync((char *)c->f[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
+    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
+        e = hipMemcpyAsync((char *)c->g[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
+    double wex = h.wall_ex;
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dacc, &wex, sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return dev_err(c, e, "load_state");
+    c->step = h.step;
+    c->n_events = h.n_events;
+    c->have_state = true;
+    return LBM_OK;
+}
+
+}  // extern "C"

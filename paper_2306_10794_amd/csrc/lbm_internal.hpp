@@ -1,0 +1,89 @@
+// lbm_internal.hpp -- context layout and kernel launchers shared by the C ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+
+#include "../../include/lbmrbc.h"
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+// Per-step kernel arguments (passed by value; lives in the kernarg segment).
+template <typename T>
+struct StepArgs {
+    const T *fin;
+    T *fout;
+    const T *gin;
+    T *gout;
+    const uint32_t *flags;
+    const uint32_t *rmask;   // reactive-link bits per node (read at special nodes)
+    const int32_t *lbase;    // first link of each node with links
+    const T *lbeta;          // per link: (1 - k)/(1 + k)
+    T *lq;                   // per link: mass exchanged in this step
+    double *phi;
+    long N;                  // nodes
+    long S;                  // stride between directions (N rounded up)
+    Box box;
+    int mech;
+    // constants of the step, FP64 (the kernels compute in FP64)
+    double omega_f, omega_g, force_fac;
+    double F[3];
+    double ws[19];           // solute weights (rest fraction)
+    double inv_cs2s;
+    double rho0, c_ref;
+    double ceq_dev;          // C_eq - C_ref
+    double c_in;
+    double vma;              // V_m a_m
+};
+
+struct Ctx {
+    lbm_params p;
+    hipStream_t stream;
+    int Q, dim;
+    long N, S;               // nodes and padded stride
+    Box box;
+    bool fp64;
+    double gamma, cs2s, ws[19];
+    int64_t max_links;
+    // device arrays carved from the caller workspace
+    void *f[2], *g[2];       // populations, [Q][S] each (T = double or float)
+    uint32_t *flags, *rmask;
+    int32_t *lbase;
+    int32_t *cnt;            // scratch [N] (link counts, then solid-side counts)
+    int32_t *sidx;           // scratch [N]
+    double *phi, *kr, *nrm;  // [N], [N], [N][3]
+    uint8_t *solid;          // [N]
+    void *lbeta, *lq;        // [max_links] of T
+    int32_t *lnode, *lsolid; // [max_links]
+    uint8_t *ldir;           // [max_links]
+    int32_t *sif, *soff, *slinks; // solid interface list [max_links], offsets [max_links+1], [max_links]
+    int32_t *bsum;           // scan scratch
+    double *dacc;            // device accumulators: [0] wall exchange, [1..3] diag sums
+    int32_t *iacc;           // device int accumulators
+    size_t ws_bytes;
+    int cur;                 // buffer holding the current state
+    int64_t n_links, n_sif, n_fluid, n_fluid_iface;
+    int64_t step, n_events;
+    bool have_geom, have_state;
+    hipEvent_t ev[4];
+    bool have_events;
+    std::string err;
+};
+
+size_t workspace_layout(const lbm_params &p, Ctx *c, char *base);
+
+// launchers (return hipError_t of the first failing launch)
+// ev: optional 4 events recorded around the two kernels of the step
+hipError_t launch_step(Ctx &c, hipEvent_t *ev = nullptr);
+hipError_t launch_geometry(Ctx &c, const uint8_t *solid, const double *normals, const double *k_r,
+                           const double *phi0, int64_t *n_links, int64_t *n_sif);
+hipError_t launch_init(Ctx &c, const double *rho, const double *u, const double *cc);
+hipError_t launch_fields(Ctx &c, double *rho, double *u, double *cc, double *phi, uint8_t *type);
+hipError_t launch_pops(Ctx &c, double *f, double *g);
+hipError_t launch_exchange(Ctx &c, double *q);
+hipError_t launch_diag(Ctx &c, double *sums, int32_t *nan_flag);
+
+}  // namespace lbm

@@ -1,0 +1,115 @@
+"""A small convenience wrapper around the C ABI for one lattice on one GPU.
+
+torch provides the device memory (the workspace, input and output arrays) and
+the stream; the library does all the work.
+"""
+from __future__ import annotations
+
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib as L
+
+
+def params_from_case(case, precision: int = L.LBM_FP32_DEV, max_links: int = 0) -> L.lbm_params:
+    """lbm_params of an ``lbm_inputs.Case`` (plain field copy)."""
+    p = L.lbm_params()
+    p.dim, p.nx, p.ny, p.nz = case.dim, case.nx, case.ny, case.nz
+    p.fluid_q = p.solute_q = case.q
+    p.precision = precision
+    p.rbc_mechanics, p.rbc_scheme = case.mechanics, case.scheme
+    p.tau_ns, p.tau_ad, p.j0 = case.tau_ns, case.tau_ad, case.j0
+    p.force[:] = list(case.force)
+    p.rho0, p.c_ref = case.rho0, case.c_ref
+    p.c_eq, p.k_r, p.v_m, p.a_m = case.c_eq, case.k_r, case.v_m, case.a_m
+    p.periodic[:] = list(case.periodic)
+    p.xwrap_shift_y, p.inlet_axis, p.c_in = case.xwrap_shift_y, case.inlet_axis, case.c_in
+    p.phase_change = case.phase_change
+    p.max_links = max_links
+    return p
+
+
+def _dev(a, dtype, device):
+    if a is None:
+        return None
+    if isinstance(a, torch.Tensor):
+        return a.to(device=device, dtype=dtype).contiguous()
+    return torch.from_numpy(np.ascontiguousarray(a)).to(device=device, dtype=dtype)
+
+
+class Simulation:
+    """One reactive-LBM context: workspace + geometry + state on ``device``."""
+
+    def __init__(self, case, precision: int = L.LBM_FP32_DEV, device="cuda", stream=None,
+                 max_links: int = 0, init: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the reactive LBM library needs a GPU (none is visible)")
+        self.case = case
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = params_from_case(case, precision, max_links)
+        self.nbytes = L.lbm_workspace_bytes(self.params)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx = L.lbm_create(self.params, self.workspace, self.nbytes, self.stream)
+        self.N, self.Q = case.n, case.q
+        self._geom = dict(
+            solid=_dev(case.solid_flat(), torch.uint8, self.device),
+            normals=_dev(case.normals_flat(), torch.float64, self.device),
+            k_r=_dev(case.k_r_field, torch.float64, self.device),
+            phi0=_dev(case.phi0, torch.float64, self.device))
+        L.lbm_set_geometry(self.ctx, **self._geom)
+        if init:
+            self.init_fields(case.rho_flat(), case.u_flat(), case.c_flat())
+
+    def init_fields(self, rho=None, u=None, c=None):
+        self._init = [_dev(rho, torch.float64, self.device), _dev(u, torch.float64, self.device),
+                      _dev(c, torch.float64, self.device)]
+        L.lbm_init_fields(self.ctx, *self._init)
+
+    def step(self, n: int = 1):
+        L.lbm_step(self.ctx, n)
+
+    def fields(self) -> dict:
+        kw = dict(rho=torch.empty(self.N, dtype=torch.float64, device=self.device),
+                  u=torch.empty((self.N, 3), dtype=torch.float64, device=self.device),
+                  c=torch.empty(self.N, dtype=torch.float64, device=self.device),
+                  phi=torch.empty(self.N, dtype=torch.float64, device=self.device),
+                  type=torch.empty(self.N, dtype=torch.uint8, device=self.device))
+        L.lbm_get_fields(self.ctx, **kw)
+        return kw
+
+    def pops(self):
+        f = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
+        g = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
+        L.lbm_get_pops(self.ctx, f, g)
+        return f, g
+
+    def exchange(self):
+        q = torch.empty((self.N, self.Q), dtype=torch.float64, device=self.device)
+        L.lbm_get_exchange(self.ctx, q)
+        return q
+
+    def diag(self) -> dict:
+        return L.lbm_get_diag(self.ctx)
+
+    def save_state(self) -> torch.Tensor:
+        n = L.lbm_state_bytes(self.ctx)
+        buf = torch.empty(n, dtype=torch.uint8, device=self.device)
+        L.lbm_save_state(self.ctx, buf, n)
+        return buf
+
+    def load_state(self, buf: torch.Tensor):
+        L.lbm_load_state(self.ctx, buf, buf.numel())
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

@@ -1,0 +1,94 @@
+"""C-ABI contract checks that need no GPU: the library loads, exports every
+function the header declares, and rejects bad parameters on the host."""
+import ctypes as C
+import subprocess
+
+import pytest
+
+
+def _L():
+    from paper_2306_10794_amd import _lib
+    return _lib
+
+
+def _good_params(**kw):
+    L = _L()
+    p = L.lbm_params()
+    p.dim, p.nx, p.ny, p.nz = 2, 64, 32, 1
+    p.fluid_q = p.solute_q = 9
+    p.precision = L.LBM_FP64
+    p.tau_ns, p.tau_ad, p.j0 = 1.0, 0.8, -1.0
+    p.c_eq, p.k_r, p.v_m, p.a_m = 1.0, 1e-3, 1.0, 1.0
+    p.periodic[:] = [1, 1, 1]
+    p.inlet_axis = -1
+    for k, v in kw.items():
+        if k in ("force", "periodic"):
+            getattr(p, k)[:] = v
+        else:
+            setattr(p, k, v)
+    return p
+
+
+def test_library_exports_every_header_symbol():
+    L = _L()
+    names = L.header_symbols()
+    assert "lbm_step" in names and "lbm_create" in names and len(names) >= 14
+    out = subprocess.run(["nm", "-D", "--defined-only", L.LIB_PATH], capture_output=True,
+                         text=True, check=True).stdout
+    exported = {line.split()[-1] for line in out.splitlines() if " T " in line}
+    missing = [n for n in names if n not in exported]
+    assert not missing, missing
+    for n in names:
+        assert getattr(L.lib, n) is not None
+
+
+def test_struct_layout_matches_header():
+    """The ctypes mirror has the header's field order; sizes are multiples of 8."""
+    L = _L()
+    assert C.sizeof(L.lbm_params) % 8 == 0
+    assert L.lbm_params.max_links.offset == C.sizeof(L.lbm_params) - 8
+    assert C.sizeof(L.lbm_diag) == 6 * 8 + 3 * 8 + 8
+
+
+def test_workspace_bytes_scales_with_lattice():
+    L = _L()
+    a = L.lbm_workspace_bytes(_good_params())
+    b = L.lbm_workspace_bytes(_good_params(nx=128))
+    c32 = L.lbm_workspace_bytes(_good_params(precision=L.LBM_FP32_DEV))
+    assert b > a > c32 > 0
+    # populations dominate: 4 buffers x Q x N x 8 bytes in FP64
+    assert a >= 4 * 9 * 64 * 32 * 8
+
+
+@pytest.mark.parametrize("kw,frag", [
+    (dict(dim=4), "dim"),
+    (dict(nz=2), "nz = 1"),
+    (dict(fluid_q=19), "fluid_q"),
+    (dict(solute_q=5), "solute_q"),
+    (dict(precision=7), "precision"),
+    (dict(rbc_mechanics=3), "rbc_mechanics"),
+    (dict(rbc_scheme=9), "rbc_scheme"),
+    (dict(tau_ns=0.5), "tau"),
+    (dict(tau_ad=0.4), "tau"),
+    (dict(j0=1.0), "j0"),
+    (dict(v_m=-1.0), "v_m"),
+    (dict(k_r=-1e-3), "k_r"),
+    (dict(xwrap_shift_y=5, periodic=(1, 0, 1)), "periodic"),
+    (dict(xwrap_shift_y=40), "xwrap"),
+    (dict(inlet_axis=2), "inlet_axis"),
+    (dict(nx=70000, ny=70000), "exceeds"),
+])
+def test_invalid_parameters_are_rejected(kw, frag):
+    L = _L()
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_workspace_bytes(_good_params(**kw))
+    assert ei.value.status == L.LBM_EINVAL
+    assert frag in L.lbm_last_error(None)
+
+
+def test_create_without_workspace_is_enomem():
+    L = _L()
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_create(_good_params(), None, 0, stream=0)
+    assert ei.value.status == L.LBM_ENOMEM
+    assert "needed" in L.lbm_last_error(None)

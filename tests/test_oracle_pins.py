@@ -274,6 +274,26 @@ def test_infinite_rate_is_anti_bounce_back():
     assert np.abs(a.pops()[1] - b.pops()[1]).max() < 1e-12
 
 
+def test_gradient_normals_of_straight_walls():
+    """Without given normals the oracle uses the isotropic lattice gradient of
+    the solid indicator.  On a straight wall that gradient is exactly normal to
+    the wall: +y for the bottom row of a channel, (1, 1)/sqrt(2) on the
+    interface of a 45 degree half-plane away from its ends."""
+    solid, _ = geometry.plane_channel(12, 10, (0, 9))
+    o = Oracle(Case(name="n", dim=2, nx=12, ny=10, nz=1, q=9, solid=solid), init=False)
+    n = o.normals().reshape(10, 12, 3)
+    assert np.allclose(n[0, :, :], [0, 1, 0], atol=1e-15)
+    assert np.allclose(n[9, :, :], [0, -1, 0], atol=1e-15)
+    N = 24
+    y, x = np.mgrid[0:N, 0:N]
+    solid = ((x + y) < N).astype(np.uint8)[None]
+    o = Oracle(Case(name="d", dim=2, nx=N, ny=N, nz=1, q=9, solid=solid, periodic=(0, 0, 1)),
+               init=False)
+    n = o.normals().reshape(N, N, 3)
+    iface = (x + y == N - 1) & (x > 2) & (y > 2)
+    assert np.allclose(n[iface][:, :2], np.sqrt(0.5), atol=1e-15)
+
+
 @pytest.mark.parametrize("nx,shift", [(512, 0), (512, 256), (512, 296), (512, 512), (300, 97)])
 def test_orientation_identity(nx, shift):
     """Sum over the reactive links of w_i max(0, e_i.n), per unit wall length,
