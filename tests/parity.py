@@ -39,9 +39,9 @@ def run_pair(case, precision, steps, log_name=None):
 def rel_errors(res, case, u_floor=0.0):
     """Max errors per field, each divided by its scale (solid nodes excluded).
 
-    u is scaled by max(max |u|, u_floor): in FP64 the rounding error of a
-    velocity is set by the populations it is summed from (~1e-16 absolute),
-    not by |u|, so slow flows use a floor of 1e-3 (a typical lattice velocity)."""
+    u is scaled by max(max |u|, u_floor); the FP64 tests pass the lattice sound
+    speed as the floor, since the rounding error of a velocity is set by the
+    populations it is summed from, not by |u|."""
     fl = res["ora"]["fields"]["type"] == 0
     g, o = res["gpu"], res["ora"]
     out = {}

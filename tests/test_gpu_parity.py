@@ -1,11 +1,12 @@
 """Parity of the HIP library (called through the C ABI) with the FP64 oracle.
 
 Tolerances: FP64 populations and fields agree to 1e-12 of their scale (the
-oracle and the kernels round differently, e.g. fused multiply-adds); FP32
+oracle and the kernels round differently, e.g. fused multiply-adds).  An FP64
+velocity is a difference of populations of size ~w_i rho, so after T steps its
+rounding error is ~T Q eps max f (about 1e-13 here) whatever |u| is: it is
+compared against the lattice sound speed c_s = 1/sqrt(3) as its scale.  FP32
 deviation storage agrees to 1e-5 of the field scale (max over fluid nodes of
-|gpu - oracle| / max |oracle|; u scaled by max |u|, C by max(|C|, C_eq); in
-FP64, u is scaled by max(max |u|, 1e-3) since its rounding error is set by the
-populations it is summed from), and
+|gpu - oracle| / max |oracle|; u scaled by max |u|, C by max(|C|, C_eq)), and
 the solid fraction's change phi - phi0 to 1e-5 of its largest value.  Node
 classes (solid / fluid) and the set of reactive links must match exactly.
 """
@@ -23,11 +24,12 @@ pytestmark = pytest.mark.gpu
 
 FP64, FP32 = 0, 1
 TOL = {FP64: 1e-12, FP32: 1e-5}
+CS = 3 ** -0.5   # lattice sound speed: the FP64 velocity scale
 
 
 def _assert_parity(case, precision, steps, name=None, tol=None):
     res = run_pair(case, precision, steps, name)
-    err = rel_errors(res, case, u_floor=1e-3 if precision == FP64 else 0.0)
+    err = rel_errors(res, case, u_floor=CS if precision == FP64 else 0.0)
     log(f"[parity] errors {err}")
     t = tol if tol is not None else TOL[precision]
     assert err["type"] == 0
