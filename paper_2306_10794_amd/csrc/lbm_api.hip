@@ -40,7 +40,7 @@ std::string check_params(const lbm_params &p) {
         if (p.xwrap_shift_y <= -p.ny || p.xwrap_shift_y >= p.ny) return "|xwrap_shift_y| must be < ny";
     }
     if (p.inlet_axis < -1 || p.inlet_axis >= p.dim) return "inlet_axis must be -1 or an axis of the lattice";
-    if (p.inlet_axis == 0 && p.xwrap_shift_y != 0) return "inlet_axis 0 is incompatible with xwrap_shift_y";
+    if (p.inlet_axis >= 0 && p.xwrap_shift_y != 0) return "an inlet axis is incompatible with xwrap_shift_y";
     const double N = (double)p.nx * p.ny * p.nz;
     if (N >= 2147483647.0) {
         snprintf(b, sizeof b, "lattice of %.0f nodes exceeds 2^31 - 1", N);
@@ -65,9 +65,16 @@ namespace lbm {
 // Carve the workspace.  With base == nullptr only the size is computed.
 size_t workspace_layout(const lbm_params &p, Ctx *c, char *base) {
     const long N = (long)p.nx * p.ny * p.nz;
-    const long S = (N + 63) / 64 * 64;
+    const long R = (long)p.ny * p.nz;
+    const int W = (p.nx + 63) / 64;
     const int Q = p.fluid_q;
     const size_t ts = p.precision == LBM_FP64 ? 8 : 4;
+    // direction stride: a multiple of 64 elements and an odd multiple of
+    // 64 * ts bytes, so the 2Q streams of a step do not all start on the same
+    // large power-of-two boundary
+    long S = (N + 63) / 64 * 64;
+    if ((S / 64) % 2 == 0) S += 64;
+    const long task_cap = R + N / 64 + 1;
     const int64_t L = default_links(p);
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
@@ -76,28 +83,39 @@ size_t workspace_layout(const lbm_params &p, Ctx *c, char *base) {
         return r;
     };
     char *f0 = take(ts * Q * S), *f1 = take(ts * Q * S), *g0 = take(ts * Q * S), *g1 = take(ts * Q * S);
-    char *flags = take(4 * S), *rmask = take(4 * S), *lbase = take(4 * S), *cnt = take(4 * S),
-         *sidx = take(4 * S);
-    char *phi = take(8 * S), *kr = take(8 * S), *nrm = take(24 * S), *solid = take(S);
+    char *rows = take(sizeof(RowWord) * R * W), *tasks = take(sizeof(Task) * task_cap);
+    char *nodeof = take(4 * N), *kof = take(4 * N), *lbase = take(4 * N);
+    char *flags = take(4 * N), *rmask = take(4 * N), *cnt = take(4 * N), *sidx = take(4 * N);
+    char *phi = take(8 * N), *kr = take(8 * N), *nrm = take(24 * N), *solid = take(N);
     char *lbeta = take(ts * L), *lq = take(ts * L), *lnode = take(4 * L), *lsolid = take(4 * L),
          *ldir = take(L);
+    char *iface = take(4 * N), *imask = take(4 * N);
     char *sif = take(4 * L), *soff = take(4 * (L + 1)), *slinks = take(4 * L);
-    char *bsum = take(4 * ((S + 4095) / 4096 + 64));
+    char *bsum = take(4 * ((N + 4095) / 4096 + 64));
+    char *dpart = take(16 * ((N + 255) / 256 + 1));
     char *dacc = take(8 * 64), *iacc = take(4 * 64);
     if (c && base) {
         c->N = N;
         c->S = S;
+        c->R = R;
+        c->W = W;
         c->Q = Q;
+        c->task_cap = task_cap;
         c->max_links = L;
         c->f[0] = f0; c->f[1] = f1; c->g[0] = g0; c->g[1] = g1;
+        c->rows = (RowWord *)rows; c->tasks = (Task *)tasks;
+        c->nodeof = (int32_t *)nodeof; c->kof = (int32_t *)kof; c->lbase = (int32_t *)lbase;
         c->flags = (uint32_t *)flags; c->rmask = (uint32_t *)rmask;
-        c->lbase = (int32_t *)lbase; c->cnt = (int32_t *)cnt; c->sidx = (int32_t *)sidx;
+        c->cnt = (int32_t *)cnt; c->sidx = (int32_t *)sidx;
         c->phi = (double *)phi; c->kr = (double *)kr; c->nrm = (double *)nrm;
         c->solid = (uint8_t *)solid;
-        c->lbeta = lbeta; c->lq = lq; c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
+        c->lbeta = lbeta; c->lq = lq;
+        c->iface = (int32_t *)iface; c->imask = (uint32_t *)imask;
+        c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
         c->ldir = (uint8_t *)ldir;
         c->sif = (int32_t *)sif; c->soff = (int32_t *)soff; c->slinks = (int32_t *)slinks;
         c->bsum = (int32_t *)bsum;
+        c->dpart = (double *)dpart;
         c->dacc = (double *)dacc; c->iacc = (int32_t *)iacc;
     }
     return off;

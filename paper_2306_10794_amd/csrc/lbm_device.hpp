@@ -1,8 +1,20 @@
-// lbm_device.hpp -- lattices, node flags and site arithmetic for the gfx950 kernels.
+// lbm_device.hpp -- lattices, the row-compressed fluid layout and site
+// arithmetic shared by the gfx950 kernels.
 //
 // Velocity sets: D2Q9 in the order of the paper's appendix (velocity sets);
 // D3Q19 as the rest vector, nine vectors and their negatives (e_{i+9} = -e_i).
 // The populations exported through the C ABI use these orders.
+//
+// Layout.  Populations are stored for fluid nodes only, in node order, one
+// contiguous array per direction ("compact index" k).  A fluid node's
+// neighbours are found from per-row bit masks: the box is cut into x-rows
+// (row = y + ny*z) and each row into 64-node words; for every word the
+// library keeps the 64-bit fluid mask and the compact index of the first fluid
+// node of the word (RowWord, 16 B per 64 nodes).  The compact index of the
+// fluid node at x in row r is pb + popcount(mask & ((1 << (x & 63)) - 1)) of
+// word (r, x >> 6).  One wavefront processes up to 64 consecutive fluid nodes
+// of one row (a "task"), so no lane is spent on a solid node and every load
+// and store of a wavefront touches one contiguous range per direction.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -35,28 +47,33 @@ struct D3Q19 {
                                      1.0 / 36, 1.0 / 36, 1.0 / 36, 1.0 / 36};
 };
 
-// Node flags (uint32 per node)
+constexpr int BLK = 256;
+
+// Node flags of the geometry pass (dense, uint32 per node; not read per step)
 //   bits 0..Q-1 : fluid view, upstream site x - e_i is solid or outside a
-//                 non-periodic face (halfway bounce-back for the fluid)
-//   bit 29      : node lies on a face of the box (site arithmetic must wrap)
+//                 non-periodic face
 //   bit 30      : node has at least one reactive link
 //   bit 31      : node is fluid
-constexpr uint32_t F_FACE = 1u << 29;
 constexpr uint32_t F_LINK = 1u << 30;
 constexpr uint32_t F_FLUID = 1u << 31;
-constexpr uint32_t F_DIRS = (1u << 19) - 1u;
 
-// classes of an incoming solute population at a fluid node
-constexpr int C_KNOWN = 0;   // pulled from a fluid site
-constexpr int C_RBC = 1;     // upstream site is solid inside the box: reactive link
-constexpr int C_WALL = 2;    // outside a non-periodic face: plain bounce-back
-constexpr int C_INLET = 3;   // outside the low face of the inlet axis
-constexpr int C_OUTLET = 4;  // outside the high face of the inlet axis
+struct RowWord {
+    unsigned long long mask;   // bit b: node x = 64*w + b of the row is fluid
+    int32_t pb;                // compact index of the first fluid node of the word
+    int32_t pad;
+};
+
+struct Task {
+    int32_t row;               // row = y + ny*z
+    int32_t k0;                // compact index of the task's first node
+    int32_t cnt;               // nodes in the task, 1..64
+    int32_t pad;
+};
 
 struct Box {
     int nx, ny, nz;
     int per[3];        // fluid periodicity
-    int shift;         // (x + nx, y) is (x, y + shift)
+    int shift;         // site (x + nx, y) is site (x, y + shift)
     int inlet_axis;    // solute: non-periodic axis with inlet/outlet, or -1
 };
 
@@ -65,48 +82,81 @@ __host__ __device__ inline int fdiv(int a, int b) {
     return (a % b != 0 && ((a < 0) != (b < 0))) ? q - 1 : q;
 }
 
-// Site reached from (x,y,z) by (dx,dy,dz).  Returns the node index, or -1
-// with *face = 2*axis + (1 on the high side) when the move leaves the box
-// through a face that is not periodic in this view (solute: the inlet axis is
-// never periodic).
-__host__ __device__ inline long site(const Box &b, int x, int y, int z, int dx, int dy,
-                                     int dz, bool solute, int *face) {
-    int c0 = x + dx, c1 = y + dy, c2 = z + dz;
+// Wrap (x, y, z) into the box under the fluid's periodicity.  Returns false,
+// with *face = 2*axis + (1 on the high side), when the site is outside a
+// non-periodic face.
+__host__ __device__ inline bool wrap_site(const Box &b, int &x, int &y, int &z, int *face) {
     *face = -1;
-    if (c0 < 0 || c0 >= b.nx) {
-        if (!b.per[0] || (solute && b.inlet_axis == 0)) { *face = c0 < 0 ? 0 : 1; return -1; }
-        int k = fdiv(c0, b.nx);
-        c0 -= k * b.nx;
-        c1 += k * b.shift;
+    if (x < 0 || x >= b.nx) {
+        if (!b.per[0]) { *face = x < 0 ? 0 : 1; return false; }
+        const int k = fdiv(x, b.nx);
+        x -= k * b.nx;
+        y += k * b.shift;
     }
-    if (c1 < 0 || c1 >= b.ny) {
-        if (!b.per[1] || (solute && b.inlet_axis == 1)) { *face = c1 < 0 ? 2 : 3; return -1; }
-        c1 -= fdiv(c1, b.ny) * b.ny;
+    if (y < 0 || y >= b.ny) {
+        if (!b.per[1]) { *face = y < 0 ? 2 : 3; return false; }
+        y -= fdiv(y, b.ny) * b.ny;
     }
-    if (c2 < 0 || c2 >= b.nz) {
-        if (!b.per[2] || (solute && b.inlet_axis == 2)) { *face = c2 < 0 ? 4 : 5; return -1; }
-        c2 -= fdiv(c2, b.nz) * b.nz;
+    if (z < 0 || z >= b.nz) {
+        if (!b.per[2]) { *face = z < 0 ? 4 : 5; return false; }
+        z -= fdiv(z, b.nz) * b.nz;
     }
-    return (long)c0 + (long)b.nx * ((long)c1 + (long)b.ny * (long)c2);
+    return true;
+}
+
+// Dense node index of the site reached from (x,y,z) by (dx,dy,dz), or -1 when
+// it leaves the box through a face that is not periodic in this view (the
+// solute sees the inlet axis as non-periodic).
+__host__ __device__ inline long site(const Box &b, int x, int y, int z, int dx, int dy, int dz,
+                                     bool solute, int *face) {
+    int c[3] = {x + dx, y + dy, z + dz};
+    if (solute && b.inlet_axis >= 0) {
+        const int a = b.inlet_axis;
+        const int n = a == 0 ? b.nx : (a == 1 ? b.ny : b.nz);
+        if (c[a] < 0 || c[a] >= n) { *face = 2 * a + (c[a] >= n ? 1 : 0); return -1; }
+    }
+    if (!wrap_site(b, c[0], c[1], c[2], face)) return -1;
+    return (long)c[0] + (long)b.nx * ((long)c[1] + (long)b.ny * (long)c[2]);
 }
 
 __host__ __device__ inline void coords(const Box &b, long n, int *x, int *y, int *z) {
-    long nxy = (long)b.nx * b.ny;
+    const long nxy = (long)b.nx * b.ny;
     *z = (int)(n / nxy);
-    long r = n - (long)(*z) * nxy;
+    const long r = n - (long)(*z) * nxy;
     *y = (int)(r / b.nx);
     *x = (int)(r - (long)(*y) * b.nx);
 }
 
-// Workgroup id remapped so that consecutive tiles of the node range run on the
-// same XCD (gfx950 dispatches workgroups round-robin over its 8 XCDs; each XCD
-// has its own L2, and neighbouring tiles share the cache lines at their edges).
+// Workgroup id remapped so that consecutive tiles of work run on the same XCD
+// (gfx950 dispatches workgroups round-robin over its 8 XCDs; each XCD has its
+// own L2, and neighbouring tiles share the cache lines at their edges).
 __device__ inline long xcd_tile(long hw, long nblocks) {
     const long nx = 8;
-    long xcd = hw % nx, local = hw / nx;
-    long base = nblocks / nx, rem = nblocks % nx;
-    long start = xcd * base + (xcd < rem ? xcd : rem);
+    const long xcd = hw % nx, local = hw / nx;
+    const long base = nblocks / nx, rem = nblocks % nx;
+    const long start = xcd * base + (xcd < rem ? xcd : rem);
     return start + local;
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    return v;
+}
+
+// sum over a workgroup of BLK threads; result valid in thread 0.  Every thread
+// of the workgroup must call it.
+__device__ __forceinline__ double block_sum(double v) {
+    __shared__ double part[BLK / 64];
+    v = wave_sum(v);
+    const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+    if (lane == 0) part[wid] = v;
+    __syncthreads();
+    double s = 0.0;
+    if (threadIdx.x == 0)
+        for (int k = 0; k < BLK / 64; k++) s += part[k];
+    __syncthreads();
+    return s;
 }
 
 }  // namespace lbm

@@ -1,0 +1,428 @@
+// lbm_geometry.hip -- geometry preparation (once per geometry, not per step).
+//
+// From the solid mask: node classes and reactive-link bits, the row words of
+// the compact fluid layout, the compact <-> dense index maps, the wavefront
+// tasks, the reactive-link list with beta = (1 - k_i)/(1 + k_i) per link
+// (k_i of the selected scheme), and, per solid interface node, the list of its
+// links in ascending direction order.
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// ---------------------------------------------------------------------------
+// exclusive scan of int32 (in place allowed); total written to *total_dev
+// ---------------------------------------------------------------------------
+constexpr int SCAN_PER = 16;
+constexpr int SCAN_TILE = BLK * SCAN_PER;
+
+__global__ __launch_bounds__(BLK) void k_scan_reduce(const int32_t *in, long n, int32_t *bsum) {
+    const long base = (long)blockIdx.x * SCAN_TILE;
+    long s = 0;
+    for (int j = 0; j < SCAN_PER; j++) {
+        const long i = base + (long)j * BLK + threadIdx.x;
+        if (i < n) s += in[i];
+    }
+    const double t = block_sum((double)s);
+    if (threadIdx.x == 0) bsum[blockIdx.x] = (int32_t)t;
+}
+
+__global__ __launch_bounds__(1024) void k_scan_blocks(int32_t *bsum, long nb, int32_t *total) {
+    __shared__ int32_t buf[1024];
+    __shared__ int32_t carry;
+    if (threadIdx.x == 0) carry = 0;
+    __syncthreads();
+    for (long c0 = 0; c0 < nb; c0 += 1024) {
+        const long i = c0 + threadIdx.x;
+        const int32_t v = i < nb ? bsum[i] : 0;
+        buf[threadIdx.x] = v;
+        __syncthreads();
+        for (int off = 1; off < 1024; off <<= 1) {
+            const int32_t add = threadIdx.x >= off ? buf[threadIdx.x - off] : 0;
+            __syncthreads();
+            buf[threadIdx.x] += add;
+            __syncthreads();
+        }
+        if (i < nb) bsum[i] = carry + buf[threadIdx.x] - v;
+        __syncthreads();
+        if (threadIdx.x == 0) carry += buf[1023];
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) *total = carry;
+}
+
+__global__ __launch_bounds__(BLK) void k_scan_down(const int32_t *in, int32_t *out, long n,
+                                                   const int32_t *bsum) {
+    __shared__ int32_t tsum[BLK];
+    const long base = (long)blockIdx.x * SCAN_TILE + (long)threadIdx.x * SCAN_PER;
+    int32_t v[SCAN_PER];
+    int32_t s = 0;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        const long i = base + j;
+        v[j] = i < n ? in[i] : 0;
+        s += v[j];
+    }
+    tsum[threadIdx.x] = s;
+    __syncthreads();
+    for (int off = 1; off < BLK; off <<= 1) {
+        const int32_t add = threadIdx.x >= off ? tsum[threadIdx.x - off] : 0;
+        __syncthreads();
+        tsum[threadIdx.x] += add;
+        __syncthreads();
+    }
+    int32_t run = bsum[blockIdx.x] + tsum[threadIdx.x] - s;
+#pragma unroll
+    for (int j = 0; j < SCAN_PER; j++) {
+        const long i = base + j;
+        if (i < n) out[i] = run;
+        run += v[j];
+    }
+}
+
+hipError_t scan_excl(Ctx &c, const int32_t *in, int32_t *out, long n, int32_t *total_dev) {
+    if (n <= 0) n = 1;
+    const long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
+    hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLK), 0, c.stream, in, n, c.bsum);
+    hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, c.stream, c.bsum, nb, total_dev);
+    hipLaunchKernelGGL(k_scan_down, dim3(nb), dim3(BLK), 0, c.stream, in, out, n, c.bsum);
+    return hipGetLastError();
+}
+
+// ---------------------------------------------------------------------------
+// node classes
+// ---------------------------------------------------------------------------
+template <class L>
+__global__ __launch_bounds__(BLK) void k_flags(Box box, long N, const uint8_t *solid,
+                                               uint32_t *flags, uint32_t *rmask) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    if (solid[n]) {
+        flags[n] = 0u;
+        rmask[n] = 0u;
+        return;
+    }
+    int X, Y, Z;
+    coords(box, n, &X, &Y, &Z);
+    uint32_t fl = F_FLUID, rm = 0u;
+    for (int i = 1; i < L::Q; i++) {
+        int fc;
+        const long y = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], false, &fc);
+        if (y < 0 || solid[y]) fl |= 1u << i;
+        const long ys = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
+        if (ys >= 0 && solid[ys]) rm |= 1u << i;
+    }
+    if (rm) fl |= F_LINK;
+    flags[n] = fl;
+    rmask[n] = rm;
+}
+
+// one thread per (row, word): fluid mask of 64 nodes and its population count
+__global__ __launch_bounds__(BLK) void k_row_words(long R, int W, int nx, const uint8_t *solid,
+                                                   RowWord *rows, int32_t *wcnt) {
+    const long j = (long)blockIdx.x * BLK + threadIdx.x;
+    if (j >= R * W) return;
+    const long r = j / W;
+    const int w = (int)(j - r * W);
+    const long base = r * nx + 64L * w;
+    const int len = min(64, nx - 64 * w);
+    unsigned long long m = 0ull;
+    for (int b = 0; b < len; b++)
+        if (!solid[base + b]) m |= 1ull << b;
+    rows[j].mask = m;
+    rows[j].pad = 0;
+    wcnt[j] = __popcll(m);
+}
+
+__global__ __launch_bounds__(BLK) void k_row_prefix(long RW, const int32_t *pre, RowWord *rows) {
+    const long j = (long)blockIdx.x * BLK + threadIdx.x;
+    if (j < RW) rows[j].pb = pre[j];
+}
+
+// dense <-> compact maps
+__global__ __launch_bounds__(BLK) void k_compact(long N, int nx, int W, const uint8_t *solid,
+                                                 const RowWord *rows, int32_t *nodeof, int32_t *kof) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    if (solid[n]) {
+        kof[n] = -1;
+        return;
+    }
+    const long r = n / nx;
+    const int x = (int)(n - r * nx);
+    const RowWord w = rows[r * W + (x >> 6)];
+    const int k = w.pb + __popcll(w.mask & ((1ull << (x & 63)) - 1ull));
+    nodeof[k] = (int32_t)n;
+    kof[n] = k;
+}
+
+__global__ __launch_bounds__(BLK) void k_row_ntasks(long R, int W, const RowWord *rows, int32_t *nt) {
+    const long r = (long)blockIdx.x * BLK + threadIdx.x;
+    if (r >= R) return;
+    int c = 0;
+    for (int w = 0; w < W; w++) c += __popcll(rows[r * W + w].mask);
+    nt[r] = (c + 63) / 64;
+}
+
+__global__ __launch_bounds__(BLK) void k_row_tasks(long R, int W, const RowWord *rows,
+                                                   const int32_t *tbase, Task *tasks) {
+    const long r = (long)blockIdx.x * BLK + threadIdx.x;
+    if (r >= R) return;
+    int c = 0;
+    for (int w = 0; w < W; w++) c += __popcll(rows[r * W + w].mask);
+    const int k0 = rows[r * W].pb;
+    const int t0 = tbase[r];
+    for (int j = 0; 64 * j < c; j++) {
+        Task t;
+        t.row = (int32_t)r;
+        t.k0 = k0 + 64 * j;
+        t.cnt = min(64, c - 64 * j);
+        t.pad = 0;
+        tasks[t0 + j] = t;
+    }
+}
+
+// reactive links per compact node, then the link records
+__global__ __launch_bounds__(BLK) void k_link_count(long nf, const int32_t *nodeof,
+                                                    const uint32_t *rmask, int32_t *cnt) {
+    const long k = (long)blockIdx.x * BLK + threadIdx.x;
+    if (k < nf) cnt[k] = __popc(rmask[nodeof[k]]);
+}
+
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_links(Box box, long nf, const int32_t *nodeof,
+                                               const uint32_t *rmask, const int32_t *lbase,
+                                               const double *nrm, const double *kr, int scheme,
+                                               int mech, double gamma, double cs2s, T *lbeta,
+                                               int32_t *lnode, int32_t *lsolid, uint8_t *ldir) {
+    const long k = (long)blockIdx.x * BLK + threadIdx.x;
+    if (k >= nf) return;
+    const long n = nodeof[k];
+    const uint32_t rm = rmask[n];
+    if (!rm) return;
+    int X, Y, Z;
+    coords(box, n, &X, &Y, &Z);
+    const int base = lbase[k];
+    int r = 0;
+    for (int i = 1; i < L::Q; i++) {
+        if (!(rm & (1u << i))) continue;
+        int fc;
+        const long s = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
+        const double en = L::ex[i] * nrm[3 * s] + L::ey[i] * nrm[3 * s + 1] + L::ez[i] * nrm[3 * s + 2];
+        const double kv = kr[s];
+        double kap;
+        if (scheme == LBM_SV) kap = en > 0 ? kv * en / cs2s : 0.0;
+        else if (scheme == LBM_SPJ) kap = en > 0 ? gamma * kv / (cs2s * en) : 0.0;
+        else kap = en > 0 ? gamma * kv * en / cs2s : 0.0;
+        // pre-collision source with both neighbours solid: fall back to the
+        // node's own post-collision population, whose effective rate is gamma k
+        if (mech == LBM_PRECOLL && (rm & (1u << L::opp[i]))) kap = kap / gamma;
+        const double beta = scheme == LBM_ABB ? -1.0 : (1.0 - kap) / (1.0 + kap);
+        lbeta[base + r] = (T)beta;
+        lnode[base + r] = (int32_t)n;
+        lsolid[base + r] = (int32_t)s;
+        ldir[base + r] = (uint8_t)i;
+        r++;
+    }
+}
+
+template <class L>
+__device__ __forceinline__ int solid_links(const Box &box, long n, const uint8_t *solid,
+                                           const uint32_t *rmask, const int32_t *kof,
+                                           const int32_t *lbase, int32_t *out) {
+    int X, Y, Z;
+    coords(box, n, &X, &Y, &Z);
+    int cnt = 0;
+    for (int i = 1; i < L::Q; i++) {
+        int fc;
+        const long x = site(box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], true, &fc);
+        if (x < 0 || solid[x]) continue;
+        const uint32_t rm = rmask[x];
+        if (!(rm & (1u << i))) continue;
+        if (out) out[cnt] = lbase[kof[x]] + __popc(rm & ((1u << i) - 1u));
+        cnt++;
+    }
+    return cnt;
+}
+
+template <class L>
+__global__ __launch_bounds__(BLK) void k_solid_count(Box box, long N, const uint8_t *solid,
+                                                     const uint32_t *rmask, int32_t *cnt,
+                                                     int32_t *ind) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    int c = 0;
+    if (solid[n]) c = solid_links<L>(box, n, solid, rmask, nullptr, nullptr, nullptr);
+    cnt[n] = c;
+    ind[n] = c > 0 ? 1 : 0;
+}
+
+template <class L>
+__global__ __launch_bounds__(BLK) void k_solid_fill(Box box, long N, const uint8_t *solid,
+                                                    const uint32_t *rmask, const int32_t *kof,
+                                                    const int32_t *lbase, const int32_t *off,
+                                                    const int32_t *idx, int32_t *sif, int32_t *soff,
+                                                    int32_t *slinks) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    if (!solid[n]) return;
+    const int c = solid_links<L>(box, n, solid, rmask, kof, lbase, slinks + off[n]);
+    if (c > 0) {
+        sif[idx[n]] = (int32_t)n;
+        soff[idx[n]] = off[n];
+    }
+}
+
+// lattice-gradient normal of the solid indicator (used when no normals are given)
+template <class L>
+__global__ __launch_bounds__(BLK) void k_fd_normals(Box box, long N, const uint8_t *solid,
+                                                    double *nrm) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    double gx = 0, gy = 0, gz = 0;
+    if (solid[n]) {
+        int X, Y, Z;
+        coords(box, n, &X, &Y, &Z);
+        for (int i = 1; i < L::Q; i++) {
+            int fc;
+            const long y = site(box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], false, &fc);
+            const double ind = (y < 0 || solid[y]) ? 1.0 : 0.0;
+            gx += L::w[i] * L::ex[i] * ind * 3.0;
+            gy += L::w[i] * L::ey[i] * ind * 3.0;
+            gz += L::w[i] * L::ez[i] * ind * 3.0;
+        }
+        const double m = sqrt(gx * gx + gy * gy + gz * gz);
+        if (m > 0) { gx = -gx / m; gy = -gy / m; gz = -gz / m; }
+        else { gx = gy = gz = 0.0; }
+    }
+    nrm[3 * n] = gx;
+    nrm[3 * n + 1] = gy;
+    nrm[3 * n + 2] = gz;
+}
+
+__global__ __launch_bounds__(BLK) void k_node_defaults(long N, const uint8_t *solid, const double *kr_in,
+                                                       double kr0, const double *phi_in, double *kr,
+                                                       double *phi) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    kr[n] = kr_in ? kr_in[n] : kr0;
+    phi[n] = phi_in ? phi_in[n] : (solid[n] ? 1.0 : 0.0);
+}
+
+__global__ __launch_bounds__(BLK) void k_copy_solid(long N, const uint8_t *in, uint8_t *out) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    out[n] = in[n] ? 1 : 0;
+}
+
+__global__ void k_set_last(int32_t *soff, long nsif, int32_t v) { soff[nsif] = v; }
+
+__global__ void k_zero_i32(int32_t *p, long n) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = 0;
+}
+
+// compacted list of the fluid interface nodes and their link bits
+__global__ __launch_bounds__(BLK) void k_iface_mark(long nf, const int32_t *lcnt, int32_t *ind) {
+    const long k = (long)blockIdx.x * BLK + threadIdx.x;
+    if (k < nf) ind[k] = lcnt[k] > 0 ? 1 : 0;
+}
+
+__global__ __launch_bounds__(BLK) void k_iface_fill(long nf, const int32_t *lcnt, const int32_t *idx,
+                                                    const int32_t *nodeof, const uint32_t *rmask,
+                                                    int32_t *iface, uint32_t *imask) {
+    const long k = (long)blockIdx.x * BLK + threadIdx.x;
+    if (k >= nf || lcnt[k] == 0) return;
+    iface[idx[k]] = (int32_t)k;
+    imask[idx[k]] = rmask[nodeof[k]];
+}
+
+static hipError_t read_ints(Ctx &c, const int32_t *dev, int32_t *host, int n) {
+    hipError_t e = hipMemcpyAsync(host, dev, n * sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c.stream);
+}
+
+template <class L, typename T>
+static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *normals,
+                                const double *k_r, const double *phi0, int64_t *n_links,
+                                int64_t *n_sif) {
+    const long N = c.N, R = c.R;
+    const int W = c.W;
+    const long RW = R * W;
+    const long nb = (N + BLK - 1) / BLK;
+    auto blocks = [](long n) { return dim3((unsigned)((n + BLK - 1) / BLK)); };
+    hipStream_t st = c.stream;
+    hipError_t e;
+    hipLaunchKernelGGL(k_copy_solid, dim3(nb), dim3(BLK), 0, st, N, solid, c.solid);
+    hipLaunchKernelGGL(k_node_defaults, dim3(nb), dim3(BLK), 0, st, N, c.solid, k_r, c.p.k_r,
+                       phi0, c.kr, c.phi);
+    if (normals) {
+        if (normals != c.nrm) {
+            e = hipMemcpyAsync(c.nrm, normals, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st);
+            if (e != hipSuccess) return e;
+        }
+    } else {
+        hipLaunchKernelGGL((k_fd_normals<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.nrm);
+    }
+    hipLaunchKernelGGL((k_flags<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.flags, c.rmask);
+    // row words and compact maps
+    hipLaunchKernelGGL(k_row_words, blocks(RW), dim3(BLK), 0, st, R, W, c.box.nx, c.solid, c.rows,
+                       c.cnt);
+    if ((e = scan_excl(c, c.cnt, c.sidx, RW, c.iacc)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_row_prefix, blocks(RW), dim3(BLK), 0, st, RW, c.sidx, c.rows);
+    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(BLK), 0, st, N, c.box.nx, W, c.solid, c.rows,
+                       c.nodeof, c.kof);
+    int32_t nf = 0;
+    if ((e = read_ints(c, c.iacc, &nf, 1)) != hipSuccess) return e;
+    c.n_fluid = nf;
+    // wavefront tasks
+    hipLaunchKernelGGL(k_row_ntasks, blocks(R), dim3(BLK), 0, st, R, W, c.rows, c.cnt);
+    if ((e = scan_excl(c, c.cnt, c.sidx, R, c.iacc)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_row_tasks, blocks(R), dim3(BLK), 0, st, R, W, c.rows, c.sidx, c.tasks);
+    int32_t nt = 0;
+    if ((e = read_ints(c, c.iacc, &nt, 1)) != hipSuccess) return e;
+    if (nt > c.task_cap) return hipErrorUnknown;
+    c.n_tasks = nt;
+    // reactive links
+    const long nfl = nf > 0 ? nf : 1;
+    hipLaunchKernelGGL(k_link_count, blocks(nfl), dim3(BLK), 0, st, (long)nf, c.nodeof, c.rmask, c.cnt);
+    if ((e = scan_excl(c, c.cnt, c.lbase, nf, c.iacc)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_iface_mark, blocks(nfl), dim3(BLK), 0, st, (long)nf, c.cnt, c.sidx);
+    if ((e = scan_excl(c, c.sidx, c.sidx, nf, c.iacc + 2)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_iface_fill, blocks(nfl), dim3(BLK), 0, st, (long)nf, c.cnt, c.sidx, c.nodeof,
+                       c.rmask, c.iface, c.imask);
+    int32_t t4[4] = {0, 0, 0, 0};
+    if ((e = read_ints(c, c.iacc, t4, 4)) != hipSuccess) return e;
+    const int32_t tot = t4[0];
+    c.n_fluid_iface = t4[2];
+    *n_links = tot;
+    if (tot > c.max_links) return hipSuccess;  // the caller reports the capacity error
+    hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, c.box, (long)nf, c.nodeof,
+                       c.rmask, c.lbase, c.nrm, c.kr, c.p.rbc_scheme, c.p.rbc_mechanics, c.gamma,
+                       c.cs2s, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir);
+    // solid side: per solid interface node, its links in direction order
+    hipLaunchKernelGGL((k_solid_count<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.rmask,
+                       c.cnt, c.sidx);
+    if ((e = scan_excl(c, c.sidx, c.sidx, N, c.iacc)) != hipSuccess) return e;
+    if ((e = scan_excl(c, c.cnt, c.cnt, N, c.iacc + 1)) != hipSuccess) return e;
+    int32_t t2[2] = {0, 0};
+    if ((e = read_ints(c, c.iacc, t2, 2)) != hipSuccess) return e;
+    *n_sif = t2[0];
+    hipLaunchKernelGGL((k_solid_fill<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.rmask,
+                       c.kof, c.lbase, c.cnt, c.sidx, c.sif, c.soff, c.slinks);
+    hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, c.soff, (long)t2[0], t2[1]);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (t2[1] != tot) return hipErrorUnknown;  // every link has exactly one solid end
+    return hipStreamSynchronize(st);
+}
+
+hipError_t launch_geometry(Ctx &c, const uint8_t *solid, const double *normals, const double *k_r,
+                           const double *phi0, int64_t *n_links, int64_t *n_sif) {
+    if (c.Q == 9)
+        return c.fp64 ? geometry_impl<D2Q9, double>(c, solid, normals, k_r, phi0, n_links, n_sif)
+                      : geometry_impl<D2Q9, float>(c, solid, normals, k_r, phi0, n_links, n_sif);
+    return c.fp64 ? geometry_impl<D3Q19, double>(c, solid, normals, k_r, phi0, n_links, n_sif)
+                  : geometry_impl<D3Q19, float>(c, solid, normals, k_r, phi0, n_links, n_sif);
+}
+
+}  // namespace lbm

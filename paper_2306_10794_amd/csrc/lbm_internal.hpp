@@ -14,58 +14,71 @@ namespace lbm {
 // Per-step kernel arguments (passed by value; lives in the kernarg segment).
 template <typename T>
 struct StepArgs {
-    const T *fin;
-    T *fout;
-    const T *gin;
-    T *gout;
-    const uint32_t *flags;
-    const uint32_t *rmask;   // reactive-link bits per node (read at special nodes)
-    const int32_t *lbase;    // first link of each node with links
-    const T *lbeta;          // per link: (1 - k)/(1 + k)
-    T *lq;                   // per link: mass exchanged in this step
-    double *phi;
-    long N;                  // nodes
-    long S;                  // stride between directions (N rounded up)
+    const T *__restrict__ fin;
+    T *__restrict__ fout;
+    const T *__restrict__ gin;
+    T *__restrict__ gout;
+    const Task *__restrict__ tasks;
+    const RowWord *__restrict__ rows;
+    const int32_t *__restrict__ nodeof;  // compact index -> dense node
+    const int32_t *__restrict__ lbase;   // compact index -> first reactive link
+    const T *__restrict__ lbeta;         // per link: (1 - k)/(1 + k)
+    T *__restrict__ lq;                  // per link: mass exchanged in this step
+    double *__restrict__ phi;            // dense
+    long ntasks;
+    long S;                              // stride between directions
+    int W;                               // 64-node words per row
     Box box;
     int mech;
     // constants of the step, FP64 (the kernels compute in FP64)
     double omega_f, omega_g, force_fac;
     double F[3];
-    double ws[19];           // solute weights (rest fraction)
+    double ws[19];                       // solute weights (rest fraction)
     double inv_cs2s;
     double rho0, c_ref;
-    double ceq_dev;          // C_eq - C_ref
+    double ceq_dev;                      // C_eq - C_ref
     double c_in;
-    double vma;              // V_m a_m
+    double vma;                          // V_m a_m
 };
 
 struct Ctx {
     lbm_params p;
     hipStream_t stream;
     int Q, dim;
-    long N, S;               // nodes and padded stride
+    long N;                  // nodes
+    long S;                  // stride between directions of the compact arrays
+    long R;                  // rows (ny * nz)
+    int W;                   // words per row
+    long task_cap;
     Box box;
     bool fp64;
     double gamma, cs2s, ws[19];
     int64_t max_links;
     // device arrays carved from the caller workspace
-    void *f[2], *g[2];       // populations, [Q][S] each (T = double or float)
-    uint32_t *flags, *rmask;
-    int32_t *lbase;
-    int32_t *cnt;            // scratch [N] (link counts, then solid-side counts)
+    void *f[2], *g[2];       // populations, [Q][S] each (T = double or float), compact
+    RowWord *rows;           // [R*W]
+    Task *tasks;             // [task_cap]
+    int32_t *nodeof;         // [N] compact -> dense
+    int32_t *kof;            // [N] dense -> compact (-1 for solid)
+    int32_t *lbase;          // [N] compact -> first link
+    uint32_t *flags, *rmask; // [N] dense geometry flags / reactive-link bits
+    int32_t *cnt;            // scratch [N]
     int32_t *sidx;           // scratch [N]
     double *phi, *kr, *nrm;  // [N], [N], [N][3]
     uint8_t *solid;          // [N]
     void *lbeta, *lq;        // [max_links] of T
+    int32_t *iface;          // [N] fluid interface nodes (compact indices)
+    uint32_t *imask;         // [N] their reactive-link bits
     int32_t *lnode, *lsolid; // [max_links]
     uint8_t *ldir;           // [max_links]
     int32_t *sif, *soff, *slinks; // solid interface list [max_links], offsets [max_links+1], [max_links]
     int32_t *bsum;           // scan scratch
-    double *dacc;            // device accumulators: [0] wall exchange, [1..3] diag sums
+    double *dpart;           // per-workgroup partial sums of the reductions
+    double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums
     int32_t *iacc;           // device int accumulators
     size_t ws_bytes;
     int cur;                 // buffer holding the current state
-    int64_t n_links, n_sif, n_fluid, n_fluid_iface;
+    int64_t n_links, n_sif, n_fluid, n_fluid_iface, n_tasks;
     int64_t step, n_events;
     bool have_geom, have_state;
     hipEvent_t ev[4];
@@ -85,5 +98,6 @@ hipError_t launch_fields(Ctx &c, double *rho, double *u, double *cc, double *phi
 hipError_t launch_pops(Ctx &c, double *f, double *g);
 hipError_t launch_exchange(Ctx &c, double *q);
 hipError_t launch_diag(Ctx &c, double *sums, int32_t *nan_flag);
+hipError_t scan_excl(Ctx &c, const int32_t *in, int32_t *out, long n, int32_t *total_dev);
 
 }  // namespace lbm

@@ -1,0 +1,226 @@
+// lbm_io.hip -- initial state, read-outs and FP64 reductions (not per step).
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_init(long N, long S, const int32_t *kof, const double *rho,
+                                              const double *u, const double *cc, double rho0,
+                                              double c_ref, const double *ws, double cs2s, T *f0,
+                                              T *g0, T *f1, T *g1) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    const int k = kof[n];
+    if (k < 0) return;
+    const double r = rho ? rho[n] : 1.0;
+    const double ux = u ? u[3 * n] : 0.0, uy = u ? u[3 * n + 1] : 0.0, uz = u ? u[3 * n + 2] : 0.0;
+    const double C = cc ? cc[n] : 0.0;
+    const double uu = ux * ux + uy * uy + uz * uz;
+    for (int i = 0; i < L::Q; i++) {
+        const double eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
+        const double feq = L::w[i] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
+        const double geq = ws[i] * C * (1.0 + eu / cs2s);
+        f0[i * S + k] = T(feq - L::w[i] * rho0);
+        g0[i * S + k] = T(geq - ws[i] * c_ref);
+        f1[i * S + k] = T(0);
+        g1[i * S + k] = T(0);
+    }
+}
+
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_fields(long N, long S, const int32_t *kof, const T *f,
+                                                const T *g, double rho0, double c_ref,
+                                                const double *F, const double *phi_in,
+                                                double *rho, double *u, double *cc, double *phi,
+                                                uint8_t *type) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    const int k = kof[n];
+    double r = 0, jx = 0, jy = 0, jz = 0, C = 0;
+    const bool sol = k < 0;
+    if (!sol) {
+        double dr = 0, dc = 0;
+        for (int i = 0; i < L::Q; i++) {
+            const double fi = (double)f[i * S + k];
+            dr += fi;
+            jx += L::ex[i] * fi;
+            jy += L::ey[i] * fi;
+            jz += L::ez[i] * fi;
+            dc += (double)g[i * S + k];
+        }
+        r = rho0 + dr;
+        C = c_ref + dc;
+    }
+    if (rho) rho[n] = r;
+    if (u) {
+        u[3 * n] = sol ? 0.0 : (jx - 0.5 * F[0]) / r;
+        u[3 * n + 1] = sol ? 0.0 : (jy - 0.5 * F[1]) / r;
+        u[3 * n + 2] = sol ? 0.0 : (jz - 0.5 * F[2]) / r;
+    }
+    if (cc) cc[n] = C;
+    if (phi) phi[n] = phi_in[n];
+    if (type) type[n] = sol ? 1 : 0;
+}
+
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_pops(long N, long S, const int32_t *kof, const T *f,
+                                              const T *g, double rho0, double c_ref,
+                                              const double *ws, double *fo, double *go) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    const int k = kof[n];
+    for (int i = 0; i < L::Q; i++) {
+        if (fo) fo[i * N + n] = k < 0 ? 0.0 : (double)f[i * S + k] + L::w[i] * rho0;
+        if (go) go[i * N + n] = k < 0 ? 0.0 : (double)g[i * S + k] + ws[i] * c_ref;
+    }
+}
+
+__global__ __launch_bounds__(BLK) void k_zero_f64(double *p, long n) {
+    const long i = (long)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+__global__ void k_zero_flag(int32_t *p) { *p = 0; }
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_scatter_q(long nl, int Q, const T *lq, const int32_t *lnode,
+                                                   const uint8_t *ldir, double *q) {
+    const long j = (long)blockIdx.x * BLK + threadIdx.x;
+    if (j < nl) q[(long)lnode[j] * Q + ldir[j]] = (double)lq[j];
+}
+
+// per-workgroup partial sums of C (fluid) and phi (all nodes), and a
+// non-finite flag; a single workgroup then adds the partials in order
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_diag(long N, long S, const int32_t *kof, const T *f,
+                                              const T *g, const double *phi, double c_ref,
+                                              double *part, int32_t *nan_flag) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    double cs = 0.0, ps = 0.0;
+    int bad = 0;
+    if (n < N) {
+        ps = phi[n];
+        const int k = kof[n];
+        if (k >= 0) {
+            double dc = 0.0;
+            for (int i = 0; i < L::Q; i++) {
+                const double fi = (double)f[i * S + k], gi = (double)g[i * S + k];
+                if (!isfinite(fi) || !isfinite(gi)) bad = 1;
+                dc += gi;
+            }
+            cs = c_ref + dc;
+        }
+    }
+    const double bc = block_sum(cs);
+    const double bp = block_sum(ps);
+    if (threadIdx.x == 0) {
+        part[2 * blockIdx.x] = bc;
+        part[2 * blockIdx.x + 1] = bp;
+    }
+    if (bad) atomicOr(nan_flag, 1);
+}
+
+__global__ __launch_bounds__(BLK) void k_sum_parts(const double *part, long nb, double *out) {
+    double a = 0.0, b = 0.0;
+    for (long j = threadIdx.x; j < nb; j += BLK) {
+        a += part[2 * j];
+        b += part[2 * j + 1];
+    }
+    a = block_sum(a);
+    b = block_sum(b);
+    if (threadIdx.x == 0) {
+        out[0] = a;
+        out[1] = b;
+    }
+}
+
+template <class L, typename T>
+static hipError_t init_impl(Ctx &c, const double *rho, const double *u, const double *cc) {
+    const long nb = (c.N + BLK - 1) / BLK;
+    double *wsd = c.dacc + 8;  // solute weights staged in the accumulator block
+    hipError_t e = hipMemcpyAsync(wsd, c.ws, sizeof(double) * 19, hipMemcpyHostToDevice, c.stream);
+    if (e != hipSuccess) return e;
+    c.cur = 0;
+    hipLaunchKernelGGL((k_init<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof, rho, u,
+                       cc, c.fp64 ? 0.0 : c.p.rho0, c.fp64 ? 0.0 : c.p.c_ref, wsd, c.cs2s,
+                       (T *)c.f[0], (T *)c.g[0], (T *)c.f[1], (T *)c.g[1]);
+    hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(BLK), 0, c.stream, c.dacc, 8);
+    return hipGetLastError();
+}
+
+hipError_t launch_init(Ctx &c, const double *rho, const double *u, const double *cc) {
+    if (c.Q == 9) return c.fp64 ? init_impl<D2Q9, double>(c, rho, u, cc) : init_impl<D2Q9, float>(c, rho, u, cc);
+    return c.fp64 ? init_impl<D3Q19, double>(c, rho, u, cc) : init_impl<D3Q19, float>(c, rho, u, cc);
+}
+
+template <class L, typename T>
+static hipError_t fields_impl(Ctx &c, double *rho, double *u, double *cc, double *phi, uint8_t *type) {
+    const long nb = (c.N + BLK - 1) / BLK;
+    double *Fd = c.dacc + 28;
+    hipError_t e = hipMemcpyAsync(Fd, c.p.force, sizeof(double) * 3, hipMemcpyHostToDevice, c.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_fields<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof,
+                       (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.fp64 ? 0.0 : c.p.rho0,
+                       c.fp64 ? 0.0 : c.p.c_ref, Fd, c.phi, rho, u, cc, phi, type);
+    return hipGetLastError();
+}
+
+hipError_t launch_fields(Ctx &c, double *rho, double *u, double *cc, double *phi, uint8_t *type) {
+    if (c.Q == 9) return c.fp64 ? fields_impl<D2Q9, double>(c, rho, u, cc, phi, type) : fields_impl<D2Q9, float>(c, rho, u, cc, phi, type);
+    return c.fp64 ? fields_impl<D3Q19, double>(c, rho, u, cc, phi, type) : fields_impl<D3Q19, float>(c, rho, u, cc, phi, type);
+}
+
+template <class L, typename T>
+static hipError_t pops_impl(Ctx &c, double *f, double *g) {
+    const long nb = (c.N + BLK - 1) / BLK;
+    double *wsd = c.dacc + 8;
+    hipError_t e = hipMemcpyAsync(wsd, c.ws, sizeof(double) * 19, hipMemcpyHostToDevice, c.stream);
+    if (e != hipSuccess) return e;
+    hipLaunchKernelGGL((k_pops<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof,
+                       (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.fp64 ? 0.0 : c.p.rho0,
+                       c.fp64 ? 0.0 : c.p.c_ref, wsd, f, g);
+    return hipGetLastError();
+}
+
+hipError_t launch_pops(Ctx &c, double *f, double *g) {
+    if (c.Q == 9) return c.fp64 ? pops_impl<D2Q9, double>(c, f, g) : pops_impl<D2Q9, float>(c, f, g);
+    return c.fp64 ? pops_impl<D3Q19, double>(c, f, g) : pops_impl<D3Q19, float>(c, f, g);
+}
+
+template <typename T>
+static hipError_t exchange_impl(Ctx &c, double *q) {
+    const long nq = c.N * c.Q;
+    hipLaunchKernelGGL(k_zero_f64, dim3((nq + BLK - 1) / BLK), dim3(BLK), 0, c.stream, q, nq);
+    if (c.n_links > 0)
+        hipLaunchKernelGGL((k_scatter_q<T>), dim3((c.n_links + BLK - 1) / BLK), dim3(BLK), 0,
+                           c.stream, (long)c.n_links, c.Q, (const T *)c.lq, c.lnode, c.ldir, q);
+    return hipGetLastError();
+}
+
+hipError_t launch_exchange(Ctx &c, double *q) {
+    return c.fp64 ? exchange_impl<double>(c, q) : exchange_impl<float>(c, q);
+}
+
+template <class L, typename T>
+static hipError_t diag_impl(Ctx &c, double *sums, int32_t *nan_flag) {
+    const long nb = (c.N + BLK - 1) / BLK;
+    hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, c.stream, c.iacc + 4);
+    hipLaunchKernelGGL((k_diag<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof,
+                       (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.phi,
+                       c.fp64 ? 0.0 : c.p.c_ref, c.dpart, c.iacc + 4);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(BLK), 0, c.stream, c.dpart, nb, c.dacc + 1);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(sums, c.dacc, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+    if (e != hipSuccess) return e;
+    e = hipMemcpyAsync(nan_flag, c.iacc + 4, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
+    if (e != hipSuccess) return e;
+    return hipStreamSynchronize(c.stream);
+}
+
+hipError_t launch_diag(Ctx &c, double *sums, int32_t *nan_flag) {
+    if (c.Q == 9) return c.fp64 ? diag_impl<D2Q9, double>(c, sums, nan_flag) : diag_impl<D2Q9, float>(c, sums, nan_flag);
+    return c.fp64 ? diag_impl<D3Q19, double>(c, sums, nan_flag) : diag_impl<D3Q19, float>(c, sums, nan_flag);
+}
+
+}  // namespace lbm

@@ -1,0 +1,358 @@
+// lbm_step.hip -- the per-step kernels of the reactive lattice Boltzmann method.
+//
+// One time step is two launches on the context stream:
+//   k_step       one wavefront per task (up to 64 consecutive fluid nodes of
+//                one x-row).  Fluid: pull-stream with halfway bounce-back,
+//                moments, Guo-forced BGK.  Solute: pull-stream, inlet/outlet
+//                planes, the general reactive boundary condition on every link
+//                that enters from a solid node, advection-diffusion BGK with
+//                the rest-fraction weights; writes the exchange q of each
+//                reactive link and credits precipitation (q < 0) to the fluid
+//                node's phi.  The boundary condition is applied branch-free to
+//                every direction (beta = 1 and the pulled value as source on a
+//                non-reactive direction leave it unchanged), so interface nodes
+//                do not diverge the bulk wavefronts.
+//   k_phi_solid  per solid interface node: dissolution (q > 0) charged to its
+//                phi in link order, and the step's total wall exchange.
+//
+// All loads of a node (both lattices) are issued before any arithmetic, so a
+// wavefront keeps 2Q loads in flight; each population value is read once by
+// k_step.  Arithmetic is FP64 in both storage precisions: the step is bound by
+// HBM traffic, and FP32 arithmetic on rounded weights would leak mass and
+// momentum by a fixed relative amount at every collision.
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+// Compact index of the fluid site (xx, yy, zz) (fluid view of the box), -1 if
+// that site is solid, -2 if it is outside a non-periodic face.
+__device__ __forceinline__ int nb_compact(const RowWord *__restrict__ rows, int W, const Box &b,
+                                          int xx, int yy, int zz) {
+    int fc;
+    if (!wrap_site(b, xx, yy, zz, &fc)) return -2;
+    const RowWord w = rows[(long)(yy + b.ny * zz) * W + (xx >> 6)];
+    const unsigned long long bit = 1ull << (xx & 63);
+    if (!(w.mask & bit)) return -1;
+    return w.pb + __popcll(w.mask & (bit - 1ull));
+}
+
+// Row slots: the rows a task pulls from are (y + dy, z + dz) with
+// (dy, dz) = (-ey, -ez); slot index (dy + 1) in 2D, (dy + 1) + 3 (dz + 1) in 3D.
+template <class L>
+__device__ constexpr int slot_of(int i) {
+    return L::DIM == 2 ? 1 - L::ey[i] : (1 - L::ey[i]) + 3 * (1 - L::ez[i]);
+}
+template <class L>
+constexpr int n_slots() {
+    return L::DIM == 2 ? 3 : 9;
+}
+
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
+    using R = double;
+    constexpr int Q = L::Q;
+    constexpr int NS = n_slots<L>();
+    const long tile = xcd_tile(blockIdx.x, nblocks);
+    const int t = __builtin_amdgcn_readfirstlane((int)(tile * (BLK / 64)) + (int)(threadIdx.x >> 6));
+    if (t >= a.ntasks) return;
+    const int lane = threadIdx.x & 63;
+    const Task tk = a.tasks[t];
+    const Box &b = a.box;
+    const long S = a.S;
+    const int W = a.W;
+    const int y = tk.row % b.ny, z = tk.row / b.ny;
+    const int ax = b.inlet_axis;
+
+    // ---- the row words of every row this task pulls from: lane j holds word
+    // (j % W) of slot (j / W); other lanes read them with cross-lane shuffles ----
+    const bool slots_fit = NS * W <= 64;
+    unsigned long long wm = 0ull;
+    int wpb = 0;
+    if (slots_fit && lane < NS * W) {
+        const int sl = lane / W, w = lane - sl * W;
+        int yy = y + (sl % 3) - 1, zz = z + (sl / 3) - 1, xx = 0, fc;
+        if (L::DIM == 2) zz = z;
+        if (wrap_site(b, xx, yy, zz, &fc)) {
+            const RowWord rw = a.rows[(long)(yy + b.ny * zz) * W + w];
+            wm = rw.mask;
+            wpb = rw.pb;
+        }
+    }
+    // every lane stays active through the shuffles below; lanes past the end
+    // of the task classify the task's first node and leave before any load
+    const bool active = lane < tk.cnt;
+    const int k = tk.k0 + (active ? lane : 0);
+    const int n = a.nodeof[k];
+    const int lb = a.lbase[k];  // first reactive link (used by interface nodes)
+    const int x = n - tk.row * b.nx;
+
+    // ---- neighbour classification (shared by both lattices) ----
+    int kk[Q];
+    uint32_t solidnb = 0u, cross = 0u, cross_hi = 0u;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const int xx = x - L::ex[i], yy = y - L::ey[i], zz = z - L::ez[i];
+        if (i == 0) {
+            kk[i] = k;
+        } else {
+            // x may wrap within the row; a wrap that shifts the row (tilted
+            // torus) or any row that does not fit the preloaded slots goes
+            // through the row words in memory
+            int xw = xx;
+            bool out = false, shifted = false;
+            if (xw < 0 || xw >= b.nx) {
+                if (!b.per[0]) out = true;
+                else {
+                    shifted = b.shift != 0;
+                    xw = xw < 0 ? xw + b.nx : xw - b.nx;
+                }
+            }
+            if ((yy < 0 || yy >= b.ny) && !b.per[1]) out = true;
+            if ((zz < 0 || zz >= b.nz) && !b.per[2]) out = true;
+            // the shuffles run on every lane: a shuffle reads zero from a lane
+            // that is inactive at that point
+            const int xs = min(max(xw, 0), b.nx - 1);
+            const int src = slots_fit ? slot_of<L>(i) * W + (xs >> 6) : 0;
+            const unsigned lo = __shfl((unsigned)(wm & 0xffffffffull), src, 64);
+            const unsigned hi = __shfl((unsigned)(wm >> 32), src, 64);
+            const int pb = __shfl(wpb, src, 64);
+            if (out) {
+                kk[i] = -2;
+            } else if (!slots_fit || shifted) {
+                kk[i] = nb_compact(a.rows, W, b, xx, yy, zz);
+            } else {
+                const unsigned long long m = ((unsigned long long)hi << 32) | lo;
+                const unsigned long long bit = 1ull << (xs & 63);
+                kk[i] = (m & bit) ? pb + __popcll(m & (bit - 1ull)) : -1;
+            }
+        }
+        if (kk[i] == -1) solidnb |= 1u << i;
+        if (ax >= 0) {
+            const int c = ax == 0 ? xx : (ax == 1 ? yy : zz);
+            const int nn = ax == 0 ? b.nx : (ax == 1 ? b.ny : b.nz);
+            if (c < 0) cross |= 1u << i;
+            if (c >= nn) { cross |= 1u << i; cross_hi |= 1u << i; }
+        }
+    }
+    const uint32_t rbc = active ? (solidnb & ~cross) : 0u;
+
+    // ---- link coefficients beta = (1 - k_i)/(1 + k_i) of this node's
+    // reactive links (contiguous from its first link, in direction order),
+    // fetched straight into LDS so that no VGPR waits on them: row [i][w] of
+    // this wavefront's slice holds dword w of lane's beta along i ----
+    constexpr int NW = (int)(sizeof(T) / 4);
+    __shared__ uint32_t sbeta[BLK / 64][Q][NW][64];
+    const int wv = threadIdx.x >> 6;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        if (rbc & (1u << i)) {
+            const uint32_t *p = (const uint32_t *)(a.lbeta + lb + __popc(rbc & ((1u << i) - 1u)));
+#pragma unroll
+            for (int w = 0; w < NW; w++)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(p + w),
+                                                 (__attribute__((address_space(3))) void *)&sbeta[wv][i][w][0],
+                                                 4, 0, 0);
+        }
+    }
+    if (!active) return;
+
+    // ---- loads: Q fluid + Q solute values per node ----
+    T fv[Q], gv[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        // fluid neighbour: pull along i; solid or box face: own value along opp(i)
+        fv[i] = kk[i] >= 0 ? a.fin[(long)i * S + kk[i]] : a.fin[(long)L::opp[i] * S + k];
+    }
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        int e = kk[i];
+        if (cross & (1u << i)) {
+            if (cross_hi & (1u << i)) {
+                // zero-gradient outlet: the same direction one site back
+                // along the inlet axis, inside the outlet plane
+                e = nb_compact(a.rows, a.W, b, x - L::ex[i] - (ax == 0),
+                               y - L::ey[i] - (ax == 1), z - L::ez[i] - (ax == 2));
+            } else {
+                e = k;  // inlet: value set below
+            }
+        }
+        // fluid neighbour: pull; solid or box face: own value along opp(i)
+        gv[i] = e >= 0 ? a.gin[(long)i * S + e] : a.gin[(long)L::opp[i] * S + k];
+    }
+
+    // ---- fluid: moments and Guo-forced BGK ----
+    R fp[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++) fp[i] = (R)fv[i];
+    R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        drho += fp[i];
+        if (L::ex[i]) jx += L::ex[i] > 0 ? fp[i] : -fp[i];
+        if (L::ey[i]) jy += L::ey[i] > 0 ? fp[i] : -fp[i];
+        if (L::ez[i]) jz += L::ez[i] > 0 ? fp[i] : -fp[i];
+    }
+    const R rho = a.rho0 + drho;
+    const R irho = R(1) / rho;
+    // rho u = j + F/2 enters the first-order equilibrium term directly, so the
+    // equilibrium carries exactly the momentum of the node
+    const R mx = jx + R(0.5) * a.F[0], my = jy + R(0.5) * a.F[1], mz = jz + R(0.5) * a.F[2];
+    const R ux = mx * irho, uy = my * irho, uz = mz * irho;
+    const R uu = ux * ux + uy * uy + uz * uz;
+    const R uF = ux * a.F[0] + uy * a.F[1] + uz * a.F[2];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
+        const R em = R(L::ex[i]) * mx + R(L::ey[i]) * my + R(L::ez[i]) * mz;
+        const R eF = R(L::ex[i]) * a.F[0] + R(L::ey[i]) * a.F[1] + R(L::ez[i]) * a.F[2];
+        const R wi = R(L::w[i]);
+        const R feq = wi * (drho + R(3) * em + rho * (R(4.5) * eu * eu - R(1.5) * uu));
+        const R src = wi * (R(3) * (eF - uF) + R(9) * eu * eF);
+        a.fout[(long)i * S + k] = (T)(fp[i] + a.omega_f * (feq - fp[i]) + a.force_fac * src);
+    }
+
+    // ---- solute: plane faces, reactive links, collision ----
+    if (cross & ~cross_hi) {
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            if ((cross & ~cross_hi) & (1u << i)) {
+                const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
+                gv[i] = (T)(a.ws[i] * (a.c_in - a.c_ref) + a.ws[i] * a.c_in * eu * a.inv_cs2s);
+            }
+        }
+    }
+    // general reactive boundary condition on each link entering from a solid
+    // node (direction order):
+    //   g_in = k/(1+k) 2 w_i C_eq + (1-k)/(1+k) g_src = (1 - beta) w_i C_eq + beta g_src
+    // (deviation form: C_eq - C_ref, since beta - 1 = -2 k/(1+k)).  g_src is the
+    // population moving toward the wall: the one pulled into this node along the
+    // opposite direction (pre-collision mechanics), or the node's own
+    // post-collision value (link-wise mechanics, and the one-node-gap fallback,
+    // whose beta already carries k/gamma).  q = g_in - g_out crossed the link.
+    if (rbc) {
+        double sneg = 0.0;
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (rbc & (1u << i)) {
+                const int o = L::opp[i];
+                const R own = (R)gv[i];  // a link direction loaded the node's own value along o
+                const R srcv = (a.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
+                T bt;
+                if constexpr (NW == 1) {
+                    bt = __builtin_bit_cast(T, sbeta[wv][i][0][lane]);
+                } else {
+                    const unsigned long long lo = sbeta[wv][i][0][lane], hi = sbeta[wv][i][NW - 1][lane];
+                    bt = __builtin_bit_cast(T, lo | (hi << 32));
+                }
+                const R beta = (R)bt;
+                const R g = (R(1) - beta) * (a.ws[i] * a.ceq_dev) + beta * srcv;
+                const T qv = (T)(g - own);
+                a.lq[lb + __popc(rbc & ((1u << i) - 1u))] = qv;
+                if (qv < T(0)) sneg -= (double)qv;
+                gv[i] = (T)g;
+            }
+        }
+        if (sneg != 0.0) a.phi[n] += a.vma * sneg;
+    }
+    R dC = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; i++) dC += (R)gv[i];
+    const R C = a.c_ref + dC;
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
+        const R gi = (R)gv[i];
+        const R geq = a.ws[i] * (dC + C * eu * a.inv_cs2s);
+        a.gout[(long)i * S + k] = (T)(gi + a.omega_g * (geq - gi));
+    }
+}
+
+// dissolution side of the solid fraction, per solid interface node, links in
+// ascending direction order; also the step's total exchange into acc[0]
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ sif,
+                                                   const int32_t *__restrict__ soff,
+                                                   const int32_t *__restrict__ slinks,
+                                                   const T *__restrict__ lq, double *__restrict__ phi,
+                                                   long nsif, double vma, double *acc) {
+    const long j = (long)blockIdx.x * BLK + threadIdx.x;
+    double tot = 0.0;
+    if (j < nsif) {
+        const int s = sif[j];
+        double pos = 0.0;
+        const int k1 = soff[j + 1];
+        for (int kq = soff[j]; kq < k1; kq++) {
+            const double qv = (double)lq[slinks[kq]];
+            tot += qv;
+            if (qv > 0.0) pos += qv;
+        }
+        phi[s] -= vma * pos;
+    }
+    tot = block_sum(tot);
+    if (threadIdx.x == 0 && tot != 0.0) atomicAdd(acc, tot);
+}
+
+template <typename T>
+static StepArgs<T> step_args(Ctx &c) {
+    StepArgs<T> a;
+    a.fin = (const T *)c.f[c.cur];
+    a.fout = (T *)c.f[1 - c.cur];
+    a.gin = (const T *)c.g[c.cur];
+    a.gout = (T *)c.g[1 - c.cur];
+    a.tasks = c.tasks;
+    a.rows = c.rows;
+    a.nodeof = c.nodeof;
+    a.lbase = c.lbase;
+    a.lbeta = (const T *)c.lbeta;
+    a.lq = (T *)c.lq;
+    a.phi = c.phi;
+    a.ntasks = c.n_tasks;
+    a.S = c.S;
+    a.W = c.W;
+    a.box = c.box;
+    a.mech = c.p.rbc_mechanics;
+    a.omega_f = 1.0 / c.p.tau_ns;
+    a.omega_g = 1.0 / c.p.tau_ad;
+    a.force_fac = 1.0 - 0.5 / c.p.tau_ns;
+    for (int d = 0; d < 3; d++) a.F[d] = c.p.force[d];
+    for (int i = 0; i < 19; i++) a.ws[i] = i < c.Q ? c.ws[i] : 0.0;
+    a.inv_cs2s = 1.0 / c.cs2s;
+    a.rho0 = c.fp64 ? 0.0 : c.p.rho0;
+    a.c_ref = c.fp64 ? 0.0 : c.p.c_ref;
+    a.ceq_dev = c.p.c_eq - (c.fp64 ? 0.0 : c.p.c_ref);
+    a.c_in = c.p.inlet_axis >= 0 ? c.p.c_in : 0.0;
+    a.vma = c.p.v_m * c.p.a_m;
+    return a;
+}
+
+template <class L, typename T>
+static hipError_t step_impl(Ctx &c, hipEvent_t *ev) {
+    hipError_t e = hipSuccess;
+    const StepArgs<T> args = step_args<T>(c);
+    if (ev) (void)hipEventRecord(ev[0], c.stream);
+    if (c.n_tasks > 0) {
+        const long nb = (c.n_tasks + BLK / 64 - 1) / (BLK / 64);
+        hipLaunchKernelGGL((k_step<L, T>), dim3(nb), dim3(BLK), 0, c.stream, args, nb);
+        e = hipGetLastError();
+    }
+    if (ev) (void)hipEventRecord(ev[1], c.stream);
+    if (e != hipSuccess) return e;
+    if (ev) (void)hipEventRecord(ev[2], c.stream);
+    if (c.n_sif > 0) {
+        const long nb2 = (c.n_sif + BLK - 1) / BLK;
+        hipLaunchKernelGGL((k_phi_solid<T>), dim3(nb2), dim3(BLK), 0, c.stream, c.sif, c.soff,
+                           c.slinks, (const T *)c.lq, c.phi, (long)c.n_sif, c.p.v_m * c.p.a_m,
+                           c.dacc);
+        e = hipGetLastError();
+    }
+    if (ev) (void)hipEventRecord(ev[3], c.stream);
+    c.cur = 1 - c.cur;
+    return e;
+}
+
+hipError_t launch_step(Ctx &c, hipEvent_t *ev) {
+    if (c.Q == 9) return c.fp64 ? step_impl<D2Q9, double>(c, ev) : step_impl<D2Q9, float>(c, ev);
+    return c.fp64 ? step_impl<D3Q19, double>(c, ev) : step_impl<D3Q19, float>(c, ev);
+}
+
+}  // namespace lbm
