@@ -26,7 +26,7 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM peak (fused step); adjoint/forward time ratio; batched vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2306_10794_amd", "csrc", "lbm_kernels.hip")
+KERNEL_SRC = os.path.join(ROOT, "paper_2306_10794_amd", "csrc", "lbm_step.hip")
 
 
 def log(msg):
@@ -34,15 +34,15 @@ def log(msg):
 
 
 def kernel_bytes(q, ts, n_fluid, n_links, n_fluid_iface):
-    """Algorithmic HBM bytes of one fused-step launch.
+    """Algorithmic HBM bytes of one launch of the fused step kernel.
 
-    Per fluid node: both lattices read and write Q populations of ts bytes,
-    plus the 4-byte node flag.  Per reactive link: the link coefficient, the
-    node's own post-collision population toward the wall and the exchange
-    written out (3 x ts).  Per fluid interface node: link base and link mask
-    (8 B) and the FP64 solid fraction read and written (16 B).
+    Per fluid node: both lattices read and write Q populations of ts bytes
+    (a reactive link reads the node's own population toward the wall in place
+    of a pulled one), plus 4 bytes of node metadata.  Per reactive link: the
+    link coefficient read and the exchange written (2 x ts).  Per fluid
+    interface node: its FP64 solid fraction read and written (16 B).
     """
-    return (n_fluid * (2 * q * ts * 2 + 4) + n_links * 3 * ts + n_fluid_iface * 24)
+    return n_fluid * (2 * q * ts * 2 + 4) + n_links * 2 * ts + n_fluid_iface * 16
 
 
 def traffic_from_profile(workload):

@@ -268,23 +268,33 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
 }
 
 // dissolution side of the solid fraction, per solid interface node, links in
-// ascending direction order; also the step's total exchange into acc[0]
-template <typename T>
+// ascending direction order; also the step's total exchange into acc[0].  A
+// solid node has at most Q - 1 links: all their indices, then all their
+// exchanges, are loaded before the ordered sum.
+template <class L, typename T>
 __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ sif,
                                                    const int32_t *__restrict__ soff,
                                                    const int32_t *__restrict__ slinks,
                                                    const T *__restrict__ lq, double *__restrict__ phi,
                                                    long nsif, double vma, double *acc) {
+    constexpr int M = L::Q - 1;
     const long j = (long)blockIdx.x * BLK + threadIdx.x;
     double tot = 0.0;
     if (j < nsif) {
         const int s = sif[j];
+        const int k0 = soff[j], nk = soff[j + 1] - k0;
+        int li[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) li[m] = m < nk ? slinks[k0 + m] : -1;
+        T qv[M];
+#pragma unroll
+        for (int m = 0; m < M; m++) qv[m] = li[m] >= 0 ? lq[li[m]] : T(0);
         double pos = 0.0;
-        const int k1 = soff[j + 1];
-        for (int kq = soff[j]; kq < k1; kq++) {
-            const double qv = (double)lq[slinks[kq]];
-            tot += qv;
-            if (qv > 0.0) pos += qv;
+#pragma unroll
+        for (int m = 0; m < M; m++) {
+            const double v = (double)qv[m];
+            tot += v;
+            if (v > 0.0) pos += v;
         }
         phi[s] -= vma * pos;
     }
@@ -340,7 +350,7 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev) {
     if (ev) (void)hipEventRecord(ev[2], c.stream);
     if (c.n_sif > 0) {
         const long nb2 = (c.n_sif + BLK - 1) / BLK;
-        hipLaunchKernelGGL((k_phi_solid<T>), dim3(nb2), dim3(BLK), 0, c.stream, c.sif, c.soff,
+        hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, c.stream, c.sif, c.soff,
                            c.slinks, (const T *)c.lq, c.phi, (long)c.n_sif, c.p.v_m * c.p.a_m,
                            c.dacc);
         e = hipGetLastError();
