@@ -126,6 +126,20 @@ lbm_status lbm_workspace_bytes(const lbm_params *params, size_t *bytes);
 lbm_status lbm_create(const lbm_params *params, void *dev_workspace, size_t bytes,
                       void *hip_stream, lbm_ctx **out);
 
+/* Batches (many independent domains advanced by the same launches).
+ * The domains share dim, lattice and precision; everything else (size,
+ * relaxation times, rest fraction, force, rate constants, boundary settings)
+ * is per domain.  All per-node arrays of a batch context (geometry, fields,
+ * populations [Q][N], exchange [N][Q]) are the domains' arrays concatenated in
+ * domain order; lbm_batch_offsets gives the first node of each domain.  A
+ * single-domain context is a batch of one.  Phase change is not available in
+ * a batch (EINVAL). */
+lbm_status lbm_batch_workspace_bytes(const lbm_params *per_domain, int32_t n, size_t *bytes);
+lbm_status lbm_create_batch(const lbm_params *per_domain, int32_t n, void *dev_workspace,
+                            size_t bytes, void *hip_stream, lbm_ctx **out);
+/* node_off: host array of n + 1 entries (the last is the total node count) */
+lbm_status lbm_batch_offsets(const lbm_ctx *ctx, int64_t *node_off);
+
 /* Geometry prep (per geometry, not per step): node classes, reactive link
  * list with k_i per link (Sec. 2.3), solid-side link lists.
  *   solid   [N]    uint8, nonzero = solid (required)

@@ -5,19 +5,20 @@ ABI of ``include/lbmrbc.h``; this package is its thin Python binding.
 """
 from . import _lib
 from ._lib import (LbmError, lbm_params, lbm_workspace_bytes, lbm_create, lbm_set_geometry,
+                   lbm_batch_workspace_bytes, lbm_create_batch, lbm_batch_offsets,
                    lbm_init_fields, lbm_step, lbm_step_timed, lbm_get_fields, lbm_get_pops, lbm_get_exchange,
                    lbm_get_diag, lbm_state_bytes, lbm_save_state, lbm_load_state,
                    lbm_last_error, lbm_destroy, LBM_FP64, LBM_FP32_DEV, LBM_PRECOLL,
                    LBM_POSTCOLL, LBM_SNEW, LBM_SV, LBM_SPJ, LBM_ABB)
 
 __all__ = [n for n in dir() if n.startswith("lbm_") or n.startswith("LBM_")] + [
-    "LbmError", "Simulation", "params_from_case"]
+    "LbmError", "Simulation", "BatchSimulation", "params_from_case"]
 
 
 def __getattr__(name):
     # torch-based helpers are imported lazily so that the C ABI can be loaded
     # and inspected without initialising torch
-    if name in ("Simulation", "params_from_case"):
+    if name in ("Simulation", "BatchSimulation", "params_from_case"):
         from . import sim
         return getattr(sim, name)
     raise AttributeError(name)

@@ -58,6 +58,9 @@ _P = C.c_void_p
 _SIGS = {
     "lbm_workspace_bytes": [C.POINTER(lbm_params), C.POINTER(C.c_size_t)],
     "lbm_create": [C.POINTER(lbm_params), _P, C.c_size_t, _P, C.POINTER(_P)],
+    "lbm_batch_workspace_bytes": [C.POINTER(lbm_params), C.c_int32, C.POINTER(C.c_size_t)],
+    "lbm_create_batch": [C.POINTER(lbm_params), C.c_int32, _P, C.c_size_t, _P, C.POINTER(_P)],
+    "lbm_batch_offsets": [_P, C.POINTER(C.c_int64)],
     "lbm_set_geometry": [_P, _P, _P, _P, _P],
     "lbm_init_fields": [_P, _P, _P, _P],
     "lbm_step": [_P, C.c_int32],
@@ -123,6 +126,28 @@ def lbm_create(params: lbm_params, workspace, nbytes: int, stream=None):
     _check(lib.lbm_create(C.byref(params), _ptr(workspace), nbytes, _stream_handle(stream),
                           C.byref(h)), "lbm_create")
     return h.value
+
+
+def lbm_batch_workspace_bytes(params_list) -> int:
+    arr = (lbm_params * len(params_list))(*params_list)
+    n = C.c_size_t(0)
+    _check(lib.lbm_batch_workspace_bytes(arr, len(params_list), C.byref(n)),
+           "lbm_batch_workspace_bytes")
+    return n.value
+
+
+def lbm_create_batch(params_list, workspace, nbytes: int, stream=None):
+    arr = (lbm_params * len(params_list))(*params_list)
+    h = C.c_void_p()
+    _check(lib.lbm_create_batch(arr, len(params_list), _ptr(workspace), nbytes,
+                                _stream_handle(stream), C.byref(h)), "lbm_create_batch")
+    return h.value
+
+
+def lbm_batch_offsets(ctx, n: int) -> list:
+    off = (C.c_int64 * (n + 1))()
+    _check(lib.lbm_batch_offsets(ctx, off), "lbm_batch_offsets", ctx)
+    return list(off)
 
 
 def lbm_set_geometry(ctx, solid, normals=None, k_r=None, phi0=None):

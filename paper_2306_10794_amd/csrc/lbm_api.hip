@@ -5,6 +5,7 @@
 
 #include <new>
 #include <string>
+#include <vector>
 
 #include "lbm_internal.hpp"
 
@@ -62,20 +63,28 @@ int64_t default_links(const lbm_params &p) {
 
 namespace lbm {
 
-// Carve the workspace.  With base == nullptr only the size is computed.
-size_t workspace_layout(const lbm_params &p, Ctx *c, char *base) {
-    const long N = (long)p.nx * p.ny * p.nz;
-    const long R = (long)p.ny * p.nz;
-    const int W = (p.nx + 63) / 64;
-    const int Q = p.fluid_q;
-    const size_t ts = p.precision == LBM_FP64 ? 8 : 4;
+// Carve the workspace for n domains.  With base == nullptr only the size is
+// computed.
+size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
+    long N = 0, R = 0, RW = 0;
+    int64_t L = 0;
+    for (int d = 0; d < nd; d++) {
+        const long Nd = (long)p[d].nx * p[d].ny * p[d].nz;
+        const long Rd = (long)p[d].ny * p[d].nz;
+        N += Nd;
+        R += Rd;
+        RW += Rd * ((p[d].nx + 63) / 64);
+        L += default_links(p[d]);
+    }
+    if (L > 2147483000LL) L = 2147483000LL;
+    const int Q = p[0].fluid_q;
+    const size_t ts = p[0].precision == LBM_FP64 ? 8 : 4;
     // direction stride: a multiple of 64 elements and an odd multiple of
     // 64 * ts bytes, so the 2Q streams of a step do not all start on the same
     // large power-of-two boundary
     long S = (N + 63) / 64 * 64;
     if ((S / 64) % 2 == 0) S += 64;
     const long task_cap = R + N / 64 + 1;
-    const int64_t L = default_links(p);
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *r = base ? base + off : nullptr;
@@ -83,14 +92,15 @@ size_t workspace_layout(const lbm_params &p, Ctx *c, char *base) {
         return r;
     };
     char *f0 = take(ts * Q * S), *f1 = take(ts * Q * S), *g0 = take(ts * Q * S), *g1 = take(ts * Q * S);
-    char *rows = take(sizeof(RowWord) * R * W), *tasks = take(sizeof(Task) * task_cap);
+    char *doms = take(sizeof(DomDev) * nd);
+    char *noff = take(8 * (nd + 1)), *woff = take(8 * (nd + 1)), *roff = take(8 * (nd + 1));
+    char *rows = take(sizeof(RowWord) * RW), *tasks = take(sizeof(Task) * task_cap);
     char *nodeof = take(4 * N), *kof = take(4 * N), *lbase = take(4 * N);
     char *flags = take(4 * N), *rmask = take(4 * N), *cnt = take(4 * N), *sidx = take(4 * N);
     char *phi = take(8 * N), *kr = take(8 * N), *nrm = take(24 * N), *solid = take(N);
     char *lbeta = take(ts * L), *lq = take(ts * L), *lnode = take(4 * L), *lsolid = take(4 * L),
          *ldir = take(L);
-    char *iface = take(4 * N), *imask = take(4 * N);
-    char *sif = take(4 * L), *soff = take(4 * (L + 1)), *slinks = take(4 * L);
+    char *sif = take(4 * L), *soff = take(4 * (L + 1)), *slinks = take(4 * L), *sdom = take(4 * L);
     char *bsum = take(4 * ((N + 4095) / 4096 + 64));
     char *dpart = take(16 * ((N + 255) / 256 + 1));
     char *dacc = take(8 * 64), *iacc = take(4 * 64);
@@ -98,22 +108,23 @@ size_t workspace_layout(const lbm_params &p, Ctx *c, char *base) {
         c->N = N;
         c->S = S;
         c->R = R;
-        c->W = W;
+        c->RW = RW;
         c->Q = Q;
         c->task_cap = task_cap;
         c->max_links = L;
         c->f[0] = f0; c->f[1] = f1; c->g[0] = g0; c->g[1] = g1;
+        c->doms = (DomDev *)doms;
+        c->dnode_off = (long *)noff; c->dword_off = (long *)woff; c->drow_off = (long *)roff;
         c->rows = (RowWord *)rows; c->tasks = (Task *)tasks;
         c->nodeof = (int32_t *)nodeof; c->kof = (int32_t *)kof; c->lbase = (int32_t *)lbase;
         c->flags = (uint32_t *)flags; c->rmask = (uint32_t *)rmask;
         c->cnt = (int32_t *)cnt; c->sidx = (int32_t *)sidx;
         c->phi = (double *)phi; c->kr = (double *)kr; c->nrm = (double *)nrm;
         c->solid = (uint8_t *)solid;
-        c->lbeta = lbeta; c->lq = lq;
-        c->iface = (int32_t *)iface; c->imask = (uint32_t *)imask;
-        c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
+        c->lbeta = lbeta; c->lq = lq; c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
         c->ldir = (uint8_t *)ldir;
         c->sif = (int32_t *)sif; c->soff = (int32_t *)soff; c->slinks = (int32_t *)slinks;
+        c->sdom = (int32_t *)sdom;
         c->bsum = (int32_t *)bsum;
         c->dpart = (double *)dpart;
         c->dacc = (double *)dacc; c->iacc = (int32_t *)iacc;
@@ -146,58 +157,93 @@ static lbm_status dev_err(Ctx *c, hipError_t e, const char *what) {
     return LBM_EDEVICE;
 }
 
-static void setup_lattice(Ctx *c) {
-    const lbm_params &p = c->p;
-    c->dim = p.dim;
-    c->fp64 = p.precision == LBM_FP64;
-    c->box.nx = p.nx;
-    c->box.ny = p.ny;
-    c->box.nz = p.nz;
-    for (int d = 0; d < 3; d++) c->box.per[d] = p.periodic[d];
-    c->box.shift = p.xwrap_shift_y;
-    c->box.inlet_axis = p.inlet_axis;
+// host view of domain d: box, rest-fraction weights and constants
+static void setup_domain(const lbm_params &p, DomHost &d) {
+    d.p = p;
+    d.box.nx = p.nx;
+    d.box.ny = p.ny;
+    d.box.nz = p.nz;
+    for (int a = 0; a < 3; a++) d.box.per[a] = p.periodic[a];
+    d.box.shift = p.xwrap_shift_y;
+    d.box.inlet_axis = p.inlet_axis;
+    d.N = (long)p.nx * p.ny * p.nz;
+    d.R = (long)p.ny * p.nz;
+    d.W = (p.nx + 63) / 64;
     const double *w = p.fluid_q == 9 ? D2Q9::w : D3Q19::w;
     const double w0 = w[0];
-    for (int i = 0; i < 19; i++) c->ws[i] = 0.0;
+    for (int i = 0; i < 19; i++) d.ws[i] = 0.0;
     if (p.j0 < 0) {
-        for (int i = 0; i < p.fluid_q; i++) c->ws[i] = w[i];
-        c->cs2s = 1.0 / 3.0;
+        for (int i = 0; i < p.fluid_q; i++) d.ws[i] = w[i];
+        d.wsc = 1.0;
+        d.cs2s = 1.0 / 3.0;
     } else {
         // rest fraction: w_0 = J0, moving weights and c_s^2 scaled by (1-J0)/(1-w0)
         const double sc = (1.0 - p.j0) / (1.0 - w0);
-        c->ws[0] = p.j0;
-        for (int i = 1; i < p.fluid_q; i++) c->ws[i] = w[i] * sc;
-        c->cs2s = sc / 3.0;
+        d.ws[0] = p.j0;
+        for (int i = 1; i < p.fluid_q; i++) d.ws[i] = w[i] * sc;
+        d.wsc = sc;
+        d.cs2s = sc / 3.0;
     }
-    c->gamma = p.tau_ad / (p.tau_ad - 0.5);
+    d.gamma = p.tau_ad / (p.tau_ad - 0.5);
 }
 
-extern "C" {
-
-lbm_status lbm_workspace_bytes(const lbm_params *params, size_t *bytes) {
-    if (!params || !bytes) return LBM_EINVAL;
-    std::string m = check_params(*params);
-    if (!m.empty()) {
-        g_create_err = m;
-        return LBM_EINVAL;
-    }
-    *bytes = workspace_layout(*params, nullptr, nullptr);
-    return LBM_OK;
+static DomDev dom_record(const DomHost &h, bool fp64) {
+    DomDev D;
+    memset(&D, 0, sizeof D);
+    const lbm_params &p = h.p;
+    D.box = h.box;
+    D.W = h.W;
+    D.mech = p.rbc_mechanics;
+    D.scheme = p.rbc_scheme;
+    D.node_off = h.node_off;
+    D.word_off = h.word_off;
+    D.row_off = h.row_off;
+    D.omega_f = 1.0 / p.tau_ns;
+    D.omega_g = 1.0 / p.tau_ad;
+    D.force_fac = 1.0 - 0.5 / p.tau_ns;
+    for (int a = 0; a < 3; a++) D.F[a] = p.force[a];
+    for (int i = 0; i < 19; i++) D.ws[i] = h.ws[i];
+    D.wsc = h.wsc;
+    D.inv_cs2s = 1.0 / h.cs2s;
+    D.cs2s = h.cs2s;
+    D.gamma = h.gamma;
+    D.rho0 = fp64 ? 0.0 : p.rho0;
+    D.c_ref = fp64 ? 0.0 : p.c_ref;
+    D.ceq_dev = p.c_eq - D.c_ref;
+    D.c_in = p.inlet_axis >= 0 ? p.c_in : 0.0;
+    D.vma = p.v_m * p.a_m;
+    D.kr0 = p.k_r;
+    return D;
 }
 
-lbm_status lbm_create(const lbm_params *params, void *dev_workspace, size_t bytes, void *hip_stream,
-                      lbm_ctx **out) {
+static std::string check_batch(const lbm_params *p, int n) {
+    if (n < 1) return "a batch needs at least one domain";
+    for (int d = 0; d < n; d++) {
+        std::string m = check_params(p[d]);
+        if (!m.empty()) return (n > 1 ? "domain " + std::to_string(d) + ": " : std::string()) + m;
+        if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].precision != p[0].precision)
+            return "all domains of a batch need the same dim, lattice and precision";
+        if (p[d].phase_change != 0 && n > 1) return "phase_change is not supported in a batch";
+    }
+    double N = 0;
+    for (int d = 0; d < n; d++) N += (double)p[d].nx * p[d].ny * p[d].nz;
+    if (N >= 2147483647.0) return "the batch exceeds 2^31 - 1 nodes";
+    return "";
+}
+
+static lbm_status create_common(const lbm_params *params, int nd, void *dev_workspace, size_t bytes,
+                                void *hip_stream, lbm_ctx **out) {
     if (!params || !out) {
         g_create_err = "null argument";
         return LBM_EINVAL;
     }
     *out = nullptr;
-    std::string m = check_params(*params);
+    std::string m = check_batch(params, nd);
     if (!m.empty()) {
         g_create_err = m;
         return LBM_EINVAL;
     }
-    const size_t need = workspace_layout(*params, nullptr, nullptr);
+    const size_t need = workspace_layout(params, nd, nullptr, nullptr);
     if (!dev_workspace || bytes < need) {
         g_create_err = "workspace of " + std::to_string(bytes) + " bytes is smaller than the " +
                        std::to_string(need) + " needed";
@@ -216,17 +262,84 @@ lbm_status lbm_create(const lbm_params *params, void *dev_workspace, size_t byte
         g_create_err = "host allocation failed";
         return LBM_ENOMEM;
     }
-    c->p = *params;
+    c->p = params[0];
     c->stream = (hipStream_t)hip_stream;
-    setup_lattice(c);
+    c->dim = params[0].dim;
+    c->fp64 = params[0].precision == LBM_FP64;
+    c->ndom = nd;
+    c->dom.resize(nd);
+    long noff = 0, woff = 0, roff = 0;
+    std::vector<long> hn(nd + 1), hw(nd + 1), hr(nd + 1);
+    std::vector<DomDev> hd(nd);
+    for (int d = 0; d < nd; d++) {
+        DomHost &h = c->dom[d];
+        setup_domain(params[d], h);
+        h.node_off = noff;
+        h.word_off = woff;
+        h.row_off = roff;
+        hn[d] = noff;
+        hw[d] = woff;
+        hr[d] = roff;
+        noff += h.N;
+        woff += h.R * h.W;
+        roff += h.R;
+        hd[d] = dom_record(h, c->fp64);
+    }
+    hn[nd] = noff;
+    hw[nd] = woff;
+    hr[nd] = roff;
     c->ws_bytes = bytes;
-    workspace_layout(c->p, c, (char *)dev_workspace);
+    workspace_layout(params, nd, c, (char *)dev_workspace);
+    hipError_t e = hipMemcpy(c->doms, hd.data(), sizeof(DomDev) * nd, hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->dnode_off, hn.data(), 8 * (nd + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->dword_off, hw.data(), 8 * (nd + 1), hipMemcpyHostToDevice);
+    if (e == hipSuccess) e = hipMemcpy(c->drow_off, hr.data(), 8 * (nd + 1), hipMemcpyHostToDevice);
+    if (e != hipSuccess) {
+        g_create_err = std::string("uploading the domain table: ") + hipGetErrorString(e);
+        delete c;
+        return LBM_EDEVICE;
+    }
     c->cur = 0;
     c->n_links = c->n_sif = 0;
     c->step = c->n_events = 0;
     c->have_geom = c->have_state = false;
     c->have_events = false;
     *out = (lbm_ctx *)c;
+    return LBM_OK;
+}
+
+extern "C" {
+
+lbm_status lbm_workspace_bytes(const lbm_params *params, size_t *bytes) {
+    return lbm_batch_workspace_bytes(params, 1, bytes);
+}
+
+lbm_status lbm_batch_workspace_bytes(const lbm_params *params, int32_t n, size_t *bytes) {
+    if (!params || !bytes) return LBM_EINVAL;
+    std::string m = check_batch(params, n);
+    if (!m.empty()) {
+        g_create_err = m;
+        return LBM_EINVAL;
+    }
+    *bytes = workspace_layout(params, n, nullptr, nullptr);
+    return LBM_OK;
+}
+
+lbm_status lbm_create(const lbm_params *params, void *dev_workspace, size_t bytes, void *hip_stream,
+                      lbm_ctx **out) {
+    return create_common(params, 1, dev_workspace, bytes, hip_stream, out);
+}
+
+lbm_status lbm_create_batch(const lbm_params *params, int32_t n, void *dev_workspace, size_t bytes,
+                            void *hip_stream, lbm_ctx **out) {
+    return create_common(params, n, dev_workspace, bytes, hip_stream, out);
+}
+
+lbm_status lbm_batch_offsets(const lbm_ctx *ctx, int64_t *node_off) {
+    const Ctx *c = (const Ctx *)ctx;
+    if (!c || !node_off) return LBM_EINVAL;
+    for (int d = 0; d < c->ndom; d++) node_off[d] = c->dom[d].node_off;
+    node_off[c->ndom] = c->N;
     return LBM_OK;
 }
 

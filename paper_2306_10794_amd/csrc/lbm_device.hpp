@@ -64,10 +64,10 @@ struct RowWord {
 };
 
 struct Task {
-    int32_t row;               // row = y + ny*z
+    int32_t row;               // row of the task's domain, y + ny*z
     int32_t k0;                // compact index of the task's first node
     int32_t cnt;               // nodes in the task, 1..64
-    int32_t pad;
+    int32_t dom;               // domain of the batch
 };
 
 struct Box {
@@ -76,6 +76,46 @@ struct Box {
     int shift;         // site (x + nx, y) is site (x, y + shift)
     int inlet_axis;    // solute: non-periodic axis with inlet/outlet, or -1
 };
+
+// One domain of a batch, as the kernels see it (a single lattice is a batch of
+// one).  Dense node arrays of all domains are concatenated in domain order, as
+// are their row words and their compact fluid arrays.
+struct DomDev {
+    Box box;
+    int W;                     // 64-node words per row
+    int mech, scheme;
+    long node_off;             // first dense node of the domain
+    long word_off;             // first row word of the domain
+    long row_off;              // first global row of the domain
+    double omega_f, omega_g, force_fac;
+    double F[3];
+    double ws[19];             // solute weights (rest fraction)
+    double wsc;                // ws[i] = w[i] * wsc for every moving direction
+    double inv_cs2s, cs2s, gamma;
+    double rho0, c_ref;        // deviation references (0 in FP64 storage)
+    double ceq_dev;            // C_eq - C_ref
+    double c_in;
+    double vma;                // V_m a_m
+    double kr0;                // uniform rate constant
+};
+
+// solute weight of direction i: the rest weight is stored, the moving ones are
+// the lattice weights times one scale (keeps the step kernel's constants few)
+template <class L>
+__device__ __forceinline__ double sol_w(const DomDev &D, int i) {
+    return i == 0 ? D.ws[0] : L::w[i] * D.wsc;
+}
+
+// domain of dense node n (off: node_off of every domain, then the total)
+__device__ inline int find_dom(const long *off, int ndom, long n) {
+    int lo = 0, hi = ndom;
+    while (hi - lo > 1) {
+        const int mid = (lo + hi) >> 1;
+        if (off[mid] <= n) lo = mid;
+        else hi = mid;
+    }
+    return lo;
+}
 
 __host__ __device__ inline int fdiv(int a, int b) {
     int q = a / b;

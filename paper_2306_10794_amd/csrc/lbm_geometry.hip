@@ -89,11 +89,25 @@ hipError_t scan_excl(Ctx &c, const int32_t *in, int32_t *out, long n, int32_t *t
 }
 
 // ---------------------------------------------------------------------------
-// node classes
+// node classes (every kernel below covers all domains of a batch; a thread
+// finds its domain from the offset tables)
 // ---------------------------------------------------------------------------
+struct Geo {
+    const DomDev *doms;
+    const long *node_off, *word_off, *row_off;
+    int ndom;
+};
+
+// domain d and local node index of global dense node n
+__device__ __forceinline__ int dom_of(const Geo &g, long n, long *nl) {
+    const int d = find_dom(g.node_off, g.ndom, n);
+    *nl = n - g.doms[d].node_off;
+    return d;
+}
+
 template <class L>
-__global__ __launch_bounds__(BLK) void k_flags(Box box, long N, const uint8_t *solid,
-                                               uint32_t *flags, uint32_t *rmask) {
+__global__ __launch_bounds__(BLK) void k_flags(Geo g, long N, const uint8_t *solid, uint32_t *flags,
+                                               uint32_t *rmask) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
     if (solid[n]) {
@@ -101,30 +115,37 @@ __global__ __launch_bounds__(BLK) void k_flags(Box box, long N, const uint8_t *s
         rmask[n] = 0u;
         return;
     }
+    long nl;
+    const int d = dom_of(g, n, &nl);
+    const Box box = g.doms[d].box;
+    const long base = g.doms[d].node_off;
     int X, Y, Z;
-    coords(box, n, &X, &Y, &Z);
+    coords(box, nl, &X, &Y, &Z);
     uint32_t fl = F_FLUID, rm = 0u;
     for (int i = 1; i < L::Q; i++) {
         int fc;
         const long y = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], false, &fc);
-        if (y < 0 || solid[y]) fl |= 1u << i;
+        if (y < 0 || solid[base + y]) fl |= 1u << i;
         const long ys = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
-        if (ys >= 0 && solid[ys]) rm |= 1u << i;
+        if (ys >= 0 && solid[base + ys]) rm |= 1u << i;
     }
     if (rm) fl |= F_LINK;
     flags[n] = fl;
     rmask[n] = rm;
 }
 
-// one thread per (row, word): fluid mask of 64 nodes and its population count
-__global__ __launch_bounds__(BLK) void k_row_words(long R, int W, int nx, const uint8_t *solid,
+// one thread per row word: fluid mask of up to 64 nodes and its population count
+__global__ __launch_bounds__(BLK) void k_row_words(Geo g, long RW, const uint8_t *solid,
                                                    RowWord *rows, int32_t *wcnt) {
     const long j = (long)blockIdx.x * BLK + threadIdx.x;
-    if (j >= R * W) return;
-    const long r = j / W;
-    const int w = (int)(j - r * W);
-    const long base = r * nx + 64L * w;
-    const int len = min(64, nx - 64 * w);
+    if (j >= RW) return;
+    const int d = find_dom(g.word_off, g.ndom, j);
+    const DomDev &D = g.doms[d];
+    const long jl = j - D.word_off;
+    const long r = jl / D.W;
+    const int w = (int)(jl - r * D.W);
+    const long base = D.node_off + r * D.box.nx + 64L * w;
+    const int len = min(64, D.box.nx - 64 * w);
     unsigned long long m = 0ull;
     for (int b = 0; b < len; b++)
         if (!solid[base + b]) m |= 1ull << b;
@@ -139,7 +160,7 @@ __global__ __launch_bounds__(BLK) void k_row_prefix(long RW, const int32_t *pre,
 }
 
 // dense <-> compact maps
-__global__ __launch_bounds__(BLK) void k_compact(long N, int nx, int W, const uint8_t *solid,
+__global__ __launch_bounds__(BLK) void k_compact(Geo g, long N, const uint8_t *solid,
                                                  const RowWord *rows, int32_t *nodeof, int32_t *kof) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
@@ -147,36 +168,46 @@ __global__ __launch_bounds__(BLK) void k_compact(long N, int nx, int W, const ui
         kof[n] = -1;
         return;
     }
-    const long r = n / nx;
-    const int x = (int)(n - r * nx);
-    const RowWord w = rows[r * W + (x >> 6)];
+    long nl;
+    const int d = dom_of(g, n, &nl);
+    const DomDev &D = g.doms[d];
+    const long r = nl / D.box.nx;
+    const int x = (int)(nl - r * D.box.nx);
+    const RowWord w = rows[D.word_off + r * D.W + (x >> 6)];
     const int k = w.pb + __popcll(w.mask & ((1ull << (x & 63)) - 1ull));
     nodeof[k] = (int32_t)n;
     kof[n] = k;
 }
 
-__global__ __launch_bounds__(BLK) void k_row_ntasks(long R, int W, const RowWord *rows, int32_t *nt) {
-    const long r = (long)blockIdx.x * BLK + threadIdx.x;
-    if (r >= R) return;
+__device__ __forceinline__ int row_fluid(const DomDev &D, const RowWord *rows, long r) {
     int c = 0;
-    for (int w = 0; w < W; w++) c += __popcll(rows[r * W + w].mask);
-    nt[r] = (c + 63) / 64;
+    for (int w = 0; w < D.W; w++) c += __popcll(rows[D.word_off + r * D.W + w].mask);
+    return c;
 }
 
-__global__ __launch_bounds__(BLK) void k_row_tasks(long R, int W, const RowWord *rows,
+__global__ __launch_bounds__(BLK) void k_row_ntasks(Geo g, long R, const RowWord *rows, int32_t *nt) {
+    const long rg = (long)blockIdx.x * BLK + threadIdx.x;
+    if (rg >= R) return;
+    const int d = find_dom(g.row_off, g.ndom, rg);
+    nt[rg] = (row_fluid(g.doms[d], rows, rg - g.doms[d].row_off) + 63) / 64;
+}
+
+__global__ __launch_bounds__(BLK) void k_row_tasks(Geo g, long R, const RowWord *rows,
                                                    const int32_t *tbase, Task *tasks) {
-    const long r = (long)blockIdx.x * BLK + threadIdx.x;
-    if (r >= R) return;
-    int c = 0;
-    for (int w = 0; w < W; w++) c += __popcll(rows[r * W + w].mask);
-    const int k0 = rows[r * W].pb;
-    const int t0 = tbase[r];
+    const long rg = (long)blockIdx.x * BLK + threadIdx.x;
+    if (rg >= R) return;
+    const int d = find_dom(g.row_off, g.ndom, rg);
+    const DomDev &D = g.doms[d];
+    const long r = rg - D.row_off;
+    const int c = row_fluid(D, rows, r);
+    const int k0 = rows[D.word_off + r * D.W].pb;
+    const int t0 = tbase[rg];
     for (int j = 0; 64 * j < c; j++) {
         Task t;
         t.row = (int32_t)r;
         t.k0 = k0 + 64 * j;
         t.cnt = min(64, c - 64 * j);
-        t.pad = 0;
+        t.dom = d;
         tasks[t0 + j] = t;
     }
 }
@@ -189,34 +220,36 @@ __global__ __launch_bounds__(BLK) void k_link_count(long nf, const int32_t *node
 }
 
 template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_links(Box box, long nf, const int32_t *nodeof,
+__global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *nodeof,
                                                const uint32_t *rmask, const int32_t *lbase,
-                                               const double *nrm, const double *kr, int scheme,
-                                               int mech, double gamma, double cs2s, T *lbeta,
+                                               const double *nrm, const double *kr, T *lbeta,
                                                int32_t *lnode, int32_t *lsolid, uint8_t *ldir) {
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
     if (k >= nf) return;
     const long n = nodeof[k];
     const uint32_t rm = rmask[n];
     if (!rm) return;
+    long nl;
+    const int d = dom_of(g, n, &nl);
+    const DomDev &D = g.doms[d];
     int X, Y, Z;
-    coords(box, n, &X, &Y, &Z);
+    coords(D.box, nl, &X, &Y, &Z);
     const int base = lbase[k];
     int r = 0;
     for (int i = 1; i < L::Q; i++) {
         if (!(rm & (1u << i))) continue;
         int fc;
-        const long s = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
+        const long s = D.node_off + site(D.box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
         const double en = L::ex[i] * nrm[3 * s] + L::ey[i] * nrm[3 * s + 1] + L::ez[i] * nrm[3 * s + 2];
         const double kv = kr[s];
         double kap;
-        if (scheme == LBM_SV) kap = en > 0 ? kv * en / cs2s : 0.0;
-        else if (scheme == LBM_SPJ) kap = en > 0 ? gamma * kv / (cs2s * en) : 0.0;
-        else kap = en > 0 ? gamma * kv * en / cs2s : 0.0;
+        if (D.scheme == LBM_SV) kap = en > 0 ? kv * en / D.cs2s : 0.0;
+        else if (D.scheme == LBM_SPJ) kap = en > 0 ? D.gamma * kv / (D.cs2s * en) : 0.0;
+        else kap = en > 0 ? D.gamma * kv * en / D.cs2s : 0.0;
         // pre-collision source with both neighbours solid: fall back to the
         // node's own post-collision population, whose effective rate is gamma k
-        if (mech == LBM_PRECOLL && (rm & (1u << L::opp[i]))) kap = kap / gamma;
-        const double beta = scheme == LBM_ABB ? -1.0 : (1.0 - kap) / (1.0 + kap);
+        if (D.mech == LBM_PRECOLL && (rm & (1u << L::opp[i]))) kap = kap / D.gamma;
+        const double beta = D.scheme == LBM_ABB ? -1.0 : (1.0 - kap) / (1.0 + kap);
         lbeta[base + r] = (T)beta;
         lnode[base + r] = (int32_t)n;
         lsolid[base + r] = (int32_t)s;
@@ -226,16 +259,18 @@ __global__ __launch_bounds__(BLK) void k_links(Box box, long nf, const int32_t *
 }
 
 template <class L>
-__device__ __forceinline__ int solid_links(const Box &box, long n, const uint8_t *solid,
+__device__ __forceinline__ int solid_links(const DomDev &D, long nl, const uint8_t *solid,
                                            const uint32_t *rmask, const int32_t *kof,
                                            const int32_t *lbase, int32_t *out) {
     int X, Y, Z;
-    coords(box, n, &X, &Y, &Z);
+    coords(D.box, nl, &X, &Y, &Z);
     int cnt = 0;
     for (int i = 1; i < L::Q; i++) {
         int fc;
-        const long x = site(box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], true, &fc);
-        if (x < 0 || solid[x]) continue;
+        const long xl = site(D.box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], true, &fc);
+        if (xl < 0) continue;
+        const long x = D.node_off + xl;
+        if (solid[x]) continue;
         const uint32_t rm = rmask[x];
         if (!(rm & (1u << i))) continue;
         if (out) out[cnt] = lbase[kof[x]] + __popc(rm & ((1u << i) - 1u));
@@ -245,47 +280,56 @@ __device__ __forceinline__ int solid_links(const Box &box, long n, const uint8_t
 }
 
 template <class L>
-__global__ __launch_bounds__(BLK) void k_solid_count(Box box, long N, const uint8_t *solid,
+__global__ __launch_bounds__(BLK) void k_solid_count(Geo g, long N, const uint8_t *solid,
                                                      const uint32_t *rmask, int32_t *cnt,
                                                      int32_t *ind) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
     int c = 0;
-    if (solid[n]) c = solid_links<L>(box, n, solid, rmask, nullptr, nullptr, nullptr);
+    if (solid[n]) {
+        long nl;
+        const int d = dom_of(g, n, &nl);
+        c = solid_links<L>(g.doms[d], nl, solid, rmask, nullptr, nullptr, nullptr);
+    }
     cnt[n] = c;
     ind[n] = c > 0 ? 1 : 0;
 }
 
 template <class L>
-__global__ __launch_bounds__(BLK) void k_solid_fill(Box box, long N, const uint8_t *solid,
+__global__ __launch_bounds__(BLK) void k_solid_fill(Geo g, long N, const uint8_t *solid,
                                                     const uint32_t *rmask, const int32_t *kof,
                                                     const int32_t *lbase, const int32_t *off,
                                                     const int32_t *idx, int32_t *sif, int32_t *soff,
-                                                    int32_t *slinks) {
+                                                    int32_t *sdom, int32_t *slinks) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
     if (!solid[n]) return;
-    const int c = solid_links<L>(box, n, solid, rmask, kof, lbase, slinks + off[n]);
+    long nl;
+    const int d = dom_of(g, n, &nl);
+    const int c = solid_links<L>(g.doms[d], nl, solid, rmask, kof, lbase, slinks + off[n]);
     if (c > 0) {
         sif[idx[n]] = (int32_t)n;
         soff[idx[n]] = off[n];
+        sdom[idx[n]] = d;
     }
 }
 
 // lattice-gradient normal of the solid indicator (used when no normals are given)
 template <class L>
-__global__ __launch_bounds__(BLK) void k_fd_normals(Box box, long N, const uint8_t *solid,
-                                                    double *nrm) {
+__global__ __launch_bounds__(BLK) void k_fd_normals(Geo g, long N, const uint8_t *solid, double *nrm) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
     double gx = 0, gy = 0, gz = 0;
     if (solid[n]) {
+        long nl;
+        const int d = dom_of(g, n, &nl);
+        const DomDev &D = g.doms[d];
         int X, Y, Z;
-        coords(box, n, &X, &Y, &Z);
+        coords(D.box, nl, &X, &Y, &Z);
         for (int i = 1; i < L::Q; i++) {
             int fc;
-            const long y = site(box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], false, &fc);
-            const double ind = (y < 0 || solid[y]) ? 1.0 : 0.0;
+            const long y = site(D.box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], false, &fc);
+            const double ind = (y < 0 || solid[D.node_off + y]) ? 1.0 : 0.0;
             gx += L::w[i] * L::ex[i] * ind * 3.0;
             gy += L::w[i] * L::ey[i] * ind * 3.0;
             gz += L::w[i] * L::ez[i] * ind * 3.0;
@@ -299,12 +343,14 @@ __global__ __launch_bounds__(BLK) void k_fd_normals(Box box, long N, const uint8
     nrm[3 * n + 2] = gz;
 }
 
-__global__ __launch_bounds__(BLK) void k_node_defaults(long N, const uint8_t *solid, const double *kr_in,
-                                                       double kr0, const double *phi_in, double *kr,
-                                                       double *phi) {
+__global__ __launch_bounds__(BLK) void k_node_defaults(Geo g, long N, const uint8_t *solid,
+                                                       const double *kr_in, const double *phi_in,
+                                                       double *kr, double *phi) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
-    kr[n] = kr_in ? kr_in[n] : kr0;
+    long nl;
+    const int d = dom_of(g, n, &nl);
+    kr[n] = kr_in ? kr_in[n] : g.doms[d].kr0;
     phi[n] = phi_in ? phi_in[n] : (solid[n] ? 1.0 : 0.0);
 }
 
@@ -321,19 +367,10 @@ __global__ void k_zero_i32(int32_t *p, long n) {
     if (i < n) p[i] = 0;
 }
 
-// compacted list of the fluid interface nodes and their link bits
+// fluid interface nodes (at least one reactive link): indicator for a scan
 __global__ __launch_bounds__(BLK) void k_iface_mark(long nf, const int32_t *lcnt, int32_t *ind) {
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
     if (k < nf) ind[k] = lcnt[k] > 0 ? 1 : 0;
-}
-
-__global__ __launch_bounds__(BLK) void k_iface_fill(long nf, const int32_t *lcnt, const int32_t *idx,
-                                                    const int32_t *nodeof, const uint32_t *rmask,
-                                                    int32_t *iface, uint32_t *imask) {
-    const long k = (long)blockIdx.x * BLK + threadIdx.x;
-    if (k >= nf || lcnt[k] == 0) return;
-    iface[idx[k]] = (int32_t)k;
-    imask[idx[k]] = rmask[nodeof[k]];
 }
 
 static hipError_t read_ints(Ctx &c, const int32_t *dev, int32_t *host, int n) {
@@ -346,42 +383,43 @@ template <class L, typename T>
 static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *normals,
                                 const double *k_r, const double *phi0, int64_t *n_links,
                                 int64_t *n_sif) {
-    const long N = c.N, R = c.R;
-    const int W = c.W;
-    const long RW = R * W;
+    const long N = c.N, R = c.R, RW = c.RW;
     const long nb = (N + BLK - 1) / BLK;
     auto blocks = [](long n) { return dim3((unsigned)((n + BLK - 1) / BLK)); };
     hipStream_t st = c.stream;
+    Geo g;
+    g.doms = c.doms;
+    g.node_off = c.dnode_off;
+    g.word_off = c.dword_off;
+    g.row_off = c.drow_off;
+    g.ndom = c.ndom;
     hipError_t e;
     hipLaunchKernelGGL(k_copy_solid, dim3(nb), dim3(BLK), 0, st, N, solid, c.solid);
-    hipLaunchKernelGGL(k_node_defaults, dim3(nb), dim3(BLK), 0, st, N, c.solid, k_r, c.p.k_r,
-                       phi0, c.kr, c.phi);
+    hipLaunchKernelGGL(k_node_defaults, dim3(nb), dim3(BLK), 0, st, g, N, c.solid, k_r, phi0, c.kr,
+                       c.phi);
     if (normals) {
         if (normals != c.nrm) {
             e = hipMemcpyAsync(c.nrm, normals, sizeof(double) * 3 * N, hipMemcpyDeviceToDevice, st);
             if (e != hipSuccess) return e;
         }
     } else {
-        hipLaunchKernelGGL((k_fd_normals<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.nrm);
+        hipLaunchKernelGGL((k_fd_normals<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.nrm);
     }
-    hipLaunchKernelGGL((k_flags<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.flags, c.rmask);
+    hipLaunchKernelGGL((k_flags<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.flags, c.rmask);
     // row words and compact maps
-    hipLaunchKernelGGL(k_row_words, blocks(RW), dim3(BLK), 0, st, R, W, c.box.nx, c.solid, c.rows,
-                       c.cnt);
+    hipLaunchKernelGGL(k_row_words, blocks(RW), dim3(BLK), 0, st, g, RW, c.solid, c.rows, c.cnt);
     if ((e = scan_excl(c, c.cnt, c.sidx, RW, c.iacc)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_row_prefix, blocks(RW), dim3(BLK), 0, st, RW, c.sidx, c.rows);
-    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(BLK), 0, st, N, c.box.nx, W, c.solid, c.rows,
-                       c.nodeof, c.kof);
+    hipLaunchKernelGGL(k_compact, dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rows, c.nodeof, c.kof);
     int32_t nf = 0;
     if ((e = read_ints(c, c.iacc, &nf, 1)) != hipSuccess) return e;
     c.n_fluid = nf;
     // wavefront tasks
-    hipLaunchKernelGGL(k_row_ntasks, blocks(R), dim3(BLK), 0, st, R, W, c.rows, c.cnt);
+    hipLaunchKernelGGL(k_row_ntasks, blocks(R), dim3(BLK), 0, st, g, R, c.rows, c.cnt);
     if ((e = scan_excl(c, c.cnt, c.sidx, R, c.iacc)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_tasks, blocks(R), dim3(BLK), 0, st, R, W, c.rows, c.sidx, c.tasks);
+    hipLaunchKernelGGL(k_row_tasks, blocks(R), dim3(BLK), 0, st, g, R, c.rows, c.sidx, c.tasks);
     int32_t nt = 0;
     if ((e = read_ints(c, c.iacc, &nt, 1)) != hipSuccess) return e;
-    if (nt > c.task_cap) return hipErrorUnknown;
     c.n_tasks = nt;
     // reactive links
     const long nfl = nf > 0 ? nf : 1;
@@ -389,27 +427,24 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     if ((e = scan_excl(c, c.cnt, c.lbase, nf, c.iacc)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_iface_mark, blocks(nfl), dim3(BLK), 0, st, (long)nf, c.cnt, c.sidx);
     if ((e = scan_excl(c, c.sidx, c.sidx, nf, c.iacc + 2)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_iface_fill, blocks(nfl), dim3(BLK), 0, st, (long)nf, c.cnt, c.sidx, c.nodeof,
-                       c.rmask, c.iface, c.imask);
     int32_t t4[4] = {0, 0, 0, 0};
     if ((e = read_ints(c, c.iacc, t4, 4)) != hipSuccess) return e;
     const int32_t tot = t4[0];
     c.n_fluid_iface = t4[2];
     *n_links = tot;
     if (tot > c.max_links) return hipSuccess;  // the caller reports the capacity error
-    hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, c.box, (long)nf, c.nodeof,
-                       c.rmask, c.lbase, c.nrm, c.kr, c.p.rbc_scheme, c.p.rbc_mechanics, c.gamma,
-                       c.cs2s, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir);
+    hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, g, (long)nf, c.nodeof,
+                       c.rmask, c.lbase, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir);
     // solid side: per solid interface node, its links in direction order
-    hipLaunchKernelGGL((k_solid_count<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.rmask,
+    hipLaunchKernelGGL((k_solid_count<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rmask,
                        c.cnt, c.sidx);
     if ((e = scan_excl(c, c.sidx, c.sidx, N, c.iacc)) != hipSuccess) return e;
     if ((e = scan_excl(c, c.cnt, c.cnt, N, c.iacc + 1)) != hipSuccess) return e;
     int32_t t2[2] = {0, 0};
     if ((e = read_ints(c, c.iacc, t2, 2)) != hipSuccess) return e;
     *n_sif = t2[0];
-    hipLaunchKernelGGL((k_solid_fill<L>), dim3(nb), dim3(BLK), 0, st, c.box, N, c.solid, c.rmask,
-                       c.kof, c.lbase, c.cnt, c.sidx, c.sif, c.soff, c.slinks);
+    hipLaunchKernelGGL((k_solid_fill<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rmask,
+                       c.kof, c.lbase, c.cnt, c.sidx, c.sif, c.soff, c.sdom, c.slinks);
     hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, c.soff, (long)t2[0], t2[1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t2[1] != tot) return hipErrorUnknown;  // every link has exactly one solid end

@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <string>
+#include <vector>
 
 #include "../../include/lbmrbc.h"
 #include "lbm_device.hpp"
@@ -20,6 +21,7 @@ struct StepArgs {
     T *__restrict__ gout;
     const Task *__restrict__ tasks;
     const RowWord *__restrict__ rows;
+    const DomDev *__restrict__ doms;
     const int32_t *__restrict__ nodeof;  // compact index -> dense node
     const int32_t *__restrict__ lbase;   // compact index -> first reactive link
     const T *__restrict__ lbeta;         // per link: (1 - k)/(1 + k)
@@ -27,36 +29,38 @@ struct StepArgs {
     double *__restrict__ phi;            // dense
     long ntasks;
     long S;                              // stride between directions
-    int W;                               // 64-node words per row
+};
+
+// host view of one domain
+struct DomHost {
+    lbm_params p;
     Box box;
-    int mech;
-    // constants of the step, FP64 (the kernels compute in FP64)
-    double omega_f, omega_g, force_fac;
-    double F[3];
-    double ws[19];                       // solute weights (rest fraction)
-    double inv_cs2s;
-    double rho0, c_ref;
-    double ceq_dev;                      // C_eq - C_ref
-    double c_in;
-    double vma;                          // V_m a_m
+    long N, R, node_off, word_off, row_off;
+    int W;
+    double gamma, cs2s, ws[19], wsc;
+    int64_t links_cap;
 };
 
 struct Ctx {
-    lbm_params p;
+    lbm_params p;            // parameters of domain 0 (precision, lattice)
     hipStream_t stream;
     int Q, dim;
-    long N;                  // nodes
+    int ndom;
+    std::vector<DomHost> dom;
+    long N;                  // nodes of all domains
     long S;                  // stride between directions of the compact arrays
-    long R;                  // rows (ny * nz)
-    int W;                   // words per row
+    long R;                  // rows of all domains
+    long RW;                 // row words of all domains
     long task_cap;
-    Box box;
     bool fp64;
-    double gamma, cs2s, ws[19];
     int64_t max_links;
     // device arrays carved from the caller workspace
     void *f[2], *g[2];       // populations, [Q][S] each (T = double or float), compact
-    RowWord *rows;           // [R*W]
+    DomDev *doms;            // [ndom]
+    long *dnode_off;         // [ndom + 1] dense node offsets
+    long *dword_off;         // [ndom + 1] row-word offsets
+    long *drow_off;          // [ndom + 1] row offsets
+    RowWord *rows;           // [RW]
     Task *tasks;             // [task_cap]
     int32_t *nodeof;         // [N] compact -> dense
     int32_t *kof;            // [N] dense -> compact (-1 for solid)
@@ -67,11 +71,10 @@ struct Ctx {
     double *phi, *kr, *nrm;  // [N], [N], [N][3]
     uint8_t *solid;          // [N]
     void *lbeta, *lq;        // [max_links] of T
-    int32_t *iface;          // [N] fluid interface nodes (compact indices)
-    uint32_t *imask;         // [N] their reactive-link bits
     int32_t *lnode, *lsolid; // [max_links]
     uint8_t *ldir;           // [max_links]
     int32_t *sif, *soff, *slinks; // solid interface list [max_links], offsets [max_links+1], [max_links]
+    int32_t *sdom;           // [max_links] domain of each solid interface node
     int32_t *bsum;           // scan scratch
     double *dpart;           // per-workgroup partial sums of the reductions
     double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums
@@ -86,7 +89,7 @@ struct Ctx {
     std::string err;
 };
 
-size_t workspace_layout(const lbm_params &p, Ctx *c, char *base);
+size_t workspace_layout(const lbm_params *p, int n, Ctx *c, char *base);
 
 // launchers (return hipError_t of the first failing launch)
 // ev: optional 4 events recorded around the two kernels of the step

@@ -1,17 +1,20 @@
 // lbm_io.hip -- initial state, read-outs and FP64 reductions (not per step).
+// Every kernel covers all domains of a batch; a thread finds its domain from
+// the node offsets.
 #include "lbm_internal.hpp"
 
 namespace lbm {
 
 template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_init(long N, long S, const int32_t *kof, const double *rho,
-                                              const double *u, const double *cc, double rho0,
-                                              double c_ref, const double *ws, double cs2s, T *f0,
-                                              T *g0, T *f1, T *g1) {
+__global__ __launch_bounds__(BLK) void k_init(long N, long S, const DomDev *doms, const long *noff,
+                                              int ndom, const int32_t *kof, const double *rho,
+                                              const double *u, const double *cc, T *f0, T *g0,
+                                              T *f1, T *g1) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
     const int k = kof[n];
     if (k < 0) return;
+    const DomDev &D = doms[find_dom(noff, ndom, n)];
     const double r = rho ? rho[n] : 1.0;
     const double ux = u ? u[3 * n] : 0.0, uy = u ? u[3 * n + 1] : 0.0, uz = u ? u[3 * n + 2] : 0.0;
     const double C = cc ? cc[n] : 0.0;
@@ -19,23 +22,23 @@ __global__ __launch_bounds__(BLK) void k_init(long N, long S, const int32_t *kof
     for (int i = 0; i < L::Q; i++) {
         const double eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
         const double feq = L::w[i] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        const double geq = ws[i] * C * (1.0 + eu / cs2s);
-        f0[i * S + k] = T(feq - L::w[i] * rho0);
-        g0[i * S + k] = T(geq - ws[i] * c_ref);
+        const double geq = D.ws[i] * C * (1.0 + eu / D.cs2s);
+        f0[i * S + k] = T(feq - L::w[i] * D.rho0);
+        g0[i * S + k] = T(geq - D.ws[i] * D.c_ref);
         f1[i * S + k] = T(0);
         g1[i * S + k] = T(0);
     }
 }
 
 template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_fields(long N, long S, const int32_t *kof, const T *f,
-                                                const T *g, double rho0, double c_ref,
-                                                const double *F, const double *phi_in,
-                                                double *rho, double *u, double *cc, double *phi,
-                                                uint8_t *type) {
+__global__ __launch_bounds__(BLK) void k_fields(long N, long S, const DomDev *doms, const long *noff,
+                                                int ndom, const int32_t *kof, const T *f, const T *g,
+                                                const double *phi_in, double *rho, double *u,
+                                                double *cc, double *phi, uint8_t *type) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
     const int k = kof[n];
+    const DomDev &D = doms[find_dom(noff, ndom, n)];
     double r = 0, jx = 0, jy = 0, jz = 0, C = 0;
     const bool sol = k < 0;
     if (!sol) {
@@ -48,14 +51,14 @@ __global__ __launch_bounds__(BLK) void k_fields(long N, long S, const int32_t *k
             jz += L::ez[i] * fi;
             dc += (double)g[i * S + k];
         }
-        r = rho0 + dr;
-        C = c_ref + dc;
+        r = D.rho0 + dr;
+        C = D.c_ref + dc;
     }
     if (rho) rho[n] = r;
     if (u) {
-        u[3 * n] = sol ? 0.0 : (jx - 0.5 * F[0]) / r;
-        u[3 * n + 1] = sol ? 0.0 : (jy - 0.5 * F[1]) / r;
-        u[3 * n + 2] = sol ? 0.0 : (jz - 0.5 * F[2]) / r;
+        u[3 * n] = sol ? 0.0 : (jx - 0.5 * D.F[0]) / r;
+        u[3 * n + 1] = sol ? 0.0 : (jy - 0.5 * D.F[1]) / r;
+        u[3 * n + 2] = sol ? 0.0 : (jz - 0.5 * D.F[2]) / r;
     }
     if (cc) cc[n] = C;
     if (phi) phi[n] = phi_in[n];
@@ -63,15 +66,16 @@ __global__ __launch_bounds__(BLK) void k_fields(long N, long S, const int32_t *k
 }
 
 template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_pops(long N, long S, const int32_t *kof, const T *f,
-                                              const T *g, double rho0, double c_ref,
-                                              const double *ws, double *fo, double *go) {
+__global__ __launch_bounds__(BLK) void k_pops(long N, long S, const DomDev *doms, const long *noff,
+                                              int ndom, const int32_t *kof, const T *f, const T *g,
+                                              double *fo, double *go) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
     const int k = kof[n];
+    const DomDev &D = doms[find_dom(noff, ndom, n)];
     for (int i = 0; i < L::Q; i++) {
-        if (fo) fo[i * N + n] = k < 0 ? 0.0 : (double)f[i * S + k] + L::w[i] * rho0;
-        if (go) go[i * N + n] = k < 0 ? 0.0 : (double)g[i * S + k] + ws[i] * c_ref;
+        if (fo) fo[i * N + n] = k < 0 ? 0.0 : (double)f[i * S + k] + L::w[i] * D.rho0;
+        if (go) go[i * N + n] = k < 0 ? 0.0 : (double)g[i * S + k] + D.ws[i] * D.c_ref;
     }
 }
 
@@ -92,9 +96,9 @@ __global__ __launch_bounds__(BLK) void k_scatter_q(long nl, int Q, const T *lq, 
 // per-workgroup partial sums of C (fluid) and phi (all nodes), and a
 // non-finite flag; a single workgroup then adds the partials in order
 template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_diag(long N, long S, const int32_t *kof, const T *f,
-                                              const T *g, const double *phi, double c_ref,
-                                              double *part, int32_t *nan_flag) {
+__global__ __launch_bounds__(BLK) void k_diag(long N, long S, const DomDev *doms, const long *noff,
+                                              int ndom, const int32_t *kof, const T *f, const T *g,
+                                              const double *phi, double *part, int32_t *nan_flag) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     double cs = 0.0, ps = 0.0;
     int bad = 0;
@@ -102,13 +106,14 @@ __global__ __launch_bounds__(BLK) void k_diag(long N, long S, const int32_t *kof
         ps = phi[n];
         const int k = kof[n];
         if (k >= 0) {
+            const DomDev &D = doms[find_dom(noff, ndom, n)];
             double dc = 0.0;
             for (int i = 0; i < L::Q; i++) {
                 const double fi = (double)f[i * S + k], gi = (double)g[i * S + k];
                 if (!isfinite(fi) || !isfinite(gi)) bad = 1;
                 dc += gi;
             }
-            cs = c_ref + dc;
+            cs = D.c_ref + dc;
         }
     }
     const double bc = block_sum(cs);
@@ -137,13 +142,10 @@ __global__ __launch_bounds__(BLK) void k_sum_parts(const double *part, long nb, 
 template <class L, typename T>
 static hipError_t init_impl(Ctx &c, const double *rho, const double *u, const double *cc) {
     const long nb = (c.N + BLK - 1) / BLK;
-    double *wsd = c.dacc + 8;  // solute weights staged in the accumulator block
-    hipError_t e = hipMemcpyAsync(wsd, c.ws, sizeof(double) * 19, hipMemcpyHostToDevice, c.stream);
-    if (e != hipSuccess) return e;
     c.cur = 0;
-    hipLaunchKernelGGL((k_init<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof, rho, u,
-                       cc, c.fp64 ? 0.0 : c.p.rho0, c.fp64 ? 0.0 : c.p.c_ref, wsd, c.cs2s,
-                       (T *)c.f[0], (T *)c.g[0], (T *)c.f[1], (T *)c.g[1]);
+    hipLaunchKernelGGL((k_init<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.doms,
+                       c.dnode_off, c.ndom, c.kof, rho, u, cc, (T *)c.f[0], (T *)c.g[0],
+                       (T *)c.f[1], (T *)c.g[1]);
     hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(BLK), 0, c.stream, c.dacc, 8);
     return hipGetLastError();
 }
@@ -156,12 +158,9 @@ hipError_t launch_init(Ctx &c, const double *rho, const double *u, const double 
 template <class L, typename T>
 static hipError_t fields_impl(Ctx &c, double *rho, double *u, double *cc, double *phi, uint8_t *type) {
     const long nb = (c.N + BLK - 1) / BLK;
-    double *Fd = c.dacc + 28;
-    hipError_t e = hipMemcpyAsync(Fd, c.p.force, sizeof(double) * 3, hipMemcpyHostToDevice, c.stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_fields<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof,
-                       (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.fp64 ? 0.0 : c.p.rho0,
-                       c.fp64 ? 0.0 : c.p.c_ref, Fd, c.phi, rho, u, cc, phi, type);
+    hipLaunchKernelGGL((k_fields<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.doms,
+                       c.dnode_off, c.ndom, c.kof, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
+                       c.phi, rho, u, cc, phi, type);
     return hipGetLastError();
 }
 
@@ -173,12 +172,8 @@ hipError_t launch_fields(Ctx &c, double *rho, double *u, double *cc, double *phi
 template <class L, typename T>
 static hipError_t pops_impl(Ctx &c, double *f, double *g) {
     const long nb = (c.N + BLK - 1) / BLK;
-    double *wsd = c.dacc + 8;
-    hipError_t e = hipMemcpyAsync(wsd, c.ws, sizeof(double) * 19, hipMemcpyHostToDevice, c.stream);
-    if (e != hipSuccess) return e;
-    hipLaunchKernelGGL((k_pops<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof,
-                       (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.fp64 ? 0.0 : c.p.rho0,
-                       c.fp64 ? 0.0 : c.p.c_ref, wsd, f, g);
+    hipLaunchKernelGGL((k_pops<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.doms,
+                       c.dnode_off, c.ndom, c.kof, (const T *)c.f[c.cur], (const T *)c.g[c.cur], f, g);
     return hipGetLastError();
 }
 
@@ -205,9 +200,9 @@ template <class L, typename T>
 static hipError_t diag_impl(Ctx &c, double *sums, int32_t *nan_flag) {
     const long nb = (c.N + BLK - 1) / BLK;
     hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, c.stream, c.iacc + 4);
-    hipLaunchKernelGGL((k_diag<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.kof,
-                       (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.phi,
-                       c.fp64 ? 0.0 : c.p.c_ref, c.dpart, c.iacc + 4);
+    hipLaunchKernelGGL((k_diag<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.doms,
+                       c.dnode_off, c.ndom, c.kof, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
+                       c.phi, c.dpart, c.iacc + 4);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(BLK), 0, c.stream, c.dpart, nb, c.dacc + 1);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;

@@ -57,9 +57,13 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
     if (t >= a.ntasks) return;
     const int lane = threadIdx.x & 63;
     const Task tk = a.tasks[t];
-    const Box &b = a.box;
+    // by value, read before the first store: loads of a uniform address that no
+    // store can precede stay on the scalar unit
+    const DomDev D = a.doms[tk.dom];
+    const Box b = D.box;
     const long S = a.S;
-    const int W = a.W;
+    const int W = D.W;
+    const RowWord *__restrict__ rows = a.rows + D.word_off;
     const int y = tk.row % b.ny, z = tk.row / b.ny;
     const int ax = b.inlet_axis;
 
@@ -73,7 +77,7 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
         int yy = y + (sl % 3) - 1, zz = z + (sl / 3) - 1, xx = 0, fc;
         if (L::DIM == 2) zz = z;
         if (wrap_site(b, xx, yy, zz, &fc)) {
-            const RowWord rw = a.rows[(long)(yy + b.ny * zz) * W + w];
+            const RowWord rw = rows[(long)(yy + b.ny * zz) * W + w];
             wm = rw.mask;
             wpb = rw.pb;
         }
@@ -84,7 +88,7 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
     const int k = tk.k0 + (active ? lane : 0);
     const int n = a.nodeof[k];
     const int lb = a.lbase[k];  // first reactive link (used by interface nodes)
-    const int x = n - tk.row * b.nx;
+    const int x = (int)(n - D.node_off) - tk.row * b.nx;
 
     // ---- neighbour classification (shared by both lattices) ----
     int kk[Q];
@@ -119,7 +123,7 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
             if (out) {
                 kk[i] = -2;
             } else if (!slots_fit || shifted) {
-                kk[i] = nb_compact(a.rows, W, b, xx, yy, zz);
+                kk[i] = nb_compact(rows, W, b, xx, yy, zz);
             } else {
                 const unsigned long long m = ((unsigned long long)hi << 32) | lo;
                 const unsigned long long bit = 1ull << (xs & 63);
@@ -170,7 +174,7 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
             if (cross_hi & (1u << i)) {
                 // zero-gradient outlet: the same direction one site back
                 // along the inlet axis, inside the outlet plane
-                e = nb_compact(a.rows, a.W, b, x - L::ex[i] - (ax == 0),
+                e = nb_compact(rows, W, b, x - L::ex[i] - (ax == 0),
                                y - L::ey[i] - (ax == 1), z - L::ez[i] - (ax == 2));
             } else {
                 e = k;  // inlet: value set below
@@ -192,23 +196,23 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
         if (L::ey[i]) jy += L::ey[i] > 0 ? fp[i] : -fp[i];
         if (L::ez[i]) jz += L::ez[i] > 0 ? fp[i] : -fp[i];
     }
-    const R rho = a.rho0 + drho;
+    const R rho = D.rho0 + drho;
     const R irho = R(1) / rho;
     // rho u = j + F/2 enters the first-order equilibrium term directly, so the
     // equilibrium carries exactly the momentum of the node
-    const R mx = jx + R(0.5) * a.F[0], my = jy + R(0.5) * a.F[1], mz = jz + R(0.5) * a.F[2];
+    const R mx = jx + R(0.5) * D.F[0], my = jy + R(0.5) * D.F[1], mz = jz + R(0.5) * D.F[2];
     const R ux = mx * irho, uy = my * irho, uz = mz * irho;
     const R uu = ux * ux + uy * uy + uz * uz;
-    const R uF = ux * a.F[0] + uy * a.F[1] + uz * a.F[2];
+    const R uF = ux * D.F[0] + uy * D.F[1] + uz * D.F[2];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
         const R em = R(L::ex[i]) * mx + R(L::ey[i]) * my + R(L::ez[i]) * mz;
-        const R eF = R(L::ex[i]) * a.F[0] + R(L::ey[i]) * a.F[1] + R(L::ez[i]) * a.F[2];
+        const R eF = R(L::ex[i]) * D.F[0] + R(L::ey[i]) * D.F[1] + R(L::ez[i]) * D.F[2];
         const R wi = R(L::w[i]);
         const R feq = wi * (drho + R(3) * em + rho * (R(4.5) * eu * eu - R(1.5) * uu));
         const R src = wi * (R(3) * (eF - uF) + R(9) * eu * eF);
-        a.fout[(long)i * S + k] = (T)(fp[i] + a.omega_f * (feq - fp[i]) + a.force_fac * src);
+        a.fout[(long)i * S + k] = (T)(fp[i] + D.omega_f * (feq - fp[i]) + D.force_fac * src);
     }
 
     // ---- solute: plane faces, reactive links, collision ----
@@ -217,7 +221,7 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
         for (int i = 0; i < Q; i++) {
             if ((cross & ~cross_hi) & (1u << i)) {
                 const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
-                gv[i] = (T)(a.ws[i] * (a.c_in - a.c_ref) + a.ws[i] * a.c_in * eu * a.inv_cs2s);
+                gv[i] = (T)(sol_w<L>(D, i) * (D.c_in - D.c_ref) + sol_w<L>(D, i) * D.c_in * eu * D.inv_cs2s);
             }
         }
     }
@@ -236,7 +240,7 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
             if (rbc & (1u << i)) {
                 const int o = L::opp[i];
                 const R own = (R)gv[i];  // a link direction loaded the node's own value along o
-                const R srcv = (a.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
+                const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
                 T bt;
                 if constexpr (NW == 1) {
                     bt = __builtin_bit_cast(T, sbeta[wv][i][0][lane]);
@@ -245,25 +249,25 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
                     bt = __builtin_bit_cast(T, lo | (hi << 32));
                 }
                 const R beta = (R)bt;
-                const R g = (R(1) - beta) * (a.ws[i] * a.ceq_dev) + beta * srcv;
+                const R g = (R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv;
                 const T qv = (T)(g - own);
                 a.lq[lb + __popc(rbc & ((1u << i) - 1u))] = qv;
                 if (qv < T(0)) sneg -= (double)qv;
                 gv[i] = (T)g;
             }
         }
-        if (sneg != 0.0) a.phi[n] += a.vma * sneg;
+        if (sneg != 0.0) a.phi[n] += D.vma * sneg;
     }
     R dC = R(0);
 #pragma unroll
     for (int i = 0; i < Q; i++) dC += (R)gv[i];
-    const R C = a.c_ref + dC;
+    const R C = D.c_ref + dC;
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
         const R gi = (R)gv[i];
-        const R geq = a.ws[i] * (dC + C * eu * a.inv_cs2s);
-        a.gout[(long)i * S + k] = (T)(gi + a.omega_g * (geq - gi));
+        const R geq = sol_w<L>(D, i) * (dC + C * eu * D.inv_cs2s);
+        a.gout[(long)i * S + k] = (T)(gi + D.omega_g * (geq - gi));
     }
 }
 
@@ -275,8 +279,10 @@ template <class L, typename T>
 __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ sif,
                                                    const int32_t *__restrict__ soff,
                                                    const int32_t *__restrict__ slinks,
+                                                   const int32_t *__restrict__ sdom,
+                                                   const DomDev *__restrict__ doms,
                                                    const T *__restrict__ lq, double *__restrict__ phi,
-                                                   long nsif, double vma, double *acc) {
+                                                   long nsif, double *acc) {
     constexpr int M = L::Q - 1;
     const long j = (long)blockIdx.x * BLK + threadIdx.x;
     double tot = 0.0;
@@ -296,7 +302,7 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
             tot += v;
             if (v > 0.0) pos += v;
         }
-        phi[s] -= vma * pos;
+        phi[s] -= doms[sdom[j]].vma * pos;
     }
     tot = block_sum(tot);
     if (threadIdx.x == 0 && tot != 0.0) atomicAdd(acc, tot);
@@ -311,6 +317,7 @@ static StepArgs<T> step_args(Ctx &c) {
     a.gout = (T *)c.g[1 - c.cur];
     a.tasks = c.tasks;
     a.rows = c.rows;
+    a.doms = c.doms;
     a.nodeof = c.nodeof;
     a.lbase = c.lbase;
     a.lbeta = (const T *)c.lbeta;
@@ -318,20 +325,6 @@ static StepArgs<T> step_args(Ctx &c) {
     a.phi = c.phi;
     a.ntasks = c.n_tasks;
     a.S = c.S;
-    a.W = c.W;
-    a.box = c.box;
-    a.mech = c.p.rbc_mechanics;
-    a.omega_f = 1.0 / c.p.tau_ns;
-    a.omega_g = 1.0 / c.p.tau_ad;
-    a.force_fac = 1.0 - 0.5 / c.p.tau_ns;
-    for (int d = 0; d < 3; d++) a.F[d] = c.p.force[d];
-    for (int i = 0; i < 19; i++) a.ws[i] = i < c.Q ? c.ws[i] : 0.0;
-    a.inv_cs2s = 1.0 / c.cs2s;
-    a.rho0 = c.fp64 ? 0.0 : c.p.rho0;
-    a.c_ref = c.fp64 ? 0.0 : c.p.c_ref;
-    a.ceq_dev = c.p.c_eq - (c.fp64 ? 0.0 : c.p.c_ref);
-    a.c_in = c.p.inlet_axis >= 0 ? c.p.c_in : 0.0;
-    a.vma = c.p.v_m * c.p.a_m;
     return a;
 }
 
@@ -351,8 +344,7 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev) {
     if (c.n_sif > 0) {
         const long nb2 = (c.n_sif + BLK - 1) / BLK;
         hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, c.stream, c.sif, c.soff,
-                           c.slinks, (const T *)c.lq, c.phi, (long)c.n_sif, c.p.v_m * c.p.a_m,
-                           c.dacc);
+                           c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phi, (long)c.n_sif, c.dacc);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[3], c.stream);

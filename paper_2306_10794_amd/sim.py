@@ -113,3 +113,90 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+class BatchSimulation:
+    """Many independent domains stepped by the same launches (one context).
+
+    Per-node arrays are the domains' arrays concatenated in domain order;
+    ``offsets`` gives the first node of every domain.
+    """
+
+    def __init__(self, cases, precision: int = L.LBM_FP32_DEV, device="cuda", stream=None,
+                 max_links: int = 0, init: bool = True):
+        if not torch.cuda.is_available():
+            raise RuntimeError("the reactive LBM library needs a GPU (none is visible)")
+        self.cases = list(cases)
+        self.device = torch.device(device)
+        self.stream = stream if stream is not None else torch.cuda.current_stream(self.device)
+        self.params = [params_from_case(c, precision, max_links) for c in self.cases]
+        self.nbytes = L.lbm_batch_workspace_bytes(self.params)
+        self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
+        self.ctx = L.lbm_create_batch(self.params, self.workspace, self.nbytes, self.stream)
+        self.offsets = L.lbm_batch_offsets(self.ctx, len(self.cases))
+        self.N, self.Q = self.offsets[-1], self.cases[0].q
+
+        def cat(get, dtype, width=None):
+            parts = [get(c) for c in self.cases]
+            if all(p is None for p in parts):
+                return None
+            full = []
+            for c, p in zip(self.cases, parts):
+                if p is None:
+                    raise ValueError("an optional per-node array must be given for all domains "
+                                     "of a batch or for none")
+                full.append(np.asarray(p).reshape(c.n, -1) if width else np.asarray(p).reshape(-1))
+            return _dev(np.concatenate(full), dtype, self.device)
+
+        self._geom = dict(solid=cat(lambda c: c.solid_flat(), torch.uint8),
+                          normals=cat(lambda c: c.normals_flat(), torch.float64, 3),
+                          k_r=cat(lambda c: c.k_r_field, torch.float64),
+                          phi0=cat(lambda c: c.phi0, torch.float64))
+        L.lbm_set_geometry(self.ctx, **self._geom)
+        if init:
+            self._init = [cat(lambda c: c.rho_flat(), torch.float64),
+                          cat(lambda c: c.u_flat(), torch.float64, 3),
+                          cat(lambda c: c.c_flat(), torch.float64)]
+            L.lbm_init_fields(self.ctx, *self._init)
+
+    def step(self, n: int = 1):
+        L.lbm_step(self.ctx, n)
+
+    def split(self, t: torch.Tensor, axis: int = 0):
+        """Per-domain views of a concatenated per-node tensor."""
+        o = self.offsets
+        return [t.narrow(axis, o[d], o[d + 1] - o[d]) for d in range(len(self.cases))]
+
+    def fields(self) -> dict:
+        kw = dict(rho=torch.empty(self.N, dtype=torch.float64, device=self.device),
+                  u=torch.empty((self.N, 3), dtype=torch.float64, device=self.device),
+                  c=torch.empty(self.N, dtype=torch.float64, device=self.device),
+                  phi=torch.empty(self.N, dtype=torch.float64, device=self.device),
+                  type=torch.empty(self.N, dtype=torch.uint8, device=self.device))
+        L.lbm_get_fields(self.ctx, **kw)
+        return kw
+
+    def pops(self):
+        f = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
+        g = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
+        L.lbm_get_pops(self.ctx, f, g)
+        return f, g
+
+    def exchange(self):
+        q = torch.empty((self.N, self.Q), dtype=torch.float64, device=self.device)
+        L.lbm_get_exchange(self.ctx, q)
+        return q
+
+    def diag(self) -> dict:
+        return L.lbm_get_diag(self.ctx)
+
+    def close(self):
+        if getattr(self, "ctx", None):
+            L.lbm_destroy(self.ctx)
+            self.ctx = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

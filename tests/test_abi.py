@@ -92,3 +92,19 @@ def test_create_without_workspace_is_enomem():
         L.lbm_create(_good_params(), None, 0, stream=0)
     assert ei.value.status == L.LBM_ENOMEM
     assert "needed" in L.lbm_last_error(None)
+
+
+def test_batch_workspace_and_checks():
+    """A batch of one is the single-lattice layout; mixed lattices and
+    precisions are rejected with the offending domain named."""
+    L = _L()
+    a, b = _good_params(), _good_params(nx=40, ny=24)
+    assert L.lbm_batch_workspace_bytes([a]) == L.lbm_workspace_bytes(a)
+    assert L.lbm_batch_workspace_bytes([a, b]) > L.lbm_workspace_bytes(a)
+    with pytest.raises(L.LbmError) as ei:
+        L.lbm_batch_workspace_bytes([a, _good_params(precision=L.LBM_FP32_DEV)])
+    assert ei.value.status == L.LBM_EINVAL
+    assert "same dim" in L.lbm_last_error(None)
+    with pytest.raises(L.LbmError):
+        L.lbm_batch_workspace_bytes([a, _good_params(tau_ns=0.5)])
+    assert "domain 1" in L.lbm_last_error(None)
