@@ -71,6 +71,68 @@ def make_case(workload):
     raise SystemExit(f"unknown workload {workload}")
 
 
+def batch_vs_plain(batch_steps, plain_steps, tune_steps):
+    """The 1024-domain 2D sweep (D2Q9 flow + solute, FP32 deviation storage):
+    one batched context stepped by graph replay under the autotuned launch
+    configuration, against one context per domain with its own launches, on
+    one stream and on eight streams."""
+    import torch
+    from lbm_inputs import configs
+    from paper_2306_10794_amd import (BatchSimulation, Simulation, LBM_FP32_DEV, lbm_step,
+                                      lbm_autotune)
+    t0 = time.perf_counter()
+    cases = configs.batch_domains(count=1024, seed=4)
+    nf = sum(c.n_fluid for c in cases)
+    log(f"[batch] 1024 domains built in {time.perf_counter() - t0:.1f} s; "
+        f"nodes {sum(c.n for c in cases)}, fluid {nf}")
+    bs = BatchSimulation(cases, precision=LBM_FP32_DEV, device="cuda:0")
+    cfg, tune_ms, tune_n = lbm_autotune(bs.ctx, tune_steps)
+    log(f"[batch] autotuned {cfg} at {tune_ms:.4f} ms/step ({tune_n} trial steps)")
+    lbm_step(bs.ctx, 2 * max(cfg["graph_steps"], 8))
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm_step(bs.ctx, batch_steps)
+    torch.cuda.synchronize()
+    tb = time.perf_counter() - t0
+    d = bs.diag()
+    bs.close()
+    del bs
+    torch.cuda.empty_cache()
+    log(f"[batch] batched: {batch_steps} steps in {tb:.3f} s; status {d['status']}")
+
+    def plain(nstreams):
+        streams = [torch.cuda.Stream(device="cuda:0") for _ in range(nstreams)]
+        sims = [Simulation(c, precision=LBM_FP32_DEV, device="cuda:0",
+                           stream=streams[i % nstreams]) for i, c in enumerate(cases)]
+        for s in sims:
+            lbm_step(s.ctx, 2)
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        for s in sims:
+            lbm_step(s.ctx, plain_steps)
+        torch.cuda.synchronize()
+        dt = time.perf_counter() - t
+        for s in sims:
+            s.close()
+        del sims
+        torch.cuda.empty_cache()
+        log(f"[batch] plain, {nstreams} stream(s): {plain_steps} steps in {dt:.3f} s")
+        return nf * plain_steps / dt / 1e6
+
+    mb = nf * batch_steps / tb / 1e6
+    p1 = plain(1)
+    p8 = plain(8)
+    return {
+        "workload": "1024 uneven 2D domains, sizes U{32..256}x U{32..128}, disk obstacles, "
+                    "porosity U[0.5,0.8], log-uniform Pe in [0.1,100] and Da in [0.01,100]; "
+                    "D2Q9 fluid + D2Q9 solute, FP32 deviation storage",
+        "fluid_nodes": int(nf), "unit": "MLUPS",
+        "batched": round(mb, 1), "batched_steps": batch_steps, "launch_config": cfg,
+        "plain_1_stream": round(p1, 1), "plain_8_streams": round(p8, 1), "plain_steps": plain_steps,
+        "speedup_vs_1_stream": round(mb / p1, 2), "speedup_vs_8_streams": round(mb / p8, 2),
+    }
+
+
 def cpu_baseline(case, steps):
     import oracle
     o = oracle.Oracle(case)
@@ -92,6 +154,10 @@ def main():
     ap.add_argument("--workload", default="spheres256")
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
+    ap.add_argument("--batch-steps", type=int, default=1000)
+    ap.add_argument("--plain-steps", type=int, default=20)
+    ap.add_argument("--tune-steps", type=int, default=32)
     args = ap.parse_args()
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
@@ -159,10 +225,14 @@ def main():
             "phi_kernel_us": round(phi_ms / args.steps * 1e3, 2),
         },
         "cpu_baseline": None,
+        "batch": None,
     }
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if not args.no_batch:
+        line["batch"] = batch_vs_plain(args.batch_steps, args.plain_steps, args.tune_steps)
+        log(f"[bench] batch {line['batch']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -169,6 +169,40 @@ lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
  * (host array of 2).  Results are identical to lbm_step. */
 lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms);
 
+/* Launch configuration of the step (a performance choice only: every
+ * configuration gives bit-identical populations and solid fractions).
+ *   wg_waves    tasks (wavefronts of 64 nodes of one row) per workgroup:
+ *               1, 2, 4 or 8 (default 4)
+ *   xcd_remap   1: consecutive tiles of tasks run on one XCD, so that the rows
+ *               they share stay in one L2 (default 1); 0: plain order
+ *   graph_steps 0: lbm_step issues two kernel launches per step (default);
+ *               > 0: lbm_step replays a HIP graph holding graph_steps steps
+ *               (rounded up to even), built on first use and rebuilt after a
+ *               geometry or configuration change; remaining steps run as
+ *               plain launches.  Graph objects are the only allocation the
+ *               library makes; lbm_destroy frees them. */
+typedef struct lbm_launch_config {
+    int32_t wg_waves;
+    int32_t xcd_remap;
+    int32_t graph_steps;
+    int32_t reserved0;
+} lbm_launch_config;
+
+/* EINVAL for values outside the ranges above. */
+lbm_status lbm_set_launch_config(lbm_ctx *ctx, const lbm_launch_config *cfg);
+lbm_status lbm_get_launch_config(const lbm_ctx *ctx, lbm_launch_config *cfg);
+
+/* Autotuner: times every (wg_waves, xcd_remap) pair over trial_steps plain
+ * steps, then graph replay of the best pair at graph_steps in {16, 64, 256}
+ * (each <= 4 * trial_steps) against plain launches, with HIP events on the
+ * context stream, and keeps the fastest configuration.  The trial steps are
+ * real steps of the simulation (the step counter advances by the number
+ * written to *steps_run); results do not depend on the configuration.
+ * best (host, may be NULL) receives the chosen configuration and ms_per_step
+ * (host, may be NULL) its time per step.  Synchronises. */
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *best,
+                        double *ms_per_step, int64_t *steps_run);
+
 /* Macroscopic fields of the current state (asynchronous; NULL skips a field):
  * rho = sum f, u = (sum e f - F/2)/rho, C = sum g (the values that entered
  * the last collision), phi, type (1 = solid).  rho/c/phi [N], u [N][3] FP64,

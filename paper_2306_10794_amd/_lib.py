@@ -49,6 +49,11 @@ class lbm_diag(C.Structure):
                 ("wall_exchange", C.c_double), ("nan_flag", C.c_int32), ("reserved0", C.c_int32)]
 
 
+class lbm_launch_config(C.Structure):
+    _fields_ = [("wg_waves", C.c_int32), ("xcd_remap", C.c_int32), ("graph_steps", C.c_int32),
+                ("reserved0", C.c_int32)]
+
+
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "or python paper_2306_10794_amd/build.py")
@@ -65,6 +70,10 @@ _SIGS = {
     "lbm_init_fields": [_P, _P, _P, _P],
     "lbm_step": [_P, C.c_int32],
     "lbm_step_timed": [_P, C.c_int32, C.POINTER(C.c_double)],
+    "lbm_set_launch_config": [_P, C.POINTER(lbm_launch_config)],
+    "lbm_get_launch_config": [_P, C.POINTER(lbm_launch_config)],
+    "lbm_autotune": [_P, C.c_int32, C.POINTER(lbm_launch_config), C.POINTER(C.c_double),
+                     C.POINTER(C.c_int64)],
     "lbm_get_fields": [_P, _P, _P, _P, _P, _P],
     "lbm_get_pops": [_P, _P, _P],
     "lbm_get_exchange": [_P, _P],
@@ -168,6 +177,28 @@ def lbm_step_timed(ctx, nsteps: int):
     ms = (C.c_double * 2)()
     _check(lib.lbm_step_timed(ctx, int(nsteps), ms), "lbm_step_timed", ctx)
     return ms[0], ms[1]
+
+
+def lbm_set_launch_config(ctx, wg_waves: int = 4, xcd_remap: int = 1, graph_steps: int = 0):
+    cfg = lbm_launch_config(int(wg_waves), int(xcd_remap), int(graph_steps), 0)
+    _check(lib.lbm_set_launch_config(ctx, C.byref(cfg)), "lbm_set_launch_config", ctx)
+
+
+def lbm_get_launch_config(ctx) -> dict:
+    cfg = lbm_launch_config()
+    _check(lib.lbm_get_launch_config(ctx, C.byref(cfg)), "lbm_get_launch_config", ctx)
+    return dict(wg_waves=cfg.wg_waves, xcd_remap=cfg.xcd_remap, graph_steps=cfg.graph_steps)
+
+
+def lbm_autotune(ctx, trial_steps: int):
+    """Returns (chosen launch config as a dict, ms per step, steps run)."""
+    cfg = lbm_launch_config()
+    ms = C.c_double(0.0)
+    n = C.c_int64(0)
+    _check(lib.lbm_autotune(ctx, int(trial_steps), C.byref(cfg), C.byref(ms), C.byref(n)),
+           "lbm_autotune", ctx)
+    return (dict(wg_waves=cfg.wg_waves, xcd_remap=cfg.xcd_remap, graph_steps=cfg.graph_steps),
+            ms.value, n.value)
 
 
 def lbm_get_fields(ctx, rho=None, u=None, c=None, phi=None, type=None):

@@ -304,8 +304,84 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
     c->step = c->n_events = 0;
     c->have_geom = c->have_state = false;
     c->have_events = false;
+    c->cfg.wg_waves = 4;
+    c->cfg.xcd_remap = 1;
+    c->cfg.graph_steps = 0;
+    c->cfg.reserved0 = 0;
+    c->gexec = nullptr;
+    c->graph_built = 0;
     *out = (lbm_ctx *)c;
     return LBM_OK;
+}
+
+static void drop_graph(Ctx *c) {
+    if (c->graph_built) (void)hipGraphExecDestroy(c->gexec);
+    c->gexec = nullptr;
+    c->graph_built = 0;
+}
+
+// Capture n (even) steps starting from buffer 0 on a private stream; the
+// graph holds kernel launches only.
+static hipError_t build_graph(Ctx *c, int n) {
+    drop_graph(c);
+    hipStream_t cs;
+    hipError_t e = hipStreamCreateWithFlags(&cs, hipStreamNonBlocking);
+    if (e != hipSuccess) return e;
+    const hipStream_t user = c->stream;
+    const int cur = c->cur;
+    e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
+    if (e == hipSuccess) {
+        c->stream = cs;
+        c->cur = 0;
+        hipError_t le = hipSuccess;
+        for (int t = 0; t < n && le == hipSuccess; t++) le = launch_step(*c);
+        c->stream = user;
+        c->cur = cur;
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(cs, &g);
+        if (le != hipSuccess) e = le;
+        if (e == hipSuccess) e = hipGraphInstantiate(&c->gexec, g, nullptr, nullptr, 0);
+        if (g) (void)hipGraphDestroy(g);
+        if (e == hipSuccess) c->graph_built = n;
+    }
+    (void)hipStreamDestroy(cs);
+    return e;
+}
+
+static hipError_t run_steps(Ctx *c, int32_t nsteps) {
+    int32_t t = 0;
+    const int gs = (c->cfg.graph_steps + 1) & ~1;
+    if (gs > 0 && nsteps >= gs) {
+        if (c->cur != 0) {   // the graph starts from buffer 0
+            hipError_t e = launch_step(*c);
+            if (e != hipSuccess) return e;
+            c->step++;
+            t++;
+        }
+        if (nsteps - t >= gs) {
+            if (c->graph_built != gs) {
+                hipError_t e = build_graph(c, gs);
+                if (e != hipSuccess) return e;
+            }
+            while (nsteps - t >= gs) {
+                hipError_t e = hipGraphLaunch(c->gexec, c->stream);
+                if (e != hipSuccess) return e;
+                c->step += gs;
+                t += gs;
+            }
+        }
+    }
+    for (; t < nsteps; t++) {
+        hipError_t e = launch_step(*c);
+        if (e != hipSuccess) return e;
+        c->step++;
+    }
+    return hipSuccess;
+}
+
+static bool cfg_ok(const lbm_launch_config &g) {
+    return (g.wg_waves == 1 || g.wg_waves == 2 || g.wg_waves == 4 || g.wg_waves == 8) &&
+           (g.xcd_remap == 0 || g.xcd_remap == 1) && g.graph_steps >= 0 && g.graph_steps <= 100000;
 }
 
 extern "C" {
@@ -348,6 +424,7 @@ void lbm_destroy(lbm_ctx *ctx) {
     if (!c) return;
     if (c->have_events)
         for (int k = 0; k < 4; k++) (void)hipEventDestroy(c->ev[k]);
+    drop_graph(c);
     delete c;
 }
 
@@ -373,6 +450,7 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *no
     if (!dev_ptr_ok(k_r)) return bad_ptr(c, "k_r");
     if (!dev_ptr_ok(phi0)) return bad_ptr(c, "phi0");
     int64_t nl = 0, ns = 0;
+    drop_graph(c);
     hipError_t e = launch_geometry(*c, solid, normals, k_r, phi0, &nl, &ns);
     if (e != hipSuccess) return dev_err(c, e, "geometry preparation");
     if (nl > c->max_links) {
@@ -416,11 +494,106 @@ lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
         c->err = "lbm_step before lbm_init_fields";
         return LBM_ESTATE;
     }
-    for (int32_t t = 0; t < nsteps; t++) {
-        hipError_t e = launch_step(*c);
-        if (e != hipSuccess) return dev_err(c, e, "step launch");
-        c->step++;
+    hipError_t e = run_steps(c, nsteps);
+    if (e != hipSuccess) return dev_err(c, e, "step launch");
+    return LBM_OK;
+}
+
+lbm_status lbm_set_launch_config(lbm_ctx *ctx, const lbm_launch_config *cfg) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c || !cfg) return LBM_EINVAL;
+    if (!cfg_ok(*cfg)) {
+        c->err = "launch config: wg_waves in {1,2,4,8}, xcd_remap in {0,1}, 0 <= graph_steps <= 100000";
+        return LBM_EINVAL;
     }
+    if (cfg->wg_waves != c->cfg.wg_waves || cfg->xcd_remap != c->cfg.xcd_remap) drop_graph(c);
+    c->cfg = *cfg;
+    c->cfg.reserved0 = 0;
+    return LBM_OK;
+}
+
+lbm_status lbm_get_launch_config(const lbm_ctx *ctx, lbm_launch_config *cfg) {
+    const Ctx *c = (const Ctx *)ctx;
+    if (!c || !cfg) return LBM_EINVAL;
+    *cfg = c->cfg;
+    return LBM_OK;
+}
+
+lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *best,
+                        double *ms_per_step, int64_t *steps_run) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (trial_steps < 1 || trial_steps > 100000) {
+        c->err = "trial_steps must be in 1..100000";
+        return LBM_EINVAL;
+    }
+    if (!c->have_state) {
+        c->err = "lbm_autotune before lbm_init_fields";
+        return LBM_ESTATE;
+    }
+    const int64_t step0 = c->step;
+    const lbm_launch_config keep = c->cfg;
+    hipEvent_t e0, e1;
+    hipError_t e = hipEventCreate(&e0);
+    if (e != hipSuccess) return dev_err(c, e, "hipEventCreate");
+    e = hipEventCreate(&e1);
+    if (e != hipSuccess) {
+        (void)hipEventDestroy(e0);
+        return dev_err(c, e, "hipEventCreate");
+    }
+    // time n steps under configuration g after w untimed steps
+    auto trial = [&](const lbm_launch_config &g, int w, int n, double *ms) -> hipError_t {
+        if (g.wg_waves != c->cfg.wg_waves || g.xcd_remap != c->cfg.xcd_remap) drop_graph(c);
+        c->cfg = g;
+        hipError_t r = run_steps(c, w);
+        if (r == hipSuccess) r = hipEventRecord(e0, c->stream);
+        if (r == hipSuccess) r = run_steps(c, n);
+        if (r == hipSuccess) r = hipEventRecord(e1, c->stream);
+        if (r == hipSuccess) r = hipEventSynchronize(e1);
+        float t = 0.f;
+        if (r == hipSuccess) r = hipEventElapsedTime(&t, e0, e1);
+        *ms = (double)t / n;
+        return r;
+    };
+    lbm_launch_config bc = keep;
+    double bms = 1e300;
+    const int waves[4] = {1, 2, 4, 8};
+    for (int wi = 0; wi < 4 && e == hipSuccess; wi++)
+        for (int rm = 0; rm < 2 && e == hipSuccess; rm++) {
+            lbm_launch_config g = {waves[wi], rm, 0, 0};
+            double ms = 0.0;
+            e = trial(g, 2, trial_steps, &ms);
+            if (e == hipSuccess && ms < bms) {
+                bms = ms;
+                bc = g;
+            }
+        }
+    const int gsteps[3] = {16, 64, 256};
+    for (int gi = 0; gi < 3 && e == hipSuccess; gi++) {
+        const int gs = gsteps[gi];
+        if (gs > 4 * trial_steps) break;
+        lbm_launch_config g = bc;
+        g.graph_steps = gs;
+        const int n = ((trial_steps + gs - 1) / gs) * gs;
+        double ms = 0.0;
+        e = trial(g, gs + 1, n, &ms);   // the untimed part builds the graph
+        if (e == hipSuccess && ms < bms) {
+            bms = ms;
+            bc = g;
+        }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (e != hipSuccess) {
+        drop_graph(c);
+        c->cfg = keep;
+        return dev_err(c, e, "autotune");
+    }
+    if (bc.wg_waves != c->cfg.wg_waves || bc.xcd_remap != c->cfg.xcd_remap) drop_graph(c);
+    c->cfg = bc;
+    if (best) *best = bc;
+    if (ms_per_step) *ms_per_step = bms;
+    if (steps_run) *steps_run = c->step - step0;
     return LBM_OK;
 }
 
@@ -619,6 +792,7 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
     const double *nrm_src = (const double *)(b + phio + 16 * c->N);
     const uint8_t *sol_src = (const uint8_t *)(b + phio + 40 * c->N);
     int64_t nl = 0, ns = 0;
+    drop_graph(c);
     e = launch_geometry(*c, sol_src, nrm_src, kr_src, phi_src, &nl, &ns);
     if (e != hipSuccess) return dev_err(c, e, "load_state geometry");
     if (nl > c->max_links) {

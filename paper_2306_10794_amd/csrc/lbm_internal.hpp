@@ -43,6 +43,7 @@ struct DomHost {
 
 struct Ctx {
     lbm_params p;            // parameters of domain 0 (precision, lattice)
+    lbm_launch_config cfg;   // tile / schedule of the step launches
     hipStream_t stream;
     int Q, dim;
     int ndom;
@@ -86,6 +87,10 @@ struct Ctx {
     bool have_geom, have_state;
     hipEvent_t ev[4];
     bool have_events;
+    // graph of cfg.graph_steps steps (even), valid while the geometry and the
+    // launch configuration are unchanged; replayed from buffer 0
+    hipGraphExec_t gexec;
+    int graph_built;         // steps in gexec, 0 = none
     std::string err;
 };
 

@@ -47,13 +47,15 @@ constexpr int n_slots() {
     return L::DIM == 2 ? 3 : 9;
 }
 
-template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
+// WV wavefronts (tasks) per workgroup; remap != 0 keeps runs of consecutive
+// tiles on one XCD
+template <class L, typename T, int WV>
+__global__ __launch_bounds__(64 * WV) void k_step(StepArgs<T> a, long nblocks, int remap) {
     using R = double;
     constexpr int Q = L::Q;
     constexpr int NS = n_slots<L>();
-    const long tile = xcd_tile(blockIdx.x, nblocks);
-    const int t = __builtin_amdgcn_readfirstlane((int)(tile * (BLK / 64)) + (int)(threadIdx.x >> 6));
+    const long tile = remap ? xcd_tile(blockIdx.x, nblocks) : (long)blockIdx.x;
+    const int t = __builtin_amdgcn_readfirstlane((int)(tile * WV) + (int)(threadIdx.x >> 6));
     if (t >= a.ntasks) return;
     const int lane = threadIdx.x & 63;
     const Task tk = a.tasks[t];
@@ -145,7 +147,7 @@ __global__ __launch_bounds__(BLK) void k_step(StepArgs<T> a, long nblocks) {
     // fetched straight into LDS so that no VGPR waits on them: row [i][w] of
     // this wavefront's slice holds dword w of lane's beta along i ----
     constexpr int NW = (int)(sizeof(T) / 4);
-    __shared__ uint32_t sbeta[BLK / 64][Q][NW][64];
+    __shared__ uint32_t sbeta[WV][Q][NW][64];
     const int wv = threadIdx.x >> 6;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
@@ -334,8 +336,15 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev) {
     const StepArgs<T> args = step_args<T>(c);
     if (ev) (void)hipEventRecord(ev[0], c.stream);
     if (c.n_tasks > 0) {
-        const long nb = (c.n_tasks + BLK / 64 - 1) / (BLK / 64);
-        hipLaunchKernelGGL((k_step<L, T>), dim3(nb), dim3(BLK), 0, c.stream, args, nb);
+        const int wv = c.cfg.wg_waves;
+        const long nb = (c.n_tasks + wv - 1) / wv;
+        const int rm = c.cfg.xcd_remap;
+        switch (wv) {
+        case 1: hipLaunchKernelGGL((k_step<L, T, 1>), dim3(nb), dim3(64), 0, c.stream, args, nb, rm); break;
+        case 2: hipLaunchKernelGGL((k_step<L, T, 2>), dim3(nb), dim3(128), 0, c.stream, args, nb, rm); break;
+        case 8: hipLaunchKernelGGL((k_step<L, T, 8>), dim3(nb), dim3(512), 0, c.stream, args, nb, rm); break;
+        default: hipLaunchKernelGGL((k_step<L, T, 4>), dim3(nb), dim3(256), 0, c.stream, args, nb, rm); break;
+        }
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[1], c.stream);

@@ -48,6 +48,7 @@ def test_struct_layout_matches_header():
     assert C.sizeof(L.lbm_params) % 8 == 0
     assert L.lbm_params.max_links.offset == C.sizeof(L.lbm_params) - 8
     assert C.sizeof(L.lbm_diag) == 6 * 8 + 3 * 8 + 8
+    assert C.sizeof(L.lbm_launch_config) == 16
 
 
 def test_workspace_bytes_scales_with_lattice():
