@@ -26,7 +26,23 @@ sys.path.insert(0, ROOT)
 
 METRIC = "MLUPS + % HBM peak (fused step); adjoint/forward time ratio; batched vs plain"
 HBM_PEAK_GBS = 8000.0
-KERNEL_SRC = os.path.join(ROOT, "paper_2306_10794_amd", "csrc", "lbm_step.hip")
+CSRC = os.path.join(ROOT, "paper_2306_10794_amd", "csrc")
+# sources that determine the step kernel's code
+KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("lbm_step.hip", "lbm_device.hpp", "lbm_internal.hpp")]
+STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4>"
+PHI_KERNEL = "lbm::k_phi_solid<lbm::D3Q19, float>"
+COPY_KERNEL = "neg_kernel"   # torch elementwise negation: one read, one write per element
+# the rocprofv3 runs whose summaries are committed (run from the repository
+# root after `cd /tmp && export TMPDIR=/tmp && cd -`)
+PROFILE_ARGS = "--steps 50 --warmup 5 --no-cpu-baseline --no-batch --calib-copy-mib 1024"
+PMC_ARGS = "--steps 5 --warmup 1 --no-cpu-baseline --no-batch --calib-copy-mib 1024"
+PROFILE_CMDS = {
+    "trace": f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run -- "
+             f"python3 bench.py {PROFILE_ARGS}",
+    "fetch": f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch -o run -- python3 bench.py {PMC_ARGS}",
+    "write": f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/write -o run -- python3 bench.py {PMC_ARGS}",
+    "summary": "python3 bench.py --summarize-profiles gpurun_out/prof",
+}
 
 
 def log(msg):
@@ -45,6 +61,13 @@ def kernel_bytes(q, ts, n_fluid, n_links, n_fluid_iface):
     return n_fluid * (2 * q * ts * 2 + 4) + n_links * 2 * ts + n_fluid_iface * 16
 
 
+def kernel_sha256():
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        h.update(open(p, "rb").read())
+    return h.hexdigest()
+
+
 def traffic_from_profile(workload):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
     were taken on the current kernel source."""
@@ -53,8 +76,7 @@ def traffic_from_profile(workload):
         return None
     try:
         rec = json.load(open(path))
-        sha = hashlib.sha256(open(KERNEL_SRC, "rb").read()).hexdigest()
-        if rec.get("kernel_sha256") != sha:
+        if rec.get("kernel_sha256") != kernel_sha256():
             return None
         return rec.get("bytes_per_launch")
     except Exception:
@@ -146,6 +168,103 @@ def cpu_baseline(case, steps):
                        f"1 warm-up step ({dt:.1f} s)")
 
 
+def _db(d):
+    import glob
+    import sqlite3
+    files = sorted(glob.glob(os.path.join(d, "**", "*results.db"), recursive=True))
+    if not files:
+        raise SystemExit(f"no rocprofv3 database under {d}")
+    return sqlite3.connect(files[-1])
+
+
+def summarize_profiles(prof_dir, workload="spheres256", calib_mib=1024):
+    """Per-kernel durations from the kernel-trace run and HBM bytes from the
+    FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), scaled by what the same
+    counters read for a device-to-device copy of calib_mib MiB (which reads
+    and writes exactly that many bytes).  Writes <prof_dir>/summary/."""
+    out_dir = os.path.join(prof_dir, "summary")
+    os.makedirs(out_dir, exist_ok=True)
+    tr = _db(os.path.join(prof_dir, "trace"))
+    rows = tr.execute("select name, count(*), avg(end - start), min(end - start), max(end - start), "
+                      "sum(end - start) from kernels group by name order by sum(end - start) desc"
+                      ).fetchall()
+    total = sum(r[5] for r in rows) or 1
+    lines = [f"# Kernel durations, {workload} (rocprofv3 --kernel-trace --stats)", "",
+             "Command (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
+             f"    {PROFILE_CMDS['trace']}", "",
+             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    step_avg = None
+    for name, n, avg, mn, mx, tot in rows[:14]:
+        short = name.split("(")[0].replace("void ", "")
+        if short == STEP_KERNEL:
+            step_avg = avg
+        lines.append(f"| `{short}` | {n} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
+                     f"{100.0 * tot / total:.1f} |")
+    if step_avg is None:
+        for name, n, avg, *_ in rows:
+            if name.split("(")[0].replace("void ", "") == STEP_KERNEL:
+                step_avg = avg
+    open(os.path.join(out_dir, f"k_step_{workload}_trace.md"), "w").write("\n".join(lines) + "\n")
+
+    def counter(d, cname):
+        db = _db(os.path.join(prof_dir, d))
+        res = {}
+        for name, val in db.execute("select kernel_name, value from counters_collection "
+                                    "where counter_name = ?", (cname,)):
+            res.setdefault(name.split("(")[0].replace("void ", ""), []).append(float(val))
+        return res
+
+    fetch, write = counter("fetch", "FETCH_SIZE"), counter("write", "WRITE_SIZE")
+    calib = calib_mib * 2 ** 20
+
+    def copy_kib(res):
+        vals = [v for k, vs in res.items() if COPY_KERNEL in k for v in vs]
+        if not vals:
+            raise SystemExit("no calibration dispatches in the counter runs")
+        return sum(vals) / len(vals)
+
+    f_fetch = calib / (copy_kib(fetch) * 1024.0)
+    f_write = calib / (copy_kib(write) * 1024.0)
+    rec = {"workload": workload, "kernel": STEP_KERNEL, "kernel_sha256": kernel_sha256(),
+           "calibration_copy_bytes": calib, "fetch_scale": f_fetch, "write_scale": f_write,
+           "commands": [PROFILE_CMDS["fetch"], PROFILE_CMDS["write"]],
+           "avg_duration_ns": step_avg}
+    lines = [f"# HBM traffic per dispatch, {workload} (rocprofv3 --pmc)", "",
+             "Commands (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
+             f"    {PROFILE_CMDS['fetch']}", f"    {PROFILE_CMDS['write']}", "",
+             f"Calibration: an elementwise negation of {calib_mib} MiB (float32) reads and writes "
+             f"{calib} B; "
+             f"FETCH_SIZE reads {copy_kib(fetch):.0f} KiB for it (scale {f_fetch:.3f}) and "
+             f"WRITE_SIZE {copy_kib(write):.0f} KiB (scale {f_write:.3f}).", "",
+             "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled read B | scaled write B | "
+             "scaled total B |", "|---|---|---|---|---|---|---|"]
+    for k in (STEP_KERNEL, PHI_KERNEL):
+        if k in fetch and k in write:
+            fk = sum(fetch[k]) / len(fetch[k])
+            wk = sum(write[k]) / len(write[k])
+            rb, wb = fk * 1024 * f_fetch, wk * 1024 * f_write
+            lines.append(f"| `{k}` | {len(fetch[k])} | {fk:.0f} | {wk:.0f} | {rb:.4g} | {wb:.4g} | "
+                         f"{rb + wb:.4g} |")
+            if k == STEP_KERNEL:
+                rec.update(read_bytes=rb, write_bytes=wb, bytes_per_launch=rb + wb)
+    open(os.path.join(out_dir, f"k_step_{workload}_pmc.md"), "w").write("\n".join(lines) + "\n")
+    json.dump(rec, open(os.path.join(out_dir, f"k_step_{workload}_pmc.json"), "w"), indent=1)
+    print(json.dumps(rec), flush=True)
+
+
+def calibration_copies(mib):
+    """Three copy-like passes of a known size (counter calibration): an
+    elementwise negation reads and writes every element once."""
+    import torch
+    x = torch.ones(mib * 2 ** 20 // 4, dtype=torch.float32, device="cuda:0")
+    y = torch.empty_like(x)
+    for _ in range(3):
+        torch.neg(x, out=y)
+    torch.cuda.synchronize()
+    del x, y
+    torch.cuda.empty_cache()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -158,7 +277,14 @@ def main():
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--tune-steps", type=int, default=32)
+    ap.add_argument("--calib-copy-mib", type=int, default=0,
+                    help="after the measurement, copy this many MiB three times (counter calibration)")
+    ap.add_argument("--summarize-profiles", metavar="DIR",
+                    help="summarise rocprofv3 runs under DIR/{trace,fetch,write} and exit")
     args = ap.parse_args()
+    if args.summarize_profiles:
+        summarize_profiles(args.summarize_profiles, args.workload)
+        return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
@@ -230,6 +356,8 @@ def main():
     sim.close()
     del sim
     torch.cuda.empty_cache()
+    if args.calib_copy_mib > 0:
+        calibration_copies(args.calib_copy_mib)
     if not args.no_batch:
         line["batch"] = batch_vs_plain(args.batch_steps, args.plain_steps, args.tune_steps)
         log(f"[bench] batch {line['batch']}")
