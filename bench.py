@@ -288,7 +288,7 @@ def main():
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
         print(f"bench.py measures one GPU only (asked for --gpus {args.gpus}, WORLD_SIZE {world}); "
-              "the multi-GPU layout is described in DESIGN.md and not run.", file=sys.stderr)
+              "runs on more than one GPU are not part of this benchmark.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -1,7 +1,6 @@
 """The workloads, as seeded synthetic ``Case`` objects.
 
-Lattice parameters follow the recipes written out in the design notes; the
-dimensionless groups are Re = U L / nu, Pe = U L / D, Da = k_r / U and
+The dimensionless groups are Re = U L / nu, Pe = U L / D, Da = k_r / U and
 PeDa = k_r L / D (paper, definitions of the dimensionless numbers), with
 D = c_s^2 (tau_AD - 1/2) and the rest fraction J0 chosen so that c_s^2 gives the
 wanted D at fixed tau_AD (paper, rest fraction method; generalised to D2Q9 and

@@ -11,7 +11,7 @@
  *   - fluid lattice: BGK collision with the second-order equilibrium
  *     (Sec. 2.1, eqs. fluid_BGK, fluid_Equilib, fluid_BGK_visc); a body force
  *     enters through Guo's forcing with the half-force velocity shift (the
- *     paper gives no forcing scheme; reading AM8 of the design notes);
+ *     paper names no forcing scheme, Guo's is the standard one for BGK);
  *     halfway bounce-back at solid neighbours.
  *   - solute lattice: advection-diffusion BGK with the linear equilibrium
  *     g_eq = C w_i (1 + u.e_i / c_s^2), u the fluid velocity of the same node
@@ -429,7 +429,13 @@ void orc_step(orc *o, int nsteps)
 /* ------------------------------------------------------------------------- */
 /* Phase change (Sec. 2.4: thresholds phi = 0 for dissolution and phi = 1 for
  * precipitation, redistribution of the excess weighted by the reaction rate).
- * Reading AM5 of the design notes; events are taken in node-index order. */
+ * The paper states the rules in words only.  Reading taken here: a dissolving
+ * solid node becomes fluid with C = mean C of its fluid neighbours and
+ * equilibrium populations, and V_m C - phi is taken from its solid neighbours
+ * in proportion to their link k (equal shares if all k are 0); a precipitating
+ * fluid node becomes solid, adds V_m C to phi and passes phi - 1 to its fluid
+ * neighbours in proportion to their link k.  Both keep the solute plus solid
+ * mass.  Events are taken in node-index order. */
 
 static double node_C(const orc *o, long n)
 {
