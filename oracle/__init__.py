@@ -60,6 +60,8 @@ def _load():
         lib.orc_get_lattice.argtypes = [P, P, P, P, P]
         lib.orc_get_normals.argtypes = [P, P]
         lib.orc_diag.argtypes = [P, dp]
+        lib.orc_adjoint.restype = C.c_int
+        lib.orc_adjoint.argtypes = [P, C.c_int, P, P, P]
         lib.orc_threads.restype = C.c_int
         _lib = lib
     return _lib
@@ -153,6 +155,18 @@ class Oracle:
         wf, ws, cs2 = np.empty(self.Q), np.empty(self.Q), np.empty(2)
         _load().orc_get_lattice(self._h, _ptr(e), _ptr(wf), _ptr(ws), _ptr(cs2))
         return dict(e=e, wf=wf, ws=ws, cs2f=cs2[0], cs2s=cs2[1])
+
+    def adjoint(self, nsteps: int, dLdC, want_lam0: bool = False):
+        """Runs nsteps forward, then the adjoint of a loss with gradient dLdC [N]
+        with respect to the final concentrations.  Returns (dL/dk_r [N],
+        dL/dg*(0) as [Q, N] or None)."""
+        dLdC = np.ascontiguousarray(dLdC, np.float64)
+        grad = np.zeros(self.N)
+        lam0 = np.zeros((self.N, self.Q)) if want_lam0 else None
+        rc = _load().orc_adjoint(self._h, int(nsteps), _ptr(dLdC), _ptr(grad), _ptr(lam0))
+        if rc != 0:
+            raise RuntimeError(f"orc_adjoint failed ({rc})")
+        return grad, (None if lam0 is None else np.ascontiguousarray(lam0.T))
 
     def diag(self) -> dict:
         d = (C.c_double * 7)()

@@ -77,6 +77,8 @@ typedef struct {
     uint8_t *kind;         /* [N][Q] link classification of last step   */
     double inlet_ex, outlet_ex, wall_ex; /* cumulative exchanges            */
     long step, n_events;
+    double *uh;            /* if set, [N][3]: the fluid velocity each node's
+                              solute collision used in the current step    */
 } orc;
 
 /* link classes of an incoming solute population */
@@ -298,6 +300,8 @@ static void update_node(orc *o, long x)
     }
     double u[3];
     for (int d = 0; d < 3; d++) u[d] = (j[d] + 0.5 * p->force[d]) / rho;
+    if (o->uh)
+        for (int d = 0; d < 3; d++) o->uh[3 * x + d] = u[d];
     double c = o->cs2f;
     double uF = u[0] * p->force[0] + u[1] * p->force[1] + u[2] * p->force[2];
     for (int i = 0; i < Q; i++) {
@@ -568,6 +572,151 @@ static void apply_phase_change(orc *o)
 /* ------------------------------------------------------------------------- */
 /* Read-outs.  rho = sum f*, u = (sum e f* - F/2)/rho (the velocity that entered
  * the last collision), C = sum g*; solid nodes read as zero. */
+/* ------------------------------------------------------------------------- */
+/* Adjoint of the solute lattice with respect to the rate constants k_r of the
+ * solid nodes, by reverse-mode differentiation of the steps above.  The fluid
+ * does not depend on k_r; its velocity is recorded during the forward run and
+ * held fixed.  The solute step is affine in the populations for a given
+ * velocity history, so the adjoint populations lambda(t) = dL/dg*(t) follow
+ * from lambda(t+1) by the transpose of one step, and dL/dk_r collects, over
+ * every step and reactive link, lambda of the link's incoming population times
+ * the derivative of the rate condition (Sec. 2.3, eq. general_RBC) with
+ * respect to k, times dk/dk_r of the scheme (eqs. k_i_S_Ve, k_i_S2,
+ * k_i_S_New). */
+
+/* dk/dk_r of link_k (all schemes are linear in k_r; anti-bounce-back has no k) */
+static double link_dk(const orc *o, long s, int i)
+{
+    const double *n = o->nrm + 3 * s;
+    double en = o->e[i][0] * n[0] + o->e[i][1] * n[1] + o->e[i][2] * n[2];
+    switch (o->p.scheme) {
+    case ORC_SV:   return en > 0 ? en / o->cs2s : 0.0;
+    case ORC_SPJ:  return en > 0 ? o->gamma / (o->cs2s * en) : 0.0;
+    case ORC_ABB:  return 0.0;
+    default:       return en > 0 ? o->gamma * en / o->cs2s : 0.0;
+    }
+}
+
+/* One fluid node x of the transposed step.  go: the post-collision solute
+ * populations the forward step started from; u: the velocity the node's
+ * collision used; mu: lambda(t+1) at x.  Adds into lam = lambda(t) and grad. */
+static void adjoint_node(const orc *o, long x, const double *go, const double *u,
+                         const double *mu, double *lam, double *grad)
+{
+    const int Q = o->Q;
+    const orc_params *p = &o->p;
+    int X, Y, Z, face;
+    coords(o, x, &X, &Y, &Z);
+    /* where every pre-collision value came from (the forward pull):
+     * population src_d[i] of node src_n[i], or a constant (src_n = -1) */
+    long src_n[ORC_QMAX], sol[ORC_QMAX];
+    int src_d[ORC_QMAX], kd[ORC_QMAX];
+    double gp[ORC_QMAX];
+    for (int i = 0; i < Q; i++) {
+        long y = site(o, X, Y, Z, -o->e[i][0], -o->e[i][1], -o->e[i][2], 1, &face);
+        sol[i] = -1;
+        src_n[i] = x;
+        src_d[i] = o->opp[i];
+        if (y >= 0) {
+            if (!o->solid[y]) { kd[i] = K_KNOWN; src_n[i] = y; src_d[i] = i; }
+            else { kd[i] = K_RBC; sol[i] = y; }
+        } else if (p->inlet_axis >= 0 && face == 2 * p->inlet_axis) {
+            kd[i] = K_INLET;
+            src_n[i] = -1;
+        } else if (p->inlet_axis >= 0 && face == 2 * p->inlet_axis + 1) {
+            int a = p->inlet_axis, ex[3] = {0, 0, 0};
+            ex[a] = 1;
+            int f2;
+            long y2 = site(o, X, Y, Z, -o->e[i][0] - ex[0], -o->e[i][1] - ex[1],
+                           -o->e[i][2] - ex[2], 1, &f2);
+            kd[i] = K_OUTLET;
+            if (y2 >= 0 && !o->solid[y2]) { src_n[i] = y2; src_d[i] = i; }
+        } else {
+            kd[i] = K_WALL;
+        }
+        if (kd[i] == K_INLET) gp[i] = geq(o, i, p->c_in, u);
+        else if (kd[i] == K_RBC) gp[i] = 0.0;
+        else gp[i] = go[src_n[i] * Q + src_d[i]];
+    }
+    /* collision g*_i = (1 - 1/tau) p_i + (1/tau) w_i C (1 + e_i.u/c_s^2),
+     * C = sum_j p_j: its transpose */
+    double m = 0.0;
+    for (int i = 0; i < Q; i++) {
+        double eu = o->e[i][0] * u[0] + o->e[i][1] * u[1] + o->e[i][2] * u[2];
+        m += mu[i] * o->ws[i] * (1.0 + eu / o->cs2s);
+    }
+    double nu[ORC_QMAX];
+    for (int i = 0; i < Q; i++) nu[i] = (1.0 - 1.0 / p->tau_ad) * mu[i] + m / p->tau_ad;
+    /* reactive links: p_i = k/(1+k) 2 w_i C_eq + (1-k)/(1+k) src */
+    for (int i = 0; i < Q; i++) {
+        if (kd[i] != K_RBC) continue;
+        int ob = o->opp[i];
+        double k = link_k(o, sol[i], i);
+        double dk = link_dk(o, sol[i], i);
+        int pulled = p->mechanics == ORC_MECH_PRE && kd[ob] != K_RBC;
+        double src = pulled ? gp[ob] : go[x * Q + ob];
+        if (!pulled && p->mechanics == ORC_MECH_PRE) { k = k / o->gamma; dk = dk / o->gamma; }
+        double csrc;
+        if (isinf(k)) {
+            csrc = -1.0;
+        } else {
+            csrc = (1.0 - k) / (1.0 + k);
+            double dpdk = 2.0 * (o->ws[i] * p->c_eq - src) / ((1.0 + k) * (1.0 + k));
+            grad[sol[i]] += nu[i] * dpdk * dk;
+        }
+        if (pulled) nu[ob] += csrc * nu[i];          /* through p_ob to its source */
+        else lam[x * Q + ob] += csrc * nu[i];        /* the node's own population */
+    }
+    for (int i = 0; i < Q; i++) {
+        if (kd[i] == K_RBC || src_n[i] < 0) continue;
+        lam[src_n[i] * Q + src_d[i]] += nu[i];
+    }
+}
+
+/* Run nsteps forward from the current state, recording every solute state and
+ * velocity, then the adjoint of the loss whose gradient with respect to the
+ * final concentrations C_T = sum_i g*_i(T) is dLdC [N].  Writes dL/dk_r into
+ * grad [N] (zero away from solid interface nodes) and, if lam0 is not NULL,
+ * dL/dg*(0) into lam0 [N][Q].  Leaves the state at step T.  Returns 0, or -1
+ * (out of memory), -2 (phase change enabled). */
+int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *lam0)
+{
+    const long N = o->N;
+    const int Q = o->Q;
+    if (o->p.phase_change) return -2;
+    double *G = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * Q);
+    double *U = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * 3);
+    double *lam = (double *)calloc((size_t)N * Q, sizeof(double));
+    double *lnew = (double *)calloc((size_t)N * Q, sizeof(double));
+    if (!G || !U || !lam || !lnew) {
+        free(G); free(U); free(lam); free(lnew);
+        return -1;
+    }
+    for (int t = 0; t < nsteps; t++) {
+        memcpy(G + (size_t)t * N * Q, o->g, sizeof(double) * N * Q);
+        memset(U + (size_t)t * N * 3, 0, sizeof(double) * N * 3);
+        o->uh = U + (size_t)t * N * 3;
+        orc_step(o, 1);
+        o->uh = NULL;
+    }
+    for (long n = 0; n < N; n++) {
+        grad[n] = 0.0;
+        if (o->solid[n]) continue;
+        for (int i = 0; i < Q; i++) lam[n * Q + i] = dLdC[n];
+    }
+    for (int t = nsteps - 1; t >= 0; t--) {
+        memset(lnew, 0, sizeof(double) * N * Q);
+        const double *go = G + (size_t)t * N * Q;
+        const double *ut = U + (size_t)t * N * 3;
+        for (long n = 0; n < N; n++)
+            if (!o->solid[n]) adjoint_node(o, n, go, ut + 3 * n, lam + n * Q, lnew, grad);
+        double *tmp = lam; lam = lnew; lnew = tmp;
+    }
+    if (lam0) memcpy(lam0, lam, sizeof(double) * N * Q);
+    free(G); free(U); free(lam); free(lnew);
+    return 0;
+}
+
 void orc_get_fields(const orc *o, double *rho, double *u, double *c, double *phi,
                     uint8_t *type)
 {
