@@ -21,6 +21,8 @@ import os
 import sys
 import time
 
+import numpy as np
+
 ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
@@ -155,6 +157,56 @@ def batch_vs_plain(batch_steps, plain_steps, tune_steps):
     }
 
 
+def adjoint_ratio(steps, ckpt):
+    """Rate-field recovery workload (128^3 sphere packing, porosity 0.45, D3Q19
+    solute, fluid at rest, log-normal k_r): time of the forward run recorded
+    for the adjoint, and of the adjoint pass (segment recomputation plus the
+    transposed steps), per step, FP32 deviation storage."""
+    import torch
+    from lbm_inputs import configs
+    from paper_2306_10794_amd import Simulation, LBM_FP32_DEV, lbm_step
+    case = configs.rate_recovery(n=128, seed=5)
+    sim = Simulation(case, precision=LBM_FP32_DEV, device="cuda:0")
+    nf = sim.diag()["n_fluid"]
+    lbm_step(sim.ctx, 20)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm_step(sim.ctx, steps)
+    torch.cuda.synchronize()
+    t_plain = time.perf_counter() - t0
+    sim.init_fields(None, None, case.c_flat())
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    sim.record(steps, ckpt)
+    torch.cuda.synchronize()
+    t_fwd = time.perf_counter() - t0
+    rng = np.random.default_rng(55)
+    dl = torch.as_tensor(rng.normal(size=case.n) * (case.solid_flat() == 0), device="cuda:0")
+    sim.adjoint(dl)
+    torch.cuda.synchronize()
+    sim.init_fields(None, None, case.c_flat())
+    sim.record(steps, ckpt)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    g = sim.adjoint(dl)
+    torch.cuda.synchronize()
+    t_adj = time.perf_counter() - t0
+    ok = bool(torch.isfinite(g).all())
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {
+        "workload": f"rate recovery, {case.nx}^3 sphere packing (porosity "
+                    f"{1 - float(case.solid.mean()):.3f}), D3Q19 solute, fluid at rest, "
+                    f"log-normal k_r, FP32 deviation storage",
+        "fluid_nodes": int(nf), "steps": steps, "checkpoint_every": ckpt,
+        "forward_ms_per_step": round(t_fwd / steps * 1e3, 4),
+        "plain_step_ms": round(t_plain / steps * 1e3, 4),
+        "adjoint_ms_per_step": round(t_adj / steps * 1e3, 4),
+        "ratio": round(t_adj / t_fwd, 3), "finite": ok,
+    }
+
+
 def cpu_baseline(case, steps):
     import oracle
     o = oracle.Oracle(case)
@@ -274,6 +326,9 @@ def main():
     ap.add_argument("--cpu-steps", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
+    ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
+    ap.add_argument("--adjoint-steps", type=int, default=2000)
+    ap.add_argument("--adjoint-ckpt", type=int, default=100)
     ap.add_argument("--batch-steps", type=int, default=1000)
     ap.add_argument("--plain-steps", type=int, default=20)
     ap.add_argument("--tune-steps", type=int, default=32)
@@ -352,6 +407,7 @@ def main():
         },
         "cpu_baseline": None,
         "batch": None,
+        "adjoint": None,
     }
     sim.close()
     del sim
@@ -361,6 +417,9 @@ def main():
     if not args.no_batch:
         line["batch"] = batch_vs_plain(args.batch_steps, args.plain_steps, args.tune_steps)
         log(f"[bench] batch {line['batch']}")
+    if not args.no_adjoint:
+        line["adjoint"] = adjoint_ratio(args.adjoint_steps, args.adjoint_ckpt)
+        log(f"[bench] adjoint {line['adjoint']}")
     if not args.no_cpu_baseline:
         log("[bench] cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)

@@ -97,7 +97,7 @@ typedef struct {
     int32_t phase_change;     /* 1: apply the phi thresholds after each step       */
     int32_t reserved0;
     int64_t max_links;        /* capacity for reactive links; <= 0 selects
-                                 max(4096, N*(Q-1)/8)                              */
+                                 max(4096, N*(Q-1)/4)                              */
 } lbm_params;
 
 typedef struct {
@@ -202,6 +202,33 @@ lbm_status lbm_get_launch_config(const lbm_ctx *ctx, lbm_launch_config *cfg);
  * (host, may be NULL) its time per step.  Synchronises. */
 lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *best,
                         double *ms_per_step, int64_t *steps_run);
+
+/* Adjoint (reverse-mode gradient) of a loss on the final concentrations with
+ * respect to the rate constants k_r of the solid nodes (Sec. 2.3: k enters
+ * every reactive link through eqs. k_i_S_Ve, k_i_S2, k_i_S_New and
+ * eq. general_RBC).  The fluid does not depend on k_r; the adjoint covers a
+ * fluid at rest (pure reaction-diffusion): single-lattice contexts with no
+ * body force, inlet_axis = -1 and phase_change = 0 (EINVAL otherwise, and
+ * lbm_record checks that no fluid node carries momentum).
+ *
+ * lbm_adjoint_workspace_bytes: device bytes that lbm_record needs for nsteps
+ *   steps with a solute checkpoint every ckpt_every steps (1 <= ckpt_every <=
+ *   nsteps): ceil(nsteps/ckpt_every) + ckpt_every + 1 solute states plus 8 B
+ *   per reactive link.
+ * lbm_record: runs nsteps steps exactly as lbm_step does and keeps the
+ *   checkpoints in dev_workspace (caller-owned, 256-byte aligned, untouched
+ *   by anything else until lbm_adjoint has run).
+ * lbm_adjoint: dL_dC [N] FP64 device, dL/dC_T at every node (C_T the final
+ *   concentration, sum of the post-collision populations; solid entries are
+ *   ignored); writes grad_k [N] FP64 device, dL/dk_r at every solid node that
+ *   has a reactive link (0 elsewhere).  ESTATE unless the context is exactly
+ *   at the end of the recorded run with the same geometry.  The state is not
+ *   changed; the call is asynchronous on the context stream. */
+lbm_status lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every,
+                                       size_t *bytes);
+lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *dev_workspace,
+                      size_t bytes);
+lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k);
 
 /* Macroscopic fields of the current state (asynchronous; NULL skips a field):
  * rho = sum f, u = (sum e f - F/2)/rho, C = sum g (the values that entered

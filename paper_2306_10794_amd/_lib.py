@@ -74,6 +74,9 @@ _SIGS = {
     "lbm_get_launch_config": [_P, C.POINTER(lbm_launch_config)],
     "lbm_autotune": [_P, C.c_int32, C.POINTER(lbm_launch_config), C.POINTER(C.c_double),
                      C.POINTER(C.c_int64)],
+    "lbm_adjoint_workspace_bytes": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
+    "lbm_record": [_P, C.c_int32, C.c_int32, _P, C.c_size_t],
+    "lbm_adjoint": [_P, _P, _P],
     "lbm_get_fields": [_P, _P, _P, _P, _P, _P],
     "lbm_get_pops": [_P, _P, _P],
     "lbm_get_exchange": [_P, _P],
@@ -199,6 +202,22 @@ def lbm_autotune(ctx, trial_steps: int):
            "lbm_autotune", ctx)
     return (dict(wg_waves=cfg.wg_waves, xcd_remap=cfg.xcd_remap, graph_steps=cfg.graph_steps),
             ms.value, n.value)
+
+
+def lbm_adjoint_workspace_bytes(ctx, nsteps: int, ckpt_every: int) -> int:
+    n = C.c_size_t(0)
+    _check(lib.lbm_adjoint_workspace_bytes(ctx, int(nsteps), int(ckpt_every), C.byref(n)),
+           "lbm_adjoint_workspace_bytes", ctx)
+    return n.value
+
+
+def lbm_record(ctx, nsteps: int, ckpt_every: int, workspace, nbytes: int):
+    _check(lib.lbm_record(ctx, int(nsteps), int(ckpt_every), _ptr(workspace), int(nbytes)),
+           "lbm_record", ctx)
+
+
+def lbm_adjoint(ctx, dL_dC, grad_k):
+    _check(lib.lbm_adjoint(ctx, _ptr(dL_dC), _ptr(grad_k)), "lbm_adjoint", ctx)
 
 
 def lbm_get_fields(ctx, rho=None, u=None, c=None, phi=None, type=None):

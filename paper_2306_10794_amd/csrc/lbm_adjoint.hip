@@ -1,0 +1,343 @@
+// lbm_adjoint.hip -- gradient of a loss on the final concentrations with
+// respect to the rate constants k_r of the solid nodes.
+//
+// The fluid does not depend on k_r; the adjoint covers a fluid at rest
+// (u = 0: pure reaction-diffusion), so only the solute lattice is
+// differentiated.  A recorded forward run keeps the solute state every
+// `ckpt` steps.  The backward pass walks the segments from the last: it
+// recomputes the segment's states from its checkpoint (solute-only step,
+// k_sol_step) and then applies the transposed step (k_adj_step) from the last
+// state of the segment to its first.
+//
+// Transposed step.  lambda(t) = dL/dg*(t), the adjoint of the post-collision
+// populations.  Forward, at a fluid node x: p_i = g*_i(x - e_i) (pull), or
+// g*_o(x) with o = opp(i) (bounce-back at a box face), or on a reactive link
+// (x - e_i solid) p_i = (1 - beta_i) w_i C_eq + beta_i src_i with src_i the
+// pulled p_o (pre-collision mechanics, when o is not reactive) or the own
+// g*_o(x); then g*_i = (1 - w) p_i + w w_i C (C = sum p).  The transpose of
+// the collision is nu_j = (1 - w) mu_j + w sum_i w_i mu_i with mu = lambda(t+1)
+// at x; the rate condition passes beta_i nu_i on to its source; the pull is
+// transposed into a pull in the opposite direction.  Every node writes, per
+// direction j, one value into an array P laid out like the populations:
+//   kk[j] >= 0 or a box face: nu_j plus what reactive links passed to p_j,
+//                             read by the node that p_j was pulled from;
+//   a reactive link:          beta_j nu_j if its source is the node's own
+//                             g*_o (else 0), the node's own lambda_o.
+// so that lambda_d(x, t) = P[d][kk[opp d]] if x + e_d is fluid, else
+// P[opp d][x]: the same gather as the forward pull, directions reversed.
+// dL/dbeta of each link accumulates nu_i (src_i - w_i C_eq) over the steps
+// (FP64, one lane per link); a last kernel turns it into dL/dk_r per solid
+// node through dbeta/dk_r of the link's scheme, summing its links in
+// direction order.
+#include "lbm_internal.hpp"
+#include "lbm_task.hpp"
+
+namespace lbm {
+
+template <typename T>
+struct AdjArgs {
+    const T *__restrict__ pin;    // adjoint array of step t+1 (P layout)
+    T *__restrict__ pout;         // adjoint array of step t
+    const T *__restrict__ gin;    // solute state the forward step started from
+    T *__restrict__ gout;         // solute state after the step (recompute)
+    const Task *__restrict__ tasks;
+    const RowWord *__restrict__ rows;
+    const DomDev *__restrict__ doms;
+    const int32_t *__restrict__ nodeof;
+    const int32_t *__restrict__ lbase;
+    const T *__restrict__ lbeta;
+    double *__restrict__ gbeta;   // per link dL/dbeta, accumulated
+    const double *__restrict__ dldc;  // dense dL/dC_T (init)
+    long ntasks, S;
+};
+
+// per-wavefront task setup shared by the three kernels; returns false for a
+// wavefront without a task
+template <class L, typename T>
+struct TaskCtx {
+    DomDev D;
+    int kk[L::Q];
+    uint32_t solidnb, cross, cross_hi;
+    int k, n, lb;
+    bool active;
+};
+
+template <class L, typename T>
+__device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c) {
+    const int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (BLK / 64)) + (int)(threadIdx.x >> 6));
+    if (t >= a.ntasks) return false;
+    const int lane = threadIdx.x & 63;
+    const Task tk = a.tasks[t];
+    c.D = a.doms[tk.dom];
+    const Box b = c.D.box;
+    const int W = c.D.W;
+    const RowWord *__restrict__ rows = a.rows + c.D.word_off;
+    const int y = tk.row % b.ny, z = tk.row / b.ny;
+    const RowSlots rs = load_row_slots<L>(rows, b, W, lane, y, z);
+    c.active = lane < tk.cnt;
+    c.k = tk.k0 + (c.active ? lane : 0);
+    c.n = a.nodeof[c.k];
+    c.lb = a.lbase[c.k];
+    const int x = (int)(c.n - c.D.node_off) - tk.row * b.nx;
+    classify<L>(rows, b, W, rs, x, y, z, c.k, c.kk, c.solidnb, c.cross, c.cross_hi);
+    return true;
+}
+
+// One solute step with the fluid at rest, from gin to gout: the arithmetic of
+// the fused step's solute half with u = 0 (no exchange or solid fraction is
+// written).
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
+    using R = double;
+    constexpr int Q = L::Q;
+    TaskCtx<L, T> c;
+    if (!task_setup<L, T>(a, c) || !c.active) return;
+    const DomDev &D = c.D;
+    const long S = a.S;
+    const uint32_t rbc = c.solidnb;
+    T gv[Q];
+#pragma unroll
+    for (int i = 0; i < Q; i++)
+        gv[i] = c.kk[i] >= 0 ? a.gin[(long)i * S + c.kk[i]] : a.gin[(long)L::opp[i] * S + c.k];
+    if (rbc) {
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (rbc & (1u << i)) {
+                const int o = L::opp[i];
+                const R own = (R)gv[i];
+                const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
+                const R beta = (R)a.lbeta[c.lb + __popc(rbc & ((1u << i) - 1u))];
+                gv[i] = (T)((R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv);
+            }
+        }
+    }
+    R dC = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; i++) dC += (R)gv[i];
+#pragma unroll
+    for (int i = 0; i < Q; i++) {
+        const R gi = (R)gv[i];
+        const R geq = sol_w<L>(D, i) * dC;
+        a.gout[(long)i * S + c.k] = (T)(gi + D.omega_g * (geq - gi));
+    }
+}
+
+// lambda(T)_i(x) = dL/dC_T(x) for every i, written in the P layout
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_adj_init(AdjArgs<T> a) {
+    constexpr int Q = L::Q;
+    TaskCtx<L, T> c;
+    if (!task_setup<L, T>(a, c) || !c.active) return;
+    const long S = a.S;
+    const double own = a.dldc[c.n];
+#pragma unroll
+    for (int j = 0; j < Q; j++)
+        a.pout[(long)j * S + c.k] = (T)(c.kk[j] >= 0 ? a.dldc[a.nodeof[c.kk[j]]] : own);
+}
+
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
+    using R = double;
+    constexpr int Q = L::Q;
+    TaskCtx<L, T> c;
+    if (!task_setup<L, T>(a, c) || !c.active) return;
+    const DomDev &D = c.D;
+    const long S = a.S;
+    const uint32_t rbc = c.solidnb;
+    // lambda(t+1) at this node: the forward pull with directions reversed
+    R mu[Q];
+#pragma unroll
+    for (int d = 0; d < Q; d++) {
+        const int kd = c.kk[L::opp[d]];
+        mu[d] = (R)(kd >= 0 ? a.pin[(long)d * S + kd] : a.pin[(long)L::opp[d] * S + c.k]);
+    }
+    R m = R(0);
+#pragma unroll
+    for (int i = 0; i < Q; i++) m += sol_w<L>(D, i) * mu[i];
+    const R om = D.omega_g;
+    R nu[Q], out[Q];
+#pragma unroll
+    for (int j = 0; j < Q; j++) {
+        nu[j] = (R(1) - om) * mu[j] + om * m;
+        out[j] = nu[j];
+    }
+    if (rbc) {
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (rbc & (1u << i)) {
+                const int o = L::opp[i];
+                const int l = c.lb + __popc(rbc & ((1u << i) - 1u));
+                const R beta = (R)a.lbeta[l];
+                const bool pulled = D.mech == LBM_PRECOLL && !(rbc & (1u << o));
+                // the forward source value at this step (deviation form)
+                R src;
+                if (pulled)
+                    src = (R)(c.kk[o] >= 0 ? a.gin[(long)o * S + c.kk[o]] : a.gin[(long)i * S + c.k]);
+                else
+                    src = (R)a.gin[(long)o * S + c.k];
+                a.gbeta[l] += nu[i] * (src - sol_w<L>(D, i) * D.ceq_dev);
+                if (pulled) {
+                    out[o] += beta * nu[i];
+                    out[i] = R(0);
+                } else {
+                    out[i] = beta * nu[i];
+                }
+            }
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < Q; j++) a.pout[(long)j * S + c.k] = (T)out[j];
+}
+
+// dL/dk_r per solid interface node from dL/dbeta of its links (direction
+// order): beta = (1 - k)/(1 + k), k = coef * k_r, dbeta/dk_r = -2 coef/(1+k)^2
+template <class L>
+__global__ __launch_bounds__(BLK) void k_adj_grad(const int32_t *__restrict__ sif,
+                                                  const int32_t *__restrict__ soff,
+                                                  const int32_t *__restrict__ slinks,
+                                                  const int32_t *__restrict__ lnode,
+                                                  const uint8_t *__restrict__ ldir,
+                                                  const uint32_t *__restrict__ rmask,
+                                                  const double *__restrict__ kr,
+                                                  const double *__restrict__ nrm,
+                                                  const DomDev *__restrict__ doms,
+                                                  const double *__restrict__ gbeta, long nsif,
+                                                  double *__restrict__ grad) {
+    const long j = (long)blockIdx.x * BLK + threadIdx.x;
+    if (j >= nsif) return;
+    const DomDev D = doms[0];
+    const long s = sif[j];
+    double gsum = 0.0;
+    for (int m = soff[j]; m < soff[j + 1]; m++) {
+        const int l = slinks[m];
+        const int i = ldir[l];
+        const double en = L::ex[i] * nrm[3 * s] + L::ey[i] * nrm[3 * s + 1] + L::ez[i] * nrm[3 * s + 2];
+        double coef;
+        if (D.scheme == LBM_SV) coef = en > 0 ? en / D.cs2s : 0.0;
+        else if (D.scheme == LBM_SPJ) coef = en > 0 ? D.gamma / (D.cs2s * en) : 0.0;
+        else if (D.scheme == LBM_ABB) coef = 0.0;
+        else coef = en > 0 ? D.gamma * en / D.cs2s : 0.0;
+        if (D.mech == LBM_PRECOLL && (rmask[lnode[l]] & (1u << L::opp[i]))) coef /= D.gamma;
+        const double kap = coef * kr[s];
+        gsum += gbeta[l] * (-2.0 * coef / ((1.0 + kap) * (1.0 + kap)));
+    }
+    grad[s] = gsum;
+}
+
+__global__ void k_zero_i32_adj(int32_t *p) { *p = 0; }
+
+__global__ __launch_bounds__(BLK) void k_adj_zero(double *p, long n) {
+    const long i = (long)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) p[i] = 0.0;
+}
+
+// the fluid is at rest when every node's momentum sum e f vanishes (to 1e-12)
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_rest_check(long nf, long S, const T *__restrict__ f,
+                                                    int32_t *flag) {
+    const long k = (long)blockIdx.x * BLK + threadIdx.x;
+    if (k >= nf) return;
+    double j[3] = {0.0, 0.0, 0.0};
+    for (int i = 0; i < L::Q; i++) {
+        const double v = (double)f[(long)i * S + k];
+        j[0] += L::ex[i] * v;
+        j[1] += L::ey[i] * v;
+        j[2] += L::ez[i] * v;
+    }
+    if (fabs(j[0]) > 1e-12 || fabs(j[1]) > 1e-12 || fabs(j[2]) > 1e-12) atomicOr(flag, 1);
+}
+
+// ---------------------------------------------------------------------------
+template <typename T>
+static AdjArgs<T> adj_args(Ctx &c) {
+    AdjArgs<T> a;
+    a.pin = nullptr;
+    a.pout = nullptr;
+    a.gin = nullptr;
+    a.gout = nullptr;
+    a.tasks = c.tasks;
+    a.rows = c.rows;
+    a.doms = c.doms;
+    a.nodeof = c.nodeof;
+    a.lbase = c.lbase;
+    a.lbeta = (const T *)c.lbeta;
+    a.gbeta = c.adj.gbeta;
+    a.dldc = nullptr;
+    a.ntasks = c.n_tasks;
+    a.S = c.S;
+    return a;
+}
+
+template <class L, typename T>
+static hipError_t rest_check_impl(Ctx &c, bool *at_rest) {
+    hipLaunchKernelGGL(k_zero_i32_adj, dim3(1), dim3(1), 0, c.stream, c.iacc + 5);
+    const long nf = c.n_fluid;
+    if (nf > 0)
+        hipLaunchKernelGGL((k_rest_check<L, T>), dim3((nf + BLK - 1) / BLK), dim3(BLK), 0, c.stream,
+                           nf, c.S, (const T *)c.f[c.cur], c.iacc + 5);
+    int32_t flag = 0;
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&flag, c.iacc + 5, 4, hipMemcpyDeviceToHost, c.stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c.stream);
+    *at_rest = flag == 0;
+    return e;
+}
+
+template <class L, typename T>
+static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
+    const AdjState &r = c.adj;
+    const long nb = (c.n_tasks + BLK / 64 - 1) / (BLK / 64);
+    const size_t slot = (size_t)c.Q * c.S;
+    AdjArgs<T> a = adj_args<T>(c);
+    T *P[2] = {(T *)r.p[0], (T *)r.p[1]};
+    const T *ck = (const T *)r.ckpt;
+    T *hist = (T *)r.hist;
+    // dL/dbeta := 0, lambda(T) from dL/dC_T
+    hipLaunchKernelGGL(k_adj_zero, dim3((c.n_links + BLK - 1) / BLK + 1), dim3(BLK), 0, c.stream,
+                       r.gbeta, (long)c.n_links);
+    a.dldc = dldc;
+    a.pout = P[0];
+    if (nb > 0) hipLaunchKernelGGL((k_adj_init<L, T>), dim3(nb), dim3(BLK), 0, c.stream, a);
+    int cur = 0;
+    const int nseg = (int)((r.nsteps + r.ckpt_every - 1) / r.ckpt_every);
+    for (int sgi = nseg - 1; sgi >= 0; sgi--) {
+        const long t0 = (long)sgi * r.ckpt_every;
+        const int len = (int)((r.nsteps - t0) < r.ckpt_every ? (r.nsteps - t0) : r.ckpt_every);
+        // state j of the segment: j = 0 the checkpoint, else hist slot j - 1
+        auto state = [&](int j) -> T * {
+            return j == 0 ? (T *)(ck + (size_t)sgi * slot) : hist + (size_t)(j - 1) * slot;
+        };
+        for (int j = 1; j < len; j++) {
+            a.gin = state(j - 1);
+            a.gout = state(j);
+            if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T>), dim3(nb), dim3(BLK), 0, c.stream, a);
+        }
+        for (int j = len - 1; j >= 0; j--) {
+            a.gin = state(j);
+            a.pin = P[cur];
+            a.pout = P[1 - cur];
+            if (nb > 0) hipLaunchKernelGGL((k_adj_step<L, T>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            cur = 1 - cur;
+        }
+        hipError_t e = hipGetLastError();
+        if (e != hipSuccess) return e;
+    }
+    hipLaunchKernelGGL(k_adj_zero, dim3((c.N + BLK - 1) / BLK), dim3(BLK), 0, c.stream, grad, c.N);
+    if (c.n_sif > 0)
+        hipLaunchKernelGGL((k_adj_grad<L>), dim3((c.n_sif + BLK - 1) / BLK), dim3(BLK), 0, c.stream,
+                           c.sif, c.soff, c.slinks, c.lnode, c.ldir, c.rmask, c.kr, c.nrm, c.doms,
+                           (const double *)r.gbeta, (long)c.n_sif, grad);
+    return hipGetLastError();
+}
+
+hipError_t launch_rest_check(Ctx &c, bool *at_rest) {
+    if (c.Q == 9) return c.fp64 ? rest_check_impl<D2Q9, double>(c, at_rest) : rest_check_impl<D2Q9, float>(c, at_rest);
+    return c.fp64 ? rest_check_impl<D3Q19, double>(c, at_rest) : rest_check_impl<D3Q19, float>(c, at_rest);
+}
+
+hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad) {
+    if (c.Q == 9) return c.fp64 ? adjoint_impl<D2Q9, double>(c, dldc, grad) : adjoint_impl<D2Q9, float>(c, dldc, grad);
+    return c.fp64 ? adjoint_impl<D3Q19, double>(c, dldc, grad) : adjoint_impl<D3Q19, float>(c, dldc, grad);
+}
+
+}  // namespace lbm

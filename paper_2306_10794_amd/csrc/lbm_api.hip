@@ -53,7 +53,7 @@ std::string check_params(const lbm_params &p) {
 
 int64_t default_links(const lbm_params &p) {
     const int64_t N = (int64_t)p.nx * p.ny * p.nz;
-    int64_t m = p.max_links > 0 ? p.max_links : N * (p.fluid_q - 1) / 8;
+    int64_t m = p.max_links > 0 ? p.max_links : N * (p.fluid_q - 1) / 4;
     if (m < 4096) m = 4096;
     if (m > 2147483000LL) m = 2147483000LL;
     return m;
@@ -310,6 +310,8 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
     c->cfg.reserved0 = 0;
     c->gexec = nullptr;
     c->graph_built = 0;
+    c->geom_epoch = 0;
+    c->adj.valid = false;
     *out = (lbm_ctx *)c;
     return LBM_OK;
 }
@@ -451,6 +453,7 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *no
     if (!dev_ptr_ok(phi0)) return bad_ptr(c, "phi0");
     int64_t nl = 0, ns = 0;
     drop_graph(c);
+    c->geom_epoch++;
     hipError_t e = launch_geometry(*c, solid, normals, k_r, phi0, &nl, &ns);
     if (e != hipSuccess) return dev_err(c, e, "geometry preparation");
     if (nl > c->max_links) {
@@ -479,6 +482,7 @@ lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u, con
     hipError_t e = launch_init(*c, rho, u, cc);
     if (e != hipSuccess) return dev_err(c, e, "init");
     c->step = 0;
+    c->adj.valid = false;
     c->have_state = true;
     return LBM_OK;
 }
@@ -625,6 +629,123 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms) {
         ms[0] += a;
         ms[1] += b;
     }
+    return LBM_OK;
+}
+
+static size_t adj_layout(const Ctx *c, int64_t nsteps, int64_t ckpt, AdjState *st, char *base) {
+    const size_t ts = c->fp64 ? 8 : 4;
+    const size_t slot = (size_t)c->Q * (size_t)c->S * ts;
+    const size_t ncp = (size_t)((nsteps + ckpt - 1) / ckpt);
+    size_t off = 0;
+    auto take = [&](size_t n) -> char * {
+        char *p = base ? base + off : nullptr;
+        off += (n + ALIGN - 1) / ALIGN * ALIGN;
+        return p;
+    };
+    char *ck = take(ncp * slot);
+    char *hi = take((size_t)(ckpt - 1) * slot);
+    char *p0 = take(slot), *p1 = take(slot);
+    char *gb = take(sizeof(double) * (size_t)(c->max_links + 1));
+    if (st) {
+        st->ckpt = ck;
+        st->hist = hi;
+        st->p[0] = p0;
+        st->p[1] = p1;
+        st->gbeta = (double *)gb;
+    }
+    return off;
+}
+
+static lbm_status adj_check(Ctx *c, int32_t nsteps, int32_t ckpt) {
+    if (nsteps < 1 || ckpt < 1 || ckpt > nsteps) {
+        c->err = "need 1 <= ckpt_every <= nsteps";
+        return LBM_EINVAL;
+    }
+    if (c->ndom != 1) {
+        c->err = "the adjoint works on single-lattice contexts";
+        return LBM_EINVAL;
+    }
+    if (c->p.inlet_axis >= 0 || c->p.phase_change) {
+        c->err = "the adjoint needs inlet_axis = -1 and phase_change = 0";
+        return LBM_EINVAL;
+    }
+    if (c->p.force[0] != 0.0 || c->p.force[1] != 0.0 || c->p.force[2] != 0.0) {
+        c->err = "the adjoint needs the fluid at rest (no body force)";
+        return LBM_EINVAL;
+    }
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every,
+                                       size_t *bytes) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c || !bytes) return LBM_EINVAL;
+    lbm_status st = adj_check(c, nsteps, ckpt_every);
+    if (st != LBM_OK) return st;
+    *bytes = adj_layout(c, nsteps, ckpt_every, nullptr, nullptr);
+    return LBM_OK;
+}
+
+lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *dev_workspace,
+                      size_t bytes) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    lbm_status st = adj_check(c, nsteps, ckpt_every);
+    if (st != LBM_OK) return st;
+    if (!c->have_state) {
+        c->err = "lbm_record before lbm_init_fields";
+        return LBM_ESTATE;
+    }
+    const size_t need = adj_layout(c, nsteps, ckpt_every, nullptr, nullptr);
+    if (!dev_workspace || bytes < need) {
+        c->err = "adjoint workspace of " + std::to_string(bytes) + " bytes is smaller than the " +
+                 std::to_string(need) + " needed";
+        return LBM_ENOMEM;
+    }
+    if (((uintptr_t)dev_workspace) % ALIGN != 0 || !dev_ptr_ok(dev_workspace)) {
+        c->err = "adjoint workspace must be 256-byte aligned device memory";
+        return LBM_EINVAL;
+    }
+    bool rest = false;
+    hipError_t e = launch_rest_check(*c, &rest);
+    if (e != hipSuccess) return dev_err(c, e, "rest check");
+    if (!rest) {
+        c->err = "the adjoint needs the fluid at rest (some node carries momentum)";
+        return LBM_EINVAL;
+    }
+    c->adj.valid = false;
+    adj_layout(c, nsteps, ckpt_every, &c->adj, (char *)dev_workspace);
+    const size_t slot = (size_t)c->Q * (size_t)c->S * (c->fp64 ? 8 : 4);
+    for (int32_t t = 0; t < nsteps; t += ckpt_every) {
+        e = hipMemcpyAsync((char *)c->adj.ckpt + (size_t)(t / ckpt_every) * slot, c->g[c->cur], slot,
+                           hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return dev_err(c, e, "checkpoint copy");
+        e = run_steps(c, nsteps - t < ckpt_every ? nsteps - t : ckpt_every);
+        if (e != hipSuccess) return dev_err(c, e, "step launch");
+    }
+    c->adj.nsteps = nsteps;
+    c->adj.ckpt_every = ckpt_every;
+    c->adj.end_step = c->step;
+    c->adj.geom_epoch = c->geom_epoch;
+    c->adj.valid = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (!dL_dC || !grad_k) {
+        c->err = "dL_dC and grad_k are required";
+        return LBM_EINVAL;
+    }
+    if (!dev_ptr_ok(dL_dC)) return bad_ptr(c, "dL_dC");
+    if (!dev_ptr_ok(grad_k)) return bad_ptr(c, "grad_k");
+    if (!c->adj.valid || c->adj.end_step != c->step || c->adj.geom_epoch != c->geom_epoch) {
+        c->err = "no recorded run ends at the current state (call lbm_record first)";
+        return LBM_ESTATE;
+    }
+    hipError_t e = launch_adjoint(*c, dL_dC, grad_k);
+    if (e != hipSuccess) return dev_err(c, e, "adjoint");
     return LBM_OK;
 }
 
@@ -793,6 +914,8 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
     const uint8_t *sol_src = (const uint8_t *)(b + phio + 40 * c->N);
     int64_t nl = 0, ns = 0;
     drop_graph(c);
+    c->geom_epoch++;
+    c->adj.valid = false;
     e = launch_geometry(*c, sol_src, nrm_src, kr_src, phi_src, &nl, &ns);
     if (e != hipSuccess) return dev_err(c, e, "load_state geometry");
     if (nl > c->max_links) {

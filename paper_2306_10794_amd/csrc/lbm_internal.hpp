@@ -41,6 +41,16 @@ struct DomHost {
     int64_t links_cap;
 };
 
+// recorded forward run for the adjoint (memory in a caller workspace)
+struct AdjState {
+    bool valid;
+    int64_t nsteps, ckpt_every, end_step, geom_epoch;
+    void *ckpt;              // [ceil(nsteps/ckpt_every)][Q][S] solute states
+    void *hist;              // [ckpt_every - 1][Q][S] recomputed states
+    void *p[2];              // [Q][S] adjoint arrays
+    double *gbeta;           // [max_links] dL/dbeta
+};
+
 struct Ctx {
     lbm_params p;            // parameters of domain 0 (precision, lattice)
     lbm_launch_config cfg;   // tile / schedule of the step launches
@@ -91,6 +101,8 @@ struct Ctx {
     // launch configuration are unchanged; replayed from buffer 0
     hipGraphExec_t gexec;
     int graph_built;         // steps in gexec, 0 = none
+    int64_t geom_epoch;      // counts geometry changes
+    AdjState adj;
     std::string err;
 };
 
@@ -106,6 +118,8 @@ hipError_t launch_fields(Ctx &c, double *rho, double *u, double *cc, double *phi
 hipError_t launch_pops(Ctx &c, double *f, double *g);
 hipError_t launch_exchange(Ctx &c, double *q);
 hipError_t launch_diag(Ctx &c, double *sums, int32_t *nan_flag);
+hipError_t launch_rest_check(Ctx &c, bool *at_rest);
+hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad);
 hipError_t scan_excl(Ctx &c, const int32_t *in, int32_t *out, long n, int32_t *total_dev);
 
 }  // namespace lbm

@@ -8,10 +8,12 @@
 //                that enters from a solid node, advection-diffusion BGK with
 //                the rest-fraction weights; writes the exchange q of each
 //                reactive link and credits precipitation (q < 0) to the fluid
-//                node's phi.  The boundary condition is applied branch-free to
-//                every direction (beta = 1 and the pulled value as source on a
-//                non-reactive direction leave it unchanged), so interface nodes
-//                do not diverge the bulk wavefronts.
+//                node's phi.  Each reactive direction is a uniform-condition
+//                block; its beta is fetched into LDS ahead of the loads.
+//
+// The neighbour classification is written out here rather than taken from
+// classify() (lbm_task.hpp, used by the adjoint kernels): the compiler
+// schedules the inlined helper differently and the step ran 1.5x slower.
 //   k_phi_solid  per solid interface node: dissolution (q > 0) charged to its
 //                phi in link order, and the step's total wall exchange.
 //
@@ -21,31 +23,9 @@
 // HBM traffic, and FP32 arithmetic on rounded weights would leak mass and
 // momentum by a fixed relative amount at every collision.
 #include "lbm_internal.hpp"
+#include "lbm_task.hpp"
 
 namespace lbm {
-
-// Compact index of the fluid site (xx, yy, zz) (fluid view of the box), -1 if
-// that site is solid, -2 if it is outside a non-periodic face.
-__device__ __forceinline__ int nb_compact(const RowWord *__restrict__ rows, int W, const Box &b,
-                                          int xx, int yy, int zz) {
-    int fc;
-    if (!wrap_site(b, xx, yy, zz, &fc)) return -2;
-    const RowWord w = rows[(long)(yy + b.ny * zz) * W + (xx >> 6)];
-    const unsigned long long bit = 1ull << (xx & 63);
-    if (!(w.mask & bit)) return -1;
-    return w.pb + __popcll(w.mask & (bit - 1ull));
-}
-
-// Row slots: the rows a task pulls from are (y + dy, z + dz) with
-// (dy, dz) = (-ey, -ez); slot index (dy + 1) in 2D, (dy + 1) + 3 (dz + 1) in 3D.
-template <class L>
-__device__ constexpr int slot_of(int i) {
-    return L::DIM == 2 ? 1 - L::ey[i] : (1 - L::ey[i]) + 3 * (1 - L::ez[i]);
-}
-template <class L>
-constexpr int n_slots() {
-    return L::DIM == 2 ? 3 : 9;
-}
 
 // WV wavefronts (tasks) per workgroup; remap != 0 keeps runs of consecutive
 // tiles on one XCD

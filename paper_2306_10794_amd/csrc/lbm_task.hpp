@@ -1,0 +1,121 @@
+// lbm_task.hpp -- neighbour classification of one task (up to 64 consecutive
+// fluid nodes of one x-row, one per lane), shared by the step kernels and the
+// adjoint kernels.
+#pragma once
+
+#include "lbm_device.hpp"
+
+namespace lbm {
+
+// Compact index of the fluid site (xx, yy, zz) (fluid view of the box), -1 if
+// that site is solid, -2 if it is outside a non-periodic face.
+__device__ __forceinline__ int nb_compact(const RowWord *__restrict__ rows, int W, const Box &b,
+                                          int xx, int yy, int zz) {
+    int fc;
+    if (!wrap_site(b, xx, yy, zz, &fc)) return -2;
+    const RowWord w = rows[(long)(yy + b.ny * zz) * W + (xx >> 6)];
+    const unsigned long long bit = 1ull << (xx & 63);
+    if (!(w.mask & bit)) return -1;
+    return w.pb + __popcll(w.mask & (bit - 1ull));
+}
+
+// Row slots: the rows a task pulls from are (y + dy, z + dz) with
+// (dy, dz) = (-ey, -ez); slot index (dy + 1) in 2D, (dy + 1) + 3 (dz + 1) in 3D.
+template <class L>
+__device__ constexpr int slot_of(int i) {
+    return L::DIM == 2 ? 1 - L::ey[i] : (1 - L::ey[i]) + 3 * (1 - L::ez[i]);
+}
+template <class L>
+constexpr int n_slots() {
+    return L::DIM == 2 ? 3 : 9;
+}
+
+// The row words of every row a task pulls from: lane j holds word (j % W) of
+// slot (j / W); other lanes read them with cross-lane shuffles.
+struct RowSlots {
+    unsigned long long wm;
+    int wpb;
+    bool fit;     // all slots fit the 64 lanes
+};
+
+template <class L>
+__device__ __forceinline__ RowSlots load_row_slots(const RowWord *__restrict__ rows, const Box &b,
+                                                   int W, int lane, int y, int z) {
+    constexpr int NS = n_slots<L>();
+    RowSlots rs;
+    rs.fit = NS * W <= 64;
+    rs.wm = 0ull;
+    rs.wpb = 0;
+    if (rs.fit && lane < NS * W) {
+        const int sl = lane / W, w = lane - sl * W;
+        int yy = y + (sl % 3) - 1, zz = z + (sl / 3) - 1, xx = 0, fc;
+        if (L::DIM == 2) zz = z;
+        if (wrap_site(b, xx, yy, zz, &fc)) {
+            const RowWord rw = rows[(long)(yy + b.ny * zz) * W + w];
+            rs.wm = rw.mask;
+            rs.wpb = rw.pb;
+        }
+    }
+    return rs;
+}
+
+// Upstream neighbour x - e_i of node (x, y, z) (compact index k) for every i:
+// kk[i] = its compact index, -1 if solid, -2 if outside a non-periodic face
+// (fluid view).  solidnb: bits of solid upstream neighbours; cross / cross_hi:
+// bits whose upstream site lies beyond the low or high face of the inlet axis
+// (cross_hi: the high one).  Every lane of the wavefront must call it (the
+// shuffles read zero from inactive lanes).
+template <class L>
+__device__ __forceinline__ void classify(const RowWord *__restrict__ rows, const Box &b, int W,
+                                         const RowSlots &rs, int x, int y, int z, int k, int *kk,
+                                         uint32_t &solidnb, uint32_t &cross, uint32_t &cross_hi) {
+    const int ax = b.inlet_axis;
+    solidnb = 0u;
+    cross = 0u;
+    cross_hi = 0u;
+#pragma unroll
+    for (int i = 0; i < L::Q; i++) {
+        const int xx = x - L::ex[i], yy = y - L::ey[i], zz = z - L::ez[i];
+        if (i == 0) {
+            kk[i] = k;
+        } else {
+            // x may wrap within the row; a wrap that shifts the row (tilted
+            // torus) or any row that does not fit the preloaded slots goes
+            // through the row words in memory
+            int xw = xx;
+            bool out = false, shifted = false;
+            if (xw < 0 || xw >= b.nx) {
+                if (!b.per[0]) out = true;
+                else {
+                    shifted = b.shift != 0;
+                    xw = xw < 0 ? xw + b.nx : xw - b.nx;
+                }
+            }
+            if ((yy < 0 || yy >= b.ny) && !b.per[1]) out = true;
+            if ((zz < 0 || zz >= b.nz) && !b.per[2]) out = true;
+            const int xs = min(max(xw, 0), b.nx - 1);
+            const int src = rs.fit ? slot_of<L>(i) * W + (xs >> 6) : 0;
+            const unsigned lo = __shfl((unsigned)(rs.wm & 0xffffffffull), src, 64);
+            const unsigned hi = __shfl((unsigned)(rs.wm >> 32), src, 64);
+            const int pb = __shfl(rs.wpb, src, 64);
+            if (out) {
+                kk[i] = -2;
+            } else if (!rs.fit || shifted) {
+                kk[i] = nb_compact(rows, W, b, xx, yy, zz);
+            } else {
+                const unsigned long long m = ((unsigned long long)hi << 32) | lo;
+                const unsigned long long bit = 1ull << (xs & 63);
+                kk[i] = (m & bit) ? pb + __popcll(m & (bit - 1ull)) : -1;
+            }
+        }
+        if (kk[i] == -1) solidnb |= 1u << i;
+        if (ax >= 0) {
+            const int c = ax == 0 ? xx : (ax == 1 ? yy : zz);
+            const int nn = ax == 0 ? b.nx : (ax == 1 ? b.ny : b.nz);
+            if (c < 0) cross |= 1u << i;
+            if (c >= nn) { cross |= 1u << i; cross_hi |= 1u << i; }
+        }
+    }
+}
+
+}  // namespace lbm

@@ -94,6 +94,27 @@ class Simulation:
     def diag(self) -> dict:
         return L.lbm_get_diag(self.ctx)
 
+    def set_rates(self, k_r):
+        """New per-node rate constants (geometry prep again; the state must be
+        initialised afterwards)."""
+        self._geom["k_r"] = _dev(k_r, torch.float64, self.device)
+        L.lbm_set_geometry(self.ctx, **self._geom)
+
+    def record(self, nsteps: int, ckpt_every: int):
+        """Run nsteps steps keeping the checkpoints the adjoint needs."""
+        n = L.lbm_adjoint_workspace_bytes(self.ctx, nsteps, ckpt_every)
+        if getattr(self, "_adj_ws", None) is None or self._adj_ws.numel() < n:
+            self._adj_ws = None
+            self._adj_ws = torch.empty(n, dtype=torch.uint8, device=self.device)
+        L.lbm_record(self.ctx, nsteps, ckpt_every, self._adj_ws, self._adj_ws.numel())
+
+    def adjoint(self, dL_dC) -> torch.Tensor:
+        """dL/dk_r [N] of the recorded run for dL/dC_T = dL_dC [N]."""
+        dl = _dev(dL_dC, torch.float64, self.device)
+        grad = torch.empty(self.N, dtype=torch.float64, device=self.device)
+        L.lbm_adjoint(self.ctx, dl, grad)
+        return grad
+
     def save_state(self) -> torch.Tensor:
         n = L.lbm_state_bytes(self.ctx)
         buf = torch.empty(n, dtype=torch.uint8, device=self.device)
@@ -113,6 +134,30 @@ class Simulation:
             self.close()
         except Exception:
             pass
+
+
+class RateToConcentration(torch.autograd.Function):
+    """C_T = final concentrations [N] of an nsteps run from the initial
+    concentration c0, as a function of the per-node rate constants k_r [N];
+    the backward pass is the library's hand-written adjoint (checkpoints every
+    ckpt_every steps)."""
+
+    @staticmethod
+    def forward(ctx, k_r, sim, nsteps, ckpt_every, c0):
+        sim.set_rates(k_r.detach())
+        sim.init_fields(None, None, c0)
+        sim.record(int(nsteps), int(ckpt_every))
+        ctx.sim = sim
+        return sim.fields()["c"]
+
+    @staticmethod
+    def backward(ctx, grad_c):
+        return ctx.sim.adjoint(grad_c.contiguous()), None, None, None, None
+
+
+def final_concentration(k_r, sim, nsteps: int, ckpt_every: int, c0=None):
+    """Differentiable C_T(k_r) (see RateToConcentration)."""
+    return RateToConcentration.apply(k_r, sim, nsteps, ckpt_every, c0)
 
 
 class BatchSimulation:

@@ -1,0 +1,177 @@
+"""The library's adjoint (dL/dk_r through the C ABI) against the FP64 oracle's
+adjoint, against central differences of the GPU forward run, and through
+torch.autograd.
+
+Tolerances: FP64 gradients agree with the oracle to 1e-11 of the largest
+component (summation order differs); FP32 deviation storage to 1e-4 (the
+adjoint populations are stored in FP32 as well).  Central differences
+(h = 1e-3 k) carry an O(h^2) truncation error: 1e-5 of the largest
+component.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from lbm_inputs import Case, configs, geometry, MECH_PRE, MECH_POST, SCHEME_SNEW, SCHEME_SV, SCHEME_SPJ
+
+from parity import log
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+
+
+def _spheres32(seed=5):
+    # the rate-recovery workload at 32^3 with radii 2..4
+    return configs.rate_recovery(n=32, seed=seed, r_min=2.0, r_max=4.0, steps=0)
+
+
+def _disks(mech, scheme):
+    solid, normals, _ = geometry.disk_medium(70, 40, 0.65, 3.0, 7.0, 13)
+    k = configs.lognormal_rate_field(solid, 77, mu=math.log(2e-2), sigma=0.5)
+    return Case(name="adj_disks_gpu", dim=2, nx=70, ny=40, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=0.8, tau_ad=0.7, j0=0.4, c_eq=1.0, k_r=2e-2, k_r_field=k, v_m=0.0,
+                periodic=(1, 1, 1), c0=0.2, mechanics=mech, scheme=scheme)
+
+
+def _target(case, seed=3):
+    rng = np.random.default_rng(seed)
+    return np.where(case.solid_flat() == 0, rng.uniform(0.0, 0.6, case.n), 0.0)
+
+
+def _gpu_grad(case, precision, steps, ckpt, target):
+    import torch
+    from paper_2306_10794_amd import Simulation
+    sim = Simulation(case, precision=precision)
+    sim.record(steps, ckpt)
+    c = sim.fields()["c"]
+    fl = torch.as_tensor(case.solid_flat() == 0, device=c.device)
+    dl = torch.where(fl, 2.0 * (c - torch.as_tensor(target, device=c.device)), 0.0)
+    g = sim.adjoint(dl)
+    torch.cuda.synchronize()
+    out = g.cpu().numpy(), float(((c - torch.as_tensor(target, device=c.device))[fl] ** 2).sum())
+    sim.close()
+    return out
+
+
+def _oracle_grad(case, steps, target):
+    from oracle import Oracle
+    o = Oracle(case)
+    o2 = Oracle(case)
+    o2.step(steps)
+    c = o2.fields()["c"]
+    fl = case.solid_flat() == 0
+    grad, _ = o.adjoint(steps, np.where(fl, 2.0 * (c - target), 0.0))
+    return grad
+
+
+@pytest.mark.parametrize("precision,name", [(FP64, "spheres32"), (FP32, "spheres32"),
+                                            (FP64, "disks R2 S.V."), (FP64, "disks R1 S.P.J."),
+                                            (FP32, "disks R1 S.New")])
+def test_adjoint_matches_oracle(precision, name):
+    case = {"spheres32": lambda: _spheres32(),
+            "disks R2 S.V.": lambda: _disks(MECH_POST, SCHEME_SV),
+            "disks R1 S.P.J.": lambda: _disks(MECH_PRE, SCHEME_SPJ),
+            "disks R1 S.New": lambda: _disks(MECH_PRE, SCHEME_SNEW)}[name]()
+    steps, ckpt = 100, 30     # segments 30, 30, 30, 10
+    target = _target(case)
+    log(f"[adjoint] {name} precision={precision} shape=({case.nx},{case.ny},{case.nz}) "
+        f"steps={steps} ckpt={ckpt}")
+    g, _ = _gpu_grad(case, precision, steps, ckpt, target)
+    go = _oracle_grad(case, steps, target)
+    scale = np.abs(go).max()
+    err = np.abs(g - go).max() / scale
+    log(f"[adjoint] max |grad| {scale:.3e}, rel err {err:.3e}, nonzero {(go != 0).sum()}")
+    assert scale > 0
+    assert np.array_equal(g != 0, go != 0) or precision == FP32
+    assert err <= (1e-11 if precision == FP64 else 1e-4)
+
+
+def test_adjoint_matches_central_differences_fp64():
+    import torch
+    from paper_2306_10794_amd import Simulation
+    case = _spheres32(seed=6)
+    steps, ckpt = 80, 20
+    target = _target(case, seed=9)
+    g, _ = _gpu_grad(case, FP64, steps, ckpt, target)
+    rng = np.random.default_rng(55)
+    cand = np.flatnonzero(np.abs(g) > 1e-3 * np.abs(g).max())
+    nodes = rng.choice(cand, size=16, replace=False)
+    sim = Simulation(case, precision=FP64)
+    k0 = case.k_r_field.copy()
+    fl = case.solid_flat() == 0
+
+    def loss(k):
+        sim.set_rates(k)
+        sim.init_fields(None, None, case.c_flat())
+        sim.step(steps)
+        c = sim.fields()["c"].cpu().numpy()
+        return float(((c - target)[fl] ** 2).sum())
+
+    worst = 0.0
+    for s in nodes:
+        h = 1e-3 * k0[s]
+        kp, km = k0.copy(), k0.copy()
+        kp[s] += h
+        km[s] -= h
+        fd = (loss(kp) - loss(km)) / (2 * h)
+        worst = max(worst, abs(fd - g[s]) / np.abs(g).max())
+    sim.close()
+    log(f"[adjoint] central differences on 16 nodes: worst rel err {worst:.3e}")
+    assert worst <= 1e-5
+
+
+def test_autograd_function_gives_the_adjoint():
+    import torch
+    from paper_2306_10794_amd import Simulation, final_concentration
+    case = _disks(MECH_PRE, SCHEME_SNEW)
+    target = torch.as_tensor(_target(case), device="cuda")
+    fl = torch.as_tensor(case.solid_flat() == 0, device="cuda")
+    sim = Simulation(case, precision=FP64)
+    k = torch.as_tensor(case.k_r_field, device="cuda").requires_grad_(True)
+    c = final_concentration(k, sim, 60, 25, case.c_flat())
+    loss = ((c - target)[fl] ** 2).sum()
+    loss.backward()
+    g_direct, _ = _gpu_grad(case, FP64, 60, 25, target.cpu().numpy())
+    np.testing.assert_allclose(k.grad.cpu().numpy(), g_direct, rtol=0, atol=1e-14 * np.abs(g_direct).max())
+    # a directional derivative of the same loss
+    d = torch.as_tensor(np.random.default_rng(4).normal(size=case.n) * case.solid_flat(),
+                        device="cuda") * k.detach()
+    h = 1e-4
+
+    def L(kk):
+        with torch.no_grad():
+            cc = final_concentration(kk, sim, 60, 25, case.c_flat())
+            return float(((cc - target)[fl] ** 2).sum())
+
+    fd = (L(k.detach() + h * d) - L(k.detach() - h * d)) / (2 * h)
+    ad = float((k.grad * d).sum())
+    sim.close()
+    assert abs(fd - ad) <= 1e-6 * abs(ad)
+
+
+def test_adjoint_state_errors():
+    import torch
+    from paper_2306_10794_amd import (Simulation, LbmError, LBM_ESTATE, LBM_EINVAL,
+                                      lbm_adjoint_workspace_bytes)
+    case = _disks(MECH_PRE, SCHEME_SNEW)
+    sim = Simulation(case, precision=FP32)
+    z = torch.zeros(case.n, dtype=torch.float64, device="cuda")
+    with pytest.raises(LbmError) as ei:
+        sim.adjoint(z)                       # nothing recorded
+    assert ei.value.status == LBM_ESTATE
+    sim.record(10, 5)
+    sim.step(1)
+    with pytest.raises(LbmError) as ei:
+        sim.adjoint(z)                       # state moved past the recording
+    assert ei.value.status == LBM_ESTATE
+    with pytest.raises(LbmError) as ei:
+        lbm_adjoint_workspace_bytes(sim.ctx, 10, 11)
+    assert ei.value.status == LBM_EINVAL
+    sim.close()
+    flow = Simulation(case.replace(force=(1e-5, 0.0, 0.0)), precision=FP32)
+    with pytest.raises(LbmError) as ei:
+        flow.record(10, 5)
+    assert ei.value.status == LBM_EINVAL
+    flow.close()
