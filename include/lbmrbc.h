@@ -94,7 +94,9 @@ typedef struct {
                                  non-periodic with a fixed-concentration inlet at
                                  coordinate 0 and a zero-gradient outlet at n-1    */
     double c_in;              /* inlet concentration                                */
-    int32_t phase_change;     /* 1: apply the phi thresholds after each step       */
+    int32_t phase_change;     /* 1: apply the phi thresholds after each step
+                                 (Sec. 2.4; single-lattice contexts; lbm_step
+                                 then synchronises once per step)            */
     int32_t reserved0;
     int64_t max_links;        /* capacity for reactive links; <= 0 selects
                                  max(4096, N*(Q-1)/4)                              */
@@ -241,7 +243,8 @@ lbm_status lbm_get_fields(lbm_ctx *ctx, double *rho, double *u, double *c, doubl
 lbm_status lbm_get_pops(lbm_ctx *ctx, double *f, double *g);
 
 /* Mass that crossed each reactive link in the last step, scattered to a dense
- * [N][Q] FP64 array (zero where there is no link). */
+ * [N][Q] FP64 array (zero where there is no link; all zero after a step
+ * whose phase change rebuilt the link list). */
 lbm_status lbm_get_exchange(lbm_ctx *ctx, double *q);
 
 /* FP64 reductions of the current state (host struct; synchronises).

@@ -9,7 +9,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 OUT = os.path.join(HERE, "liblbmrbc.so")
 BUILD = os.path.join(os.path.dirname(HERE), "_build")
-SOURCES = ["lbm_step.hip", "lbm_geometry.hip", "lbm_io.hip", "lbm_adjoint.hip", "lbm_api.hip"]
+SOURCES = ["lbm_step.hip", "lbm_geometry.hip", "lbm_io.hip", "lbm_adjoint.hip", "lbm_events.hip", "lbm_api.hip"]
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = ["--offload-arch=gfx950", "-O3", "-std=c++17", "-fPIC",
          # packed FP32 instructions are kept out of the generated code

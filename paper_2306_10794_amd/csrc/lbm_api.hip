@@ -104,7 +104,17 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *bsum = take(4 * ((N + 4095) / 4096 + 64));
     char *dpart = take(16 * ((N + 255) / 256 + 1));
     char *dacc = take(8 * 64), *iacc = take(4 * 64);
+    // phase change (single lattice): old compact map, candidates, records
+    const bool pc = nd == 1 && p[0].phase_change != 0;
+    const long ev_cap = pc ? (N < 65536 ? N : 65536) : 0;
+    char *kof_old = take(pc ? 4 * N : 0), *evlist = take(4 * ev_cap);
+    char *evrec = take(event_record_bytes() * ev_cap);
     if (c && base) {
+        c->kof_old = (int32_t *)kof_old;
+        c->evlist = (int32_t *)evlist;
+        c->evrec = evrec;
+        c->ev_cap = ev_cap;
+        c->ev_capacity = false;
         c->N = N;
         c->S = S;
         c->R = R;
@@ -212,6 +222,7 @@ static DomDev dom_record(const DomHost &h, bool fp64) {
     D.ceq_dev = p.c_eq - D.c_ref;
     D.c_in = p.inlet_axis >= 0 ? p.c_in : 0.0;
     D.vma = p.v_m * p.a_m;
+    D.v_m = p.v_m;
     D.kr0 = p.k_r;
     return D;
 }
@@ -224,6 +235,7 @@ static std::string check_batch(const lbm_params *p, int n) {
         if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].precision != p[0].precision)
             return "all domains of a batch need the same dim, lattice and precision";
         if (p[d].phase_change != 0 && n > 1) return "phase_change is not supported in a batch";
+        if (p[d].phase_change != 0 && p[d].phase_change != 1) return "phase_change must be 0 or 1";
     }
     double N = 0;
     for (int d = 0; d < n; d++) N += (double)p[d].nx * p[d].ny * p[d].nz;
@@ -350,8 +362,52 @@ static hipError_t build_graph(Ctx *c, int n) {
     return e;
 }
 
+// Phase change after a step: event pass, then (if anything changed) the
+// geometry rebuilt in place and the populations moved to the new layout.
+static hipError_t phase_change_pass(Ctx *c, bool *capacity) {
+    int64_t nev = 0;
+    bool ovf = false;
+    hipError_t e = launch_events(*c, &nev, &ovf);
+    if (e != hipSuccess) return e;
+    if (ovf) *capacity = true;
+    if (nev == 0) return hipSuccess;
+    drop_graph(c);
+    c->geom_epoch++;
+    c->adj.valid = false;
+    int64_t nl = 0, ns = 0;
+    e = launch_geometry(*c, c->solid, c->nrm, c->kr, c->phi, &nl, &ns);
+    if (e != hipSuccess) return e;
+    if (nl > c->max_links) {
+        *capacity = true;
+        c->have_geom = c->have_state = false;
+        return hipSuccess;
+    }
+    c->n_links = nl;
+    c->n_sif = ns;
+    e = launch_relayout(*c);
+    c->n_events += nev;
+    return e;
+}
+
 static hipError_t run_steps(Ctx *c, int32_t nsteps) {
     int32_t t = 0;
+    if (c->p.phase_change) {
+        // events need a decision on the host after every step (no graphs)
+        for (; t < nsteps; t++) {
+            hipError_t e = launch_step(*c);
+            if (e != hipSuccess) return e;
+            c->step++;
+            bool cap = false;
+            e = phase_change_pass(c, &cap);
+            if (e != hipSuccess) return e;
+            if (cap) {
+                c->err = "phase change exceeded a capacity (events per step or reactive links)";
+                c->ev_capacity = true;
+                return hipErrorOutOfMemory;
+            }
+        }
+        return hipSuccess;
+    }
     const int gs = (c->cfg.graph_steps + 1) & ~1;
     if (gs > 0 && nsteps >= gs) {
         if (c->cur != 0) {   // the graph starts from buffer 0
@@ -443,10 +499,6 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *no
         c->err = "solid mask is required";
         return LBM_EINVAL;
     }
-    if (c->p.phase_change) {
-        c->err = "phase_change is not supported by this build";
-        return LBM_EINVAL;
-    }
     if (!dev_ptr_ok(solid)) return bad_ptr(c, "solid");
     if (!dev_ptr_ok(normals)) return bad_ptr(c, "normals");
     if (!dev_ptr_ok(k_r)) return bad_ptr(c, "k_r");
@@ -499,6 +551,10 @@ lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps) {
         return LBM_ESTATE;
     }
     hipError_t e = run_steps(c, nsteps);
+    if (c->ev_capacity) {
+        c->ev_capacity = false;
+        return LBM_ECAPACITY;
+    }
     if (e != hipSuccess) return dev_err(c, e, "step launch");
     return LBM_OK;
 }
@@ -628,6 +684,15 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms) {
         if (e != hipSuccess) return dev_err(c, e, "event timing");
         ms[0] += a;
         ms[1] += b;
+        if (c->p.phase_change) {
+            bool cap = false;
+            e = phase_change_pass(c, &cap);
+            if (e != hipSuccess) return dev_err(c, e, "phase change");
+            if (cap) {
+                c->err = "phase change exceeded a capacity (events per step or reactive links)";
+                return LBM_ECAPACITY;
+            }
+        }
     }
     return LBM_OK;
 }

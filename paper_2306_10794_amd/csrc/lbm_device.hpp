@@ -96,6 +96,7 @@ struct DomDev {
     double ceq_dev;            // C_eq - C_ref
     double c_in;
     double vma;                // V_m a_m
+    double v_m;                // molar volume (phase change)
     double kr0;                // uniform rate constant
 };
 

@@ -1,0 +1,405 @@
+// lbm_events.hip -- phase change after a step (Sec. 2.4): a solid node whose
+// solid fraction has fallen to 0 becomes fluid, a fluid node whose solid
+// fraction has reached 1 becomes solid, and the geometry is rebuilt.
+//
+// Rules (the paper states them in words; the reading taken): a dissolving
+// solid node (phi <= 0, at least one fluid neighbour) becomes fluid with C =
+// mean C and rho = mean rho of its fluid neighbours and equilibrium
+// populations at rest, and V_m C - phi is taken from the solid fraction of its
+// solid neighbours in proportion to their rate constants (equal shares if all
+// are 0; kept by the node itself if it has none); a precipitating fluid node
+// (phi >= 1) adds V_m C to phi, passes phi - 1 in equal shares to its fluid
+// neighbours (phi = 1) and drops its populations.  Both keep solute plus solid
+// mass.  Events are taken in node order: a node pushed over its threshold by
+// an earlier event of the same pass is taken in that pass if its index is
+// larger, else at the next step.  Wall normals of solid nodes within two sites
+// of a change are recomputed from the solid indicator.
+//
+// On the GPU: a scan over all nodes marks candidates; one wavefront takes
+// them in node order (lanes gather the neighbours' moments, lane 0 applies
+// the rule and keeps a sorted list of nodes that later events push over a
+// threshold); then the wall normals near the changes are refreshed, the
+// geometry (row words, tasks, links) is rebuilt in place and the populations
+// are moved into the new compact layout.
+#include "lbm_internal.hpp"
+
+namespace lbm {
+
+constexpr int EV_PENDING = 2048;  // nodes pushed over a threshold within one pass
+
+struct EvRec {
+    int64_t node;
+    int32_t type;      // 0 dissolution, 1 precipitation
+    int32_t pad;
+    double C, rho;     // dissolution: the new node's concentration and density
+};
+
+template <class L>
+__device__ __forceinline__ bool has_fluid_nb(const DomDev &D, long n, const uint8_t *solid) {
+    int X, Y, Z;
+    coords(D.box, n, &X, &Y, &Z);
+    for (int i = 1; i < L::Q; i++) {
+        int fc;
+        const long y = site(D.box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], true, &fc);
+        if (y >= 0 && !solid[y]) return true;
+    }
+    return false;
+}
+
+// candidates: solid with phi <= 0 and a fluid neighbour, fluid with phi >= 1
+template <class L>
+__global__ __launch_bounds__(BLK) void k_event_scan(const DomDev *doms, long N, const uint8_t *solid,
+                                                    const double *phi, int32_t *cand, int32_t *any) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    int c = 0;
+    if (solid[n]) c = phi[n] <= 0.0 && has_fluid_nb<L>(doms[0], n, solid);
+    else c = phi[n] >= 1.0;
+    cand[n] = c;
+    if (c) atomicOr(any, 1);
+}
+
+__global__ __launch_bounds__(BLK) void k_event_list(long N, const int32_t *cand, const int32_t *pos,
+                                                    int32_t *list, long cap) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N || !cand[n]) return;
+    const long j = pos[n];
+    if (j < cap) list[j] = (int32_t)n;
+}
+
+__global__ __launch_bounds__(BLK) void k_copy_i32(const int32_t *src, int32_t *dst, long n) {
+    const long i = (long)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) dst[i] = src[i];
+}
+
+// C and rho of the fluid node at compact index ko of the state before this
+// pass (FP64 sums in direction order)
+template <class L, typename T>
+__device__ __forceinline__ void pop_moments(const DomDev &D, int ko, const T *f, const T *g, long S,
+                                            double *C, double *rho) {
+    double c = 0.0, r = 0.0;
+    for (int i = 0; i < L::Q; i++) {
+        r += (double)f[(long)i * S + ko] + L::w[i] * D.rho0;
+        c += (double)g[(long)i * S + ko] + sol_w<L>(D, i) * D.c_ref;
+    }
+    *C = c;
+    *rho = r;
+}
+
+// moments of a node that became fluid earlier in this pass: equilibrium at
+// rest of its record
+template <class L>
+__device__ __forceinline__ void rec_moments(const DomDev &D, const EvRec &e, double *C, double *rho) {
+    double c = 0.0, r = 0.0;
+    for (int i = 0; i < L::Q; i++) {
+        r += L::w[i] * e.rho;
+        c += sol_w<L>(D, i) * e.C;
+    }
+    *C = c;
+    *rho = r;
+}
+
+// sorted insert into the pending list (lane 0 only); false when full
+__device__ __forceinline__ bool pend_push(int32_t *pend, int &np, int32_t v) {
+    for (int j = 0; j < np; j++)
+        if (pend[j] == v) return true;
+    if (np >= EV_PENDING) return false;
+    int j = np++;
+    while (j > 0 && pend[j - 1] > v) {
+        pend[j] = pend[j - 1];
+        j--;
+    }
+    pend[j] = v;
+    return true;
+}
+
+// One wavefront.  Lanes 1..Q-1 read the moments of the neighbour along their
+// direction from the populations (data no event of the pass changes); lane 0
+// reads and writes everything an event changes (solid, phi, kof_old, the
+// records), so it always sees its own earlier writes.  out[0] = events,
+// out[1] = 1 if the records or the pending list overflowed (the pass stops).
+template <class L, typename T>
+__global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t *list, long nlist,
+                                               uint8_t *solid, double *phi, const double *kr,
+                                               const int32_t *kof, int32_t *kof_old, const T *f,
+                                               const T *g, long S, EvRec *rec, long cap,
+                                               int32_t *out) {
+    __shared__ int32_t pend[EV_PENDING];
+    __shared__ int np_s, ne_s, ovf_s;
+    __shared__ long cur_s;
+    const int lane = threadIdx.x;
+    const DomDev D = doms[0];
+    if (lane == 0) { np_s = 0; ne_s = 0; ovf_s = 0; }
+    __syncthreads();
+    long pos = 0;
+    while (true) {
+        if (lane == 0) {
+            // next node: the smaller of the list head and the pending head
+            long nxt = -1;
+            const long a = pos < nlist ? (long)list[pos] : -1;
+            const long b = np_s > 0 ? (long)pend[0] : -1;
+            bool pop = false;
+            if (a >= 0 && (b < 0 || a <= b)) {
+                nxt = a;
+                pos++;
+                pop = b == a;   // the same node in both lists
+            } else if (b >= 0) {
+                nxt = b;
+                pop = true;
+            }
+            if (pop) {
+                for (int j = 1; j < np_s; j++) pend[j - 1] = pend[j];
+                np_s--;
+            }
+            if (ovf_s) nxt = -1;
+            cur_s = nxt;
+        }
+        __syncthreads();
+        const long n = cur_s;
+        __syncthreads();
+        if (n < 0) break;
+        int X, Y, Z;
+        coords(D.box, n, &X, &Y, &Z);
+        long y = -1;
+        double Cy = 0.0, Ry = 0.0;
+        if (lane >= 1 && lane < L::Q) {
+            int fc;
+            y = site(D.box, X, Y, Z, L::ex[lane], L::ey[lane], L::ez[lane], true, &fc);
+            if (y >= 0 && kof[y] >= 0) pop_moments<L, T>(D, kof[y], f, g, S, &Cy, &Ry);
+        }
+        long ys[L::Q];
+        double cs[L::Q], rs[L::Q];
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+            ys[i] = __shfl(y, i, 64);
+            cs[i] = __shfl(Cy, i, 64);
+            rs[i] = __shfl(Ry, i, 64);
+        }
+        if (lane == 0) {
+            // moments of neighbours that became fluid earlier in this pass
+            for (int i = 1; i < L::Q; i++)
+                if (ys[i] >= 0 && kof_old[ys[i]] <= -2)
+                    rec_moments<L>(D, rec[-2 - kof_old[ys[i]]], &cs[i], &rs[i]);
+            const bool sol_n = solid[n] != 0;
+            if (sol_n && phi[n] <= 0.0) {
+                double csum = 0.0, rsum = 0.0, wsum = 0.0;
+                int nf = 0, nn = 0;
+                for (int i = 1; i < L::Q; i++)
+                    if (ys[i] >= 0 && !solid[ys[i]]) { csum += cs[i]; rsum += rs[i]; nf++; }
+                if (nf > 0) {
+                    const double Cs = csum / nf, Rs = rsum / nf;
+                    const double need = D.v_m * Cs - phi[n];
+                    for (int i = 1; i < L::Q; i++)
+                        if (ys[i] >= 0 && solid[ys[i]]) { wsum += kr[ys[i]]; nn++; }
+                    const int e = ne_s;
+                    if (e >= cap) {
+                        ovf_s = 1;
+                    } else {
+                        solid[n] = 0;
+                        phi[n] = 0.0;
+                        rec[e].node = n;
+                        rec[e].type = 0;
+                        rec[e].C = Cs;
+                        rec[e].rho = Rs;
+                        kof_old[n] = -2 - e;
+                        ne_s = e + 1;
+                        if (nn > 0) {
+                            for (int i = 1; i < L::Q; i++) {
+                                const long s = ys[i];
+                                if (s < 0 || !solid[s]) continue;
+                                phi[s] -= need * (wsum > 0 ? kr[s] / wsum : 1.0 / nn);
+                            }
+                        } else {
+                            phi[n] -= need;
+                        }
+                        // later solid neighbours at or below zero now have a
+                        // fluid neighbour: take them in this pass
+                        for (int i = 1; i < L::Q; i++) {
+                            const long s = ys[i];
+                            if (s > n && solid[s] && phi[s] <= 0.0)
+                                if (!pend_push(pend, np_s, (int32_t)s)) ovf_s = 1;
+                        }
+                    }
+                }
+            } else if (!sol_n && phi[n] >= 1.0) {
+                const int e = ne_s;
+                if (e >= cap) {
+                    ovf_s = 1;
+                } else {
+                    double Cx, Rx;
+                    if (kof_old[n] >= 0) pop_moments<L, T>(D, kof_old[n], f, g, S, &Cx, &Rx);
+                    else rec_moments<L>(D, rec[-2 - kof_old[n]], &Cx, &Rx);
+                    phi[n] += D.v_m * Cx;
+                    const double excess = phi[n] - 1.0;
+                    int nn = 0;
+                    double wsum = 0.0;
+                    for (int i = 1; i < L::Q; i++)
+                        if (ys[i] >= 0 && !solid[ys[i]]) { wsum += kr[n]; nn++; }
+                    if (nn > 0) {
+                        for (int i = 1; i < L::Q; i++) {
+                            const long s = ys[i];
+                            if (s < 0 || solid[s]) continue;
+                            phi[s] += excess * (wsum > 0 ? kr[n] / wsum : 1.0 / nn);
+                            if (s > n && phi[s] >= 1.0)
+                                if (!pend_push(pend, np_s, (int32_t)s)) ovf_s = 1;
+                        }
+                        phi[n] = 1.0;
+                    }
+                    solid[n] = 1;
+                    rec[e].node = n;
+                    rec[e].type = 1;
+                    rec[e].C = Cx;
+                    rec[e].rho = Rx;
+                    ne_s = e + 1;
+                }
+            }
+        }
+        __syncthreads();
+    }
+    if (lane == 0) {
+        out[0] = ne_s;
+        out[1] = ovf_s;
+    }
+}
+
+// wall normals of solid nodes within two sites of every change (fluid view)
+template <class L>
+__global__ __launch_bounds__(BLK) void k_event_normals(const DomDev *doms, const EvRec *rec, long nev,
+                                                       const uint8_t *solid, double *nrm) {
+    constexpr int R = 2, SZ = 2 * R + 1;
+    constexpr int NB = L::DIM == 3 ? SZ * SZ * SZ : SZ * SZ;
+    const long t = (long)blockIdx.x * BLK + threadIdx.x;
+    if (t >= nev * NB) return;
+    const DomDev D = doms[0];
+    const long e = t / NB;
+    const int o = (int)(t - e * NB);
+    const int dx = o % SZ - R, dy = (o / SZ) % SZ - R, dz = L::DIM == 3 ? o / (SZ * SZ) - R : 0;
+    int X, Y, Z, fc;
+    coords(D.box, rec[e].node, &X, &Y, &Z);
+    const long s = site(D.box, X, Y, Z, dx, dy, dz, false, &fc);
+    if (s < 0 || !solid[s]) return;
+    int SX, SY, SZz;
+    coords(D.box, s, &SX, &SY, &SZz);
+    double gx = 0, gy = 0, gz = 0;
+    for (int i = 1; i < L::Q; i++) {
+        const long y = site(D.box, SX, SY, SZz, L::ex[i], L::ey[i], L::ez[i], false, &fc);
+        const double ind = (y < 0 || solid[y]) ? 1.0 : 0.0;
+        gx += L::w[i] * L::ex[i] * ind * 3.0;
+        gy += L::w[i] * L::ey[i] * ind * 3.0;
+        gz += L::w[i] * L::ez[i] * ind * 3.0;
+    }
+    const double m = sqrt(gx * gx + gy * gy + gz * gz);
+    if (m > 0) { gx = -gx / m; gy = -gy / m; gz = -gz / m; }
+    else { gx = gy = gz = 0.0; }
+    nrm[3 * s] = gx;
+    nrm[3 * s + 1] = gy;
+    nrm[3 * s + 2] = gz;
+}
+
+// populations into the new compact layout: kept nodes move, a dissolved node
+// starts at the equilibrium at rest of its event record
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_relayout(const DomDev *doms, long nf, const int32_t *nodeof,
+                                                  const int32_t *kof_old, const EvRec *rec, long S,
+                                                  const T *fo, const T *go, T *fn, T *gn) {
+    const long k = (long)blockIdx.x * BLK + threadIdx.x;
+    if (k >= nf) return;
+    const DomDev D = doms[0];
+    const long n = nodeof[k];
+    const int ko = kof_old[n];
+    if (ko >= 0) {
+        for (int i = 0; i < L::Q; i++) {
+            fn[(long)i * S + k] = fo[(long)i * S + ko];
+            gn[(long)i * S + k] = go[(long)i * S + ko];
+        }
+    } else {
+        const EvRec &e = rec[-2 - ko];
+        for (int i = 0; i < L::Q; i++) {
+            fn[(long)i * S + k] = (T)(L::w[i] * e.rho - L::w[i] * D.rho0);
+            gn[(long)i * S + k] = (T)(sol_w<L>(D, i) * e.C - sol_w<L>(D, i) * D.c_ref);
+        }
+    }
+}
+
+__global__ void k_zero2_i32(int32_t *p) {
+    p[0] = 0;
+    p[1] = 0;
+}
+
+template <class L, typename T>
+static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
+    hipStream_t st = c.stream;
+    const long N = c.N;
+    const long nb = (N + BLK - 1) / BLK;
+    *n_events = 0;
+    *overflow = false;
+    int32_t *any = c.iacc + 8, *cnt2 = c.iacc + 10;
+    hipLaunchKernelGGL(k_zero2_i32, dim3(1), dim3(1), 0, st, any);
+    hipLaunchKernelGGL((k_event_scan<L>), dim3(nb), dim3(BLK), 0, st, c.doms, N, c.solid, c.phi,
+                       c.cnt, any);
+    int32_t h[2] = {0, 0};
+    hipError_t e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(h, any, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess || h[0] == 0) return e;
+    // candidates in node order
+    if ((e = scan_excl(c, c.cnt, c.sidx, N, any + 1)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_event_list, dim3(nb), dim3(BLK), 0, st, N, c.cnt, c.sidx, c.evlist,
+                       (long)c.ev_cap);
+    hipLaunchKernelGGL(k_copy_i32, dim3(nb), dim3(BLK), 0, st, c.kof, c.kof_old, N);
+    if ((e = hipMemcpyAsync(h, any + 1, 4, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    const long nlist = h[0] < c.ev_cap ? h[0] : c.ev_cap;
+    if (h[0] > c.ev_cap) *overflow = true;
+    hipLaunchKernelGGL((k_events<L, T>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
+                       c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
+                       c.S, (EvRec *)c.evrec, (long)c.ev_cap, cnt2);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if ((e = hipMemcpyAsync(h, cnt2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
+    if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
+    if (h[1]) *overflow = true;
+    *n_events = h[0];
+    if (h[0] == 0) return hipSuccess;
+    constexpr int NB = L::DIM == 3 ? 125 : 25;
+    const long nt = (long)h[0] * NB;
+    hipLaunchKernelGGL((k_event_normals<L>), dim3((nt + BLK - 1) / BLK), dim3(BLK), 0, st, c.doms,
+                       (const EvRec *)c.evrec, (long)h[0], c.solid, c.nrm);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    return hipSuccess;
+}
+
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_zero_links(T *p, long n) {
+    const long i = (long)blockIdx.x * BLK + threadIdx.x;
+    if (i < n) p[i] = T(0);
+}
+
+template <class L, typename T>
+static hipError_t relayout_impl(Ctx &c) {
+    const long nf = c.n_fluid;
+    // the last step's exchanges belong to the old link list
+    if (c.n_links > 0)
+        hipLaunchKernelGGL((k_zero_links<T>), dim3((c.n_links + BLK - 1) / BLK), dim3(BLK), 0,
+                           c.stream, (T *)c.lq, (long)c.n_links);
+    if (nf > 0)
+        hipLaunchKernelGGL((k_relayout<L, T>), dim3((nf + BLK - 1) / BLK), dim3(BLK), 0, c.stream,
+                           c.doms, nf, c.nodeof, c.kof_old, (const EvRec *)c.evrec, c.S,
+                           (const T *)c.f[c.cur], (const T *)c.g[c.cur], (T *)c.f[1 - c.cur],
+                           (T *)c.g[1 - c.cur]);
+    c.cur = 1 - c.cur;
+    return hipGetLastError();
+}
+
+hipError_t launch_events(Ctx &c, int64_t *n_events, bool *overflow) {
+    if (c.Q == 9) return c.fp64 ? events_impl<D2Q9, double>(c, n_events, overflow) : events_impl<D2Q9, float>(c, n_events, overflow);
+    return c.fp64 ? events_impl<D3Q19, double>(c, n_events, overflow) : events_impl<D3Q19, float>(c, n_events, overflow);
+}
+
+hipError_t launch_relayout(Ctx &c) {
+    if (c.Q == 9) return c.fp64 ? relayout_impl<D2Q9, double>(c) : relayout_impl<D2Q9, float>(c);
+    return c.fp64 ? relayout_impl<D3Q19, double>(c) : relayout_impl<D3Q19, float>(c);
+}
+
+size_t event_record_bytes() { return sizeof(EvRec); }
+
+}  // namespace lbm

@@ -87,6 +87,11 @@ struct Ctx {
     int32_t *sif, *soff, *slinks; // solid interface list [max_links], offsets [max_links+1], [max_links]
     int32_t *sdom;           // [max_links] domain of each solid interface node
     int32_t *bsum;           // scan scratch
+    int32_t *kof_old;        // [N] phase change: compact map before the events
+    int32_t *evlist;         // [ev_cap] phase-change candidates in node order
+    void *evrec;             // [ev_cap] event records
+    long ev_cap;
+    bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions
     double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums
     int32_t *iacc;           // device int accumulators
@@ -119,6 +124,9 @@ hipError_t launch_pops(Ctx &c, double *f, double *g);
 hipError_t launch_exchange(Ctx &c, double *q);
 hipError_t launch_diag(Ctx &c, double *sums, int32_t *nan_flag);
 hipError_t launch_rest_check(Ctx &c, bool *at_rest);
+hipError_t launch_events(Ctx &c, int64_t *n_events, bool *overflow);
+hipError_t launch_relayout(Ctx &c);
+size_t event_record_bytes();
 hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad);
 hipError_t scan_excl(Ctx &c, const int32_t *in, int32_t *out, long n, int32_t *total_dev);
 

@@ -1,0 +1,97 @@
+"""Phase change on the GPU (thresholds phi <= 0 and phi >= 1 after a step,
+geometry rebuilt, populations moved to the new layout) against the FP64
+oracle: the same events in the same order, the same node classes, and the
+fields to the parity tolerances (FP64 1e-12, FP32 deviation storage 1e-5).
+The exchange of the last step is not compared: an event step rebuilds the
+link list."""
+import numpy as np
+import pytest
+
+from lbm_inputs import Case, geometry, MECH_PRE, MECH_POST, SCHEME_SNEW, SCHEME_SV
+
+from parity import log, rel_errors, run_pair
+
+pytestmark = pytest.mark.gpu
+
+FP64, FP32 = 0, 1
+TOL = {FP64: 1e-12, FP32: 1e-5}
+CS = 3 ** -0.5
+
+
+def _dissolving(mech=MECH_PRE, scheme=SCHEME_SNEW):
+    solid, normals = geometry.plane_channel(40, 20, (0, 19))
+    solid[0, 1:5, 10:14] = 1
+    normals[0, 1:5, 10:14, 1] = 1.0
+    solid[0, 12:19, 25:29] = 1
+    normals[0, 12:19, 25:29, 1] = -1.0
+    rng = np.random.default_rng(4)
+    phi0 = np.where(solid.reshape(-1) == 1, rng.uniform(0.005, 0.05, solid.size), 0.0)
+    return Case(name="dissolving", dim=2, nx=40, ny=20, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=0.8, tau_ad=0.8, force=(1e-5, 0.0, 0.0), c_eq=0.0, k_r=0.05, v_m=1.0,
+                phase_change=1, phi0=phi0, c_init=rng.uniform(0.5, 1.5, solid.size),
+                mechanics=mech, scheme=scheme)
+
+
+def _precipitating(mech=MECH_POST, scheme=SCHEME_SV):
+    solid, normals = geometry.plane_channel(36, 18, (0, 17))
+    solid[0, 6:11, 14:19] = 1
+    normals[0, 6:11, 14:19, 0] = 1.0
+    rng = np.random.default_rng(5)
+    return Case(name="precipitating", dim=2, nx=36, ny=18, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=0.9, tau_ad=0.75, j0=0.3, c_eq=1.0, k_r=0.08, v_m=0.35, phase_change=1,
+                c_init=rng.uniform(1.8, 2.6, solid.size), mechanics=mech, scheme=scheme)
+
+
+def _spheres_events():
+    nx, ny, nz = 18, 16, 14
+    rng = np.random.default_rng(8)
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    normals = np.zeros((nz, ny, nx, 3))
+    for c, r in zip(rng.uniform(0, [nx, ny, nz], size=(5, 3)), rng.uniform(2.0, 3.5, size=5)):
+        d = np.stack([x - c[0], y - c[1], z - c[2]], -1)
+        for a, n in enumerate((nx, ny, nz)):
+            d[..., a] -= n * np.round(d[..., a] / n)
+        dist = np.sqrt((d ** 2).sum(-1))
+        inside = dist <= r
+        solid[inside] = 1
+        normals[inside] = d[inside] / np.maximum(dist[inside], 1e-12)[:, None]
+    return Case(name="spheres_events", dim=3, nx=nx, ny=ny, nz=nz, q=19, solid=solid,
+                normals=normals, tau_ns=0.9, tau_ad=0.8, j0=0.5, c_eq=1.0, k_r=0.05, v_m=0.48,
+                phase_change=1, c0=2.2)
+
+
+CASES = {"dissolving": _dissolving, "precipitating": _precipitating,
+         "dissolving R2 S.V.": lambda: _dissolving(MECH_POST, SCHEME_SV),
+         "spheres": _spheres_events}
+
+
+@pytest.mark.parametrize("name,precision,steps", [
+    ("dissolving", FP64, 300), ("precipitating", FP64, 200), ("dissolving R2 S.V.", FP64, 300),
+    ("spheres", FP64, 60), ("dissolving", FP32, 300), ("spheres", FP32, 60)])
+def test_events_match_oracle(name, precision, steps):
+    case = CASES[name]()
+    res = run_pair(case, precision, steps, f"events {name}")
+    ng, no = res["gpu"]["diag"]["n_events"], res["ora"]["diag"]["n_events"]
+    log(f"[events] {name}: gpu events {ng}, oracle events {no}")
+    assert no > 0 and ng == no
+    err = rel_errors(res, case, u_floor=CS if precision == FP64 else 0.0)
+    log(f"[events] errors {err}")
+    assert err["type"] == 0
+    for k in ("rho", "u", "c", "f", "g", "phi"):
+        assert err[k] <= TOL[precision], (k, err[k])
+
+
+def test_events_conserve_mass_fp64():
+    import torch
+    from paper_2306_10794_amd import Simulation
+    case = _dissolving()
+    sim = Simulation(case, precision=FP64)
+    d0 = sim.diag()
+    sim.step(300)
+    d = sim.diag()
+    sim.close()
+    assert d["n_events"] > 0
+    m0 = d0["mass_c"] + d0["phi_sum"] / case.v_m
+    m1 = d["mass_c"] + d["phi_sum"] / case.v_m
+    assert abs(m1 - m0) <= 1e-12 * abs(m0)
