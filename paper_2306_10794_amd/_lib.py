@@ -58,6 +58,15 @@ if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is not built; run __graft_entry__.build() "
                       "or python paper_2306_10794_amd/build.py")
 
+# torch carries its own copy of the HIP runtime (same soname).  Loading torch
+# first makes this library bind to that copy, so that both share one runtime
+# and torch's device pointers are valid here; loaded the other way round, the
+# process would hold two runtimes that do not know each other's allocations.
+try:
+    import torch  # noqa: F401
+except ImportError:  # the ABI can still be inspected without torch
+    pass
+
 lib = C.CDLL(LIB_PATH)
 _P = C.c_void_p
 _SIGS = {

@@ -72,14 +72,16 @@ __device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c
     const Box b = c.D.box;
     const int W = c.D.W;
     const RowWord *__restrict__ rows = a.rows + c.D.word_off;
-    const int y = tk.row % b.ny, z = tk.row / b.ny;
-    const RowSlots rs = load_row_slots<L>(rows, b, W, lane, y, z);
-    c.active = lane < tk.cnt;
+    const int y0 = tk.row % b.ny, z = tk.row / b.ny;
+    const int cnt = tk.cnt & 255, nr = tk.cnt >> 8;
+    const RowSlots rs = load_row_slots<L>(rows, b, W, lane, y0, z, nr);
+    c.active = lane < cnt;
     c.k = tk.k0 + (c.active ? lane : 0);
+    const int ry = task_row<L>(rs, W, nr, c.k);
     c.n = a.nodeof[c.k];
     c.lb = a.lbase[c.k];
-    const int x = (int)(c.n - c.D.node_off) - tk.row * b.nx;
-    classify<L>(rows, b, W, rs, x, y, z, c.k, c.kk, c.solidnb, c.cross, c.cross_hi);
+    const int x = (int)(c.n - c.D.node_off) - (tk.row + ry) * b.nx;
+    classify<L>(rows, b, W, rs, ry, x, y0 + ry, z, c.k, c.kk, c.solidnb, c.cross, c.cross_hi);
     return true;
 }
 

@@ -13,8 +13,9 @@
 // node of the word (RowWord, 16 B per 64 nodes).  The compact index of the
 // fluid node at x in row r is pb + popcount(mask & ((1 << (x & 63)) - 1)) of
 // word (r, x >> 6).  One wavefront processes up to 64 consecutive fluid nodes
-// of one row (a "task"), so no lane is spent on a solid node and every load
-// and store of a wavefront touches one contiguous range per direction.
+// (a "task") of one row, or of a few consecutive rows of one plane when their
+// fluid nodes fit together, so no lane is spent on a solid node and every
+// load and store of a wavefront touches one contiguous range per direction.
 #pragma once
 
 #include <hip/hip_runtime.h>
@@ -64,9 +65,9 @@ struct RowWord {
 };
 
 struct Task {
-    int32_t row;               // row of the task's domain, y + ny*z
+    int32_t row;               // first row of the task (of its domain), y + ny*z
     int32_t k0;                // compact index of the task's first node
-    int32_t cnt;               // nodes in the task, 1..64
+    int32_t cnt;               // nodes in the task (1..64) | rows spanned << 8
     int32_t dom;               // domain of the batch
 };
 

@@ -185,13 +185,74 @@ __device__ __forceinline__ int row_fluid(const DomDev &D, const RowWord *rows, l
     return c;
 }
 
+// Tasks of one plane: its fluid nodes in compact order cut into runs of 64
+// (the last run of the plane shorter), each run spanning at most M rows, so
+// that the row words of every row a task pulls from fit the 64 lanes of a
+// wavefront (3 planes x (rows + 2) rows in 3D, rows + 2 in 2D).  A run that
+// would need more rows ends early.
+template <class L>
+__device__ __forceinline__ int task_max_rows(const DomDev &D) {
+    const int per = 64 / D.W;                 // table rows that fit
+    const int m = (L::DIM == 3 ? per / 3 : per) - 2;
+    return m < 1 ? 1 : (m > 255 ? 255 : m);
+}
+
+// Walk the rows of the plane starting at domain row r0 (y = 0); count the
+// tasks, and write them when `tasks` is given.
+template <class L>
+__device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0, Task *tasks) {
+    const int M = task_max_rows<L>(D);
+    const int ny = D.box.ny;
+    int nt = 0;
+    int count = 0, srow = 0, sk = 0;   // the open run: nodes, first row, first node
+    auto emit = [&](int last_row) {
+        if (count == 0) return;
+        if (tasks) {
+            Task t;
+            t.row = (int)(r0 + srow);
+            t.k0 = sk;
+            t.cnt = count | ((last_row - srow + 1) << 8);
+            t.dom = d;
+            tasks[nt] = t;
+        }
+        nt++;
+        count = 0;
+    };
+    int last = 0;
+    for (int y = 0; y < ny; y++) {
+        const long r = r0 + y;
+        int c = row_fluid(D, rows, r);
+        if (c == 0) continue;
+        int k = rows[D.word_off + r * D.W].pb;
+        if (count > 0 && y - srow + 1 > M) emit(last);
+        while (c > 0) {
+            if (count == 0) {
+                srow = y;
+                sk = k;
+            }
+            const int take = min(c, 64 - count);
+            count += take;
+            c -= take;
+            k += take;
+            last = y;
+            if (count == 64) emit(y);
+        }
+    }
+    emit(last);
+    return nt;
+}
+
+template <class L>
 __global__ __launch_bounds__(BLK) void k_row_ntasks(Geo g, long R, const RowWord *rows, int32_t *nt) {
     const long rg = (long)blockIdx.x * BLK + threadIdx.x;
     if (rg >= R) return;
     const int d = find_dom(g.row_off, g.ndom, rg);
-    nt[rg] = (row_fluid(g.doms[d], rows, rg - g.doms[d].row_off) + 63) / 64;
+    const DomDev &D = g.doms[d];
+    const long r = rg - D.row_off;
+    nt[rg] = (r % D.box.ny == 0) ? plane_tasks<L>(D, d, rows, r, nullptr) : 0;
 }
 
+template <class L>
 __global__ __launch_bounds__(BLK) void k_row_tasks(Geo g, long R, const RowWord *rows,
                                                    const int32_t *tbase, Task *tasks) {
     const long rg = (long)blockIdx.x * BLK + threadIdx.x;
@@ -199,17 +260,7 @@ __global__ __launch_bounds__(BLK) void k_row_tasks(Geo g, long R, const RowWord 
     const int d = find_dom(g.row_off, g.ndom, rg);
     const DomDev &D = g.doms[d];
     const long r = rg - D.row_off;
-    const int c = row_fluid(D, rows, r);
-    const int k0 = rows[D.word_off + r * D.W].pb;
-    const int t0 = tbase[rg];
-    for (int j = 0; 64 * j < c; j++) {
-        Task t;
-        t.row = (int32_t)r;
-        t.k0 = k0 + 64 * j;
-        t.cnt = min(64, c - 64 * j);
-        t.dom = d;
-        tasks[t0 + j] = t;
-    }
+    if (r % D.box.ny == 0) plane_tasks<L>(D, d, rows, r, tasks + tbase[rg]);
 }
 
 // reactive links per compact node, then the link records
@@ -415,9 +466,9 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     if ((e = read_ints(c, c.iacc, &nf, 1)) != hipSuccess) return e;
     c.n_fluid = nf;
     // wavefront tasks
-    hipLaunchKernelGGL(k_row_ntasks, blocks(R), dim3(BLK), 0, st, g, R, c.rows, c.cnt);
+    hipLaunchKernelGGL((k_row_ntasks<L>), blocks(R), dim3(BLK), 0, st, g, R, c.rows, c.cnt);
     if ((e = scan_excl(c, c.cnt, c.sidx, R, c.iacc)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_row_tasks, blocks(R), dim3(BLK), 0, st, g, R, c.rows, c.sidx, c.tasks);
+    hipLaunchKernelGGL((k_row_tasks<L>), blocks(R), dim3(BLK), 0, st, g, R, c.rows, c.sidx, c.tasks);
     int32_t nt = 0;
     if ((e = read_ints(c, c.iacc, &nt, 1)) != hipSuccess) return e;
     c.n_tasks = nt;

@@ -33,7 +33,6 @@ template <class L, typename T, int WV>
 __global__ __launch_bounds__(64 * WV) void k_step(StepArgs<T> a, long nblocks, int remap) {
     using R = double;
     constexpr int Q = L::Q;
-    constexpr int NS = n_slots<L>();
     const long tile = remap ? xcd_tile(blockIdx.x, nblocks) : (long)blockIdx.x;
     const int t = __builtin_amdgcn_readfirstlane((int)(tile * WV) + (int)(threadIdx.x >> 6));
     if (t >= a.ntasks) return;
@@ -46,18 +45,22 @@ __global__ __launch_bounds__(64 * WV) void k_step(StepArgs<T> a, long nblocks, i
     const long S = a.S;
     const int W = D.W;
     const RowWord *__restrict__ rows = a.rows + D.word_off;
-    const int y = tk.row % b.ny, z = tk.row / b.ny;
+    const int y0 = tk.row % b.ny, z = tk.row / b.ny;
+    const int cnt = tk.cnt & 255, nr = tk.cnt >> 8;
     const int ax = b.inlet_axis;
 
-    // ---- the row words of every row this task pulls from: lane j holds word
-    // (j % W) of slot (j / W); other lanes read them with cross-lane shuffles ----
-    const bool slots_fit = NS * W <= 64;
+    // ---- the row words of every row this task pulls from: a table of the
+    // rows y0 - 1 .. y0 + nr of the planes z - 1 .. z + 1 (one plane in 2D);
+    // lane j holds word (j % W) of table row (j / W); other lanes read them
+    // with cross-lane shuffles ----
+    const int TY = nr + 2;
+    const int NSL = (L::DIM == 3 ? 3 : 1) * TY;
+    const bool slots_fit = NSL * W <= 64;
     unsigned long long wm = 0ull;
     int wpb = 0;
-    if (slots_fit && lane < NS * W) {
+    if (slots_fit && lane < NSL * W) {
         const int sl = lane / W, w = lane - sl * W;
-        int yy = y + (sl % 3) - 1, zz = z + (sl / 3) - 1, xx = 0, fc;
-        if (L::DIM == 2) zz = z;
+        int yy = y0 - 1 + sl % TY, zz = L::DIM == 3 ? z - 1 + sl / TY : z, xx = 0, fc;
         if (wrap_site(b, xx, yy, zz, &fc)) {
             const RowWord rw = rows[(long)(yy + b.ny * zz) * W + w];
             wm = rw.mask;
@@ -66,11 +69,19 @@ __global__ __launch_bounds__(64 * WV) void k_step(StepArgs<T> a, long nblocks, i
     }
     // every lane stays active through the shuffles below; lanes past the end
     // of the task classify the task's first node and leave before any load
-    const bool active = lane < tk.cnt;
+    const bool active = lane < cnt;
     const int k = tk.k0 + (active ? lane : 0);
+    // the lane's row: the last of the task's rows that starts at or before k
+    // (a row's first compact index is the base of its first word)
+    int ry = 0;
+    for (int j = 1; j < nr; j++) {
+        const int pbj = __shfl(wpb, ((L::DIM == 3 ? TY : 0) + j + 1) * W, 64);
+        if (k >= pbj) ry = j;
+    }
+    const int y = y0 + ry;
     const int n = a.nodeof[k];
     const int lb = a.lbase[k];  // first reactive link (used by interface nodes)
-    const int x = (int)(n - D.node_off) - tk.row * b.nx;
+    const int x = (int)(n - D.node_off) - (tk.row + ry) * b.nx;
 
     // ---- neighbour classification (shared by both lattices) ----
     int kk[Q];
@@ -98,7 +109,7 @@ __global__ __launch_bounds__(64 * WV) void k_step(StepArgs<T> a, long nblocks, i
             // the shuffles run on every lane: a shuffle reads zero from a lane
             // that is inactive at that point
             const int xs = min(max(xw, 0), b.nx - 1);
-            const int src = slots_fit ? slot_of<L>(i) * W + (xs >> 6) : 0;
+            const int src = slots_fit ? (((L::DIM == 3 ? (1 - L::ez[i]) * TY : 0) + ry + 1 - L::ey[i]) * W + (xs >> 6)) : 0;
             const unsigned lo = __shfl((unsigned)(wm & 0xffffffffull), src, 64);
             const unsigned hi = __shfl((unsigned)(wm >> 32), src, 64);
             const int pb = __shfl(wpb, src, 64);

@@ -19,37 +19,29 @@ __device__ __forceinline__ int nb_compact(const RowWord *__restrict__ rows, int 
     return w.pb + __popcll(w.mask & (bit - 1ull));
 }
 
-// Row slots: the rows a task pulls from are (y + dy, z + dz) with
-// (dy, dz) = (-ey, -ez); slot index (dy + 1) in 2D, (dy + 1) + 3 (dz + 1) in 3D.
-template <class L>
-__device__ constexpr int slot_of(int i) {
-    return L::DIM == 2 ? 1 - L::ey[i] : (1 - L::ey[i]) + 3 * (1 - L::ez[i]);
-}
-template <class L>
-constexpr int n_slots() {
-    return L::DIM == 2 ? 3 : 9;
-}
-
-// The row words of every row a task pulls from: lane j holds word (j % W) of
-// slot (j / W); other lanes read them with cross-lane shuffles.
+// The row words of every row a task pulls from: a table of the rows
+// y0 - 1 .. y0 + nr of the planes z - 1 .. z + 1 (one plane in 2D) for a task
+// of nr rows from (y0, z); lane j holds word (j % W) of table row (j / W);
+// other lanes read them with cross-lane shuffles.
 struct RowSlots {
     unsigned long long wm;
     int wpb;
-    bool fit;     // all slots fit the 64 lanes
+    int TY;       // table rows per plane, nr + 2
+    bool fit;     // the table fits the 64 lanes
 };
 
 template <class L>
 __device__ __forceinline__ RowSlots load_row_slots(const RowWord *__restrict__ rows, const Box &b,
-                                                   int W, int lane, int y, int z) {
-    constexpr int NS = n_slots<L>();
+                                                   int W, int lane, int y0, int z, int nr) {
     RowSlots rs;
-    rs.fit = NS * W <= 64;
+    rs.TY = nr + 2;
+    const int NSL = (L::DIM == 3 ? 3 : 1) * rs.TY;
+    rs.fit = NSL * W <= 64;
     rs.wm = 0ull;
     rs.wpb = 0;
-    if (rs.fit && lane < NS * W) {
+    if (rs.fit && lane < NSL * W) {
         const int sl = lane / W, w = lane - sl * W;
-        int yy = y + (sl % 3) - 1, zz = z + (sl / 3) - 1, xx = 0, fc;
-        if (L::DIM == 2) zz = z;
+        int yy = y0 - 1 + sl % rs.TY, zz = L::DIM == 3 ? z - 1 + sl / rs.TY : z, xx = 0, fc;
         if (wrap_site(b, xx, yy, zz, &fc)) {
             const RowWord rw = rows[(long)(yy + b.ny * zz) * W + w];
             rs.wm = rw.mask;
@@ -57,6 +49,17 @@ __device__ __forceinline__ RowSlots load_row_slots(const RowWord *__restrict__ r
         }
     }
     return rs;
+}
+
+// row of the task (0 .. nr - 1) that compact index k lies in
+template <class L>
+__device__ __forceinline__ int task_row(const RowSlots &rs, int W, int nr, int k) {
+    int ry = 0;
+    for (int j = 1; j < nr; j++) {
+        const int pbj = __shfl(rs.wpb, ((L::DIM == 3 ? rs.TY : 0) + j + 1) * W, 64);
+        if (k >= pbj) ry = j;
+    }
+    return ry;
 }
 
 // Upstream neighbour x - e_i of node (x, y, z) (compact index k) for every i:
@@ -67,7 +70,7 @@ __device__ __forceinline__ RowSlots load_row_slots(const RowWord *__restrict__ r
 // shuffles read zero from inactive lanes).
 template <class L>
 __device__ __forceinline__ void classify(const RowWord *__restrict__ rows, const Box &b, int W,
-                                         const RowSlots &rs, int x, int y, int z, int k, int *kk,
+                                         const RowSlots &rs, int ry, int x, int y, int z, int k, int *kk,
                                          uint32_t &solidnb, uint32_t &cross, uint32_t &cross_hi) {
     const int ax = b.inlet_axis;
     solidnb = 0u;
@@ -94,7 +97,7 @@ __device__ __forceinline__ void classify(const RowWord *__restrict__ rows, const
             if ((yy < 0 || yy >= b.ny) && !b.per[1]) out = true;
             if ((zz < 0 || zz >= b.nz) && !b.per[2]) out = true;
             const int xs = min(max(xw, 0), b.nx - 1);
-            const int src = rs.fit ? slot_of<L>(i) * W + (xs >> 6) : 0;
+            const int src = rs.fit ? (((L::DIM == 3 ? (1 - L::ez[i]) * rs.TY : 0) + ry + 1 - L::ey[i]) * W + (xs >> 6)) : 0;
             const unsigned lo = __shfl((unsigned)(rs.wm & 0xffffffffull), src, 64);
             const unsigned hi = __shfl((unsigned)(rs.wm >> 32), src, 64);
             const int pb = __shfl(rs.wpb, src, 64);
