@@ -173,7 +173,7 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms);
 
 /* Launch configuration of the step (a performance choice only: every
  * configuration gives bit-identical populations and solid fractions).
- *   wg_waves    tasks (wavefronts of 64 nodes of one row) per workgroup:
+ *   wg_waves    tasks (wavefronts of up to 64 fluid nodes) per workgroup:
  *               1, 2, 4 or 8 (default 4)
  *   xcd_remap   1: consecutive tiles of tasks run on one XCD, so that the rows
  *               they share stay in one L2 (default 1); 0: plain order
@@ -182,12 +182,18 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms);
  *               (rounded up to even), built on first use and rebuilt after a
  *               geometry or configuration change; remaining steps run as
  *               plain launches.  Graph objects are the only allocation the
- *               library makes; lbm_destroy frees them. */
+ *               library makes; lbm_destroy frees them.
+ *   overlap     1: the solid-side solid-fraction kernel of a step runs on a
+ *               second stream of the library, concurrently with the next
+ *               step's fused kernel (two exchange buffers); every lbm_step
+ *               call still ends ordered on the context stream.  0: both
+ *               kernels on the context stream (default).  Ignored with
+ *               phase_change = 1. */
 typedef struct lbm_launch_config {
     int32_t wg_waves;
     int32_t xcd_remap;
     int32_t graph_steps;
-    int32_t reserved0;
+    int32_t overlap;
 } lbm_launch_config;
 
 /* EINVAL for values outside the ranges above. */
@@ -195,8 +201,9 @@ lbm_status lbm_set_launch_config(lbm_ctx *ctx, const lbm_launch_config *cfg);
 lbm_status lbm_get_launch_config(const lbm_ctx *ctx, lbm_launch_config *cfg);
 
 /* Autotuner: times every (wg_waves, xcd_remap) pair over trial_steps plain
- * steps, then graph replay of the best pair at graph_steps in {16, 64, 256}
- * (each <= 4 * trial_steps) against plain launches, with HIP events on the
+ * steps, then overlap on and off for the best pair, then graph replay at
+ * graph_steps in {16, 64, 256} (each <= 4 * trial_steps) against plain
+ * launches, with HIP events on the
  * context stream, and keeps the fastest configuration.  The trial steps are
  * real steps of the simulation (the step counter advances by the number
  * written to *steps_run); results do not depend on the configuration.

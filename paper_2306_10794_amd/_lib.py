@@ -51,7 +51,7 @@ class lbm_diag(C.Structure):
 
 class lbm_launch_config(C.Structure):
     _fields_ = [("wg_waves", C.c_int32), ("xcd_remap", C.c_int32), ("graph_steps", C.c_int32),
-                ("reserved0", C.c_int32)]
+                ("overlap", C.c_int32)]
 
 
 if not os.path.exists(LIB_PATH):
@@ -191,15 +191,17 @@ def lbm_step_timed(ctx, nsteps: int):
     return ms[0], ms[1]
 
 
-def lbm_set_launch_config(ctx, wg_waves: int = 4, xcd_remap: int = 1, graph_steps: int = 0):
-    cfg = lbm_launch_config(int(wg_waves), int(xcd_remap), int(graph_steps), 0)
+def lbm_set_launch_config(ctx, wg_waves: int = 4, xcd_remap: int = 1, graph_steps: int = 0,
+                          overlap: int = 0):
+    cfg = lbm_launch_config(int(wg_waves), int(xcd_remap), int(graph_steps), int(overlap))
     _check(lib.lbm_set_launch_config(ctx, C.byref(cfg)), "lbm_set_launch_config", ctx)
 
 
 def lbm_get_launch_config(ctx) -> dict:
     cfg = lbm_launch_config()
     _check(lib.lbm_get_launch_config(ctx, C.byref(cfg)), "lbm_get_launch_config", ctx)
-    return dict(wg_waves=cfg.wg_waves, xcd_remap=cfg.xcd_remap, graph_steps=cfg.graph_steps)
+    return dict(wg_waves=cfg.wg_waves, xcd_remap=cfg.xcd_remap, graph_steps=cfg.graph_steps,
+                overlap=cfg.overlap)
 
 
 def lbm_autotune(ctx, trial_steps: int):
@@ -209,8 +211,8 @@ def lbm_autotune(ctx, trial_steps: int):
     n = C.c_int64(0)
     _check(lib.lbm_autotune(ctx, int(trial_steps), C.byref(cfg), C.byref(ms), C.byref(n)),
            "lbm_autotune", ctx)
-    return (dict(wg_waves=cfg.wg_waves, xcd_remap=cfg.xcd_remap, graph_steps=cfg.graph_steps),
-            ms.value, n.value)
+    return (dict(wg_waves=cfg.wg_waves, xcd_remap=cfg.xcd_remap, graph_steps=cfg.graph_steps,
+                 overlap=cfg.overlap), ms.value, n.value)
 
 
 def lbm_adjoint_workspace_bytes(ctx, nsteps: int, ckpt_every: int) -> int:

@@ -98,7 +98,8 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *nodeof = take(4 * N), *kof = take(4 * N), *lbase = take(4 * N);
     char *flags = take(4 * N), *rmask = take(4 * N), *cnt = take(4 * N), *sidx = take(4 * N);
     char *phi = take(8 * N), *kr = take(8 * N), *nrm = take(24 * N), *solid = take(N);
-    char *lbeta = take(ts * L), *lq = take(ts * L), *lnode = take(4 * L), *lsolid = take(4 * L),
+    char *lbeta = take(ts * L), *lq = take(ts * L), *lq2 = take(ts * L), *lnode = take(4 * L),
+         *lsolid = take(4 * L),
          *ldir = take(L);
     char *sif = take(4 * L), *soff = take(4 * (L + 1)), *slinks = take(4 * L), *sdom = take(4 * L);
     char *bsum = take(4 * ((N + 4095) / 4096 + 64));
@@ -132,6 +133,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->phi = (double *)phi; c->kr = (double *)kr; c->nrm = (double *)nrm;
         c->solid = (uint8_t *)solid;
         c->lbeta = lbeta; c->lq = lq; c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
+        c->lqb[0] = lq; c->lqb[1] = lq2; c->lq_next = 1;
         c->ldir = (uint8_t *)ldir;
         c->sif = (int32_t *)sif; c->soff = (int32_t *)soff; c->slinks = (int32_t *)slinks;
         c->sdom = (int32_t *)sdom;
@@ -319,10 +321,33 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
     c->cfg.wg_waves = 4;
     c->cfg.xcd_remap = 1;
     c->cfg.graph_steps = 0;
-    c->cfg.reserved0 = 0;
+    c->cfg.overlap = 0;
     c->gexec = nullptr;
     c->graph_built = 0;
     c->geom_epoch = 0;
+    c->have_side = false;
+    c->phi_pending[0] = c->phi_pending[1] = false;
+    c->last_phi = -1;
+    {
+        hipError_t es = hipStreamCreateWithFlags(&c->side, hipStreamNonBlocking);
+        bool ok = es == hipSuccess;
+        int made = 0;
+        for (int b = 0; ok && b < 2; b++) {
+            ok = hipEventCreateWithFlags(&c->ev_stp[b], hipEventDisableTiming) == hipSuccess;
+            if (ok) made++;
+            ok = ok && hipEventCreateWithFlags(&c->ev_phi[b], hipEventDisableTiming) == hipSuccess;
+            if (ok) made++;
+        }
+        if (!ok) {   // run without the overlap
+            (void)hipGetLastError();
+            if (es == hipSuccess) (void)hipStreamDestroy(c->side);
+            for (int b = 0; b < 2; b++) {
+                if (made > 2 * b) (void)hipEventDestroy(c->ev_stp[b]);
+                if (made > 2 * b + 1) (void)hipEventDestroy(c->ev_phi[b]);
+            }
+        }
+        c->have_side = ok;
+    }
     c->adj.valid = false;
     *out = (lbm_ctx *)c;
     return LBM_OK;
@@ -347,10 +372,21 @@ static hipError_t build_graph(Ctx *c, int n) {
     if (e == hipSuccess) {
         c->stream = cs;
         c->cur = 0;
+        const int lqn = c->lq_next;
+        void *lq = c->lq;
+        // inside the capture only waits on events recorded in it
+        c->phi_pending[0] = c->phi_pending[1] = false;
+        c->last_phi = -1;
+        c->lq_next = 1;
         hipError_t le = hipSuccess;
-        for (int t = 0; t < n && le == hipSuccess; t++) le = launch_step(*c);
+        for (int t = 0; t < n && le == hipSuccess; t++) le = launch_step(*c, nullptr, c->have_side && c->cfg.overlap);
+        if (le == hipSuccess) le = join_side(*c);
         c->stream = user;
         c->cur = cur;
+        c->lq_next = lqn;
+        c->lq = lq;
+        c->phi_pending[0] = c->phi_pending[1] = false;
+        c->last_phi = -1;
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(cs, &g);
         if (le != hipSuccess) e = le;
@@ -422,24 +458,31 @@ static hipError_t run_steps(Ctx *c, int32_t nsteps) {
                 if (e != hipSuccess) return e;
             }
             while (nsteps - t >= gs) {
-                hipError_t e = hipGraphLaunch(c->gexec, c->stream);
+                hipError_t e = join_side(*c);   // eager work before the graph
+                if (e != hipSuccess) return e;
+                e = hipGraphLaunch(c->gexec, c->stream);
                 if (e != hipSuccess) return e;
                 c->step += gs;
                 t += gs;
+                // the graph starts at buffer 1 and runs an even number of steps
+                c->lq_next = 1;
+                c->lq = c->lqb[0];
             }
         }
     }
     for (; t < nsteps; t++) {
-        hipError_t e = launch_step(*c);
+        hipError_t e = launch_step(*c, nullptr, c->have_side && c->cfg.overlap);
         if (e != hipSuccess) return e;
         c->step++;
     }
-    return hipSuccess;
+    // every later operation on the context stream sees the solid fractions
+    return join_side(*c);
 }
 
 static bool cfg_ok(const lbm_launch_config &g) {
     return (g.wg_waves == 1 || g.wg_waves == 2 || g.wg_waves == 4 || g.wg_waves == 8) &&
-           (g.xcd_remap == 0 || g.xcd_remap == 1) && g.graph_steps >= 0 && g.graph_steps <= 100000;
+           (g.xcd_remap == 0 || g.xcd_remap == 1) && g.graph_steps >= 0 && g.graph_steps <= 100000 &&
+           (g.overlap == 0 || g.overlap == 1);
 }
 
 extern "C" {
@@ -483,6 +526,14 @@ void lbm_destroy(lbm_ctx *ctx) {
     if (c->have_events)
         for (int k = 0; k < 4; k++) (void)hipEventDestroy(c->ev[k]);
     drop_graph(c);
+    if (c->have_side) {
+        (void)hipStreamSynchronize(c->side);
+        for (int b = 0; b < 2; b++) {
+            (void)hipEventDestroy(c->ev_stp[b]);
+            (void)hipEventDestroy(c->ev_phi[b]);
+        }
+        (void)hipStreamDestroy(c->side);
+    }
     delete c;
 }
 
@@ -563,12 +614,14 @@ lbm_status lbm_set_launch_config(lbm_ctx *ctx, const lbm_launch_config *cfg) {
     Ctx *c = (Ctx *)ctx;
     if (!c || !cfg) return LBM_EINVAL;
     if (!cfg_ok(*cfg)) {
-        c->err = "launch config: wg_waves in {1,2,4,8}, xcd_remap in {0,1}, 0 <= graph_steps <= 100000";
+        c->err = "launch config: wg_waves in {1,2,4,8}, xcd_remap in {0,1}, "
+                 "0 <= graph_steps <= 100000, overlap in {0,1}";
         return LBM_EINVAL;
     }
-    if (cfg->wg_waves != c->cfg.wg_waves || cfg->xcd_remap != c->cfg.xcd_remap) drop_graph(c);
+    if (cfg->wg_waves != c->cfg.wg_waves || cfg->xcd_remap != c->cfg.xcd_remap ||
+        cfg->overlap != c->cfg.overlap)
+        drop_graph(c);
     c->cfg = *cfg;
-    c->cfg.reserved0 = 0;
     return LBM_OK;
 }
 
@@ -603,7 +656,9 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
     }
     // time n steps under configuration g after w untimed steps
     auto trial = [&](const lbm_launch_config &g, int w, int n, double *ms) -> hipError_t {
-        if (g.wg_waves != c->cfg.wg_waves || g.xcd_remap != c->cfg.xcd_remap) drop_graph(c);
+        if (g.wg_waves != c->cfg.wg_waves || g.xcd_remap != c->cfg.xcd_remap ||
+            g.overlap != c->cfg.overlap)
+            drop_graph(c);
         c->cfg = g;
         hipError_t r = run_steps(c, w);
         if (r == hipSuccess) r = hipEventRecord(e0, c->stream);
@@ -628,6 +683,16 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
                 bc = g;
             }
         }
+    if (e == hipSuccess && c->have_side && !c->p.phase_change) {
+        lbm_launch_config g = bc;
+        g.overlap = 1;
+        double ms = 0.0;
+        e = trial(g, 2, trial_steps, &ms);
+        if (e == hipSuccess && ms < bms) {
+            bms = ms;
+            bc = g;
+        }
+    }
     const int gsteps[3] = {16, 64, 256};
     for (int gi = 0; gi < 3 && e == hipSuccess; gi++) {
         const int gs = gsteps[gi];
@@ -649,7 +714,9 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
         c->cfg = keep;
         return dev_err(c, e, "autotune");
     }
-    if (bc.wg_waves != c->cfg.wg_waves || bc.xcd_remap != c->cfg.xcd_remap) drop_graph(c);
+    if (bc.wg_waves != c->cfg.wg_waves || bc.xcd_remap != c->cfg.xcd_remap ||
+        bc.overlap != c->cfg.overlap)
+        drop_graph(c);
     c->cfg = bc;
     if (best) *best = bc;
     if (ms_per_step) *ms_per_step = bms;

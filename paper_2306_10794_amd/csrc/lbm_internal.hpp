@@ -81,7 +81,16 @@ struct Ctx {
     int32_t *sidx;           // scratch [N]
     double *phi, *kr, *nrm;  // [N], [N], [N][3]
     uint8_t *solid;          // [N]
-    void *lbeta, *lq;        // [max_links] of T
+    void *lbeta, *lq;        // [max_links] of T; lq: exchanges of the last step
+    void *lqb[2];            // the two exchange buffers lq alternates between
+    int lq_next;             // buffer the next step writes
+    // overlap of the solid-side phi kernel of step t with the fused kernel of
+    // step t + 1 (second stream; default priority)
+    hipStream_t side;
+    hipEvent_t ev_stp[2], ev_phi[2];
+    bool have_side;
+    bool phi_pending[2];     // ev_phi[b] marks a solid-side kernel still to be waited for
+    int last_phi;            // buffer of the last overlapped solid-side kernel, -1 none
     int32_t *lnode, *lsolid; // [max_links]
     uint8_t *ldir;           // [max_links]
     int32_t *sif, *soff, *slinks; // solid interface list [max_links], offsets [max_links+1], [max_links]
@@ -115,7 +124,9 @@ size_t workspace_layout(const lbm_params *p, int n, Ctx *c, char *base);
 
 // launchers (return hipError_t of the first failing launch)
 // ev: optional 4 events recorded around the two kernels of the step
-hipError_t launch_step(Ctx &c, hipEvent_t *ev = nullptr);
+hipError_t launch_step(Ctx &c, hipEvent_t *ev = nullptr, bool overlap = false);
+// make the context stream wait for an overlapped solid-side kernel
+hipError_t join_side(Ctx &c);
 hipError_t launch_geometry(Ctx &c, const uint8_t *solid, const double *normals, const double *k_r,
                            const double *phi0, int64_t *n_links, int64_t *n_sif);
 hipError_t launch_init(Ctx &c, const double *rho, const double *u, const double *cc);

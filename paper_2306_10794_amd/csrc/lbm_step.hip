@@ -321,9 +321,22 @@ static StepArgs<T> step_args(Ctx &c) {
     return a;
 }
 
+// One step.  The exchanges alternate between two buffers, so that with
+// `overlap` the solid-side kernel of this step runs on the side stream while
+// the next step's fused kernel (which writes the other buffer) runs on the
+// context stream; a fused kernel waits only for the solid-side kernel that
+// read its buffer two steps before.  The solid-side kernel touches the solid
+// fractions of solid nodes only, the fused kernel those of fluid nodes.
 template <class L, typename T>
-static hipError_t step_impl(Ctx &c, hipEvent_t *ev) {
+static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
     hipError_t e = hipSuccess;
+    const int b = c.lq_next;
+    if (c.phi_pending[b]) {
+        e = hipStreamWaitEvent(c.stream, c.ev_phi[b], 0);
+        if (e != hipSuccess) return e;
+        c.phi_pending[b] = false;
+    }
+    c.lq = c.lqb[b];
     const StepArgs<T> args = step_args<T>(c);
     if (ev) (void)hipEventRecord(ev[0], c.stream);
     if (c.n_tasks > 0) {
@@ -340,21 +353,42 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev) {
     }
     if (ev) (void)hipEventRecord(ev[1], c.stream);
     if (e != hipSuccess) return e;
-    if (ev) (void)hipEventRecord(ev[2], c.stream);
+    hipStream_t ps = c.stream;
+    if (overlap && c.n_sif > 0) {
+        if ((e = hipEventRecord(c.ev_stp[b], c.stream)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(c.side, c.ev_stp[b], 0)) != hipSuccess) return e;
+        ps = c.side;
+    }
+    if (ev) (void)hipEventRecord(ev[2], ps);
     if (c.n_sif > 0) {
         const long nb2 = (c.n_sif + BLK - 1) / BLK;
-        hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, c.stream, c.sif, c.soff,
+        hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, ps, c.sif, c.soff,
                            c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phi, (long)c.n_sif, c.dacc);
         e = hipGetLastError();
     }
-    if (ev) (void)hipEventRecord(ev[3], c.stream);
+    if (ev) (void)hipEventRecord(ev[3], ps);
+    if (e == hipSuccess && ps != c.stream) {
+        e = hipEventRecord(c.ev_phi[b], ps);
+        c.phi_pending[b] = true;
+        c.last_phi = b;
+    }
+    c.lq_next = 1 - b;
     c.cur = 1 - c.cur;
     return e;
 }
 
-hipError_t launch_step(Ctx &c, hipEvent_t *ev) {
-    if (c.Q == 9) return c.fp64 ? step_impl<D2Q9, double>(c, ev) : step_impl<D2Q9, float>(c, ev);
-    return c.fp64 ? step_impl<D3Q19, double>(c, ev) : step_impl<D3Q19, float>(c, ev);
+hipError_t launch_step(Ctx &c, hipEvent_t *ev, bool overlap) {
+    if (c.Q == 9) return c.fp64 ? step_impl<D2Q9, double>(c, ev, overlap) : step_impl<D2Q9, float>(c, ev, overlap);
+    return c.fp64 ? step_impl<D3Q19, double>(c, ev, overlap) : step_impl<D3Q19, float>(c, ev, overlap);
+}
+
+hipError_t join_side(Ctx &c) {
+    hipError_t e = hipSuccess;
+    if (c.last_phi >= 0 && c.phi_pending[c.last_phi])
+        e = hipStreamWaitEvent(c.stream, c.ev_phi[c.last_phi], 0);
+    c.phi_pending[0] = c.phi_pending[1] = false;
+    c.last_phi = -1;
+    return e;
 }
 
 }  // namespace lbm

@@ -39,7 +39,8 @@ def _run(cfg, pre=0, steps=300):
 @pytest.mark.parametrize("cfg,pre", [
     (dict(wg_waves=1, xcd_remap=0, graph_steps=0), 0),
     (dict(wg_waves=2, xcd_remap=1, graph_steps=16), 1),
-    (dict(wg_waves=8, xcd_remap=0, graph_steps=64), 3),
+    (dict(wg_waves=8, xcd_remap=0, graph_steps=64, overlap=1), 3),
+    (dict(wg_waves=4, xcd_remap=1, graph_steps=0, overlap=1), 1),
     (dict(wg_waves=4, xcd_remap=1, graph_steps=7), 0),
 ])
 def test_launch_config_is_bitwise_neutral(cfg, pre):
@@ -86,7 +87,7 @@ def test_graph_on_a_batch_matches_plain_launches():
 def test_bad_launch_config_rejected():
     from paper_2306_10794_amd import Simulation, lbm_set_launch_config, LbmError, LBM_EINVAL
     sim = Simulation(_case(), precision=FP32)
-    for bad in (dict(wg_waves=3), dict(xcd_remap=2), dict(graph_steps=-1)):
+    for bad in (dict(wg_waves=3), dict(xcd_remap=2), dict(graph_steps=-1), dict(overlap=2)):
         with pytest.raises(LbmError) as ei:
             lbm_set_launch_config(sim.ctx, **bad)
         assert ei.value.status == LBM_EINVAL
