@@ -28,9 +28,12 @@
 namespace lbm {
 
 // WV wavefronts (tasks) per workgroup; remap != 0 keeps runs of consecutive
-// tiles on one XCD
+// tiles on one XCD.  FP32 storage asks for 4 waves per SIMD (at most 128
+// VGPRs, a few spilled): the extra wave hides more memory latency than the
+// spills cost (256^3 sphere packing: 732 -> 660 us).
 template <class L, typename T, int WV>
-__global__ __launch_bounds__(64 * WV) void k_step(StepArgs<T> a, long nblocks, int remap) {
+__global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepArgs<T> a, long nblocks,
+                                                                         int remap) {
     using R = double;
     constexpr int Q = L::Q;
     const long tile = remap ? xcd_tile(blockIdx.x, nblocks) : (long)blockIdx.x;
