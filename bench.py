@@ -36,8 +36,10 @@ PHI_KERNEL = "lbm::k_phi_solid<lbm::D3Q19, float>"
 COPY_KERNEL = "neg_kernel"   # torch elementwise negation: one read, one write per element
 # the rocprofv3 runs whose summaries are committed (run from the repository
 # root after `cd /tmp && export TMPDIR=/tmp && cd -`)
-PROFILE_ARGS = "--steps 50 --warmup 5 --no-cpu-baseline --no-batch --calib-copy-mib 1024"
-PMC_ARGS = "--steps 5 --warmup 1 --no-cpu-baseline --no-batch --calib-copy-mib 1024"
+PROFILE_ARGS = ("--steps 50 --warmup 5 --no-cpu-baseline --no-batch --no-adjoint --no-phase-change "
+                "--calib-copy-mib 1024")
+PMC_ARGS = ("--steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-adjoint --no-phase-change "
+            "--calib-copy-mib 1024")
 PROFILE_CMDS = {
     "trace": f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run -- "
              f"python3 bench.py {PROFILE_ARGS}",
@@ -207,6 +209,32 @@ def adjoint_ratio(steps, ckpt):
     }
 
 
+def phase_change_run(case, steps, planes, phi_near):
+    """The same workload with the phase-change thresholds on.  The fluid nodes
+    of the first `planes` planes at the inlet start at solid fraction
+    phi_near, just below the precipitation threshold, so that a burst of
+    events (each with relinking and re-layout) happens within a short run;
+    all other nodes start as in the workload.  Time per step including the
+    per-step candidate scan and the event passes, and the events applied."""
+    import torch
+    from paper_2306_10794_amd import Simulation, LBM_FP32_DEV, lbm_step
+    zi = np.arange(case.n) // (case.nx * case.ny)
+    phi0 = np.where(case.solid_flat() == 1, 1.0, np.where(zi < planes, phi_near, 0.0))
+    sim = Simulation(case.replace(phase_change=1, phi0=phi0), precision=LBM_FP32_DEV, device="cuda:0")
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm_step(sim.ctx, steps)
+    torch.cuda.synchronize()
+    dt = time.perf_counter() - t0
+    d = sim.diag()
+    sim.close()
+    del sim
+    torch.cuda.empty_cache()
+    return {"steps": steps, "near_threshold_planes": planes, "initial_phi": phi_near,
+            "ms_per_step": round(dt / steps * 1e3, 4), "events": int(d["n_events"]),
+            "fluid_nodes_after": int(d["n_fluid"]), "status": int(d["status"])}
+
+
 def cpu_baseline(case, steps):
     import oracle
     o = oracle.Oracle(case)
@@ -327,6 +355,11 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batch", action="store_true", help="skip the batched-vs-plain sweep")
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
+    ap.add_argument("--no-phase-change", action="store_true",
+                    help="skip the run with the phase-change thresholds on")
+    ap.add_argument("--phase-change-steps", type=int, default=300)
+    ap.add_argument("--phase-change-planes", type=int, default=2,
+                    help="inlet planes whose fluid nodes start near the precipitation threshold")
     ap.add_argument("--adjoint-steps", type=int, default=2000)
     ap.add_argument("--adjoint-ckpt", type=int, default=100)
     ap.add_argument("--batch-steps", type=int, default=1000)
@@ -408,6 +441,7 @@ def main():
         "cpu_baseline": None,
         "batch": None,
         "adjoint": None,
+        "phase_change": None,
     }
     sim.close()
     del sim
@@ -417,6 +451,10 @@ def main():
     if not args.no_batch:
         line["batch"] = batch_vs_plain(args.batch_steps, args.plain_steps, args.tune_steps)
         log(f"[bench] batch {line['batch']}")
+    if not args.no_phase_change:
+        line["phase_change"] = phase_change_run(case, args.phase_change_steps,
+                                                args.phase_change_planes, 0.9999)
+        log(f"[bench] phase change {line['phase_change']}")
     if not args.no_adjoint:
         line["adjoint"] = adjoint_ratio(args.adjoint_steps, args.adjoint_ckpt)
         log(f"[bench] adjoint {line['adjoint']}")

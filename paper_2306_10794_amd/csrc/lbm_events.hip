@@ -25,7 +25,7 @@
 
 namespace lbm {
 
-constexpr int EV_PENDING = 2048;  // nodes pushed over a threshold within one pass
+constexpr uint32_t F_PEND = 1u << 29;  // geometry-flag bit: node waits in the heap
 
 struct EvRec {
     int64_t node;
@@ -99,32 +99,52 @@ __device__ __forceinline__ void rec_moments(const DomDev &D, const EvRec &e, dou
     *rho = r;
 }
 
-// sorted insert into the pending list (lane 0 only); false when full
-__device__ __forceinline__ bool pend_push(int32_t *pend, int &np, int32_t v) {
-    for (int j = 0; j < np; j++)
-        if (pend[j] == v) return true;
-    if (np >= EV_PENDING) return false;
-    int j = np++;
-    while (j > 0 && pend[j - 1] > v) {
-        pend[j] = pend[j - 1];
-        j--;
+// min-heap of the nodes that events push over a threshold during a pass
+// (lane 0 only; global memory)
+__device__ __forceinline__ void heap_push(int32_t *h, int &n, int32_t v) {
+    int i = n++;
+    while (i > 0) {
+        const int p = (i - 1) >> 1;
+        if (h[p] <= v) break;
+        h[i] = h[p];
+        i = p;
     }
-    pend[j] = v;
-    return true;
+    h[i] = v;
+}
+
+__device__ __forceinline__ int32_t heap_pop(int32_t *h, int &n) {
+    const int32_t top = h[0];
+    const int32_t last = h[--n];
+    int i = 0;
+    while (true) {
+        const int l = 2 * i + 1;
+        if (l >= n) break;
+        const int r = l + 1;
+        const int m = (r < n && h[r] < h[l]) ? r : l;
+        if (h[m] >= last) break;
+        h[i] = h[m];
+        i = m;
+    }
+    if (n > 0) h[i] = last;
+    return top;
 }
 
 // One wavefront.  Lanes 1..Q-1 read the moments of the neighbour along their
 // direction from the populations (data no event of the pass changes); lane 0
 // reads and writes everything an event changes (solid, phi, kof_old, the
-// records), so it always sees its own earlier writes.  out[0] = events,
-// out[1] = 1 if the records or the pending list overflowed (the pass stops).
+// records, the heap and its marks), so it always sees its own earlier writes.
+// A node pushed over its threshold that is not a candidate of the pass goes
+// into a min-heap (marked in the geometry flags, which the rebuild after the
+// pass recomputes); the next node is the smaller of the list head and the
+// heap top.  out[0] = events, out[1] = 1 if the records or the heap
+// overflowed (the pass stops there).
 template <class L, typename T>
 __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t *list, long nlist,
                                                uint8_t *solid, double *phi, const double *kr,
                                                const int32_t *kof, int32_t *kof_old, const T *f,
                                                const T *g, long S, EvRec *rec, long cap,
-                                               int32_t *out) {
-    __shared__ int32_t pend[EV_PENDING];
+                                               const int32_t *cand, uint32_t *gflags,
+                                               int32_t *heap, int32_t *out) {
     __shared__ int np_s, ne_s, ovf_s;
     __shared__ long cur_s;
     const int lane = threadIdx.x;
@@ -134,22 +154,18 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
     long pos = 0;
     while (true) {
         if (lane == 0) {
-            // next node: the smaller of the list head and the pending head
+            // next node: the smaller of the list head and the heap top (a
+            // node is never in both)
             long nxt = -1;
             const long a = pos < nlist ? (long)list[pos] : -1;
-            const long b = np_s > 0 ? (long)pend[0] : -1;
-            bool pop = false;
-            if (a >= 0 && (b < 0 || a <= b)) {
+            const long b = np_s > 0 ? (long)heap[0] : -1;
+            if (a >= 0 && (b < 0 || a < b)) {
                 nxt = a;
                 pos++;
-                pop = b == a;   // the same node in both lists
             } else if (b >= 0) {
-                nxt = b;
-                pop = true;
-            }
-            if (pop) {
-                for (int j = 1; j < np_s; j++) pend[j - 1] = pend[j];
-                np_s--;
+                int np = np_s;
+                nxt = heap_pop(heap, np);
+                np_s = np;
             }
             if (ovf_s) nxt = -1;
             cur_s = nxt;
@@ -176,6 +192,17 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
             rs[i] = __shfl(Ry, i, 64);
         }
         if (lane == 0) {
+            auto push = [&](long v) {
+                if (gflags[v] & F_PEND) return;
+                if (np_s >= cap) {
+                    ovf_s = 1;
+                    return;
+                }
+                int np = np_s;
+                heap_push(heap, np, (int32_t)v);
+                np_s = np;
+                gflags[v] |= F_PEND;
+            };
             // moments of neighbours that became fluid earlier in this pass
             for (int i = 1; i < L::Q; i++)
                 if (ys[i] >= 0 && kof_old[ys[i]] <= -2)
@@ -216,8 +243,8 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                         // fluid neighbour: take them in this pass
                         for (int i = 1; i < L::Q; i++) {
                             const long s = ys[i];
-                            if (s > n && solid[s] && phi[s] <= 0.0)
-                                if (!pend_push(pend, np_s, (int32_t)s)) ovf_s = 1;
+                            if (s > n && !cand[s] && solid[s] && phi[s] <= 0.0)
+                                push(s);
                         }
                     }
                 }
@@ -240,8 +267,8 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                             const long s = ys[i];
                             if (s < 0 || solid[s]) continue;
                             phi[s] += excess * (wsum > 0 ? kr[n] / wsum : 1.0 / nn);
-                            if (s > n && phi[s] >= 1.0)
-                                if (!pend_push(pend, np_s, (int32_t)s)) ovf_s = 1;
+                            if (s > n && !cand[s] && phi[s] >= 1.0)
+                                push(s);
                         }
                         phi[n] = 1.0;
                     }
@@ -353,7 +380,7 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     if (h[0] > c.ev_cap) *overflow = true;
     hipLaunchKernelGGL((k_events<L, T>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
                        c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
-                       c.S, (EvRec *)c.evrec, (long)c.ev_cap, cnt2);
+                       c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, c.evheap, cnt2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(h, cnt2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;

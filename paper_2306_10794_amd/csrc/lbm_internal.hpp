@@ -99,6 +99,7 @@ struct Ctx {
     int32_t *kof_old;        // [N] phase change: compact map before the events
     int32_t *evlist;         // [ev_cap] phase-change candidates in node order
     void *evrec;             // [ev_cap] event records
+    int32_t *evheap;         // [ev_cap] pending nodes of an event pass
     long ev_cap;
     bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions

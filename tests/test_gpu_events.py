@@ -61,14 +61,24 @@ def _spheres_events():
                 phase_change=1, c0=2.2)
 
 
-CASES = {"dissolving": _dissolving, "precipitating": _precipitating,
+def _burst():
+    """Inlet planes start just below the precipitation threshold: a burst of
+    events in which precipitating nodes push their neighbours over it."""
+    from lbm_inputs import configs
+    c = configs.sphere_precipitation(n=24, seed=3, phase_change=1, r_min=2.0, r_max=4.0)
+    zi = np.arange(c.n) // (c.nx * c.ny)
+    phi0 = np.where(c.solid_flat() == 1, 1.0, np.where(zi < 2, 0.9999, 0.0))
+    return c.replace(name="burst", phi0=phi0)
+
+
+CASES = {"dissolving": _dissolving, "precipitating": _precipitating, "burst": _burst,
          "dissolving R2 S.V.": lambda: _dissolving(MECH_POST, SCHEME_SV),
          "spheres": _spheres_events}
 
 
 @pytest.mark.parametrize("name,precision,steps", [
     ("dissolving", FP64, 300), ("precipitating", FP64, 200), ("dissolving R2 S.V.", FP64, 300),
-    ("spheres", FP64, 60), ("dissolving", FP32, 300), ("spheres", FP32, 60)])
+    ("spheres", FP64, 60), ("burst", FP64, 80), ("dissolving", FP32, 300), ("spheres", FP32, 60)])
 def test_events_match_oracle(name, precision, steps):
     case = CASES[name]()
     res = run_pair(case, precision, steps, f"events {name}")
