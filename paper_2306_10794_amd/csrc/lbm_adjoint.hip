@@ -74,7 +74,7 @@ __device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c
     const RowWord *__restrict__ rows = a.rows + c.D.word_off;
     const int y0 = tk.row % b.ny, z = tk.row / b.ny;
     const int cnt = tk.cnt & 255, nr = tk.cnt >> 8;
-    const RowSlots rs = load_row_slots<L>(rows, b, W, lane, y0, z, nr);
+    const RowSlots rs = load_row_slots<L>(rows, b, W, lane, y0, z, nr, tk.wlo, tk.nwd);
     c.active = lane < cnt;
     c.k = tk.k0 + (c.active ? lane : 0);
     const int ry = task_row<L>(rs, W, nr, c.k);

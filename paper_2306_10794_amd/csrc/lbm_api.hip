@@ -84,7 +84,10 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     // large power-of-two boundary
     long S = (N + 63) / 64 * 64;
     if ((S / 64) % 2 == 0) S += 64;
-    const long task_cap = R + N / 64 + 1;
+    // a task holds 64 nodes, or ends at a row (narrow rows: at most one task
+    // per row ends early) or at a word-window limit (wide rows: advances at
+    // least one word)
+    const long task_cap = 2 * R + RW + N / 64 + 1;
     size_t off = 0;
     auto take = [&](size_t bytes) -> char * {
         char *r = base ? base + off : nullptr;

@@ -69,6 +69,8 @@ struct Task {
     int32_t k0;                // compact index of the task's first node
     int32_t cnt;               // nodes in the task (1..64) | rows spanned << 8
     int32_t dom;               // domain of the batch
+    int32_t wlo, nwd;          // window of row words the task's table holds
+    int32_t pad0, pad1;
 };
 
 struct Box {

@@ -185,20 +185,43 @@ __device__ __forceinline__ int row_fluid(const DomDev &D, const RowWord *rows, l
     return c;
 }
 
-// Tasks of one plane: its fluid nodes in compact order cut into runs of 64
-// (the last run of the plane shorter), each run spanning at most M rows, so
-// that the row words of every row a task pulls from fit the 64 lanes of a
-// wavefront (3 planes x (rows + 2) rows in 3D, rows + 2 in 2D).  A run that
-// would need more rows ends early.
+// Tasks.  A task is a run of at most 64 consecutive fluid nodes (compact
+// order) whose pulls can be classified from a table of row words held one
+// per lane: the rows y0 - 1 .. y0 + nr of the planes z - 1 .. z + 1 (one
+// plane in 2D), words wlo .. wlo + nwd - 1 of each, at most 64 entries.
+//  * Narrow rows (full rows fit for at least one task row, M >= 1): each
+//    plane's fluid nodes cut into runs of 64 spanning at most M rows
+//    (wlo = 0, nwd = W); a run that would need more rows ends early.
+//  * Wide rows: runs stay within one row and cover a window of at most
+//    maxw words (the words of x_first - 1 .. x_last + 1); a run whose nodes
+//    would spread wider ends early.
 template <class L>
 __device__ __forceinline__ int task_max_rows(const DomDev &D) {
-    const int per = 64 / D.W;                 // table rows that fit
+    const int per = 64 / D.W;                 // full table rows that fit
     const int m = (L::DIM == 3 ? per / 3 : per) - 2;
-    return m < 1 ? 1 : (m > 255 ? 255 : m);
+    return m > 255 ? 255 : m;                 // < 1: wide rows
+}
+
+template <class L>
+__device__ __forceinline__ int task_max_words() {
+    return 64 / (L::DIM == 3 ? 9 : 3);       // one task row: 3 (x 3) table rows
+}
+
+__device__ __forceinline__ void put_task(Task *tasks, int nt, long row, int k0, int cnt, int nr,
+                                         int d, int wlo, int nwd) {
+    Task t;
+    t.row = (int32_t)row;
+    t.k0 = k0;
+    t.cnt = cnt | (nr << 8);
+    t.dom = d;
+    t.wlo = wlo;
+    t.nwd = nwd;
+    t.pad0 = t.pad1 = 0;
+    tasks[nt] = t;
 }
 
 // Walk the rows of the plane starting at domain row r0 (y = 0); count the
-// tasks, and write them when `tasks` is given.
+// tasks, and write them when `tasks` is given (narrow rows).
 template <class L>
 __device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0, Task *tasks) {
     const int M = task_max_rows<L>(D);
@@ -207,14 +230,7 @@ __device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0,
     int count = 0, srow = 0, sk = 0;   // the open run: nodes, first row, first node
     auto emit = [&](int last_row) {
         if (count == 0) return;
-        if (tasks) {
-            Task t;
-            t.row = (int)(r0 + srow);
-            t.k0 = sk;
-            t.cnt = count | ((last_row - srow + 1) << 8);
-            t.dom = d;
-            tasks[nt] = t;
-        }
+        if (tasks) put_task(tasks, nt, r0 + srow, sk, count, last_row - srow + 1, d, 0, D.W);
         nt++;
         count = 0;
     };
@@ -242,6 +258,39 @@ __device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0,
     return nt;
 }
 
+// Tasks of one wide row r (count; write when `tasks` is given).
+template <class L>
+__device__ int wide_row_tasks(const DomDev &D, int d, const RowWord *rows, long r, Task *tasks) {
+    const int W = D.W, maxw = task_max_words<L>();
+    int nt = 0, count = 0, k0 = 0, wlo = 0, whi = 0;
+    auto emit = [&]() {
+        if (count == 0) return;
+        if (tasks) put_task(tasks, nt, r, k0, count, 1, d, wlo, whi - wlo + 1);
+        nt++;
+        count = 0;
+    };
+    for (int w = 0; w < W; w++) {
+        const RowWord rw = rows[D.word_off + r * W + w];
+        unsigned long long m = rw.mask;
+        int k = rw.pb;
+        while (m) {
+            const int x = 64 * w + __ffsll((long long)m) - 1;
+            m &= m - 1ull;
+            const int hi = min(W - 1, (x + 1) >> 6);
+            if (count > 0 && (count == 64 || hi - wlo + 1 > maxw)) emit();
+            if (count == 0) {
+                k0 = k;
+                wlo = x == 0 ? 0 : (x - 1) >> 6;
+            }
+            whi = hi;
+            count++;
+            k++;
+        }
+    }
+    emit();
+    return nt;
+}
+
 template <class L>
 __global__ __launch_bounds__(BLK) void k_row_ntasks(Geo g, long R, const RowWord *rows, int32_t *nt) {
     const long rg = (long)blockIdx.x * BLK + threadIdx.x;
@@ -249,7 +298,10 @@ __global__ __launch_bounds__(BLK) void k_row_ntasks(Geo g, long R, const RowWord
     const int d = find_dom(g.row_off, g.ndom, rg);
     const DomDev &D = g.doms[d];
     const long r = rg - D.row_off;
-    nt[rg] = (r % D.box.ny == 0) ? plane_tasks<L>(D, d, rows, r, nullptr) : 0;
+    if (task_max_rows<L>(D) >= 1)
+        nt[rg] = (r % D.box.ny == 0) ? plane_tasks<L>(D, d, rows, r, nullptr) : 0;
+    else
+        nt[rg] = wide_row_tasks<L>(D, d, rows, r, nullptr);
 }
 
 template <class L>
@@ -260,7 +312,11 @@ __global__ __launch_bounds__(BLK) void k_row_tasks(Geo g, long R, const RowWord 
     const int d = find_dom(g.row_off, g.ndom, rg);
     const DomDev &D = g.doms[d];
     const long r = rg - D.row_off;
-    if (r % D.box.ny == 0) plane_tasks<L>(D, d, rows, r, tasks + tbase[rg]);
+    if (task_max_rows<L>(D) >= 1) {
+        if (r % D.box.ny == 0) plane_tasks<L>(D, d, rows, r, tasks + tbase[rg]);
+    } else {
+        wide_row_tasks<L>(D, d, rows, r, tasks + tbase[rg]);
+    }
 }
 
 // reactive links per compact node, then the link records

@@ -58,12 +58,17 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // with cross-lane shuffles ----
     const int TY = nr + 2;
     const int NSL = (L::DIM == 3 ? 3 : 1) * TY;
-    const bool slots_fit = NSL * W <= 64;
+    const int wlo = tk.wlo, nwd = tk.nwd;   // window of words of each table row
+    const bool slots_fit = NSL * nwd <= 64;
     unsigned long long wm = 0ull;
     int wpb = 0;
-    if (slots_fit && lane < NSL * W) {
-        const int sl = lane / W, w = lane - sl * W;
-        int yy = y0 - 1 + sl % TY, zz = L::DIM == 3 ? z - 1 + sl / TY : z, xx = 0, fc;
+    if (slots_fit && lane < NSL * nwd) {
+        // small quotients by float reciprocal (exact: the dividend is offset by
+        // one half, far from a multiple of the divisor)
+        const int sl = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nwd));
+        const int w = wlo + (lane - sl * nwd);
+        const int sq = (int)(((float)sl + 0.5f) * __builtin_amdgcn_rcpf((float)TY));
+        int yy = y0 - 1 + (sl - sq * TY), zz = L::DIM == 3 ? z - 1 + sq : z, xx = 0, fc;
         if (wrap_site(b, xx, yy, zz, &fc)) {
             const RowWord rw = rows[(long)(yy + b.ny * zz) * W + w];
             wm = rw.mask;
@@ -78,7 +83,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // (a row's first compact index is the base of its first word)
     int ry = 0;
     for (int j = 1; j < nr; j++) {
-        const int pbj = __shfl(wpb, ((L::DIM == 3 ? TY : 0) + j + 1) * W, 64);
+        const int pbj = __shfl(wpb, ((L::DIM == 3 ? TY : 0) + j + 1) * nwd, 64);
         if (k >= pbj) ry = j;
     }
     const int y = y0 + ry;
@@ -112,13 +117,15 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             // the shuffles run on every lane: a shuffle reads zero from a lane
             // that is inactive at that point
             const int xs = min(max(xw, 0), b.nx - 1);
-            const int src = slots_fit ? (((L::DIM == 3 ? (1 - L::ez[i]) * TY : 0) + ry + 1 - L::ey[i]) * W + (xs >> 6)) : 0;
+            const int tw = (xs >> 6) - wlo;
+            const bool in_tab = slots_fit && tw >= 0 && tw < nwd;
+            const int src = in_tab ? (((L::DIM == 3 ? (1 - L::ez[i]) * TY : 0) + ry + 1 - L::ey[i]) * nwd + tw) : 0;
             const unsigned lo = __shfl((unsigned)(wm & 0xffffffffull), src, 64);
             const unsigned hi = __shfl((unsigned)(wm >> 32), src, 64);
             const int pb = __shfl(wpb, src, 64);
             if (out) {
                 kk[i] = -2;
-            } else if (!slots_fit || shifted) {
+            } else if (!in_tab || shifted) {
                 kk[i] = nb_compact(rows, W, b, xx, yy, zz);
             } else {
                 const unsigned long long m = ((unsigned long long)hi << 32) | lo;

@@ -27,21 +27,27 @@ struct RowSlots {
     unsigned long long wm;
     int wpb;
     int TY;       // table rows per plane, nr + 2
+    int wlo, nwd; // window of words of each table row
     bool fit;     // the table fits the 64 lanes
 };
 
 template <class L>
 __device__ __forceinline__ RowSlots load_row_slots(const RowWord *__restrict__ rows, const Box &b,
-                                                   int W, int lane, int y0, int z, int nr) {
+                                                   int W, int lane, int y0, int z, int nr, int wlo,
+                                                   int nwd) {
     RowSlots rs;
     rs.TY = nr + 2;
+    rs.wlo = wlo;
+    rs.nwd = nwd;
     const int NSL = (L::DIM == 3 ? 3 : 1) * rs.TY;
-    rs.fit = NSL * W <= 64;
+    rs.fit = NSL * nwd <= 64;
     rs.wm = 0ull;
     rs.wpb = 0;
-    if (rs.fit && lane < NSL * W) {
-        const int sl = lane / W, w = lane - sl * W;
-        int yy = y0 - 1 + sl % rs.TY, zz = L::DIM == 3 ? z - 1 + sl / rs.TY : z, xx = 0, fc;
+    if (rs.fit && lane < NSL * nwd) {
+        const int sl = (int)(((float)lane + 0.5f) * __builtin_amdgcn_rcpf((float)nwd));
+        const int w = wlo + (lane - sl * nwd);
+        const int sq = (int)(((float)sl + 0.5f) * __builtin_amdgcn_rcpf((float)rs.TY));
+        int yy = y0 - 1 + (sl - sq * rs.TY), zz = L::DIM == 3 ? z - 1 + sq : z, xx = 0, fc;
         if (wrap_site(b, xx, yy, zz, &fc)) {
             const RowWord rw = rows[(long)(yy + b.ny * zz) * W + w];
             rs.wm = rw.mask;
@@ -56,7 +62,7 @@ template <class L>
 __device__ __forceinline__ int task_row(const RowSlots &rs, int W, int nr, int k) {
     int ry = 0;
     for (int j = 1; j < nr; j++) {
-        const int pbj = __shfl(rs.wpb, ((L::DIM == 3 ? rs.TY : 0) + j + 1) * W, 64);
+        const int pbj = __shfl(rs.wpb, ((L::DIM == 3 ? rs.TY : 0) + j + 1) * rs.nwd, 64);
         if (k >= pbj) ry = j;
     }
     return ry;
@@ -97,13 +103,15 @@ __device__ __forceinline__ void classify(const RowWord *__restrict__ rows, const
             if ((yy < 0 || yy >= b.ny) && !b.per[1]) out = true;
             if ((zz < 0 || zz >= b.nz) && !b.per[2]) out = true;
             const int xs = min(max(xw, 0), b.nx - 1);
-            const int src = rs.fit ? (((L::DIM == 3 ? (1 - L::ez[i]) * rs.TY : 0) + ry + 1 - L::ey[i]) * W + (xs >> 6)) : 0;
+            const int tw = (xs >> 6) - rs.wlo;
+            const bool in_tab = rs.fit && tw >= 0 && tw < rs.nwd;
+            const int src = in_tab ? (((L::DIM == 3 ? (1 - L::ez[i]) * rs.TY : 0) + ry + 1 - L::ey[i]) * rs.nwd + tw) : 0;
             const unsigned lo = __shfl((unsigned)(rs.wm & 0xffffffffull), src, 64);
             const unsigned hi = __shfl((unsigned)(rs.wm >> 32), src, 64);
             const int pb = __shfl(rs.wpb, src, 64);
             if (out) {
                 kk[i] = -2;
-            } else if (!rs.fit || shifted) {
+            } else if (!in_tab || shifted) {
                 kk[i] = nb_compact(rows, W, b, xx, yy, zz);
             } else {
                 const unsigned long long m = ((unsigned long long)hi << 32) | lo;

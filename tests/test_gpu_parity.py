@@ -247,3 +247,34 @@ def test_invalid_pointer_rejected():
     with pytest.raises(LbmError) as ei:
         _lib.lbm_get_fields(sim.ctx, host.data_ptr())
     assert ei.value.status == -1
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_wide_rows_3d(precision):
+    """Rows of 10 words (600 wide): tasks hold a window of row words instead of
+    whole rows; random spheres, an inlet and periodic x wrap."""
+    rng = np.random.default_rng(21)
+    nx, ny, nz = 600, 10, 12
+    z, y, x = np.meshgrid(np.arange(nz), np.arange(ny), np.arange(nx), indexing="ij")
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    normals = np.zeros((nz, ny, nx, 3))
+    for c, r in zip(rng.uniform(0, [nx, ny, nz], size=(60, 3)), rng.uniform(2.0, 4.5, size=60)):
+        d = np.stack([x - c[0], y - c[1], z - c[2]], -1)
+        for a, n in enumerate((nx, ny, nz)):
+            d[..., a] -= n * np.round(d[..., a] / n)
+        dist = np.sqrt((d ** 2).sum(-1))
+        inside = dist <= r
+        solid[inside] = 1
+        normals[inside] = d[inside] / np.maximum(dist[inside], 1e-12)[:, None]
+    case = Case(name="wide3d", dim=3, nx=nx, ny=ny, nz=nz, q=19, solid=solid, normals=normals,
+                tau_ns=0.9, tau_ad=0.8, j0=0.5, force=(2e-5, 0.0, 0.0), c_eq=1.0, k_r=2e-2,
+                v_m=0.1, inlet_axis=2, c_in=2.0, c0=1.0, c_ref=1.0)
+    _assert_parity(case, precision, 80)
+
+
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_wide_rows_2d_tilted(precision):
+    """A 1500-wide tilted band (24 words per row, shifted x wrap, Poiseuille
+    flow, dissolution from the walls)."""
+    case = configs.tilted_channel(pe=10.0, da=1.0, n=1500, shift=866, width=60.0, steps=0)
+    _assert_parity(case, precision, 60)
