@@ -101,6 +101,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *nodeof = take(4 * N), *kof = take(4 * N), *lbase = take(4 * N);
     char *flags = take(4 * N), *rmask = take(4 * N), *cnt = take(4 * N), *sidx = take(4 * N);
     char *phi = take(8 * N), *kr = take(8 * N), *nrm = take(24 * N), *solid = take(N);
+    char *phif = take(8 * S), *phis = take(8 * L);
     char *lbeta = take(ts * L), *lq = take(ts * L), *lq2 = take(ts * L), *lnode = take(4 * L),
          *lsolid = take(4 * L),
          *ldir = take(L);
@@ -108,6 +109,8 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *bsum = take(4 * ((N + 4095) / 4096 + 64));
     char *dpart = take(16 * ((N + 255) / 256 + 1));
     char *dacc = take(8 * 64), *iacc = take(4 * 64);
+    const long nxp = (N + 255) / 256 + 1;
+    char *xpart = take(8 * nxp);
     // phase change (single lattice): old compact map, candidates, records
     const bool pc = nd == 1 && p[0].phase_change != 0;
     const long ev_cap = pc ? (N < 65536 ? N : 65536) : 0;
@@ -135,6 +138,8 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->flags = (uint32_t *)flags; c->rmask = (uint32_t *)rmask;
         c->cnt = (int32_t *)cnt; c->sidx = (int32_t *)sidx;
         c->phi = (double *)phi; c->kr = (double *)kr; c->nrm = (double *)nrm;
+        c->phif = (double *)phif; c->phis = (double *)phis;
+        c->phi_stale = false;
         c->solid = (uint8_t *)solid;
         c->lbeta = lbeta; c->lq = lq; c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
         c->lqb[0] = lq; c->lqb[1] = lq2; c->lq_next = 1;
@@ -144,6 +149,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->bsum = (int32_t *)bsum;
         c->dpart = (double *)dpart;
         c->dacc = (double *)dacc; c->iacc = (int32_t *)iacc;
+        c->xpart = (double *)xpart; c->n_xpart = nxp;
     }
     return off;
 }
@@ -407,7 +413,8 @@ static hipError_t build_graph(Ctx *c, int n) {
 static hipError_t phase_change_pass(Ctx *c, bool *capacity) {
     int64_t nev = 0;
     bool ovf = false;
-    hipError_t e = launch_events(*c, &nev, &ovf);
+    hipError_t e = launch_phi_flush(*c);
+    if (e == hipSuccess) e = launch_events(*c, &nev, &ovf);
     if (e != hipSuccess) return e;
     if (ovf) *capacity = true;
     if (nev == 0) return hipSuccess;
@@ -997,7 +1004,9 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes) {
     h.magic = 0x4c424d5242433031ULL;
     h.N = c->N; h.Q = c->Q; h.precision = c->p.precision; h.step = c->step; h.n_events = c->n_events;
     double wex = 0;
-    hipError_t e = hipMemcpyAsync(&wex, c->dacc, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    hipError_t e = launch_fold_exchange(*c);
+    if (e == hipSuccess) e = launch_phi_flush(*c);
+    if (e == hipSuccess) e = hipMemcpyAsync(&wex, c->dacc, sizeof(double), hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_err(c, e, "save_state");
     h.wall_ex = wex;
@@ -1069,6 +1078,7 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
         e = hipMemcpyAsync((char *)c->g[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
     double wex = h.wall_ex;
     if (e == hipSuccess) e = hipMemcpyAsync(c->dacc, &wex, sizeof(double), hipMemcpyHostToDevice, c->stream);
+    if (e == hipSuccess) e = launch_zero_exchange(*c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_err(c, e, "load_state");
     c->step = h.step;

@@ -555,6 +555,7 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, c.soff, (long)t2[0], t2[1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t2[1] != tot) return hipErrorUnknown;  // every link has exactly one solid end
+    if ((e = launch_phi_gather(c, nf, t2[0])) != hipSuccess) return e;
     return hipStreamSynchronize(st);
 }
 

@@ -26,7 +26,7 @@ struct StepArgs {
     const int32_t *__restrict__ lbase;   // compact index -> first reactive link
     const T *__restrict__ lbeta;         // per link: (1 - k)/(1 + k)
     T *__restrict__ lq;                  // per link: mass exchanged in this step
-    double *__restrict__ phi;            // dense
+    double *__restrict__ phif;           // [S] solid fraction of fluid nodes, compact order
     long ntasks;
     long S;                              // stride between directions
 };
@@ -80,6 +80,13 @@ struct Ctx {
     int32_t *cnt;            // scratch [N]
     int32_t *sidx;           // scratch [N]
     double *phi, *kr, *nrm;  // [N], [N], [N][3]
+    // working copies of the solid fraction that the step kernels update with
+    // coalesced accesses: fluid nodes in compact order, solid interface nodes
+    // in solid-side order; phi[] is brought up to date from them (flush)
+    // before anything reads it, and they are refilled from phi[] (gather)
+    // whenever the geometry is rebuilt
+    double *phif, *phis;     // [S], [max_links]
+    bool phi_stale;          // phi[] lags the working copies
     uint8_t *solid;          // [N]
     void *lbeta, *lq;        // [max_links] of T; lq: exchanges of the last step
     void *lqb[2];            // the two exchange buffers lq alternates between
@@ -104,6 +111,9 @@ struct Ctx {
     bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions
     double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums
+    double *xpart;           // [n_xpart] wall exchange of the solid-side workgroups, one
+                             // slot per workgroup, folded into dacc[0] when read
+    long n_xpart;
     int32_t *iacc;           // device int accumulators
     size_t ws_bytes;
     int cur;                 // buffer holding the current state
@@ -135,6 +145,10 @@ hipError_t launch_fields(Ctx &c, double *rho, double *u, double *cc, double *phi
 hipError_t launch_pops(Ctx &c, double *f, double *g);
 hipError_t launch_exchange(Ctx &c, double *q);
 hipError_t launch_diag(Ctx &c, double *sums, int32_t *nan_flag);
+hipError_t launch_fold_exchange(Ctx &c);
+hipError_t launch_phi_gather(Ctx &c, long nf, long nsif);
+hipError_t launch_phi_flush(Ctx &c);
+hipError_t launch_zero_exchange(Ctx &c);
 hipError_t launch_rest_check(Ctx &c, bool *at_rest);
 hipError_t launch_events(Ctx &c, int64_t *n_events, bool *overflow);
 hipError_t launch_relayout(Ctx &c);

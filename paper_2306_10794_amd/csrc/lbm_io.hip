@@ -139,6 +139,32 @@ __global__ __launch_bounds__(BLK) void k_sum_parts(const double *part, long nb, 
     }
 }
 
+// adds the per-workgroup wall-exchange slots to acc[0] (fixed order: lane
+// stride, then the block reduction) and clears them
+__global__ __launch_bounds__(BLK) void k_fold_exchange(double *part, long n, double *acc) {
+    double a = 0.0;
+    for (long j = threadIdx.x; j < n; j += BLK) {
+        const double v = part[j];
+        if (v != 0.0) {
+            a += v;
+            part[j] = 0.0;
+        }
+    }
+    a = block_sum(a);
+    if (threadIdx.x == 0) acc[0] += a;
+}
+
+hipError_t launch_fold_exchange(Ctx &c) {
+    hipLaunchKernelGGL(k_fold_exchange, dim3(1), dim3(BLK), 0, c.stream, c.xpart, c.n_xpart, c.dacc);
+    return hipGetLastError();
+}
+
+hipError_t launch_zero_exchange(Ctx &c) {
+    hipLaunchKernelGGL(k_zero_f64, dim3((c.n_xpart + BLK - 1) / BLK), dim3(BLK), 0, c.stream, c.xpart,
+                       c.n_xpart);
+    return hipGetLastError();
+}
+
 template <class L, typename T>
 static hipError_t init_impl(Ctx &c, const double *rho, const double *u, const double *cc) {
     const long nb = (c.N + BLK - 1) / BLK;
@@ -147,7 +173,8 @@ static hipError_t init_impl(Ctx &c, const double *rho, const double *u, const do
                        c.dnode_off, c.ndom, c.kof, rho, u, cc, (T *)c.f[0], (T *)c.g[0],
                        (T *)c.f[1], (T *)c.g[1]);
     hipLaunchKernelGGL(k_zero_f64, dim3(1), dim3(BLK), 0, c.stream, c.dacc, 8);
-    return hipGetLastError();
+    hipError_t e = hipGetLastError();
+    return e == hipSuccess ? launch_zero_exchange(c) : e;
 }
 
 hipError_t launch_init(Ctx &c, const double *rho, const double *u, const double *cc) {
@@ -158,6 +185,8 @@ hipError_t launch_init(Ctx &c, const double *rho, const double *u, const double 
 template <class L, typename T>
 static hipError_t fields_impl(Ctx &c, double *rho, double *u, double *cc, double *phi, uint8_t *type) {
     const long nb = (c.N + BLK - 1) / BLK;
+    hipError_t e = launch_phi_flush(c);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL((k_fields<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.doms,
                        c.dnode_off, c.ndom, c.kof, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
                        c.phi, rho, u, cc, phi, type);
@@ -199,12 +228,15 @@ hipError_t launch_exchange(Ctx &c, double *q) {
 template <class L, typename T>
 static hipError_t diag_impl(Ctx &c, double *sums, int32_t *nan_flag) {
     const long nb = (c.N + BLK - 1) / BLK;
+    hipError_t e = launch_fold_exchange(c);
+    if (e == hipSuccess) e = launch_phi_flush(c);
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero_flag, dim3(1), dim3(1), 0, c.stream, c.iacc + 4);
     hipLaunchKernelGGL((k_diag<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.doms,
                        c.dnode_off, c.ndom, c.kof, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
                        c.phi, c.dpart, c.iacc + 4);
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(BLK), 0, c.stream, c.dpart, nb, c.dacc + 1);
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(sums, c.dacc, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
     if (e != hipSuccess) return e;

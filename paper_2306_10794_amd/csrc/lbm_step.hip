@@ -259,7 +259,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
                 gv[i] = (T)g;
             }
         }
-        if (sneg != 0.0) a.phi[n] += D.vma * sneg;
+        if (sneg != 0.0) a.phif[k] += D.vma * sneg;
     }
     R dC = R(0);
 #pragma unroll
@@ -275,22 +275,22 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
 }
 
 // dissolution side of the solid fraction, per solid interface node, links in
-// ascending direction order; also the step's total exchange into acc[0].  A
-// solid node has at most Q - 1 links: all their indices, then all their
-// exchanges, are loaded before the ordered sum.
+// ascending direction order; also the step's total exchange, added to this
+// workgroup's own slot xpart[blockIdx.x] (no atomics: the slots are folded
+// into the running total when it is read).  A solid node has at most Q - 1
+// links: all their indices, then all their exchanges, are loaded before the
+// ordered sum.
 template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ sif,
-                                                   const int32_t *__restrict__ soff,
+__global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ soff,
                                                    const int32_t *__restrict__ slinks,
                                                    const int32_t *__restrict__ sdom,
                                                    const DomDev *__restrict__ doms,
-                                                   const T *__restrict__ lq, double *__restrict__ phi,
-                                                   long nsif, double *acc) {
+                                                   const T *__restrict__ lq, double *__restrict__ phis,
+                                                   long nsif, double *__restrict__ xpart) {
     constexpr int M = L::Q - 1;
     const long j = (long)blockIdx.x * BLK + threadIdx.x;
     double tot = 0.0;
     if (j < nsif) {
-        const int s = sif[j];
         const int k0 = soff[j], nk = soff[j + 1] - k0;
         int li[M];
 #pragma unroll
@@ -305,10 +305,10 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
             tot += v;
             if (v > 0.0) pos += v;
         }
-        phi[s] -= doms[sdom[j]].vma * pos;
+        phis[j] -= doms[sdom[j]].vma * pos;
     }
     tot = block_sum(tot);
-    if (threadIdx.x == 0 && tot != 0.0) atomicAdd(acc, tot);
+    if (threadIdx.x == 0 && tot != 0.0) xpart[blockIdx.x] += tot;
 }
 
 template <typename T>
@@ -325,7 +325,7 @@ static StepArgs<T> step_args(Ctx &c) {
     a.lbase = c.lbase;
     a.lbeta = (const T *)c.lbeta;
     a.lq = (T *)c.lq;
-    a.phi = c.phi;
+    a.phif = c.phif;
     a.ntasks = c.n_tasks;
     a.S = c.S;
     return a;
@@ -372,8 +372,8 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
     if (ev) (void)hipEventRecord(ev[2], ps);
     if (c.n_sif > 0) {
         const long nb2 = (c.n_sif + BLK - 1) / BLK;
-        hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, ps, c.sif, c.soff,
-                           c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phi, (long)c.n_sif, c.dacc);
+        hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
+                           c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[3], ps);
@@ -384,6 +384,7 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
     }
     c.lq_next = 1 - b;
     c.cur = 1 - c.cur;
+    c.phi_stale = true;
     return e;
 }
 
@@ -399,6 +400,46 @@ hipError_t join_side(Ctx &c) {
     c.phi_pending[0] = c.phi_pending[1] = false;
     c.last_phi = -1;
     return e;
+}
+
+// working copies of the solid fraction <-> phi[] (site order)
+__global__ __launch_bounds__(BLK) void k_phi_gather(long nf, const int32_t *__restrict__ nodeof,
+                                                    long nsif, const int32_t *__restrict__ sif,
+                                                    const double *__restrict__ phi,
+                                                    double *__restrict__ phif, double *__restrict__ phis) {
+    const long t = (long)blockIdx.x * BLK + threadIdx.x;
+    if (t < nf) phif[t] = phi[nodeof[t]];
+    if (t < nsif) phis[t] = phi[sif[t]];
+}
+
+__global__ __launch_bounds__(BLK) void k_phi_scatter(long nf, const int32_t *__restrict__ nodeof,
+                                                     long nsif, const int32_t *__restrict__ sif,
+                                                     const double *__restrict__ phif,
+                                                     const double *__restrict__ phis,
+                                                     double *__restrict__ phi) {
+    const long t = (long)blockIdx.x * BLK + threadIdx.x;
+    if (t < nf) phi[nodeof[t]] = phif[t];
+    if (t < nsif) phi[sif[t]] = phis[t];
+}
+
+hipError_t launch_phi_gather(Ctx &c, long nf, long nsif) {
+    const long n = nf > nsif ? nf : nsif;
+    if (n > 0)
+        hipLaunchKernelGGL(k_phi_gather, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, c.stream, nf, c.nodeof,
+                           nsif, c.sif, c.phi, c.phif, c.phis);
+    c.phi_stale = false;
+    return hipGetLastError();
+}
+
+hipError_t launch_phi_flush(Ctx &c) {
+    if (!c.phi_stale) return hipSuccess;
+    const long nf = c.n_fluid, nsif = c.n_sif;
+    const long n = nf > nsif ? nf : nsif;
+    if (n > 0)
+        hipLaunchKernelGGL(k_phi_scatter, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, c.stream, nf, c.nodeof,
+                           nsif, c.sif, c.phif, c.phis, c.phi);
+    c.phi_stale = false;
+    return hipGetLastError();
 }
 
 }  // namespace lbm
