@@ -81,6 +81,29 @@ def test_tilted_channel_flow(precision):
     _assert_parity(_tilted(), precision, 300)
 
 
+@pytest.mark.parametrize("dim", [2, 3])
+def test_fp32_long_run_steady_channel(dim):
+    """FP32 deviation storage over a run long enough for a force-driven
+    channel with reactive walls (H = 62 fluid rows) to approach its steady
+    profile (12,000 steps, about half the viscous time H^2/nu).  A relative
+    bias b in the momentum or mass that each collision returns (lattice
+    weights rounded to FP32 and used as they are, for instance) acts at every
+    step; near steady state it shifts the velocity by about omega b H^2/(8 nu),
+    several 1e-5 for b = 3e-8.  Short runs cannot tell a biased FP32 collision
+    from an unbiased one; this one can."""
+    h = 62
+    nx, ny, nz, q = (4, h + 2, 1, 9) if dim == 2 else (4, h + 2, 4, 19)
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, -1, :] = 1
+    nu = (1.0 - 0.5) / 3.0
+    force = 0.04 * 8.0 * nu / h ** 2   # centre-line velocity 0.04
+    case = Case(name=f"long channel {dim}D", dim=dim, nx=nx, ny=ny, nz=nz, q=q, solid=solid,
+                tau_ns=1.0, tau_ad=0.9, j0=0.3 if dim == 2 else -1.0, force=(force, 0.0, 0.0),
+                c_eq=1.0, k_r=2e-3, v_m=0.05, c0=0.2, c_ref=0.5)
+    _assert_parity(case, FP32, 12000)
+
+
 @pytest.mark.parametrize("precision", [FP64, FP32])
 def test_spheres_3d_inlet_outlet(precision):
     """3D D3Q19 sphere pack with an inlet and a zero-gradient outlet on z,
