@@ -220,12 +220,35 @@ __device__ __forceinline__ void put_task(Task *tasks, int nt, long row, int k0, 
     tasks[nt] = t;
 }
 
-// Walk the rows of the plane starting at domain row r0 (y = 0); count the
-// tasks, and write them when `tasks` is given (narrow rows).
+// Task order.  In 3D the tasks are listed slab by slab: rows y in
+// [s SL, (s + 1) SL) of every plane, planes in order, then the next slab.
+// Consecutive tasks run on one XCD (the launch keeps runs of tiles
+// together), so the tasks an XCD has in flight pull from a few planes of one
+// slab, whose lines its L2 still holds from the neighbouring planes' tasks;
+// in plane order the same reuse spans whole planes, more than the L2 keeps.
+// A 2D lattice keeps row order (one slab).
 template <class L>
-__device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0, Task *tasks) {
+__device__ __forceinline__ int slab_rows(const DomDev &D) {
+    if (L::DIM == 2) return D.box.ny;
+    const int s = 8192 / D.box.nx;            // about 32 rows of 256 nodes
+    return s < 1 ? 1 : (s > D.box.ny ? D.box.ny : s);
+}
+
+// position of domain row r in the task order
+template <class L>
+__device__ __forceinline__ long row_pos(const DomDev &D, long r) {
+    const int SL = slab_rows<L>(D), ny = D.box.ny;
+    const int y = (int)(r % ny), z = (int)(r / ny);
+    const int sl = y / SL, h = min(SL, ny - sl * SL);
+    return (long)sl * SL * D.box.nz + (long)z * h + (y - sl * SL);
+}
+
+// Walk rows ya .. yb - 1 of the plane starting at domain row r0 (y = 0);
+// count the tasks, and write them when `tasks` is given (narrow rows).
+template <class L>
+__device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0, int ya, int yb,
+                           Task *tasks) {
     const int M = task_max_rows<L>(D);
-    const int ny = D.box.ny;
     int nt = 0;
     int count = 0, srow = 0, sk = 0;   // the open run: nodes, first row, first node
     auto emit = [&](int last_row) {
@@ -234,8 +257,8 @@ __device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0,
         nt++;
         count = 0;
     };
-    int last = 0;
-    for (int y = 0; y < ny; y++) {
+    int last = ya;
+    for (int y = ya; y < yb; y++) {
         const long r = r0 + y;
         int c = row_fluid(D, rows, r);
         if (c == 0) continue;
@@ -298,10 +321,14 @@ __global__ __launch_bounds__(BLK) void k_row_ntasks(Geo g, long R, const RowWord
     const int d = find_dom(g.row_off, g.ndom, rg);
     const DomDev &D = g.doms[d];
     const long r = rg - D.row_off;
-    if (task_max_rows<L>(D) >= 1)
-        nt[rg] = (r % D.box.ny == 0) ? plane_tasks<L>(D, d, rows, r, nullptr) : 0;
-    else
-        nt[rg] = wide_row_tasks<L>(D, d, rows, r, nullptr);
+    const long pos = D.row_off + row_pos<L>(D, r);
+    if (task_max_rows<L>(D) >= 1) {
+        // the first row of each slab segment of a plane walks the segment
+        const int SL = slab_rows<L>(D), y = (int)(r % D.box.ny);
+        nt[pos] = y % SL == 0 ? plane_tasks<L>(D, d, rows, r - y, y, min(y + SL, D.box.ny), nullptr) : 0;
+    } else {
+        nt[pos] = wide_row_tasks<L>(D, d, rows, r, nullptr);
+    }
 }
 
 template <class L>
@@ -312,10 +339,12 @@ __global__ __launch_bounds__(BLK) void k_row_tasks(Geo g, long R, const RowWord 
     const int d = find_dom(g.row_off, g.ndom, rg);
     const DomDev &D = g.doms[d];
     const long r = rg - D.row_off;
+    const long pos = D.row_off + row_pos<L>(D, r);
     if (task_max_rows<L>(D) >= 1) {
-        if (r % D.box.ny == 0) plane_tasks<L>(D, d, rows, r, tasks + tbase[rg]);
+        const int SL = slab_rows<L>(D), y = (int)(r % D.box.ny);
+        if (y % SL == 0) plane_tasks<L>(D, d, rows, r - y, y, min(y + SL, D.box.ny), tasks + tbase[pos]);
     } else {
-        wide_row_tasks<L>(D, d, rows, r, tasks + tbase[rg]);
+        wide_row_tasks<L>(D, d, rows, r, tasks + tbase[pos]);
     }
 }
 
