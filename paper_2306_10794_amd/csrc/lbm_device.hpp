@@ -50,6 +50,15 @@ struct D3Q19 {
 
 constexpr int BLK = 256;
 
+// bit mask of the directions whose component along axis a (0 x, 1 y, 2 z) is s
+template <class L>
+__host__ __device__ constexpr uint32_t dir_mask(int a, int s) {
+    uint32_t m = 0u;
+    for (int i = 0; i < L::Q; i++)
+        if ((a == 0 ? L::ex[i] : a == 1 ? L::ey[i] : L::ez[i]) == s) m |= 1u << i;
+    return m;
+}
+
 // Node flags of the geometry pass (dense, uint32 per node; not read per step)
 //   bits 0..Q-1 : fluid view, upstream site x - e_i is solid or outside a
 //                 non-periodic face
