@@ -160,10 +160,11 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     constexpr int NW = (int)(sizeof(T) / 4);
     __shared__ uint32_t sbeta[WV][Q][NW][64];
     const int wv = threadIdx.x >> 6;
+    int lp = lb;   // the node's next link (its links follow direction order)
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (rbc & (1u << i)) {
-            const uint32_t *p = (const uint32_t *)(a.lbeta + lb + __popc(rbc & ((1u << i) - 1u)));
+            const uint32_t *p = (const uint32_t *)(a.lbeta + lp++);
 #pragma unroll
             for (int w = 0; w < NW; w++)
                 __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(p + w),
@@ -217,15 +218,24 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const R ux = mx * irho, uy = my * irho, uz = mz * irho;
     const R uu = ux * ux + uy * uy + uz * uz;
     const R uF = ux * D.F[0] + uy * D.F[1] + uz * D.F[2];
+    // f* = f + om (f_eq - f) + ff S, a direction and its opposite together:
+    // e.u, e.m and e.F change sign with e, so f*_(i, opp i) = (1 - om) f + A
+    // +- B with the even part A = w (om (drho + rho (9/2 (e.u)^2 - 3/2 u.u))
+    // + ff (9 (e.u)(e.F) - 3 u.F)) and the odd part B = 3 w (om e.m + ff e.F)
+    const R om = D.omega_f, ff = D.force_fac, om1 = R(1) - om;
+    a.fout[k] = (T)(om1 * fp[0] + R(L::w[0]) * (om * (drho - R(1.5) * rho * uu) - R(3) * ff * uF));
 #pragma unroll
-    for (int i = 0; i < Q; i++) {
+    for (int i = 1; i < Q; i++) {
+        if (L::opp[i] < i) continue;
+        const int o = L::opp[i];
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
         const R em = R(L::ex[i]) * mx + R(L::ey[i]) * my + R(L::ez[i]) * mz;
         const R eF = R(L::ex[i]) * D.F[0] + R(L::ey[i]) * D.F[1] + R(L::ez[i]) * D.F[2];
         const R wi = R(L::w[i]);
-        const R feq = wi * (drho + R(3) * em + rho * (R(4.5) * eu * eu - R(1.5) * uu));
-        const R src = wi * (R(3) * (eF - uF) + R(9) * eu * eF);
-        a.fout[(long)i * S + k] = (T)(fp[i] + D.omega_f * (feq - fp[i]) + D.force_fac * src);
+        const R A = wi * (om * (drho + rho * (R(4.5) * eu * eu - R(1.5) * uu)) + ff * (R(9) * eu * eF - R(3) * uF));
+        const R B = R(3) * wi * (om * em + ff * eF);
+        a.fout[(long)i * S + k] = (T)(om1 * fp[i] + (A + B));
+        a.fout[(long)o * S + k] = (T)(om1 * fp[o] + (A - B));
     }
 
     // ---- solute: plane faces, reactive links, collision ----
@@ -248,6 +258,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // whose beta already carries k/gamma).  q = g_in - g_out crossed the link.
     if (rbc) {
         double sneg = 0.0;
+        int l = lb;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             if (rbc & (1u << i)) {
@@ -262,10 +273,11 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
                     bt = __builtin_bit_cast(T, lo | (hi << 32));
                 }
                 const R beta = (R)bt;
+                // (1 - beta) w C_eq + beta g_src: exactly g_src at beta = 1
                 const R g = (R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv;
                 const T qv = (T)(g - own);
-                a.lq[lb + __popc(rbc & ((1u << i) - 1u))] = qv;
-                if (qv < T(0)) sneg -= (double)qv;
+                a.lq[l++] = qv;
+                sneg -= (double)(qv < T(0) ? qv : T(0));
                 gv[i] = (T)g;
             }
         }
@@ -275,12 +287,19 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
 #pragma unroll
     for (int i = 0; i < Q; i++) dC += (R)gv[i];
     const R C = D.c_ref + dC;
+    // g* = g + omg (g_eq - g), g_eq = ws (dC + C e.u / c_s^2): in pairs as
+    // above, (1 - omg) g + As +- Bs with As = omg ws dC, Bs = omg ws C e.u / c_s^2
+    const R omg = D.omega_g, omg1 = R(1) - omg, Cu = omg * C * D.inv_cs2s;
+    a.gout[k] = (T)(omg1 * (R)gv[0] + omg * sol_w<L>(D, 0) * dC);
 #pragma unroll
-    for (int i = 0; i < Q; i++) {
+    for (int i = 1; i < Q; i++) {
+        if (L::opp[i] < i) continue;
+        const int o = L::opp[i];
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
-        const R gi = (R)gv[i];
-        const R geq = sol_w<L>(D, i) * (dC + C * eu * D.inv_cs2s);
-        a.gout[(long)i * S + k] = (T)(gi + D.omega_g * (geq - gi));
+        const R ws = sol_w<L>(D, i);
+        const R As = omg * ws * dC, Bs = ws * Cu * eu;
+        a.gout[(long)i * S + k] = (T)(omg1 * (R)gv[i] + (As + Bs));
+        a.gout[(long)o * S + k] = (T)(omg1 * (R)gv[o] + (As - Bs));
     }
 }
 
