@@ -72,7 +72,7 @@ __device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c
     const Box b = c.D.box;
     const int W = c.D.W;
     const RowWord *__restrict__ rows = a.rows + c.D.word_off;
-    const int y0 = tk.row % b.ny, z = tk.row / b.ny;
+    const int y0 = tk.y0, z = tk.z;
     const int cnt = tk.cnt & 255, nr = tk.cnt >> 8;
     const RowSlots rs = load_row_slots<L>(rows, b, W, lane, y0, z, nr, tk.wlo, tk.nwd);
     c.active = lane < cnt;
@@ -102,13 +102,14 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     for (int i = 0; i < Q; i++)
         gv[i] = c.kk[i] >= 0 ? a.gin[(long)i * S + c.kk[i]] : a.gin[(long)L::opp[i] * S + c.k];
     if (rbc) {
+        int l = c.lb;   // the node's links follow direction order
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             if (rbc & (1u << i)) {
                 const int o = L::opp[i];
                 const R own = (R)gv[i];
                 const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
-                const R beta = (R)a.lbeta[c.lb + __popc(rbc & ((1u << i) - 1u))];
+                const R beta = (R)a.lbeta[l++];
                 gv[i] = (T)((R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv);
             }
         }
@@ -164,11 +165,12 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
         out[j] = nu[j];
     }
     if (rbc) {
+        int ln = c.lb;   // the node's links follow direction order
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             if (rbc & (1u << i)) {
                 const int o = L::opp[i];
-                const int l = c.lb + __popc(rbc & ((1u << i) - 1u));
+                const int l = ln++;
                 const R beta = (R)a.lbeta[l];
                 const bool pulled = D.mech == LBM_PRECOLL && !(rbc & (1u << o));
                 // the forward source value at this step (deviation form)

@@ -79,7 +79,7 @@ struct Task {
     int32_t cnt;               // nodes in the task (1..64) | rows spanned << 8
     int32_t dom;               // domain of the batch
     int32_t wlo, nwd;          // window of row words the task's table holds
-    int32_t pad0, pad1;
+    int32_t y0, z;             // the first row's y and z (row = y0 + ny*z)
 };
 
 struct Box {

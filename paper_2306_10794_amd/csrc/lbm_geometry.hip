@@ -208,7 +208,7 @@ __device__ __forceinline__ int task_max_words() {
 }
 
 __device__ __forceinline__ void put_task(Task *tasks, int nt, long row, int k0, int cnt, int nr,
-                                         int d, int wlo, int nwd) {
+                                         int d, int wlo, int nwd, int ny) {
     Task t;
     t.row = (int32_t)row;
     t.k0 = k0;
@@ -216,7 +216,8 @@ __device__ __forceinline__ void put_task(Task *tasks, int nt, long row, int k0, 
     t.dom = d;
     t.wlo = wlo;
     t.nwd = nwd;
-    t.pad0 = t.pad1 = 0;
+    t.y0 = (int32_t)(row % ny);
+    t.z = (int32_t)(row / ny);
     tasks[nt] = t;
 }
 
@@ -253,7 +254,7 @@ __device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0,
     int count = 0, srow = 0, sk = 0;   // the open run: nodes, first row, first node
     auto emit = [&](int last_row) {
         if (count == 0) return;
-        if (tasks) put_task(tasks, nt, r0 + srow, sk, count, last_row - srow + 1, d, 0, D.W);
+        if (tasks) put_task(tasks, nt, r0 + srow, sk, count, last_row - srow + 1, d, 0, D.W, D.box.ny);
         nt++;
         count = 0;
     };
@@ -288,7 +289,7 @@ __device__ int wide_row_tasks(const DomDev &D, int d, const RowWord *rows, long 
     int nt = 0, count = 0, k0 = 0, wlo = 0, whi = 0;
     auto emit = [&]() {
         if (count == 0) return;
-        if (tasks) put_task(tasks, nt, r, k0, count, 1, d, wlo, whi - wlo + 1);
+        if (tasks) put_task(tasks, nt, r, k0, count, 1, d, wlo, whi - wlo + 1, D.box.ny);
         nt++;
         count = 0;
     };

@@ -29,6 +29,7 @@ struct StepArgs {
     double *__restrict__ phif;           // [S] solid fraction of fluid nodes, compact order
     long ntasks;
     long S;                              // stride between directions
+    int ndom;                            // domains of the context
 };
 
 // host view of one domain

@@ -42,13 +42,15 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const int lane = threadIdx.x & 63;
     const Task tk = a.tasks[t];
     // by value, read before the first store: loads of a uniform address that no
-    // store can precede stay on the scalar unit
-    const DomDev D = a.doms[tk.dom];
+    // store can precede stay on the scalar unit.  A single-domain context's
+    // record does not wait for the task.
+    DomDev D = a.doms[0];
+    if (a.ndom > 1) D = a.doms[tk.dom];
     const Box b = D.box;
     const long S = a.S;
     const int W = D.W;
     const RowWord *__restrict__ rows = a.rows + D.word_off;
-    const int y0 = tk.row % b.ny, z = tk.row / b.ny;
+    const int y0 = tk.y0, z = tk.z;
     const int cnt = tk.cnt & 255, nr = tk.cnt >> 8;
     const int ax = b.inlet_axis;
 
@@ -356,6 +358,7 @@ static StepArgs<T> step_args(Ctx &c) {
     a.lq = (T *)c.lq;
     a.phif = c.phif;
     a.ntasks = c.n_tasks;
+    a.ndom = c.ndom;
     a.S = c.S;
     return a;
 }

@@ -78,54 +78,57 @@ template <class L>
 __device__ __forceinline__ void classify(const RowWord *__restrict__ rows, const Box &b, int W,
                                          const RowSlots &rs, int ry, int x, int y, int z, int k, int *kk,
                                          uint32_t &solidnb, uint32_t &cross, uint32_t &cross_hi) {
+    // the faces the node lies on give the directions whose pull leaves the
+    // box, crosses the inlet or outlet plane, or wraps with a row shift
+    constexpr uint32_t PX = dir_mask<L>(0, 1), NX = dir_mask<L>(0, -1);
+    constexpr uint32_t PY = dir_mask<L>(1, 1), NY = dir_mask<L>(1, -1);
+    constexpr uint32_t PZ = dir_mask<L>(2, 1), NZ = dir_mask<L>(2, -1);
+    const uint32_t fx = (x == 0 ? PX : 0u) | (x == b.nx - 1 ? NX : 0u);
+    const uint32_t fy = (y == 0 ? PY : 0u) | (y == b.ny - 1 ? NY : 0u);
+    const uint32_t fz = (z == 0 ? PZ : 0u) | (z == b.nz - 1 ? NZ : 0u);
+    const uint32_t outm = (b.per[0] ? 0u : fx) | (b.per[1] ? 0u : fy) | (b.per[2] ? 0u : fz);
+    const uint32_t shiftm = (b.per[0] && b.shift != 0) ? fx : 0u;
     const int ax = b.inlet_axis;
-    solidnb = 0u;
     cross = 0u;
     cross_hi = 0u;
+    if (ax >= 0) {
+        const uint32_t f = ax == 0 ? fx : (ax == 1 ? fy : fz);
+        cross = f;
+        cross_hi = f & ~(ax == 0 ? PX : (ax == 1 ? PY : PZ));
+    }
+    // the three x offsets x + 1, x, x - 1 (e_x = -1, 0, 1): table column (-1:
+    // outside the table) and bit within the row word
+    int tcol[3];
+    unsigned long long tbit[3];
 #pragma unroll
-    for (int i = 0; i < L::Q; i++) {
-        const int xx = x - L::ex[i], yy = y - L::ey[i], zz = z - L::ez[i];
-        if (i == 0) {
-            kk[i] = k;
+    for (int v = 0; v < 3; v++) {
+        const int xn = x + 1 - v;
+        const int xw = !b.per[0] ? xn : (xn < 0 ? xn + b.nx : (xn >= b.nx ? xn - b.nx : xn));
+        const int xs = min(max(xw, 0), b.nx - 1);
+        const int tw = (xs >> 6) - rs.wlo;
+        tcol[v] = (rs.fit && tw >= 0 && tw < rs.nwd) ? ry * rs.nwd + tw : -1;
+        tbit[v] = 1ull << (xs & 63);
+    }
+    solidnb = 0u;
+    kk[0] = k;
+#pragma unroll
+    for (int i = 1; i < L::Q; i++) {
+        const int v = L::ex[i] + 1;
+        const bool in_tab = tcol[v] >= 0;
+        const int src = in_tab ? ((L::DIM == 3 ? (1 - L::ez[i]) * rs.TY : 0) + 1 - L::ey[i]) * rs.nwd + tcol[v] : 0;
+        const unsigned lo = __shfl((unsigned)(rs.wm & 0xffffffffull), src, 64);
+        const unsigned hi = __shfl((unsigned)(rs.wm >> 32), src, 64);
+        const int pb = __shfl(rs.wpb, src, 64);
+        if (outm & (1u << i)) {
+            kk[i] = -2;
+        } else if (!in_tab || (shiftm & (1u << i))) {
+            kk[i] = nb_compact(rows, W, b, x - L::ex[i], y - L::ey[i], z - L::ez[i]);
         } else {
-            // x may wrap within the row; a wrap that shifts the row (tilted
-            // torus) or any row that does not fit the preloaded slots goes
-            // through the row words in memory
-            int xw = xx;
-            bool out = false, shifted = false;
-            if (xw < 0 || xw >= b.nx) {
-                if (!b.per[0]) out = true;
-                else {
-                    shifted = b.shift != 0;
-                    xw = xw < 0 ? xw + b.nx : xw - b.nx;
-                }
-            }
-            if ((yy < 0 || yy >= b.ny) && !b.per[1]) out = true;
-            if ((zz < 0 || zz >= b.nz) && !b.per[2]) out = true;
-            const int xs = min(max(xw, 0), b.nx - 1);
-            const int tw = (xs >> 6) - rs.wlo;
-            const bool in_tab = rs.fit && tw >= 0 && tw < rs.nwd;
-            const int src = in_tab ? (((L::DIM == 3 ? (1 - L::ez[i]) * rs.TY : 0) + ry + 1 - L::ey[i]) * rs.nwd + tw) : 0;
-            const unsigned lo = __shfl((unsigned)(rs.wm & 0xffffffffull), src, 64);
-            const unsigned hi = __shfl((unsigned)(rs.wm >> 32), src, 64);
-            const int pb = __shfl(rs.wpb, src, 64);
-            if (out) {
-                kk[i] = -2;
-            } else if (!in_tab || shifted) {
-                kk[i] = nb_compact(rows, W, b, xx, yy, zz);
-            } else {
-                const unsigned long long m = ((unsigned long long)hi << 32) | lo;
-                const unsigned long long bit = 1ull << (xs & 63);
-                kk[i] = (m & bit) ? pb + __popcll(m & (bit - 1ull)) : -1;
-            }
+            const unsigned long long m = ((unsigned long long)hi << 32) | lo;
+            const unsigned long long bit = tbit[v];
+            kk[i] = (m & bit) ? pb + __popcll(m & (bit - 1ull)) : -1;
         }
         if (kk[i] == -1) solidnb |= 1u << i;
-        if (ax >= 0) {
-            const int c = ax == 0 ? xx : (ax == 1 ? yy : zz);
-            const int nn = ax == 0 ? b.nx : (ax == 1 ? b.ny : b.nz);
-            if (c < 0) cross |= 1u << i;
-            if (c >= nn) { cross |= 1u << i; cross_hi |= 1u << i; }
-        }
     }
 }
 
