@@ -174,6 +174,15 @@ __host__ __device__ inline long site(const Box &b, int x, int y, int z, int dx, 
 
 __host__ __device__ inline void coords(const Box &b, long n, int *x, int *y, int *z) {
     const long nxy = (long)b.nx * b.ny;
+    if (n >= 0 && n <= 0xffffffffL && nxy <= 0xffffffffL) {
+        // 32-bit quotients (a 64-bit division is a long software sequence)
+        const unsigned un = (unsigned)n, uxy = (unsigned)nxy, unx = (unsigned)b.nx;
+        const unsigned zz = un / uxy, r = un - zz * uxy, yy = r / unx;
+        *z = (int)zz;
+        *y = (int)yy;
+        *x = (int)(r - yy * unx);
+        return;
+    }
     *z = (int)(n / nxy);
     const long r = n - (long)(*z) * nxy;
     *y = (int)(r / b.nx);

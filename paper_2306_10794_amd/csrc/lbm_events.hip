@@ -129,10 +129,12 @@ __device__ __forceinline__ int32_t heap_pop(int32_t *h, int &n) {
     return top;
 }
 
-// One wavefront.  Lanes 1..Q-1 read the moments of the neighbour along their
-// direction from the populations (data no event of the pass changes); lane 0
-// reads and writes everything an event changes (solid, phi, kof_old, the
-// records, the heap and its marks), so it always sees its own earlier writes.
+// One wavefront.  Lanes 1..Q-1 read, in parallel, the state of the neighbour
+// along their direction (solid, phi, rate, marks, and its moments from the
+// populations or from its record if it became fluid earlier in the pass);
+// lane 0 applies the rule and writes everything an event changes (solid, phi,
+// kof_old, the records, the heap and its marks); the barrier at the end of
+// every event makes those writes visible to the next event's reads.
 // A node pushed over its threshold that is not a candidate of the pass goes
 // into a min-heap (marked in the geometry flags, which the rebuild after the
 // pass recomputes); the next node is the smaller of the list head and the
@@ -176,24 +178,58 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
         if (n < 0) break;
         int X, Y, Z;
         coords(D.box, n, &X, &Y, &Z);
+        // lanes 1..Q-1: the neighbour along their direction, its state as the
+        // earlier events of the pass left it (lane 0's writes, visible after
+        // the barrier) and its moments
         long y = -1;
-        double Cy = 0.0, Ry = 0.0;
+        double Cy = 0.0, Ry = 0.0, Py = 0.0, Ky = 0.0;
+        int fy = 0;   // bit 0 solid, bit 1 candidate of the pass, bit 2 in the heap
         if (lane >= 1 && lane < L::Q) {
             int fc;
             y = site(D.box, X, Y, Z, L::ex[lane], L::ey[lane], L::ez[lane], true, &fc);
-            if (y >= 0 && kof[y] >= 0) pop_moments<L, T>(D, kof[y], f, g, S, &Cy, &Ry);
+            if (y >= 0) {
+                fy = (solid[y] ? 1 : 0) | (cand[y] ? 2 : 0) | ((gflags[y] & F_PEND) ? 4 : 0);
+                Py = phi[y];
+                Ky = kr[y];
+                // kof_old: the compact index before the pass, or the record
+                // of a node that became fluid in it
+                const int ko = kof_old[y];
+                if (ko <= -2) rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
+                else if (ko >= 0) pop_moments<L, T>(D, ko, f, g, S, &Cy, &Ry);
+            }
+        }
+        // lane 0: the node's own state, read alongside its neighbours'
+        bool sol_n = false;
+        double phn = 0.0, krn = 0.0, Cx = 0.0, Rx = 0.0;
+        if (lane == 0) {
+            sol_n = solid[n] != 0;
+            phn = phi[n];
+            krn = kr[n];
+            if (!sol_n && phn >= 1.0) {
+                const int ko = kof_old[n];
+                if (ko >= 0) pop_moments<L, T>(D, ko, f, g, S, &Cx, &Rx);
+                else rec_moments<L>(D, rec[-2 - ko], &Cx, &Rx);
+            }
         }
         long ys[L::Q];
-        double cs[L::Q], rs[L::Q];
+        double cs[L::Q], rs[L::Q], ps[L::Q], ks[L::Q];
+        int fs[L::Q];
 #pragma unroll
         for (int i = 1; i < L::Q; i++) {
             ys[i] = __shfl(y, i, 64);
             cs[i] = __shfl(Cy, i, 64);
             rs[i] = __shfl(Ry, i, 64);
+            ps[i] = __shfl(Py, i, 64);
+            ks[i] = __shfl(Ky, i, 64);
+            fs[i] = __shfl(fy, i, 64);
         }
         if (lane == 0) {
-            auto push = [&](long v) {
-                if (gflags[v] & F_PEND) return;
+            // on a box 3 or more sites wide along every axis the Q - 1
+            // neighbours are distinct sites; otherwise a site may be reached
+            // twice and its phi is read back after each update
+            const bool distinct = D.box.nx >= 3 && D.box.ny >= 3 && (L::DIM == 2 || D.box.nz >= 3);
+            auto push = [&](long v, bool pend) {
+                if (distinct ? pend : (gflags[v] & F_PEND) != 0u) return;
                 if (np_s >= cap) {
                     ovf_s = 1;
                     return;
@@ -203,21 +239,16 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                 np_s = np;
                 gflags[v] |= F_PEND;
             };
-            // moments of neighbours that became fluid earlier in this pass
-            for (int i = 1; i < L::Q; i++)
-                if (ys[i] >= 0 && kof_old[ys[i]] <= -2)
-                    rec_moments<L>(D, rec[-2 - kof_old[ys[i]]], &cs[i], &rs[i]);
-            const bool sol_n = solid[n] != 0;
-            if (sol_n && phi[n] <= 0.0) {
+            if (sol_n && phn <= 0.0) {
                 double csum = 0.0, rsum = 0.0, wsum = 0.0;
                 int nf = 0, nn = 0;
                 for (int i = 1; i < L::Q; i++)
-                    if (ys[i] >= 0 && !solid[ys[i]]) { csum += cs[i]; rsum += rs[i]; nf++; }
+                    if (ys[i] >= 0 && !(fs[i] & 1)) { csum += cs[i]; rsum += rs[i]; nf++; }
                 if (nf > 0) {
                     const double Cs = csum / nf, Rs = rsum / nf;
-                    const double need = D.v_m * Cs - phi[n];
+                    const double need = D.v_m * Cs - phn;
                     for (int i = 1; i < L::Q; i++)
-                        if (ys[i] >= 0 && solid[ys[i]]) { wsum += kr[ys[i]]; nn++; }
+                        if (ys[i] >= 0 && (fs[i] & 1)) { wsum += ks[i]; nn++; }
                     const int e = ne_s;
                     if (e >= cap) {
                         ovf_s = 1;
@@ -233,42 +264,42 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                         if (nn > 0) {
                             for (int i = 1; i < L::Q; i++) {
                                 const long s = ys[i];
-                                if (s < 0 || !solid[s]) continue;
-                                phi[s] -= need * (wsum > 0 ? kr[s] / wsum : 1.0 / nn);
+                                if (s < 0 || !(fs[i] & 1)) continue;
+                                ps[i] = (distinct ? ps[i] : phi[s]) - need * (wsum > 0 ? ks[i] / wsum : 1.0 / nn);
+                                phi[s] = ps[i];
                             }
                         } else {
-                            phi[n] -= need;
+                            phi[n] = 0.0 - need;
                         }
                         // later solid neighbours at or below zero now have a
                         // fluid neighbour: take them in this pass
                         for (int i = 1; i < L::Q; i++) {
                             const long s = ys[i];
-                            if (s > n && !cand[s] && solid[s] && phi[s] <= 0.0)
-                                push(s);
+                            if (s > n && !(fs[i] & 2) && (fs[i] & 1) && (distinct ? ps[i] : phi[s]) <= 0.0)
+                                push(s, (fs[i] & 4) != 0);
                         }
                     }
                 }
-            } else if (!sol_n && phi[n] >= 1.0) {
+            } else if (!sol_n && phn >= 1.0) {
                 const int e = ne_s;
                 if (e >= cap) {
                     ovf_s = 1;
                 } else {
-                    double Cx, Rx;
-                    if (kof_old[n] >= 0) pop_moments<L, T>(D, kof_old[n], f, g, S, &Cx, &Rx);
-                    else rec_moments<L>(D, rec[-2 - kof_old[n]], &Cx, &Rx);
-                    phi[n] += D.v_m * Cx;
-                    const double excess = phi[n] - 1.0;
+                    const double phx = phn + D.v_m * Cx;
+                    phi[n] = phx;
+                    const double excess = phx - 1.0;
                     int nn = 0;
                     double wsum = 0.0;
                     for (int i = 1; i < L::Q; i++)
-                        if (ys[i] >= 0 && !solid[ys[i]]) { wsum += kr[n]; nn++; }
+                        if (ys[i] >= 0 && !(fs[i] & 1)) { wsum += krn; nn++; }
                     if (nn > 0) {
                         for (int i = 1; i < L::Q; i++) {
                             const long s = ys[i];
-                            if (s < 0 || solid[s]) continue;
-                            phi[s] += excess * (wsum > 0 ? kr[n] / wsum : 1.0 / nn);
-                            if (s > n && !cand[s] && phi[s] >= 1.0)
-                                push(s);
+                            if (s < 0 || (fs[i] & 1)) continue;
+                            const double pnew = (distinct ? ps[i] : phi[s]) + excess * (wsum > 0 ? krn / wsum : 1.0 / nn);
+                            phi[s] = pnew;
+                            if (s > n && !(fs[i] & 2) && pnew >= 1.0)
+                                push(s, (fs[i] & 4) != 0);
                         }
                         phi[n] = 1.0;
                     }
