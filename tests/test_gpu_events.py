@@ -71,14 +71,37 @@ def _burst():
     return c.replace(name="burst", phi0=phi0)
 
 
+def _thin(kind):
+    """A periodic box two sites thick along z: the pulls along +z and -z
+    (and the diagonals that differ only in z) reach the same site, so one
+    event updates some neighbours twice."""
+    nx, ny, nz = 20, 12, 2
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    if kind == "precipitating":
+        solid[:, 4:8, 8:12] = 1
+        rng = np.random.default_rng(11)
+        return Case(name="thin precipitating", dim=3, nx=nx, ny=ny, nz=nz, q=19, solid=solid,
+                    tau_ns=0.9, tau_ad=0.75, j0=0.4, c_eq=1.0, k_r=0.08, v_m=0.35,
+                    phase_change=1, c_init=rng.uniform(1.8, 2.6, solid.size))
+    solid[:, 3:9, 6:14] = 1
+    rng = np.random.default_rng(12)
+    phi0 = np.where(solid.reshape(-1) == 1, rng.uniform(0.005, 0.05, solid.size), 0.0)
+    return Case(name="thin dissolving", dim=3, nx=nx, ny=ny, nz=nz, q=19, solid=solid,
+                tau_ns=0.8, tau_ad=0.8, force=(1e-5, 0.0, 0.0), c_eq=0.0, k_r=0.05, v_m=1.0,
+                phase_change=1, phi0=phi0, c_init=rng.uniform(0.5, 1.5, solid.size))
+
+
 CASES = {"dissolving": _dissolving, "precipitating": _precipitating, "burst": _burst,
          "dissolving R2 S.V.": lambda: _dissolving(MECH_POST, SCHEME_SV),
-         "spheres": _spheres_events}
+         "spheres": _spheres_events,
+         "thin precipitating": lambda: _thin("precipitating"),
+         "thin dissolving": lambda: _thin("dissolving")}
 
 
 @pytest.mark.parametrize("name,precision,steps", [
     ("dissolving", FP64, 300), ("precipitating", FP64, 200), ("dissolving R2 S.V.", FP64, 300),
-    ("spheres", FP64, 60), ("burst", FP64, 80), ("dissolving", FP32, 300), ("spheres", FP32, 60)])
+    ("spheres", FP64, 60), ("burst", FP64, 80), ("dissolving", FP32, 300), ("spheres", FP32, 60),
+    ("thin precipitating", FP64, 200), ("thin dissolving", FP64, 300)])
 def test_events_match_oracle(name, precision, steps):
     case = CASES[name]()
     res = run_pair(case, precision, steps, f"events {name}")
