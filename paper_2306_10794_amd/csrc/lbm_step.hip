@@ -175,6 +175,9 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         }
     }
     if (!active) return;
+    // the solid fraction of an interface node, read now so that its latency
+    // hides behind the population loads (updated at the end)
+    const double phi_in = rbc ? a.phif[k] : 0.0;
 
     // ---- loads: Q fluid + Q solute values per node ----
     T fv[Q], gv[Q];
@@ -283,7 +286,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
                 gv[i] = (T)g;
             }
         }
-        if (sneg != 0.0) a.phif[k] += D.vma * sneg;
+        if (sneg != 0.0) a.phif[k] = phi_in + D.vma * sneg;
     }
     R dC = R(0);
 #pragma unroll
