@@ -101,15 +101,23 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < Q; i++)
         gv[i] = c.kk[i] >= 0 ? a.gin[(long)i * S + c.kk[i]] : a.gin[(long)L::opp[i] * S + c.k];
+    // link index: the task's base (lbase of its first node, lane 0, which is
+    // active), then by direction, then by lane
+    const int lt = __builtin_amdgcn_readfirstlane(c.lb);
     if (rbc) {
-        int l = c.lb;   // the node's links follow direction order
+        const int lane = threadIdx.x & 63;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int loff = lt;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
+            const unsigned long long bal = __ballot((rbc >> i) & 1u);
+            const int l = loff + __popcll(bal & below);
+            loff += __popcll(bal);
             if (rbc & (1u << i)) {
                 const int o = L::opp[i];
                 const R own = (R)gv[i];
                 const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
-                const R beta = (R)a.lbeta[l++];
+                const R beta = (R)a.lbeta[l];
                 gv[i] = (T)((R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv);
             }
         }
@@ -164,13 +172,20 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
         nu[j] = (R(1) - om) * mu[j] + om * m;
         out[j] = nu[j];
     }
+    // link index: the task's base (lbase of its first node, lane 0, which is
+    // active), then by direction, then by lane
+    const int lt = __builtin_amdgcn_readfirstlane(c.lb);
     if (rbc) {
-        int ln = c.lb;   // the node's links follow direction order
+        const int lane = threadIdx.x & 63;
+        const unsigned long long below = (1ull << lane) - 1ull;
+        int loff = lt;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
+            const unsigned long long bal = __ballot((rbc >> i) & 1u);
+            const int l = loff + __popcll(bal & below);
+            loff += __popcll(bal);
             if (rbc & (1u << i)) {
                 const int o = L::opp[i];
-                const int l = ln++;
                 const R beta = (R)a.lbeta[l];
                 const bool pulled = D.mech == LBM_PRECOLL && !(rbc & (1u << o));
                 // the forward source value at this step (deviation form)

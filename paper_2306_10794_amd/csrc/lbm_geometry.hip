@@ -356,9 +356,40 @@ __global__ __launch_bounds__(BLK) void k_link_count(long nf, const int32_t *node
     if (k < nf) cnt[k] = __popc(rmask[nodeof[k]]);
 }
 
+// Link order.  The links of a task's nodes occupy one range (from lbase of
+// its first node); within it they are ordered by direction, then by node, so
+// that the lanes of a wavefront holding a link along the same direction read
+// its coefficient and write its exchange at consecutive addresses.  lmap takes
+// a link's slot in node order (lbase[k] + its rank among k's directions) to
+// its index.  One wavefront per task.
+template <class L>
+__global__ __launch_bounds__(BLK) void k_link_map(const Task *tasks, long ntasks, const int32_t *nodeof,
+                                                  const uint32_t *rmask, const int32_t *lbase,
+                                                  int32_t *lmap) {
+    const long t = (long)blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
+    if (t >= ntasks) return;
+    const int lane = threadIdx.x & 63;
+    const Task tk = tasks[t];
+    const int cnt = tk.cnt & 255;
+    const bool active = lane < cnt;
+    const int k = tk.k0 + (active ? lane : 0);
+    const uint32_t rm = active ? rmask[nodeof[k]] : 0u;
+    const int ob = lbase[k];
+    const int base = __shfl(ob, 0, 64);   // the task's first link
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int off = 0, m = 0;
+    for (int i = 1; i < L::Q; i++) {
+        const bool has = (rm >> i) & 1u;
+        const unsigned long long bal = __ballot(has);
+        if (has) lmap[ob + m++] = base + off + __popcll(bal & below);
+        off += __popcll(bal);
+    }
+}
+
 template <class L, typename T>
 __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *nodeof,
                                                const uint32_t *rmask, const int32_t *lbase,
+                                               const int32_t *lmap,
                                                const double *nrm, const double *kr, T *lbeta,
                                                int32_t *lnode, int32_t *lsolid, uint8_t *ldir) {
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
@@ -387,10 +418,11 @@ __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *no
         // node's own post-collision population, whose effective rate is gamma k
         if (D.mech == LBM_PRECOLL && (rm & (1u << L::opp[i]))) kap = kap / D.gamma;
         const double beta = D.scheme == LBM_ABB ? -1.0 : (1.0 - kap) / (1.0 + kap);
-        lbeta[base + r] = (T)beta;
-        lnode[base + r] = (int32_t)n;
-        lsolid[base + r] = (int32_t)s;
-        ldir[base + r] = (uint8_t)i;
+        const int l = lmap[base + r];
+        lbeta[l] = (T)beta;
+        lnode[l] = (int32_t)n;
+        lsolid[l] = (int32_t)s;
+        ldir[l] = (uint8_t)i;
         r++;
     }
 }
@@ -398,7 +430,7 @@ __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *no
 template <class L>
 __device__ __forceinline__ int solid_links(const DomDev &D, long nl, const uint8_t *solid,
                                            const uint32_t *rmask, const int32_t *kof,
-                                           const int32_t *lbase, int32_t *out) {
+                                           const int32_t *lbase, const int32_t *lmap, int32_t *out) {
     int X, Y, Z;
     coords(D.box, nl, &X, &Y, &Z);
     int cnt = 0;
@@ -410,7 +442,7 @@ __device__ __forceinline__ int solid_links(const DomDev &D, long nl, const uint8
         if (solid[x]) continue;
         const uint32_t rm = rmask[x];
         if (!(rm & (1u << i))) continue;
-        if (out) out[cnt] = lbase[kof[x]] + __popc(rm & ((1u << i) - 1u));
+        if (out) out[cnt] = lmap[lbase[kof[x]] + __popc(rm & ((1u << i) - 1u))];
         cnt++;
     }
     return cnt;
@@ -426,7 +458,7 @@ __global__ __launch_bounds__(BLK) void k_solid_count(Geo g, long N, const uint8_
     if (solid[n]) {
         long nl;
         const int d = dom_of(g, n, &nl);
-        c = solid_links<L>(g.doms[d], nl, solid, rmask, nullptr, nullptr, nullptr);
+        c = solid_links<L>(g.doms[d], nl, solid, rmask, nullptr, nullptr, nullptr, nullptr);
     }
     cnt[n] = c;
     ind[n] = c > 0 ? 1 : 0;
@@ -435,7 +467,8 @@ __global__ __launch_bounds__(BLK) void k_solid_count(Geo g, long N, const uint8_
 template <class L>
 __global__ __launch_bounds__(BLK) void k_solid_fill(Geo g, long N, const uint8_t *solid,
                                                     const uint32_t *rmask, const int32_t *kof,
-                                                    const int32_t *lbase, const int32_t *off,
+                                                    const int32_t *lbase, const int32_t *lmap,
+                                                    const int32_t *off,
                                                     const int32_t *idx, int32_t *sif, int32_t *soff,
                                                     int32_t *sdom, int32_t *slinks) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
@@ -443,7 +476,7 @@ __global__ __launch_bounds__(BLK) void k_solid_fill(Geo g, long N, const uint8_t
     if (!solid[n]) return;
     long nl;
     const int d = dom_of(g, n, &nl);
-    const int c = solid_links<L>(g.doms[d], nl, solid, rmask, kof, lbase, slinks + off[n]);
+    const int c = solid_links<L>(g.doms[d], nl, solid, rmask, kof, lbase, lmap, slinks + off[n]);
     if (c > 0) {
         sif[idx[n]] = (int32_t)n;
         soff[idx[n]] = off[n];
@@ -570,8 +603,11 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     c.n_fluid_iface = t4[2];
     *n_links = tot;
     if (tot > c.max_links) return hipSuccess;  // the caller reports the capacity error
+    if (c.n_tasks > 0)
+        hipLaunchKernelGGL((k_link_map<L>), dim3((c.n_tasks + BLK / 64 - 1) / (BLK / 64)), dim3(BLK), 0, st,
+                           c.tasks, (long)c.n_tasks, c.nodeof, c.rmask, c.lbase, c.lmap);
     hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, g, (long)nf, c.nodeof,
-                       c.rmask, c.lbase, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir);
+                       c.rmask, c.lbase, c.lmap, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir);
     // solid side: per solid interface node, its links in direction order
     hipLaunchKernelGGL((k_solid_count<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rmask,
                        c.cnt, c.sidx);
@@ -581,7 +617,7 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     if ((e = read_ints(c, c.iacc, t2, 2)) != hipSuccess) return e;
     *n_sif = t2[0];
     hipLaunchKernelGGL((k_solid_fill<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rmask,
-                       c.kof, c.lbase, c.cnt, c.sidx, c.sif, c.soff, c.sdom, c.slinks);
+                       c.kof, c.lbase, c.lmap, c.cnt, c.sidx, c.sif, c.soff, c.sdom, c.slinks);
     hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, c.soff, (long)t2[0], t2[1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t2[1] != tot) return hipErrorUnknown;  // every link has exactly one solid end

@@ -162,11 +162,19 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     constexpr int NW = (int)(sizeof(T) / 4);
     __shared__ uint32_t sbeta[WV][Q][NW][64];
     const int wv = threadIdx.x >> 6;
-    int lp = lb;   // the node's next link (its links follow direction order)
+    // the task's links: from lbase of its first node, by direction, then by
+    // lane (a link's index is the task's base, the links of the earlier
+    // directions, and the lanes below holding the same direction)
+    const int lt = __builtin_amdgcn_readfirstlane(lb);
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int loff = lt;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
+        const unsigned long long bal = __ballot((rbc >> i) & 1u);
+        const int li = loff + __popcll(bal & below);
+        loff += __popcll(bal);
         if (rbc & (1u << i)) {
-            const uint32_t *p = (const uint32_t *)(a.lbeta + lp++);
+            const uint32_t *p = (const uint32_t *)(a.lbeta + li);
 #pragma unroll
             for (int w = 0; w < NW; w++)
                 __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(p + w),
@@ -263,9 +271,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // whose beta already carries k/gamma).  q = g_in - g_out crossed the link.
     if (rbc) {
         double sneg = 0.0;
-        int l = lb;
+        int loff2 = lt;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
+            const unsigned long long bal = __ballot((rbc >> i) & 1u);
+            const int l = loff2 + __popcll(bal & below);
+            loff2 += __popcll(bal);
             if (rbc & (1u << i)) {
                 const int o = L::opp[i];
                 const R own = (R)gv[i];  // a link direction loaded the node's own value along o
@@ -281,7 +292,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
                 // (1 - beta) w C_eq + beta g_src: exactly g_src at beta = 1
                 const R g = (R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv;
                 const T qv = (T)(g - own);
-                a.lq[l++] = qv;
+                a.lq[l] = qv;
                 sneg -= (double)(qv < T(0) ? qv : T(0));
                 gv[i] = (T)g;
             }
