@@ -155,30 +155,28 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     }
     const uint32_t rbc = active ? (solidnb & ~cross) : 0u;
 
-    // ---- link coefficients beta = (1 - k_i)/(1 + k_i) of this node's
-    // reactive links (contiguous from its first link, in direction order),
-    // fetched straight into LDS so that no VGPR waits on them: row [i][w] of
-    // this wavefront's slice holds dword w of lane's beta along i ----
+    // ---- the task's reactive links: one range from lbase of its first node,
+    // ordered by direction, then by lane (a link's index is the task's base,
+    // the links of the earlier directions, and the lanes below holding the
+    // same direction).  Their coefficients beta = (1 - k_i)/(1 + k_i) are
+    // fetched straight into LDS in link order (no VGPR waits on them); each
+    // link's exchange later replaces its coefficient there, and the whole
+    // range is stored at once at the end ----
     constexpr int NW = (int)(sizeof(T) / 4);
-    __shared__ uint32_t sbeta[WV][Q][NW][64];
+    __shared__ uint32_t slink[WV][NW][64 * (Q - 1)];
     const int wv = threadIdx.x >> 6;
-    // the task's links: from lbase of its first node, by direction, then by
-    // lane (a link's index is the task's base, the links of the earlier
-    // directions, and the lanes below holding the same direction)
     const int lt = __builtin_amdgcn_readfirstlane(lb);
     const unsigned long long below = (1ull << lane) - 1ull;
-    int loff = lt;
+    int nlt = 0;
 #pragma unroll
-    for (int i = 1; i < Q; i++) {
-        const unsigned long long bal = __ballot((rbc >> i) & 1u);
-        const int li = loff + __popcll(bal & below);
-        loff += __popcll(bal);
-        if (rbc & (1u << i)) {
-            const uint32_t *p = (const uint32_t *)(a.lbeta + li);
+    for (int i = 1; i < Q; i++) nlt += __popcll(__ballot((rbc >> i) & 1u));
+    for (int c = 0; c < nlt; c += 64) {
+        if (c + lane < nlt) {
+            const uint32_t *p = (const uint32_t *)(a.lbeta + lt + c + lane);
 #pragma unroll
             for (int w = 0; w < NW; w++)
                 __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(p + w),
-                                                 (__attribute__((address_space(3))) void *)&sbeta[wv][i][w][0],
+                                                 (__attribute__((address_space(3))) void *)&slink[wv][w][c],
                                                  4, 0, 0);
         }
     }
@@ -271,33 +269,48 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // whose beta already carries k/gamma).  q = g_in - g_out crossed the link.
     if (rbc) {
         double sneg = 0.0;
-        int loff2 = lt;
+        int off = 0;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             const unsigned long long bal = __ballot((rbc >> i) & 1u);
-            const int l = loff2 + __popcll(bal & below);
-            loff2 += __popcll(bal);
+            const int pos = off + __popcll(bal & below);   // position in the task's range
+            off += __popcll(bal);
             if (rbc & (1u << i)) {
                 const int o = L::opp[i];
                 const R own = (R)gv[i];  // a link direction loaded the node's own value along o
                 const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
                 T bt;
                 if constexpr (NW == 1) {
-                    bt = __builtin_bit_cast(T, sbeta[wv][i][0][lane]);
+                    bt = __builtin_bit_cast(T, slink[wv][0][pos]);
                 } else {
-                    const unsigned long long lo = sbeta[wv][i][0][lane], hi = sbeta[wv][i][NW - 1][lane];
+                    const unsigned long long lo = slink[wv][0][pos], hi = slink[wv][NW - 1][pos];
                     bt = __builtin_bit_cast(T, lo | (hi << 32));
                 }
                 const R beta = (R)bt;
                 // (1 - beta) w C_eq + beta g_src: exactly g_src at beta = 1
                 const R g = (R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv;
                 const T qv = (T)(g - own);
-                a.lq[l] = qv;
+                if constexpr (NW == 1) {
+                    slink[wv][0][pos] = __builtin_bit_cast(uint32_t, qv);
+                } else {
+                    const unsigned long long qb = __builtin_bit_cast(unsigned long long, qv);
+                    slink[wv][0][pos] = (uint32_t)qb;
+                    slink[wv][NW - 1][pos] = (uint32_t)(qb >> 32);
+                }
                 sneg -= (double)(qv < T(0) ? qv : T(0));
                 gv[i] = (T)g;
             }
         }
         if (sneg != 0.0) a.phif[k] = phi_in + D.vma * sneg;
+    }
+    // the task's exchanges, stored in link order by the active lanes
+    for (int j = lane; j < nlt; j += cnt) {
+        if constexpr (NW == 1) {
+            a.lq[lt + j] = __builtin_bit_cast(T, slink[wv][0][j]);
+        } else {
+            const unsigned long long lo = slink[wv][0][j], hi = slink[wv][NW - 1][j];
+            a.lq[lt + j] = __builtin_bit_cast(T, lo | (hi << 32));
+        }
     }
     R dC = R(0);
 #pragma unroll
