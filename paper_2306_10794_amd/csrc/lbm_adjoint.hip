@@ -156,56 +156,75 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     const long S = a.S;
     const uint32_t rbc = c.solidnb;
     // lambda(t+1) at this node: the forward pull with directions reversed
-    R mu[Q];
+    T mu[Q];
 #pragma unroll
     for (int d = 0; d < Q; d++) {
         const int kd = c.kk[L::opp[d]];
-        mu[d] = (R)(kd >= 0 ? a.pin[(long)d * S + kd] : a.pin[(long)L::opp[d] * S + c.k]);
+        mu[d] = kd >= 0 ? a.pin[(long)d * S + kd] : a.pin[(long)L::opp[d] * S + c.k];
     }
     R m = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; i++) m += sol_w<L>(D, i) * mu[i];
-    const R om = D.omega_g;
-    R nu[Q], out[Q];
-#pragma unroll
-    for (int j = 0; j < Q; j++) {
-        nu[j] = (R(1) - om) * mu[j] + om * m;
-        out[j] = nu[j];
-    }
+    for (int i = 0; i < Q; i++) m += sol_w<L>(D, i) * (R)mu[i];
+    const R om = D.omega_g, om1 = R(1) - om;
+    a.pout[c.k] = (T)(om1 * (R)mu[0] + om * m);
     // link index: the task's base (lbase of its first node, lane 0, which is
     // active), then by direction, then by lane
     const int lt = __builtin_amdgcn_readfirstlane(c.lb);
-    if (rbc) {
-        const int lane = threadIdx.x & 63;
-        const unsigned long long below = (1ull << lane) - 1ull;
-        int loff = lt;
+    const int lane = threadIdx.x & 63;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int lpos[Q];
+    {
+        int off = lt;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             const unsigned long long bal = __ballot((rbc >> i) & 1u);
-            const int l = loff + __popcll(bal & below);
-            loff += __popcll(bal);
-            if (rbc & (1u << i)) {
-                const int o = L::opp[i];
-                const R beta = (R)a.lbeta[l];
-                const bool pulled = D.mech == LBM_PRECOLL && !(rbc & (1u << o));
-                // the forward source value at this step (deviation form)
-                R src;
-                if (pulled)
-                    src = (R)(c.kk[o] >= 0 ? a.gin[(long)o * S + c.kk[o]] : a.gin[(long)i * S + c.k]);
-                else
-                    src = (R)a.gin[(long)o * S + c.k];
-                a.gbeta[l] += nu[i] * (src - sol_w<L>(D, i) * D.ceq_dev);
-                if (pulled) {
-                    out[o] += beta * nu[i];
-                    out[i] = R(0);
-                } else {
-                    out[i] = beta * nu[i];
-                }
-            }
+            lpos[i] = off + __popcll(bal & below);
+            off += __popcll(bal);
         }
     }
+    // a direction and its opposite together.  Without links: out = nu.  A
+    // link along i whose source is the value pulled along o (pre-collision
+    // mechanics, o not a link): out_i = 0, out_o = nu_o + beta nu_i; any other
+    // link: out_i = beta nu_i.  Each link also adds nu_i (g_src - w_i C_eq) to
+    // its dL/dbeta.
 #pragma unroll
-    for (int j = 0; j < Q; j++) a.pout[(long)j * S + c.k] = (T)out[j];
+    for (int i = 1; i < Q; i++) {
+        if (L::opp[i] < i) continue;
+        const int o = L::opp[i];
+        const R nui = om1 * (R)mu[i] + om * m, nuo = om1 * (R)mu[o] + om * m;
+        R outi = nui, outo = nuo;
+        const bool li = (rbc >> i) & 1u, lo = (rbc >> o) & 1u;
+        if (li) {
+            const int l = lpos[i];
+            const R beta = (R)a.lbeta[l];
+            const bool pulled = D.mech == LBM_PRECOLL && !lo;
+            const R src = pulled ? (R)(c.kk[o] >= 0 ? a.gin[(long)o * S + c.kk[o]] : a.gin[(long)i * S + c.k])
+                                 : (R)a.gin[(long)o * S + c.k];
+            a.gbeta[l] += nui * (src - sol_w<L>(D, i) * D.ceq_dev);
+            if (pulled) {
+                outo += beta * nui;
+                outi = R(0);
+            } else {
+                outi = beta * nui;
+            }
+        }
+        if (lo) {
+            const int l = lpos[o];
+            const R beta = (R)a.lbeta[l];
+            const bool pulled = D.mech == LBM_PRECOLL && !li;
+            const R src = pulled ? (R)(c.kk[i] >= 0 ? a.gin[(long)i * S + c.kk[i]] : a.gin[(long)o * S + c.k])
+                                 : (R)a.gin[(long)i * S + c.k];
+            a.gbeta[l] += nuo * (src - sol_w<L>(D, o) * D.ceq_dev);
+            if (pulled) {
+                outi += beta * nuo;
+                outo = R(0);
+            } else {
+                outo = beta * nuo;
+            }
+        }
+        a.pout[(long)i * S + c.k] = (T)outi;
+        a.pout[(long)o * S + c.k] = (T)outo;
+    }
 }
 
 // dL/dk_r per solid interface node from dL/dbeta of its links (direction
