@@ -420,11 +420,13 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        # populations stored as FP32 deviations, computed in FP64 registers
+        "dtype": "f64",
         "data": "synthetic",
         "config": {
             "workload": f"{case.name}: D3Q19 fluid + D3Q19 solute, FP32 deviation storage, "
-                        f"FP64 solid fraction",
+                        f"FP64 arithmetic and solid fraction",
+            "storage": "f32 deviations", "arithmetic": "f64",
             "nodes": case.n, "fluid_nodes": int(n_fluid), "reactive_links": int(d["n_links"]),
             "porosity": round(1 - float(case.solid.mean()), 4),
             "phase_change_in_step": False,
