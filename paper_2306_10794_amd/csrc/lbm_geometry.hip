@@ -3,8 +3,9 @@
 // From the solid mask: node classes and reactive-link bits, the row words of
 // the compact fluid layout, the compact <-> dense index maps, the wavefront
 // tasks, the reactive-link list with beta = (1 - k_i)/(1 + k_i) per link
-// (k_i of the selected scheme), and, per solid interface node, the list of its
-// links in ascending direction order.
+// (k_i of the selected scheme; a task's links form one range, by direction,
+// then lane), and, per solid interface node, the list of its links in
+// ascending direction order.
 #include "lbm_internal.hpp"
 
 namespace lbm {

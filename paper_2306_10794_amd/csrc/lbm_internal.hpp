@@ -23,7 +23,7 @@ struct StepArgs {
     const RowWord *__restrict__ rows;
     const DomDev *__restrict__ doms;
     const int32_t *__restrict__ nodeof;  // compact index -> dense node
-    const int32_t *__restrict__ lbase;   // compact index -> first reactive link
+    const int32_t *__restrict__ lbase;   // compact index -> links of the nodes before it
     const T *__restrict__ lbeta;         // per link: (1 - k)/(1 + k)
     T *__restrict__ lq;                  // per link: mass exchanged in this step
     double *__restrict__ phif;           // [S] solid fraction of fluid nodes, compact order

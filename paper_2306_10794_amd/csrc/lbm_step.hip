@@ -8,8 +8,10 @@
 //                that enters from a solid node, advection-diffusion BGK with
 //                the rest-fraction weights; writes the exchange q of each
 //                reactive link and credits precipitation (q < 0) to the fluid
-//                node's phi.  Each reactive direction is a uniform-condition
-//                block; its beta is fetched into LDS ahead of the loads.
+//                node's phi.  The task's links are one range (by direction,
+//                then lane): their betas are fetched into LDS in one pass
+//                ahead of the loads, each link's q replaces its beta there,
+//                and the range is stored in one pass.
 //
 // The neighbour classification is written out here rather than taken from
 // classify() (lbm_task.hpp, used by the adjoint kernels): the compiler
@@ -19,9 +21,10 @@
 //
 // All loads of a node (both lattices) are issued before any arithmetic, so a
 // wavefront keeps 2Q loads in flight; each population value is read once by
-// k_step.  Arithmetic is FP64 in both storage precisions: the step is bound by
-// HBM traffic, and FP32 arithmetic on rounded weights would leak mass and
-// momentum by a fixed relative amount at every collision.
+// k_step.  Arithmetic is FP64 in both storage precisions: near a steady state
+// every node rounds the same moment sums and equilibria the same way at every
+// step, and in FP32 that rounding acts as a fixed spurious body force and
+// source (velocity errors of a few 1e-5 after ~10^4 steps in a channel).
 #include "lbm_internal.hpp"
 #include "lbm_task.hpp"
 
@@ -90,7 +93,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     }
     const int y = y0 + ry;
     const int n = a.nodeof[k];
-    const int lb = a.lbase[k];  // first reactive link (used by interface nodes)
+    const int lb = a.lbase[k];  // the links of the nodes before k (lane 0: the task's first link)
     const int x = (int)(n - D.node_off) - (tk.row + ry) * b.nx;
 
     // ---- neighbour classification (shared by both lattices) ----
