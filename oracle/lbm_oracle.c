@@ -379,7 +379,9 @@ void orc_step(orc *o, int nsteps)
     for (int t = 0; t < nsteps; t++) {
         long n;
 #ifdef _OPENMP
-#pragma omp parallel for schedule(static)
+        /* threads only for large lattices: on small ones the per-step fork and
+         * barrier cost more than the work (nodes are independent either way) */
+#pragma omp parallel for schedule(static) if (N >= 32768)
 #endif
         for (n = 0; n < N; n++) {
             if (o->solid[n]) {

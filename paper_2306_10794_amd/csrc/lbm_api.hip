@@ -414,8 +414,7 @@ static hipError_t build_graph(Ctx *c, int n) {
 static hipError_t phase_change_pass(Ctx *c, bool *capacity) {
     int64_t nev = 0;
     bool ovf = false;
-    hipError_t e = launch_phi_flush(*c);
-    if (e == hipSuccess) e = launch_events(*c, &nev, &ovf);
+    hipError_t e = launch_events(*c, &nev, &ovf);
     if (e != hipSuccess) return e;
     if (ovf) *capacity = true;
     if (nev == 0) return hipSuccess;

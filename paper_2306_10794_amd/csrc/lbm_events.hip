@@ -384,6 +384,19 @@ __global__ void k_zero2_i32(int32_t *p) {
     p[1] = 0;
 }
 
+// whether any node crossed a threshold: only the solid fraction of fluid
+// nodes and of solid interface nodes changes in a step (the working copies,
+// compact and solid-side order), and a solid node with a fluid neighbour is a
+// solid interface node, so this covers every candidate of the full scan
+__global__ __launch_bounds__(BLK) void k_event_check(long nf, const double *phif, long nsif,
+                                                     const double *phis, int32_t *any) {
+    const long t = (long)blockIdx.x * BLK + threadIdx.x;
+    bool c = false;
+    if (t < nf && phif[t] >= 1.0) c = true;
+    if (t < nsif && phis[t] <= 0.0) c = true;
+    if (__any(c) && (threadIdx.x & 63) == 0) atomicOr(any, 1);
+}
+
 template <class L, typename T>
 static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     hipStream_t st = c.stream;
@@ -392,11 +405,26 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     *n_events = 0;
     *overflow = false;
     int32_t *any = c.iacc + 8, *cnt2 = c.iacc + 10;
+    int32_t h[2] = {0, 0};
+    hipError_t e = hipSuccess;
+    {
+        const long nf = c.n_fluid, ns = c.n_sif, n = nf > ns ? nf : ns;
+        hipLaunchKernelGGL(k_zero2_i32, dim3(1), dim3(1), 0, st, any);
+        if (n > 0)
+            hipLaunchKernelGGL(k_event_check, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, st, nf, c.phif, ns,
+                               c.phis, any);
+        e = hipGetLastError();
+        if (e == hipSuccess) e = hipMemcpyAsync(h, any, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess || h[0] == 0) return e;
+    }
+    // some node crossed: the site-ordered phi is brought up to date for the
+    // full scan and the event pass
+    if ((e = launch_phi_flush(c)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_zero2_i32, dim3(1), dim3(1), 0, st, any);
     hipLaunchKernelGGL((k_event_scan<L>), dim3(nb), dim3(BLK), 0, st, c.doms, N, c.solid, c.phi,
                        c.cnt, any);
-    int32_t h[2] = {0, 0};
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(h, any, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess || h[0] == 0) return e;
