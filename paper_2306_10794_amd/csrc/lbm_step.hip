@@ -347,7 +347,7 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
                                                    const int32_t *__restrict__ sdom,
                                                    const DomDev *__restrict__ doms,
                                                    const T *__restrict__ lq, double *__restrict__ phis,
-                                                   long nsif, double *__restrict__ xpart) {
+                                                   long nsif, double *__restrict__ xpart, int ndom) {
     constexpr int M = L::Q - 1;
     const long j = (long)blockIdx.x * BLK + threadIdx.x;
     double tot = 0.0;
@@ -366,7 +366,7 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
             tot += v;
             if (v > 0.0) pos += v;
         }
-        phis[j] -= doms[sdom[j]].vma * pos;
+        phis[j] -= doms[ndom > 1 ? sdom[j] : 0].vma * pos;
     }
     tot = block_sum(tot);
     if (threadIdx.x == 0 && tot != 0.0) xpart[blockIdx.x] += tot;
@@ -435,7 +435,7 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
     if (c.n_sif > 0) {
         const long nb2 = (c.n_sif + BLK - 1) / BLK;
         hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
-                           c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart);
+                           c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[3], ps);
