@@ -50,6 +50,7 @@ class Case:
     rho0: float = 1.0           # deviation reference for the fluid populations
     c_ref: float = 0.0          # deviation reference for the solute populations
     phase_change: int = 0
+    collision: int = 0          # 0 BGK, 1 TRT (magic parameter 3/16 for both lattices)
     normals: Optional[np.ndarray] = None   # float64 [N, 3], unit normal solid -> fluid
     k_r_field: Optional[np.ndarray] = None  # float64 [N]
     phi0: Optional[np.ndarray] = None       # float64 [N]

@@ -35,7 +35,7 @@ class _Params(C.Structure):
                 ("force", C.c_double * 3), ("c_eq", C.c_double), ("k_r", C.c_double),
                 ("v_m", C.c_double), ("a_m", C.c_double), ("periodic", C.c_int * 3),
                 ("xwrap_shift_y", C.c_int), ("inlet_axis", C.c_int), ("c_in", C.c_double),
-                ("phase_change", C.c_int)]
+                ("phase_change", C.c_int), ("collision", C.c_int)]
 
 
 _lib = None
@@ -90,6 +90,7 @@ class Oracle:
         p.periodic[:] = list(case.periodic)
         p.xwrap_shift_y, p.inlet_axis, p.c_in = case.xwrap_shift_y, case.inlet_axis, case.c_in
         p.phase_change = case.phase_change
+        p.collision = getattr(case, "collision", 0)
         self._solid = case.solid_flat()
         self._normals = case.normals_flat()
         self._kr = None if case.k_r_field is None else np.ascontiguousarray(case.k_r_field, np.float64)

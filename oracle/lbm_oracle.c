@@ -44,6 +44,10 @@
 
 enum { ORC_MECH_PRE = 0, ORC_MECH_POST = 1 };
 enum { ORC_SNEW = 0, ORC_SV = 1, ORC_SPJ = 2, ORC_ABB = 3 };
+enum { ORC_BGK = 0, ORC_TRT = 1 };
+/* the TRT "magic" parameter (Sec. 2.1, eq. fluid_TRT_visc): 3/16 puts
+ * bounce-back walls exactly halfway */
+#define ORC_MAGIC (3.0 / 16.0)
 
 typedef struct {
     int dim, nx, ny, nz, q;
@@ -56,6 +60,7 @@ typedef struct {
     int inlet_axis;
     double c_in;
     int phase_change;
+    int collision;          /* ORC_BGK | ORC_TRT */
 } orc_params;
 
 typedef struct {
@@ -304,13 +309,32 @@ static void update_node(orc *o, long x)
         for (int d = 0; d < 3; d++) o->uh[3 * x + d] = u[d];
     double c = o->cs2f;
     double uF = u[0] * p->force[0] + u[1] * p->force[1] + u[2] * p->force[2];
+    double fe[ORC_QMAX], S[ORC_QMAX];
     for (int i = 0; i < Q; i++) {
         double eu = o->e[i][0] * u[0] + o->e[i][1] * u[1] + o->e[i][2] * u[2];
         double eF = o->e[i][0] * p->force[0] + o->e[i][1] * p->force[1] +
                     o->e[i][2] * p->force[2];
-        double S = o->wf[i] * ((eF - uF) / c + eu * eF / (c * c));
-        o->fn[x * Q + i] = fp[i] - (fp[i] - feq(o, i, rho, u)) / p->tau_ns +
-                           (1.0 - 0.5 / p->tau_ns) * S;
+        S[i] = o->wf[i] * ((eF - uF) / c + eu * eF / (c * c));
+        fe[i] = feq(o, i, rho, u);
+    }
+    if (p->collision == ORC_TRT) {
+        /* TRT (Sec. 2.1, eqs. fluid_TRT, fluid_TRT_terms, fluid_TRT_visc):
+         * the parts of f, f_eq even and odd in e_i relax with tau+ (viscosity)
+         * and tau- (from the magic parameter); the Guo source term is split the
+         * same way, each part with its own factor 1 - 1/(2 tau) (reading: the
+         * paper gives no TRT forcing) */
+        const double tp = p->tau_ns, tm = 0.5 + ORC_MAGIC / (p->tau_ns - 0.5);
+        for (int i = 0; i < Q; i++) {
+            const int ob = o->opp[i];
+            const double fpl = 0.5 * (fp[i] + fp[ob]), fmi = 0.5 * (fp[i] - fp[ob]);
+            const double epl = 0.5 * (fe[i] + fe[ob]), emi = 0.5 * (fe[i] - fe[ob]);
+            const double spl = 0.5 * (S[i] + S[ob]), smi = 0.5 * (S[i] - S[ob]);
+            o->fn[x * Q + i] = fp[i] - (fpl - epl) / tp - (fmi - emi) / tm +
+                               (1.0 - 0.5 / tp) * spl + (1.0 - 0.5 / tm) * smi;
+        }
+    } else {
+        for (int i = 0; i < Q; i++)
+            o->fn[x * Q + i] = fp[i] - (fp[i] - fe[i]) / p->tau_ns + (1.0 - 0.5 / p->tau_ns) * S[i];
     }
 
     /* solute: pull, plane conditions, then the reactive links */
@@ -366,8 +390,23 @@ static void update_node(orc *o, long x)
     }
     double C = 0;
     for (int i = 0; i < Q; i++) C += gp[i];
-    for (int i = 0; i < Q; i++)
-        o->gn[x * Q + i] = gp[i] - (gp[i] - geq(o, i, C, u)) / p->tau_ad;
+    if (p->collision == ORC_TRT) {
+        /* TRT for the solute (Sec. 2.1, eqs. solute_TRT, solute_TRT_terms,
+         * solute_TRT_visc): the even parts relax with 1/tau-, the odd parts
+         * with 1/tau+; D = c_s^2 (tau+ - 1/2) sets tau+ = tau_AD */
+        const double tp = p->tau_ad, tm = 0.5 + ORC_MAGIC / (p->tau_ad - 0.5);
+        double ge[ORC_QMAX];
+        for (int i = 0; i < Q; i++) ge[i] = geq(o, i, C, u);
+        for (int i = 0; i < Q; i++) {
+            const int ob = o->opp[i];
+            const double gpl = 0.5 * (gp[i] + gp[ob]), gmi = 0.5 * (gp[i] - gp[ob]);
+            const double epl = 0.5 * (ge[i] + ge[ob]), emi = 0.5 * (ge[i] - ge[ob]);
+            o->gn[x * Q + i] = gp[i] - (gpl - epl) / tm - (gmi - emi) / tp;
+        }
+    } else {
+        for (int i = 0; i < Q; i++)
+            o->gn[x * Q + i] = gp[i] - (gp[i] - geq(o, i, C, u)) / p->tau_ad;
+    }
 }
 
 static void apply_phase_change(orc *o);
@@ -686,6 +725,7 @@ int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *la
     const long N = o->N;
     const int Q = o->Q;
     if (o->p.phase_change) return -2;
+    if (o->p.collision != ORC_BGK) return -3;   /* the transposed step below is BGK's */
     double *G = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * Q);
     double *U = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * 3);
     double *lam = (double *)calloc((size_t)N * Q, sizeof(double));

@@ -172,6 +172,84 @@ def test_poiseuille_body_force(tau):
 
 
 # --------------------------------------------------------------------------
+# TRT collision
+# --------------------------------------------------------------------------
+COLL_BGK, COLL_TRT = 0, 1
+
+
+@pytest.mark.parametrize("tau", [0.6, 1.7, 3.0])
+def test_trt_poiseuille_walls_halfway_at_any_tau(tau):
+    """TRT with the magic parameter 3/16 (eq. fluid_TRT_visc) places the
+    bounce-back walls exactly halfway whatever tau+ is: the whole steady
+    profile of a force-driven channel equals the parabola with walls at
+    y = 1/2 and ny - 3/2.  BGK at the same tau does not (checked at 1.7)."""
+    ny, nx, F = 18, 2, 1e-5
+    solid, normals = geometry.plane_channel(nx, ny, (0, ny - 1))
+    nu = (tau - 0.5) / 3
+    y = np.arange(1, ny - 1)
+    exact = F / (2 * nu) * (y - 0.5) * (ny - 1.5 - y)
+    steps = int(40 * ny * ny / nu) + 2000
+    errs = {}
+    for coll in (COLL_TRT, COLL_BGK) if tau == 1.7 else (COLL_TRT,):
+        case = Case(name="p", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid, normals=normals,
+                    tau_ns=tau, force=(F, 0, 0), collision=coll)
+        o = Oracle(case)
+        o.step(steps)
+        u = o.fields()["u"].reshape(ny, nx, 3)[1:-1, 0, 0]
+        errs[coll] = np.abs(u - exact).max() / exact.max()
+    assert errs[COLL_TRT] < 1e-9
+    if COLL_BGK in errs:
+        assert errs[COLL_BGK] > 1e-3
+
+
+def test_trt_equals_bgk_when_the_rates_coincide():
+    """At (tau - 1/2)^2 = 3/16 the TRT rates tau+ and tau- coincide and the
+    operator is BGK (eqs. fluid_TRT and solute_TRT with equal rates): the same
+    run agrees with the BGK run, flow, solute, reactive walls and force."""
+    tau = 0.5 + math.sqrt(3 / 16)
+    solid, normals, _ = geometry.disk_medium(40, 30, 0.65, 3.0, 6.0, seed=3)
+    rng = np.random.default_rng(2)
+    base = dict(name="trt", dim=2, nx=40, ny=30, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=tau, tau_ad=tau, j0=0.3, force=(2e-5, 1e-5, 0), c_eq=1.0, k_r=0.03,
+                v_m=0.2, c_init=rng.uniform(0.0, 2.0, solid.size))
+    a, b = Oracle(Case(**base, collision=COLL_TRT)), Oracle(Case(**base, collision=COLL_BGK))
+    a.step(150)
+    b.step(150)
+    fa, ga = a.pops()
+    fb, gb = b.pops()
+    assert np.abs(fa - fb).max() < 1e-13
+    assert np.abs(ga - gb).max() < 1e-13
+
+
+@pytest.mark.parametrize("tau", [0.7, 1.2, 2.5])
+def test_trt_diffusion_from_the_odd_rate(tau):
+    """Solute TRT (eqs. solute_TRT, solute_TRT_visc): the odd parts relax with
+    1/tau+ and D = c_s^2 (tau+ - 1/2), so a long-wavelength mode decays as
+    exp(-D k^2 t) with D from tau_AD = tau+, not from tau- (which differs from
+    tau+ at these tau)."""
+    nx = 128
+    solid = np.zeros((1, 1, nx), np.uint8)
+    x = np.arange(nx)
+    k = 2 * np.pi / nx
+    case = Case(name="d", dim=2, nx=nx, ny=1, nz=1, q=9, solid=solid, tau_ad=tau,
+                c_init=1.0 + 0.1 * np.cos(k * x), collision=COLL_TRT)
+    o = Oracle(case)
+    steps = 400
+    o.step(steps)
+    c = o.fields()["c"]
+    amp = 2 * np.abs(np.fft.rfft(c - c.mean())[1]) / nx
+    D = (tau - 0.5) / 3
+    assert amp / 0.1 == pytest.approx(math.exp(-D * k * k * steps), rel=2e-3)
+
+
+def test_trt_adjoint_is_refused():
+    """The hand-written adjoint transposes the BGK step only."""
+    o = Oracle(_small_case(collision=COLL_TRT, k_r=0.01))
+    with pytest.raises(RuntimeError):
+        o.adjoint(2, np.zeros(o.N))
+
+
+# --------------------------------------------------------------------------
 # reactive boundary condition
 # --------------------------------------------------------------------------
 READINGS = [  # (mechanics, scheme, wall offset, factor on k_r that is realised)
