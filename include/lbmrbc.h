@@ -63,6 +63,16 @@ typedef enum {
 #define LBM_POSTCOLL 1   /* the node's own post-collision population that
                             streamed into the wall (halfway, link-wise)       */
 
+/* collision operator of both lattices */
+#define LBM_BGK 0        /* single relaxation time (Sec. 2.1, eqs. fluid_BGK,
+                            solute_BGK)                                       */
+#define LBM_TRT 1        /* two relaxation times with the magic parameter 3/16
+                            (Sec. 2.1, eqs. fluid_TRT, solute_TRT): fluid even
+                            parts relax with tau_ns, odd parts with tau-; the
+                            solute's odd parts with tau_ad, even parts with
+                            tau-; the Guo force term is split the same way.
+                            Not with lbm_record / lbm_adjoint.               */
+
 /* k_i of the reactive boundary condition */
 #define LBM_SNEW 0       /* c_s^-2 gamma k_r (e.n)   -- the paper's new scheme  */
 #define LBM_SV 1         /* c_s^-2 k_r (e.n)         -- Verhaeghe              */
@@ -97,7 +107,7 @@ typedef struct {
     int32_t phase_change;     /* 1: apply the phi thresholds after each step
                                  (Sec. 2.4; single-lattice contexts; lbm_step
                                  then synchronises once per step)            */
-    int32_t reserved0;
+    int32_t collision;        /* LBM_BGK | LBM_TRT                                 */
     int64_t max_links;        /* capacity for reactive links; <= 0 selects
                                  max(4096, N*(Q-1)/4)                              */
 } lbm_params;

@@ -11,7 +11,8 @@ from ._lib import (LbmError, lbm_params, lbm_workspace_bytes, lbm_create, lbm_se
                    lbm_record, lbm_adjoint, lbm_get_fields, lbm_get_pops, lbm_get_exchange,
                    lbm_get_diag, lbm_state_bytes, lbm_save_state, lbm_load_state,
                    lbm_last_error, lbm_destroy, LBM_FP64, LBM_FP32_DEV, LBM_PRECOLL,
-                   LBM_POSTCOLL, LBM_SNEW, LBM_SV, LBM_SPJ, LBM_ABB, LBM_OK, LBM_EINVAL,
+                   LBM_POSTCOLL, LBM_SNEW, LBM_SV, LBM_SPJ, LBM_ABB, LBM_BGK, LBM_TRT, LBM_OK,
+                   LBM_EINVAL,
                    LBM_ENOMEM, LBM_EDEVICE, LBM_ESTATE, LBM_ENUMERIC, LBM_ECAPACITY)
 
 __all__ = [n for n in dir() if n.startswith("lbm_") or n.startswith("LBM_")] + [

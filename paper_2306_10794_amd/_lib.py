@@ -22,6 +22,7 @@ STATUS_NAMES = {0: "LBM_OK", -1: "LBM_EINVAL", -2: "LBM_ENOMEM", -3: "LBM_EDEVIC
 LBM_FP64, LBM_FP32_DEV = 0, 1
 LBM_PRECOLL, LBM_POSTCOLL = 0, 1
 LBM_SNEW, LBM_SV, LBM_SPJ, LBM_ABB = 0, 1, 2, 3
+LBM_BGK, LBM_TRT = 0, 1
 
 
 class LbmError(RuntimeError):
@@ -39,7 +40,7 @@ class lbm_params(C.Structure):
                 ("c_eq", C.c_double), ("k_r", C.c_double), ("v_m", C.c_double),
                 ("a_m", C.c_double), ("periodic", C.c_int32 * 3), ("xwrap_shift_y", C.c_int32),
                 ("inlet_axis", C.c_int32), ("c_in", C.c_double), ("phase_change", C.c_int32),
-                ("reserved0", C.c_int32), ("max_links", C.c_int64)]
+                ("collision", C.c_int32), ("max_links", C.c_int64)]
 
 
 class lbm_diag(C.Structure):

@@ -48,6 +48,7 @@ std::string check_params(const lbm_params &p) {
         return b;
     }
     if (p.phase_change != 0 && p.phase_change != 1) return "phase_change must be 0 or 1";
+    if (p.collision != LBM_BGK && p.collision != LBM_TRT) return "collision must be LBM_BGK or LBM_TRT";
     return "";
 }
 
@@ -224,6 +225,13 @@ static DomDev dom_record(const DomHost &h, bool fp64) {
     D.omega_f = 1.0 / p.tau_ns;
     D.omega_g = 1.0 / p.tau_ad;
     D.force_fac = 1.0 - 0.5 / p.tau_ns;
+    // TRT: the second rate of each lattice from the magic parameter 3/16,
+    // (tau+ - 1/2)(tau- - 1/2) = 3/16; BGK: both rates equal
+    D.trt = p.collision == LBM_TRT;
+    const double tfm = 0.5 + (3.0 / 16.0) / (p.tau_ns - 0.5), tgm = 0.5 + (3.0 / 16.0) / (p.tau_ad - 0.5);
+    D.omega_fm = D.trt ? 1.0 / tfm : D.omega_f;
+    D.force_fac_m = 1.0 - 0.5 * D.omega_fm;
+    D.omega_gs = D.trt ? 1.0 / tgm : D.omega_g;
     for (int a = 0; a < 3; a++) D.F[a] = p.force[a];
     for (int i = 0; i < 19; i++) D.ws[i] = h.ws[i];
     D.wsc = h.wsc;
@@ -245,8 +253,9 @@ static std::string check_batch(const lbm_params *p, int n) {
     for (int d = 0; d < n; d++) {
         std::string m = check_params(p[d]);
         if (!m.empty()) return (n > 1 ? "domain " + std::to_string(d) + ": " : std::string()) + m;
-        if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].precision != p[0].precision)
-            return "all domains of a batch need the same dim, lattice and precision";
+        if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].precision != p[0].precision ||
+            p[d].collision != p[0].collision)
+            return "all domains of a batch need the same dim, lattice, precision and collision";
         if (p[d].phase_change != 0 && n > 1) return "phase_change is not supported in a batch";
         if (p[d].phase_change != 0 && p[d].phase_change != 1) return "phase_change must be 0 or 1";
     }
@@ -814,6 +823,10 @@ static lbm_status adj_check(Ctx *c, int32_t nsteps, int32_t ckpt) {
     }
     if (c->p.force[0] != 0.0 || c->p.force[1] != 0.0 || c->p.force[2] != 0.0) {
         c->err = "the adjoint needs the fluid at rest (no body force)";
+        return LBM_EINVAL;
+    }
+    if (c->p.collision != LBM_BGK) {
+        c->err = "the adjoint transposes the BGK step (collision = LBM_BGK)";
         return LBM_EINVAL;
     }
     return LBM_OK;

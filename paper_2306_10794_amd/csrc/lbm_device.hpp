@@ -100,6 +100,11 @@ struct DomDev {
     long word_off;             // first row word of the domain
     long row_off;              // first global row of the domain
     double omega_f, omega_g, force_fac;
+    // TRT (trt = 1): fluid odd parts relax with omega_fm, their force share
+    // scaled by force_fac_m; solute even parts relax with omega_gs (odd ones
+    // with omega_g).  BGK: omega_fm = omega_f, omega_gs = omega_g
+    int trt;
+    double omega_fm, force_fac_m, omega_gs;
     double F[3];
     double ws[19];             // solute weights (rest fraction)
     double wsc;                // ws[i] = w[i] * wsc for every moving direction

@@ -34,7 +34,7 @@ namespace lbm {
 // tiles on one XCD.  FP32 storage asks for 4 waves per SIMD (at most 128
 // VGPRs, a few spilled): the extra wave hides more memory latency than the
 // spills cost (256^3 sphere packing: 732 -> 660 us).
-template <class L, typename T, int WV>
+template <class L, typename T, int WV, bool TRT>
 __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepArgs<T> a, long nblocks,
                                                                          int remap) {
     using R = double;
@@ -247,9 +247,18 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         const R eF = R(L::ex[i]) * D.F[0] + R(L::ey[i]) * D.F[1] + R(L::ez[i]) * D.F[2];
         const R wi = R(L::w[i]);
         const R A = wi * (om * (drho + rho * (R(4.5) * eu * eu - R(1.5) * uu)) + ff * (R(9) * eu * eF - R(3) * uF));
-        const R B = R(3) * wi * (om * em + ff * eF);
-        a.fout[(long)i * S + k] = (T)(om1 * fp[i] + (A + B));
-        a.fout[(long)o * S + k] = (T)(om1 * fp[o] + (A - B));
+        if constexpr (TRT) {
+            // TRT: the odd parts (f_i - f_o)/2, e.m and e.F relax with the
+            // second rate, the even ones with om
+            const R B = R(3) * wi * (D.omega_fm * em + D.force_fac_m * eF);
+            const R hp = R(0.5) * om * (fp[i] + fp[o]), hm = R(0.5) * D.omega_fm * (fp[i] - fp[o]);
+            a.fout[(long)i * S + k] = (T)(fp[i] - hp - hm + (A + B));
+            a.fout[(long)o * S + k] = (T)(fp[o] - hp + hm + (A - B));
+        } else {
+            const R B = R(3) * wi * (om * em + ff * eF);
+            a.fout[(long)i * S + k] = (T)(om1 * fp[i] + (A + B));
+            a.fout[(long)o * S + k] = (T)(om1 * fp[o] + (A - B));
+        }
     }
 
     // ---- solute: plane faces, reactive links, collision ----
@@ -321,17 +330,27 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const R C = D.c_ref + dC;
     // g* = g + omg (g_eq - g), g_eq = ws (dC + C e.u / c_s^2): in pairs as
     // above, (1 - omg) g + As +- Bs with As = omg ws dC, Bs = omg ws C e.u / c_s^2
-    const R omg = D.omega_g, omg1 = R(1) - omg, Cu = omg * C * D.inv_cs2s;
-    a.gout[k] = (T)(omg1 * (R)gv[0] + omg * sol_w<L>(D, 0) * dC);
+    // TRT: the even parts relax with omega_gs (BGK: omega_gs = omg)
+    const R omg = D.omega_g, omg1 = R(1) - omg, Cu = omg * C * D.inv_cs2s, oms = D.omega_gs;
+    a.gout[k] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i) continue;
         const int o = L::opp[i];
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
         const R ws = sol_w<L>(D, i);
-        const R As = omg * ws * dC, Bs = ws * Cu * eu;
-        a.gout[(long)i * S + k] = (T)(omg1 * (R)gv[i] + (As + Bs));
-        a.gout[(long)o * S + k] = (T)(omg1 * (R)gv[o] + (As - Bs));
+        const R Bs = ws * Cu * eu;
+        if constexpr (TRT) {
+            const R As = oms * ws * dC;
+            const R gi = (R)gv[i], go = (R)gv[o];
+            const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * omg * (gi - go);
+            a.gout[(long)i * S + k] = (T)(gi - hs - ha + (As + Bs));
+            a.gout[(long)o * S + k] = (T)(go - hs + ha + (As - Bs));
+        } else {
+            const R As = omg * ws * dC;
+            a.gout[(long)i * S + k] = (T)(omg1 * (R)gv[i] + (As + Bs));
+            a.gout[(long)o * S + k] = (T)(omg1 * (R)gv[o] + (As - Bs));
+        }
     }
 }
 
@@ -415,11 +434,22 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
         const int wv = c.cfg.wg_waves;
         const long nb = (c.n_tasks + wv - 1) / wv;
         const int rm = c.cfg.xcd_remap;
-        switch (wv) {
-        case 1: hipLaunchKernelGGL((k_step<L, T, 1>), dim3(nb), dim3(64), 0, c.stream, args, nb, rm); break;
-        case 2: hipLaunchKernelGGL((k_step<L, T, 2>), dim3(nb), dim3(128), 0, c.stream, args, nb, rm); break;
-        case 8: hipLaunchKernelGGL((k_step<L, T, 8>), dim3(nb), dim3(512), 0, c.stream, args, nb, rm); break;
-        default: hipLaunchKernelGGL((k_step<L, T, 4>), dim3(nb), dim3(256), 0, c.stream, args, nb, rm); break;
+        // TRT is a separate instantiation: its extra terms would cost the
+        // BGK kernel registers (every domain of a context shares the choice)
+        if (c.p.collision == LBM_TRT) {
+            switch (wv) {
+            case 1: hipLaunchKernelGGL((k_step<L, T, 1, true>), dim3(nb), dim3(64), 0, c.stream, args, nb, rm); break;
+            case 2: hipLaunchKernelGGL((k_step<L, T, 2, true>), dim3(nb), dim3(128), 0, c.stream, args, nb, rm); break;
+            case 8: hipLaunchKernelGGL((k_step<L, T, 8, true>), dim3(nb), dim3(512), 0, c.stream, args, nb, rm); break;
+            default: hipLaunchKernelGGL((k_step<L, T, 4, true>), dim3(nb), dim3(256), 0, c.stream, args, nb, rm); break;
+            }
+        } else {
+            switch (wv) {
+            case 1: hipLaunchKernelGGL((k_step<L, T, 1, false>), dim3(nb), dim3(64), 0, c.stream, args, nb, rm); break;
+            case 2: hipLaunchKernelGGL((k_step<L, T, 2, false>), dim3(nb), dim3(128), 0, c.stream, args, nb, rm); break;
+            case 8: hipLaunchKernelGGL((k_step<L, T, 8, false>), dim3(nb), dim3(512), 0, c.stream, args, nb, rm); break;
+            default: hipLaunchKernelGGL((k_step<L, T, 4, false>), dim3(nb), dim3(256), 0, c.stream, args, nb, rm); break;
+            }
         }
         e = hipGetLastError();
     }

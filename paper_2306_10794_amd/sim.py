@@ -27,6 +27,7 @@ def params_from_case(case, precision: int = L.LBM_FP32_DEV, max_links: int = 0) 
     p.periodic[:] = list(case.periodic)
     p.xwrap_shift_y, p.inlet_axis, p.c_in = case.xwrap_shift_y, case.inlet_axis, case.c_in
     p.phase_change = case.phase_change
+    p.collision = getattr(case, "collision", 0)
     p.max_links = max_links
     return p
 
