@@ -31,7 +31,7 @@ class Case:
     nx: int
     ny: int
     nz: int
-    q: int                      # 9 (D2Q9 fluid + D2Q9 solute) or 19 (D3Q19 + D3Q19)
+    q: int                      # fluid lattice: 9 (D2Q9) or 19 (D3Q19)
     solid: np.ndarray           # uint8 [nz, ny, nx], 1 = solid
     tau_ns: float = 1.0
     tau_ad: float = 1.0
@@ -51,6 +51,7 @@ class Case:
     c_ref: float = 0.0          # deviation reference for the solute populations
     phase_change: int = 0
     collision: int = 0          # 0 BGK, 1 TRT (magic parameter 3/16 for both lattices)
+    qs: int = 0                 # solute lattice: 0 (the fluid's), 5 (D2Q5) or 7 (D3Q7)
     normals: Optional[np.ndarray] = None   # float64 [N, 3], unit normal solid -> fluid
     k_r_field: Optional[np.ndarray] = None  # float64 [N]
     phi0: Optional[np.ndarray] = None       # float64 [N]

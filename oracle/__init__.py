@@ -35,7 +35,7 @@ class _Params(C.Structure):
                 ("force", C.c_double * 3), ("c_eq", C.c_double), ("k_r", C.c_double),
                 ("v_m", C.c_double), ("a_m", C.c_double), ("periodic", C.c_int * 3),
                 ("xwrap_shift_y", C.c_int), ("inlet_axis", C.c_int), ("c_in", C.c_double),
-                ("phase_change", C.c_int), ("collision", C.c_int)]
+                ("phase_change", C.c_int), ("collision", C.c_int), ("qs", C.c_int)]
 
 
 _lib = None
@@ -63,6 +63,8 @@ def _load():
         lib.orc_adjoint.restype = C.c_int
         lib.orc_adjoint.argtypes = [P, C.c_int, P, P, P]
         lib.orc_threads.restype = C.c_int
+        lib.orc_get_solute_set.restype = C.c_int
+        lib.orc_get_solute_set.argtypes = [P, P]
         _lib = lib
     return _lib
 
@@ -91,13 +93,19 @@ class Oracle:
         p.xwrap_shift_y, p.inlet_axis, p.c_in = case.xwrap_shift_y, case.inlet_axis, case.c_in
         p.phase_change = case.phase_change
         p.collision = getattr(case, "collision", 0)
+        p.qs = getattr(case, "qs", 0)
         self._solid = case.solid_flat()
         self._normals = case.normals_flat()
         self._kr = None if case.k_r_field is None else np.ascontiguousarray(case.k_r_field, np.float64)
         self._phi0 = None if case.phi0 is None else np.ascontiguousarray(case.phi0, np.float64)
         self._h = lib.orc_create(C.byref(p), _ptr(self._solid), _ptr(self._normals),
                                  _ptr(self._kr), _ptr(self._phi0))
+        if not self._h:
+            raise ValueError(f"oracle refuses solute lattice qs={p.qs} with q={p.q}")
         self.N, self.Q = case.n, case.q
+        sd = np.empty(19, np.int32)
+        self.QS = int(lib.orc_get_solute_set(self._h, _ptr(sd)))
+        self.sdirs = sd[:self.QS].copy()
         if init:
             self.init(case.rho_flat(), case.u_flat(), case.c_flat())
 
@@ -124,8 +132,9 @@ class Oracle:
         return dict(rho=rho, u=u, c=c, phi=phi, type=typ)
 
     def pops(self):
+        """(f [Q, N], g [QS, N]); g in the solute set's order."""
         f = np.empty((self.Q, self.N))
-        g = np.empty((self.Q, self.N))
+        g = np.empty((self.QS, self.N))
         _load().orc_get_pops(self._h, _ptr(f), _ptr(g))
         return f, g
 
@@ -155,7 +164,9 @@ class Oracle:
         e = np.empty((self.Q, 3), np.int32)
         wf, ws, cs2 = np.empty(self.Q), np.empty(self.Q), np.empty(2)
         _load().orc_get_lattice(self._h, _ptr(e), _ptr(wf), _ptr(ws), _ptr(cs2))
-        return dict(e=e, wf=wf, ws=ws, cs2f=cs2[0], cs2s=cs2[1])
+        # ws by fluid direction (0 outside the solute set); sd: the fluid
+        # direction of each solute direction
+        return dict(e=e, wf=wf, ws=ws, cs2f=cs2[0], cs2s=cs2[1], sd=self.sdirs.copy())
 
     def adjoint(self, nsteps: int, dLdC, want_lam0: bool = False):
         """Runs nsteps forward, then the adjoint of a loss with gradient dLdC [N]

@@ -17,10 +17,14 @@
  *     g_eq = C w_i (1 + u.e_i / c_s^2), u the fluid velocity of the same node
  *     and step (Sec. 2.1, eqs. solute_BGK, solute_equilibrium_function,
  *     solute_diffu).
- *   - rest fraction (Sec. 2.2, eqs. RestFraction, RestFractionCs2): w_0 = J0,
- *     the moving weights scaled by (1 - J0)/(1 - w0_std) and c_s^2 likewise,
- *     which reduces to the paper's D2Q5/D3Q7 form and keeps sum w e e = c_s^2 I
- *     on D2Q9/D3Q19.
+ *   - solute velocity set: the paper's reduced lattices D2Q5 / D3Q7 (appendix,
+ *     velocity sets; rest vector and the axis vectors), or the fluid's own
+ *     D2Q9 / D3Q19.  A reduced set is located inside the fluid set by its
+ *     vectors, so both lattices pull along the same geometry.
+ *   - rest fraction (Sec. 2.2, eqs. RestFraction, RestFractionCs2): on D2Q5 /
+ *     D3Q7 exactly the paper's w_0 = J0, w_i = c_s^2/2, c_s^2 = (1 - J0)/dim;
+ *     on D2Q9 / D3Q19 w_0 = J0 and the moving weights scaled by
+ *     (1 - J0)/(1 - w0_std), c_s^2 likewise (keeps sum w e e = c_s^2 I).
  *   - reactive boundary condition (Sec. 2.3, eq. general_RBC and the k_i of
  *     eqs. k_i_S_Ve, k_i_S2, k_i_S_New; gamma of eq. gammaAppendix):
  *        g_out = k/(1+k) 2 w C_eq + (1-k)/(1+k) g_src
@@ -61,16 +65,21 @@ typedef struct {
     double c_in;
     int phase_change;
     int collision;          /* ORC_BGK | ORC_TRT */
+    int qs;                 /* solute lattice: 0 or q (the fluid's), 5 (D2Q5 with
+                               D2Q9) or 7 (D3Q7 with D3Q19) */
 } orc_params;
 
 typedef struct {
     orc_params p;
     int Q;
+    int QS;                /* solute directions                           */
+    int sd[ORC_QMAX];      /* solute direction s is fluid direction sd[s] */
     long N;
     int e[ORC_QMAX][3];
     int opp[ORC_QMAX];
     double wf[ORC_QMAX];   /* fluid weights: standard lattice            */
-    double ws[ORC_QMAX];   /* solute weights: rest-fraction lattice      */
+    double ws[ORC_QMAX];   /* solute weights: rest-fraction lattice, by
+                              fluid direction (0 outside the solute set)  */
     double cs2f, cs2s;
     double gamma;          /* tau_AD / (tau_AD - 1/2)                     */
     uint8_t *solid;
@@ -88,6 +97,12 @@ typedef struct {
 
 /* link classes of an incoming solute population */
 enum { K_KNOWN = 0, K_RBC = 1, K_WALL = 2, K_INLET = 3, K_OUTLET = 4 };
+
+/* the solute runs on the reduced D2Q5 / D3Q7 set */
+static int orc_reduced(const orc_params *p)
+{
+    return (p->q == 9 && p->qs == 5) || (p->q == 19 && p->qs == 7);
+}
 
 static void set_lattice(orc *o)
 {
@@ -125,16 +140,40 @@ static void set_lattice(orc *o)
                 o->e[j][2] == -o->e[i][2])
                 o->opp[i] = j;
     o->cs2f = 1.0 / 3.0;
-    /* rest fraction: J0 < 0 keeps the standard weights */
-    double w0 = o->wf[0];
-    if (o->p.j0 < 0) {
-        for (int i = 0; i < Q; i++) o->ws[i] = o->wf[i];
-        o->cs2s = 1.0 / 3.0;
+    for (int i = 0; i < Q; i++) o->ws[i] = 0.0;
+    if (orc_reduced(&o->p)) {
+        /* D2Q5 in the paper's appendix order; D3Q7 as the rest vector, the
+         * three axis vectors and their negatives */
+        static const int E5[5][3] = {{0, 0, 0}, {-1, 0, 0}, {0, -1, 0}, {1, 0, 0}, {0, 1, 0}};
+        static const int E7[7][3] = {{0, 0, 0}, {1, 0, 0}, {0, 1, 0}, {0, 0, 1},
+                                     {-1, 0, 0}, {0, -1, 0}, {0, 0, -1}};
+        const int dim = Q == 9 ? 2 : 3;
+        o->QS = Q == 9 ? 5 : 7;
+        for (int s = 0; s < o->QS; s++) {
+            const int *v = Q == 9 ? E5[s] : E7[s];
+            for (int i = 0; i < Q; i++)
+                if (o->e[i][0] == v[0] && o->e[i][1] == v[1] && o->e[i][2] == v[2]) o->sd[s] = i;
+        }
+        /* eqs. RestFraction, RestFractionCs2; without a rest fraction the
+         * common lattice (J0 = 1/3 on D2Q5, 1/4 on D3Q7) */
+        const double j0 = o->p.j0 < 0 ? (dim == 2 ? 1.0 / 3.0 : 1.0 / 4.0) : o->p.j0;
+        o->cs2s = (1.0 - j0) / dim;
+        o->ws[o->sd[0]] = j0;
+        for (int s = 1; s < o->QS; s++) o->ws[o->sd[s]] = o->cs2s / 2.0;
     } else {
-        double sc = (1.0 - o->p.j0) / (1.0 - w0);
-        o->ws[0] = o->p.j0;
-        for (int i = 1; i < Q; i++) o->ws[i] = o->wf[i] * sc;
-        o->cs2s = (1.0 / 3.0) * sc;
+        o->QS = Q;
+        for (int i = 0; i < Q; i++) o->sd[i] = i;
+        /* rest fraction: J0 < 0 keeps the standard weights */
+        double w0 = o->wf[0];
+        if (o->p.j0 < 0) {
+            for (int i = 0; i < Q; i++) o->ws[i] = o->wf[i];
+            o->cs2s = 1.0 / 3.0;
+        } else {
+            double sc = (1.0 - o->p.j0) / (1.0 - w0);
+            o->ws[0] = o->p.j0;
+            for (int i = 1; i < Q; i++) o->ws[i] = o->wf[i] * sc;
+            o->cs2s = (1.0 / 3.0) * sc;
+        }
     }
     o->gamma = o->p.tau_ad / (o->p.tau_ad - 0.5);
 }
@@ -191,6 +230,7 @@ static void fd_normal(orc *o, long s);
 orc *orc_create(const orc_params *p, const uint8_t *solid, const double *normals,
                 const double *k_r, const double *phi0)
 {
+    if (!(p->qs == 0 || p->qs == p->q || orc_reduced(p))) return NULL;
     orc *o = (orc *)calloc(1, sizeof(orc));
     o->p = *p;
     set_lattice(o);
@@ -337,13 +377,20 @@ static void update_node(orc *o, long x)
             o->fn[x * Q + i] = fp[i] - (fp[i] - fe[i]) / p->tau_ns + (1.0 - 0.5 / p->tau_ns) * S[i];
     }
 
-    /* solute: pull, plane conditions, then the reactive links */
+    /* solute: pull, plane conditions, then the reactive links; only the
+     * directions of the solute set (a fluid direction outside it carries no
+     * solute population and no link) */
     double gp[ORC_QMAX];
     uint8_t kd[ORC_QMAX];
     long sol[ORC_QMAX];
     for (int i = 0; i < Q; i++) {
-        long y = site(o, X, Y, Z, -o->e[i][0], -o->e[i][1], -o->e[i][2], 1, &face);
+        gp[i] = 0.0;
+        kd[i] = K_KNOWN;
         sol[i] = -1;
+    }
+    for (int s = 0; s < o->QS; s++) {
+        const int i = o->sd[s];
+        long y = site(o, X, Y, Z, -o->e[i][0], -o->e[i][1], -o->e[i][2], 1, &face);
         if (y >= 0) {
             if (!o->solid[y]) { gp[i] = go[y * Q + i]; kd[i] = K_KNOWN; }
             else { kd[i] = K_RBC; sol[i] = y; gp[i] = 0.0; }
@@ -389,7 +436,7 @@ static void update_node(orc *o, long x)
         o->qx[x * Q + i] = gout - go[x * Q + ob];
     }
     double C = 0;
-    for (int i = 0; i < Q; i++) C += gp[i];
+    for (int s = 0; s < o->QS; s++) C += gp[o->sd[s]];
     if (p->collision == ORC_TRT) {
         /* TRT for the solute (Sec. 2.1, eqs. solute_TRT, solute_TRT_terms,
          * solute_TRT_visc): the even parts relax with 1/tau-, the odd parts
@@ -397,15 +444,17 @@ static void update_node(orc *o, long x)
         const double tp = p->tau_ad, tm = 0.5 + ORC_MAGIC / (p->tau_ad - 0.5);
         double ge[ORC_QMAX];
         for (int i = 0; i < Q; i++) ge[i] = geq(o, i, C, u);
-        for (int i = 0; i < Q; i++) {
-            const int ob = o->opp[i];
+        for (int s = 0; s < o->QS; s++) {
+            const int i = o->sd[s], ob = o->opp[i];
             const double gpl = 0.5 * (gp[i] + gp[ob]), gmi = 0.5 * (gp[i] - gp[ob]);
             const double epl = 0.5 * (ge[i] + ge[ob]), emi = 0.5 * (ge[i] - ge[ob]);
             o->gn[x * Q + i] = gp[i] - (gpl - epl) / tm - (gmi - emi) / tp;
         }
     } else {
-        for (int i = 0; i < Q; i++)
+        for (int s = 0; s < o->QS; s++) {
+            const int i = o->sd[s];
             o->gn[x * Q + i] = gp[i] - (gp[i] - geq(o, i, C, u)) / p->tau_ad;
+        }
     }
 }
 
@@ -726,6 +775,7 @@ int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *la
     const int Q = o->Q;
     if (o->p.phase_change) return -2;
     if (o->p.collision != ORC_BGK) return -3;   /* the transposed step below is BGK's */
+    if (o->QS != Q) return -4;                  /* ... on the fluid's velocity set */
     double *G = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * Q);
     double *U = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * 3);
     double *lam = (double *)calloc((size_t)N * Q, sizeof(double));
@@ -782,25 +832,35 @@ void orc_get_fields(const orc *o, double *rho, double *u, double *c, double *phi
     }
 }
 
-/* post-collision populations, structure-of-arrays [Q][N] */
+/* post-collision populations, structure-of-arrays: f [Q][N], g [QS][N] in
+ * the solute set's order */
 void orc_get_pops(const orc *o, double *f, double *g)
 {
     const int Q = o->Q;
-    for (long n = 0; n < o->N; n++)
-        for (int i = 0; i < Q; i++) {
+    for (long n = 0; n < o->N; n++) {
+        for (int i = 0; i < Q; i++)
             if (f) f[(long)i * o->N + n] = o->f[n * Q + i];
-            if (g) g[(long)i * o->N + n] = o->g[n * Q + i];
-        }
+        for (int s = 0; s < o->QS; s++)
+            if (g) g[(long)s * o->N + n] = o->g[n * Q + o->sd[s]];
+    }
 }
 
 void orc_set_pops(orc *o, const double *f, const double *g)
 {
     const int Q = o->Q;
-    for (long n = 0; n < o->N; n++)
-        for (int i = 0; i < Q; i++) {
+    for (long n = 0; n < o->N; n++) {
+        for (int i = 0; i < Q; i++)
             if (f) o->f[n * Q + i] = f[(long)i * o->N + n];
-            if (g) o->g[n * Q + i] = g[(long)i * o->N + n];
-        }
+        for (int s = 0; s < o->QS; s++)
+            if (g) o->g[n * Q + o->sd[s]] = g[(long)s * o->N + n];
+    }
+}
+
+/* the solute set: its size, and the fluid direction of each solute direction */
+int orc_get_solute_set(const orc *o, int *sd)
+{
+    for (int s = 0; s < o->QS; s++) sd[s] = o->sd[s];
+    return o->QS;
 }
 
 /* mass exchanged over each reactive link in the last step, [N][Q] */
@@ -812,7 +872,8 @@ void orc_get_exchange(const orc *o, double *q, uint8_t *kind)
 }
 
 /* k_i per (fluid node, direction) of the current geometry, [N][Q]; -1 where
- * the incoming population is not a reactive link */
+ * the incoming population is not a reactive link (a direction outside the
+ * solute set has weight 0 and no link) */
 void orc_get_link_k(const orc *o, double *k)
 {
     const int Q = o->Q;
@@ -823,7 +884,7 @@ void orc_get_link_k(const orc *o, double *k)
             k[n * Q + i] = -1.0;
             if (o->solid[n]) continue;
             long y = site(o, X, Y, Z, -o->e[i][0], -o->e[i][1], -o->e[i][2], 1, &face);
-            if (y >= 0 && o->solid[y]) k[n * Q + i] = link_k(o, y, i);
+            if (y >= 0 && o->solid[y] && o->ws[i] > 0.0) k[n * Q + i] = link_k(o, y, i);
         }
     }
 }

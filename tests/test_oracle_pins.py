@@ -250,6 +250,225 @@ def test_trt_adjoint_is_refused():
 
 
 # --------------------------------------------------------------------------
+# reduced solute lattices D2Q5 / D3Q7 (the paper's solute lattices)
+# --------------------------------------------------------------------------
+def _box3(n=(3, 3, 3), **kw):
+    solid = np.zeros((n[2], n[1], n[0]), np.uint8)
+    base = dict(name="t", dim=3, nx=n[0], ny=n[1], nz=n[2], q=19, solid=solid)
+    base.update(kw)
+    return Case(**base)
+
+
+def test_d2q5_matches_paper_table():
+    """The solute set of a D2Q5 run is the paper's D2Q5 (appendix, velocity
+    sets; golden file) in the paper's order, with its weights 1/3, 1/6 and
+    c_s^2 = 1/3 when no rest fraction is set."""
+    rows = np.loadtxt(os.path.join(GOLDEN, "d2q5_velocity_set.txt"))
+    o = Oracle(_small_case(qs=5))
+    lat = o.lattice()
+    sd = lat["sd"]
+    assert o.QS == 5
+    assert np.array_equal(lat["e"][sd, :2], rows[:, 1:3].astype(int))
+    assert np.allclose(lat["ws"][sd], rows[:, 3] / rows[:, 4], rtol=0, atol=1e-16)
+    assert lat["cs2s"] == pytest.approx(1 / 3, abs=1e-16)
+    outside = np.setdiff1d(np.arange(9), sd)
+    assert (lat["ws"][outside] == 0).all()
+
+
+@pytest.mark.parametrize("q,qs", [(9, 5), (19, 7)])
+@pytest.mark.parametrize("j0", [-1.0, 0.0, 0.25, 0.6, 0.99])
+def test_reduced_lattice_moments_and_rest_fraction(q, qs, j0):
+    """D2Q5 / D3Q7: the solute set is the rest vector plus the 2 dim unit
+    vectors; sum w = 1, sum w e = 0, sum w e e = c_s^2 I; with a rest fraction
+    w_0 = J0 and c_s^2 = (1 - J0)/dim (eqs. RestFraction, RestFractionCs2),
+    without one the common lattice (J0 = 1/3 in 2D, 1/4 in 3D)."""
+    dim = 2 if q == 9 else 3
+    case = _small_case(j0=j0, qs=qs) if q == 9 else _box3(j0=j0, qs=qs)
+    o = Oracle(case)
+    lat = o.lattice()
+    sd = lat["sd"]
+    e = lat["e"][sd, :dim].astype(float)
+    w = lat["ws"][sd]
+    assert len(sd) == qs == 1 + 2 * dim
+    assert sorted(map(tuple, e.astype(int))) == sorted(
+        [tuple([0] * dim)] + [tuple(s * np.eye(dim, dtype=int)[a]) for a in range(dim) for s in (1, -1)])
+    jj = j0 if j0 >= 0 else (1 / 3 if dim == 2 else 1 / 4)
+    cs2 = (1 - jj) / dim
+    assert lat["cs2s"] == pytest.approx(cs2, abs=1e-16)
+    assert w.sum() == pytest.approx(1.0, abs=1e-15)
+    assert np.abs(w @ e).max() < 1e-16
+    assert np.allclose(np.einsum("i,ia,ib->ab", w, e, e), cs2 * np.eye(dim), atol=1e-15)
+    assert w[0] == pytest.approx(jj, abs=1e-16)
+
+
+@pytest.mark.parametrize("q,qs,j0,tau,u", [
+    (9, 5, -1.0, 0.8, (0.0, 0.0, 0.0)),
+    (9, 5, 0.6, 1.3, (0.02, -0.01, 0.0)),
+    (19, 7, 0.1, 0.7, (0.01, 0.015, -0.02)),
+])
+def test_reduced_fourier_mode_matches_matrix_power(q, qs, j0, tau, u):
+    """As for the full lattices: one periodic Fourier mode of C on D2Q5 / D3Q7
+    evolves by the power of the QS x QS von Neumann step matrix."""
+    dim = 2 if q == 9 else 3
+    n = (16, 12, 1) if dim == 2 else (8, 6, 10)
+    solid = np.zeros((n[2], n[1], n[0]), np.uint8)
+    N = solid.size
+    z, y, x = np.meshgrid(np.arange(n[2]), np.arange(n[1]), np.arange(n[0]), indexing="ij")
+    kv = np.array([2 * np.pi * 2 / n[0], 2 * np.pi * 1 / n[1], (2 * np.pi / n[2]) if dim == 3 else 0.0])
+    phase = (kv[0] * x + kv[1] * y + kv[2] * z).reshape(-1)
+    A, C0 = 0.3, 1.1
+    c = C0 + A * np.cos(phase + 0.4)
+    uu = np.tile(np.array(u, float), (N, 1))
+    case = Case(name="f", dim=dim, nx=n[0], ny=n[1], nz=n[2], q=q, qs=qs, solid=solid,
+                tau_ns=0.9, tau_ad=tau, j0=j0, c_init=c, u_init=uu)
+    o = Oracle(case)
+    lat = o.lattice()
+    sd = lat["sd"]
+    e, ws, cs2 = lat["e"][sd].astype(float), lat["ws"][sd], lat["cs2s"]
+    steps = 25
+    o.step(steps)
+    _, g = o.pops()
+    assert g.shape == (qs, N)
+    E = np.outer(ws * (1 + e @ np.array(u) / cs2), np.ones(qs))
+    S = np.diag(np.exp(-1j * (e @ kv)))
+    M = (np.eye(qs) - (np.eye(qs) - E) / tau) @ S
+    v0 = A * np.exp(0.4j) * ws * (1 + e @ np.array(u) / cs2)
+    vn = np.linalg.matrix_power(M, steps) @ v0
+    pred = C0 * ws[:, None] * (1 + e @ np.array(u) / cs2)[:, None] + \
+        np.real(vn[:, None] * np.exp(1j * phase)[None, :])
+    assert np.abs(g - pred).max() < 1e-12
+
+
+@pytest.mark.parametrize("q,qs,j0", [(9, 5, -1.0), (9, 5, 0.8), (19, 7, -1.0), (19, 7, 0.9)])
+def test_reduced_diffusion_coefficient_from_mode_decay(q, qs, j0):
+    """A long-wavelength mode decays as exp(-D k^2 t) with the paper's
+    D = (1 - J0)/dim (tau_AD - 1/2) (rest fraction section)."""
+    nx, tau = 128, 0.9
+    dim = 2 if q == 9 else 3
+    solid = np.zeros((1, 1, nx), np.uint8)
+    x = np.arange(nx)
+    k = 2 * np.pi / nx
+    case = Case(name="d", dim=dim, nx=nx, ny=1, nz=1, q=q, qs=qs, solid=solid, tau_ad=tau,
+                j0=j0, c_init=1.0 + 0.1 * np.cos(k * x))
+    o = Oracle(case)
+    steps = 400
+    o.step(steps)
+    c = o.fields()["c"]
+    amp = 2 * np.abs(np.fft.rfft(c - c.mean())[1]) / nx
+    jj = j0 if j0 >= 0 else (1 / 3 if dim == 2 else 1 / 4)
+    D = (1 - jj) / dim * (tau - 0.5)
+    assert amp / 0.1 == pytest.approx(math.exp(-D * k * k * steps), rel=2e-3)
+
+
+@pytest.mark.parametrize("mech,scheme,offset,factor", [
+    (MECH_PRE, SCHEME_SNEW, 0.0, "1"),
+    (MECH_POST, SCHEME_SV, 0.5, "1"),
+    (MECH_PRE, SCHEME_SV, 0.0, "1/gamma"),
+])
+@pytest.mark.parametrize("j0", [-1.0, 0.6])
+def test_reduced_linear_steady_robin(mech, scheme, offset, factor, j0):
+    """The exact linear steady state between an equilibrium inlet and a
+    reactive wall holds on D2Q5 with c_s^2 = (1 - J0)/2, the wall on the node
+    (pre-collision source) or halfway (post-collision source)."""
+    tau, k_r = 0.8, 2e-2
+    case = configs.robin_1d(ny_fluid=20, tau_ad=tau, k_r=k_r, mechanics=mech, scheme=scheme)
+    case = case.replace(qs=5, j0=j0)
+    o = Oracle(case)
+    o.step(40000)
+    c = o.fields()["c"].reshape(case.ny, case.nx)[:-1]
+    gamma = tau / (tau - 0.5)
+    keff = {"1": k_r, "gamma": gamma * k_r, "1/gamma": k_r / gamma}[factor]
+    cs2 = (1 - (j0 if j0 >= 0 else 1 / 3)) / 2
+    exact = linear_robin_steady(case.ny - 1, tau, cs2, keff, case.c_in, case.c_eq, offset)
+    for col in range(case.nx):
+        assert np.abs(c[:, col] - exact).max() < 1e-11
+
+
+@pytest.mark.parametrize("coll", [COLL_BGK, COLL_TRT])
+def test_reduced_equals_full_lattice_on_a_plane_channel(coll):
+    """Fields that vary only across a flat reactive channel reduce both solute
+    lattices to the same three-velocity lattice: the populations of D2Q9 with
+    e_y = +1 sum to D2Q5's (0, 1) (weights 1/36 + 1/9 + 1/36 = 1/6), and all of
+    them see the same k_i (e_i.n = 1).  With flow along the channel and a
+    force, the concentration and the total wall exchange of D2Q5 (J0 = 1/3)
+    and D2Q9 runs agree to rounding; likewise D3Q7 with J0 = 0 (c_s^2 = 1/3)
+    and D3Q19."""
+    rng = np.random.default_rng(5)
+    for dim in (2, 3):
+        if dim == 2:
+            nx, ny, nz = 4, 14, 1
+            solid, normals = geometry.plane_channel(nx, ny, (0, ny - 1))
+            prof = rng.uniform(0.0, 2.0, ny)
+            c0 = np.broadcast_to(prof[None, :, None], (1, ny, nx)).copy()
+            full = dict(q=9, j0=-1.0)
+            red = dict(q=9, qs=5, j0=-1.0)
+            F = (1e-5, 0.0, 0.0)
+        else:
+            nx, ny, nz = 3, 3, 12
+            solid = np.zeros((nz, ny, nx), np.uint8)
+            solid[0], solid[-1] = 1, 1
+            normals = np.zeros((nz, ny, nx, 3))
+            normals[0, ..., 2], normals[-1, ..., 2] = 1.0, -1.0
+            prof = rng.uniform(0.0, 2.0, nz)
+            c0 = np.broadcast_to(prof[:, None, None], (nz, ny, nx)).copy()
+            full = dict(q=19, j0=-1.0)
+            red = dict(q=19, qs=7, j0=0.0)
+            F = (1e-5, 0.0, 0.0)
+        runs = []
+        for lat in (full, red):
+            case = Case(name="eq", dim=dim, nx=nx, ny=ny, nz=nz, solid=solid, normals=normals,
+                        tau_ns=0.8, tau_ad=1.1, force=F, c_eq=1.0, k_r=0.02, v_m=0.1,
+                        c_init=c0, collision=coll, **lat)
+            o = Oracle(case)
+            o.step(300)
+            runs.append((o.fields()["c"], o.diag()["wall_exchange"]))
+        assert np.abs(runs[0][0] - runs[1][0]).max() < 1e-13
+        assert runs[0][1] == pytest.approx(runs[1][1], rel=1e-12)
+        assert abs(runs[0][1]) > 1e-3
+
+
+@pytest.mark.parametrize("q,qs", [(9, 5), (19, 7)])
+def test_reduced_solute_plus_solid_mass_invariant(q, qs):
+    """Closed periodic domain on D2Q5 / D3Q7: sum C + sum phi / V_m is
+    invariant and the solute mass changes by the wall exchange."""
+    rng = np.random.default_rng(6)
+    if q == 9:
+        solid, normals, _ = geometry.disk_medium(40, 32, 0.65, 3.0, 6.0, seed=12)
+        dims = dict(dim=2, nx=40, ny=32, nz=1)
+    else:
+        solid, normals, _ = geometry.sphere_packing(16, 2.0, 4.0, 0.7, seed=5)
+        dims = dict(dim=3, nx=16, ny=16, nz=16)
+    case = Case(name="m", q=q, qs=qs, solid=solid, normals=normals, tau_ns=0.8, tau_ad=0.75,
+                j0=0.4, force=(2e-5, 0, 0), c_eq=1.0, k_r_field=rng.uniform(0, 0.05, solid.size),
+                v_m=0.3, mechanics=MECH_POST, scheme=SCHEME_SV,
+                c_init=rng.uniform(0.0, 2.0, solid.size), **dims)
+    o = Oracle(case)
+    d0 = o.diag()
+    tot0 = d0["mass_c"] + d0["phi_sum"] / case.v_m
+    o.step(200)
+    d = o.diag()
+    assert d["mass_c"] + d["phi_sum"] / case.v_m == pytest.approx(tot0, rel=1e-12)
+    assert d["mass_c"] - d0["mass_c"] == pytest.approx(d["wall_exchange"], rel=1e-9, abs=1e-12)
+    q_, kind = o.exchange()
+    lat = o.lattice()
+    outside = np.setdiff1d(np.arange(q), lat["sd"])
+    assert (kind[:, outside] == 0).all() and (q_[:, outside] == 0).all()
+    assert (kind[:, lat["sd"]] == 1).any()
+
+
+def test_reduced_refusals():
+    """The oracle takes D2Q5 only with D2Q9 and D3Q7 only with D3Q19, and the
+    hand-written adjoint transposes the full-lattice step only."""
+    with pytest.raises(ValueError):
+        Oracle(_small_case(qs=7))
+    with pytest.raises(ValueError):
+        Oracle(_box3(qs=5))
+    o = Oracle(_small_case(qs=5, k_r=0.01))
+    with pytest.raises(RuntimeError):
+        o.adjoint(2, np.zeros(o.N))
+
+
+# --------------------------------------------------------------------------
 # reactive boundary condition
 # --------------------------------------------------------------------------
 READINGS = [  # (mechanics, scheme, wall offset, factor on k_r that is realised)
