@@ -31,15 +31,18 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2306_10794_amd", "csrc")
 # sources that determine the step kernel's code
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("lbm_step.hip", "lbm_device.hpp", "lbm_internal.hpp")]
-STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4, false>"
-PHI_KERNEL = "lbm::k_phi_solid<lbm::D3Q19, float>"
+STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4, false, false>"
+PHI_KERNEL = "lbm::k_phi_solid<lbm::D3Q19, float, false>"
+# the same workload with the solute on D3Q7
+RED_STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4, false, true>"
+RED_PHI_KERNEL = "lbm::k_phi_solid<lbm::D3Q19, float, true>"
 COPY_KERNEL = "neg_kernel"   # torch elementwise negation: one read, one write per element
 # the rocprofv3 runs whose summaries are committed (run from the repository
 # root after `cd /tmp && export TMPDIR=/tmp && cd -`)
 PROFILE_ARGS = ("--steps 50 --warmup 5 --no-cpu-baseline --no-batch --no-adjoint --no-phase-change "
-                "--calib-copy-mib 1024")
+                "--reduced-steps 50 --calib-copy-mib 1024")
 PMC_ARGS = ("--steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-adjoint --no-phase-change "
-            "--calib-copy-mib 1024")
+            "--reduced-steps 5 --calib-copy-mib 1024")
 PROFILE_CMDS = {
     "trace": f"rocprofv3 --kernel-trace --stats -d gpurun_out/prof/trace -o run -- "
              f"python3 bench.py {PROFILE_ARGS}",
@@ -53,16 +56,18 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(q, ts, n_fluid, n_links, n_fluid_iface):
+def kernel_bytes(q, ts, n_fluid, n_links, n_fluid_iface, qs=None):
     """Algorithmic HBM bytes of one launch of the fused step kernel.
 
-    Per fluid node: both lattices read and write Q populations of ts bytes
-    (a reactive link reads the node's own population toward the wall in place
-    of a pulled one), plus 4 bytes of node metadata.  Per reactive link: the
-    link coefficient read and the exchange written (2 x ts).  Per fluid
+    Per fluid node: the fluid lattice reads and writes Q populations and the
+    solute lattice QS (= Q unless the solute runs on D2Q5 / D3Q7) of ts bytes
+    each (a reactive link reads the node's own population toward the wall in
+    place of a pulled one), plus 4 bytes of node metadata.  Per reactive link:
+    the link coefficient read and the exchange written (2 x ts).  Per fluid
     interface node: its FP64 solid fraction read and written (16 B).
     """
-    return n_fluid * (2 * q * ts * 2 + 4) + n_links * 2 * ts + n_fluid_iface * 16
+    qs = q if qs is None else qs
+    return n_fluid * ((q + qs) * ts * 2 + 4) + n_links * 2 * ts + n_fluid_iface * 16
 
 
 def kernel_sha256():
@@ -235,6 +240,33 @@ def phase_change_run(case, steps, planes, phi_near):
             "fluid_nodes_after": int(d["n_fluid"]), "status": int(d["status"])}
 
 
+def reduced_run(case, steps, warmup):
+    """The same workload with the solute on D3Q7 (the paper's 3D solute set)
+    at the same diffusivity: fewer solute populations and links per node."""
+    import torch
+    from lbm_inputs import configs
+    from paper_2306_10794_amd import Simulation, LBM_FP32_DEV, lbm_step, lbm_step_timed
+    rc = configs.with_reduced_solute(case)
+    sim = Simulation(rc, precision=LBM_FP32_DEV, device="cuda:0")
+    lbm_step(sim.ctx, warmup)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    lbm_step(sim.ctx, steps)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    k_ms, phi_ms = lbm_step_timed(sim.ctx, steps)
+    d = sim.diag()
+    sim.close()
+    kb = kernel_bytes(rc.q, 4, d["n_fluid"], d["n_links"], d["n_fluid_iface"], qs=rc.qs)
+    k_s = k_ms / steps / 1e3
+    return {"lattices": f"D3Q19 fluid + D3Q{rc.qs} solute", "j0": round(rc.j0, 6),
+            "mlups": round(d["n_fluid"] * steps / wall / 1e6, 1), "ms_per_step": round(wall / steps * 1e3, 4),
+            "steps": steps, "reactive_links": int(d["n_links"]), "bytes_per_launch": int(kb),
+            "avg_kernel_us": round(k_s * 1e6, 2), "phi_kernel_us": round(phi_ms / steps * 1e3, 2),
+            "achieved_gbs": round(kb / k_s / 1e9, 1), "frac": round(kb / k_s / 1e9 / HBM_PEAK_GBS, 4),
+            "status": d["status"]}
+
+
 def cpu_baseline(case, steps):
     import oracle
     o = oracle.Oracle(case)
@@ -318,7 +350,7 @@ def summarize_profiles(prof_dir, workload="spheres256", calib_mib=1024):
              f"WRITE_SIZE {copy_kib(write):.0f} KiB (scale {f_write:.3f}).", "",
              "| kernel | dispatches | FETCH_SIZE KiB | WRITE_SIZE KiB | scaled read B | scaled write B | "
              "scaled total B |", "|---|---|---|---|---|---|---|"]
-    for k in (STEP_KERNEL, PHI_KERNEL):
+    for k in (STEP_KERNEL, PHI_KERNEL, RED_STEP_KERNEL, RED_PHI_KERNEL):
         if k in fetch and k in write:
             fk = sum(fetch[k]) / len(fetch[k])
             wk = sum(write[k]) / len(write[k])
@@ -357,6 +389,9 @@ def main():
     ap.add_argument("--no-adjoint", action="store_true", help="skip the adjoint/forward ratio")
     ap.add_argument("--no-phase-change", action="store_true",
                     help="skip the run with the phase-change thresholds on")
+    ap.add_argument("--no-reduced", action="store_true",
+                    help="skip the run with the solute on D3Q7")
+    ap.add_argument("--reduced-steps", type=int, default=200)
     ap.add_argument("--phase-change-steps", type=int, default=300)
     ap.add_argument("--phase-change-planes", type=int, default=2,
                     help="inlet planes whose fluid nodes start near the precipitation threshold")
@@ -444,12 +479,16 @@ def main():
         "batch": None,
         "adjoint": None,
         "phase_change": None,
+        "reduced_solute": None,
     }
     sim.close()
     del sim
     torch.cuda.empty_cache()
     if args.calib_copy_mib > 0:
         calibration_copies(args.calib_copy_mib)
+    if not args.no_reduced:
+        line["reduced_solute"] = reduced_run(case, args.reduced_steps, max(5, args.warmup // 2))
+        log(f"[bench] reduced solute {line['reduced_solute']}")
     if not args.no_batch:
         line["batch"] = batch_vs_plain(args.batch_steps, args.plain_steps, args.tune_steps)
         log(f"[bench] batch {line['batch']}")

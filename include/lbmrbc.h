@@ -9,7 +9,9 @@
  *     equilibrium g_eq = C w_i (1 + u.e_i / c_s^2), u taken from the fluid at
  *     the same node and step (Sec. 2.1, eqs. solute_BGK,
  *     solute_equilibrium_function, solute_diffu), with the rest-fraction
- *     weights (Sec. 2.2, eqs. RestFraction, RestFractionCs2);
+ *     weights (Sec. 2.2, eqs. RestFraction, RestFractionCs2), on the fluid's
+ *     velocity set or on the paper's reduced D2Q5 / D3Q7 (appendix, velocity
+ *     sets; params.solute_q);
  *   - the general reactive boundary condition on every link that enters a
  *     fluid node from a solid node (Sec. 2.3, eq. general_RBC with the k_i of
  *     eqs. k_i_S_Ve, k_i_S2, k_i_S_New and gamma of eq. gammaAppendix);
@@ -83,13 +85,23 @@ typedef struct {
     int32_t dim;              /* 2 or 3                                            */
     int32_t nx, ny, nz;       /* lattice size; nz = 1 when dim = 2                 */
     int32_t fluid_q;          /* 9 (D2Q9) or 19 (D3Q19)                            */
-    int32_t solute_q;         /* must equal fluid_q                                */
+    int32_t solute_q;         /* fluid_q, or 5 (D2Q5, with D2Q9) / 7 (D3Q7, with
+                                 D3Q19): the solute's velocity set.  D2Q5 is the
+                                 rest vector and the four axis vectors in the
+                                 paper's appendix order; D3Q7 the rest vector,
+                                 +x, +y, +z, -x, -y, -z.  On these sets w_0 = J0,
+                                 w_i = c_s^2/2, c_s^2 = (1 - J0)/dim (J0 = 1/3
+                                 resp. 1/4 when j0 < 0), and reactive links exist
+                                 along their directions only.  Not with
+                                 lbm_record / lbm_adjoint.                    */
     int32_t precision;        /* LBM_FP64 | LBM_FP32_DEV                           */
     int32_t rbc_mechanics;    /* LBM_PRECOLL | LBM_POSTCOLL                        */
     int32_t rbc_scheme;       /* LBM_SNEW | LBM_SV | LBM_SPJ | LBM_ABB             */
     double tau_ns;            /* fluid relaxation time, > 1/2                      */
     double tau_ad;            /* solute relaxation time, > 1/2                     */
-    double j0;                /* rest fraction in [0,1); < 0: standard weights     */
+    double j0;                /* rest fraction in [0,1); < 0: standard weights.  On
+                                 D2Q9 / D3Q19 w_0 = J0 and the moving weights
+                                 and c_s^2 scale by (1 - J0)/(1 - w_0,std)     */
     double force[3];          /* body force on the fluid (lattice units)           */
     double rho0;              /* FP32_DEV reference density (ignored in FP64)      */
     double c_ref;             /* FP32_DEV reference concentration (ignored in FP64)*/
@@ -227,7 +239,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
  * every reactive link through eqs. k_i_S_Ve, k_i_S2, k_i_S_New and
  * eq. general_RBC).  The fluid does not depend on k_r; the adjoint covers a
  * fluid at rest (pure reaction-diffusion): single-lattice contexts with no
- * body force, inlet_axis = -1 and phase_change = 0 (EINVAL otherwise, and
+ * body force, inlet_axis = -1, phase_change = 0, collision = LBM_BGK and
+ * solute_q = fluid_q (EINVAL otherwise, and
  * lbm_record checks that no fluid node carries momentum).
  *
  * lbm_adjoint_workspace_bytes: device bytes that lbm_record needs for nsteps
@@ -256,12 +269,15 @@ lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k);
 lbm_status lbm_get_fields(lbm_ctx *ctx, double *rho, double *u, double *c, double *phi,
                           uint8_t *type);
 
-/* Post-collision populations as absolute FP64 values, [Q][N] (NULL skips). */
+/* Post-collision populations as absolute FP64 values (NULL skips): f
+ * [fluid_q][N] in the fluid set's order, g [solute_q][N] in the solute set's
+ * order. */
 lbm_status lbm_get_pops(lbm_ctx *ctx, double *f, double *g);
 
 /* Mass that crossed each reactive link in the last step, scattered to a dense
- * [N][Q] FP64 array (zero where there is no link; all zero after a step
- * whose phase change rebuilt the link list). */
+ * [N][fluid_q] FP64 array indexed by fluid direction (zero where there is no
+ * link, e.g. along a direction outside a reduced solute set; all zero after a
+ * step whose phase change rebuilt the link list). */
 lbm_status lbm_get_exchange(lbm_ctx *ctx, double *q);
 
 /* FP64 reductions of the current state (host struct; synchronises).

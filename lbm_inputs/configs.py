@@ -23,6 +23,20 @@ def j0_for_cs2(q: int, cs2: float) -> float:
     return 1.0 - cs2 * 3.0 * (1.0 - w0)
 
 
+def j0_reduced_for_cs2(dim: int, cs2: float) -> float:
+    """Rest fraction giving cs2 on D2Q5 / D3Q7 (c_s^2 = (1 - J0)/dim)."""
+    return 1.0 - dim * cs2
+
+
+def with_reduced_solute(case):
+    """The same workload with the solute on D2Q5 / D3Q7 at the same c_s^2
+    (so the same diffusivity at the same tau_AD)."""
+    w0 = 4.0 / 9.0 if case.q == 9 else 1.0 / 3.0
+    cs2 = 1.0 / 3.0 if case.j0 < 0 else (1.0 - case.j0) / (3.0 * (1.0 - w0))
+    return case.replace(qs=5 if case.q == 9 else 7, j0=j0_reduced_for_cs2(case.dim, cs2),
+                        name=case.name + ("_d2q5" if case.q == 9 else "_d3q7"))
+
+
 # --------------------------------------------------------------------------
 # workload 0: 64 x 32 reactive channel, pure diffusion, FP64
 # --------------------------------------------------------------------------

@@ -26,7 +26,8 @@ std::string check_params(const lbm_params &p) {
     if (p.dim == 2 && (p.nz != 1 || p.fluid_q != 9)) return "dim = 2 requires nz = 1 and fluid_q = 9";
     if (p.dim == 3 && p.fluid_q != 19) return "dim = 3 requires fluid_q = 19";
     if (p.dim == 3 && p.nz < 2) return "dim = 3 requires nz >= 2";
-    if (p.solute_q != p.fluid_q) return "solute_q must equal fluid_q";
+    if (!(p.solute_q == p.fluid_q || (p.fluid_q == 9 && p.solute_q == 5) || (p.fluid_q == 19 && p.solute_q == 7)))
+        return "solute_q must equal fluid_q, or be 5 (D2Q5) with D2Q9 or 7 (D3Q7) with D3Q19";
     if (p.precision != LBM_FP64 && p.precision != LBM_FP32_DEV) return "unknown precision";
     if (p.rbc_mechanics != LBM_PRECOLL && p.rbc_mechanics != LBM_POSTCOLL) return "unknown rbc_mechanics";
     if (p.rbc_scheme < LBM_SNEW || p.rbc_scheme > LBM_ABB) return "unknown rbc_scheme";
@@ -78,7 +79,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         L += default_links(p[d]);
     }
     if (L > 2147483000LL) L = 2147483000LL;
-    const int Q = p[0].fluid_q;
+    const int Q = p[0].fluid_q, QS = p[0].solute_q;
     const size_t ts = p[0].precision == LBM_FP64 ? 8 : 4;
     // direction stride: a multiple of 64 elements and an odd multiple of
     // 64 * ts bytes, so the 2Q streams of a step do not all start on the same
@@ -95,7 +96,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         off += up(bytes);
         return r;
     };
-    char *f0 = take(ts * Q * S), *f1 = take(ts * Q * S), *g0 = take(ts * Q * S), *g1 = take(ts * Q * S);
+    char *f0 = take(ts * Q * S), *f1 = take(ts * Q * S), *g0 = take(ts * QS * S), *g1 = take(ts * QS * S);
     char *doms = take(sizeof(DomDev) * nd);
     char *noff = take(8 * (nd + 1)), *woff = take(8 * (nd + 1)), *roff = take(8 * (nd + 1));
     char *rows = take(sizeof(RowWord) * RW), *tasks = take(sizeof(Task) * task_cap);
@@ -129,6 +130,10 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->R = R;
         c->RW = RW;
         c->Q = Q;
+        c->QS = QS;
+        c->red = QS != Q;
+        c->smask = Q == 9 ? (c->red ? axis_mask<D2Q9>() : sol_mask<D2Q9, false>())
+                          : (c->red ? axis_mask<D3Q19>() : sol_mask<D3Q19, false>());
         c->task_cap = task_cap;
         c->max_links = L;
         c->f[0] = f0; c->f[1] = f1; c->g[0] = g0; c->g[1] = g1;
@@ -196,7 +201,19 @@ static void setup_domain(const lbm_params &p, DomHost &d) {
     const double *w = p.fluid_q == 9 ? D2Q9::w : D3Q19::w;
     const double w0 = w[0];
     for (int i = 0; i < 19; i++) d.ws[i] = 0.0;
-    if (p.j0 < 0) {
+    if (p.solute_q != p.fluid_q) {
+        // D2Q5 / D3Q7 (Sec. 2.2, eqs. RestFraction, RestFractionCs2): w_0 = J0,
+        // every axis direction c_s^2 / 2, c_s^2 = (1 - J0)/dim; without a rest
+        // fraction the common lattice, J0 = 1/3 (D2Q5) or 1/4 (D3Q7).  The
+        // axis directions of the fluid lattice all weigh w_ax, so ws = w * wsc.
+        const uint32_t m = p.fluid_q == 9 ? axis_mask<D2Q9>() : axis_mask<D3Q19>();
+        const double j0 = p.j0 < 0 ? (p.dim == 2 ? 1.0 / 3.0 : 0.25) : p.j0;
+        const double w_ax = p.fluid_q == 9 ? D2Q9::w[2] : D3Q19::w[1];
+        d.cs2s = (1.0 - j0) / p.dim;
+        d.wsc = 0.5 * d.cs2s / w_ax;
+        d.ws[0] = j0;
+        for (int i = 1; i < p.fluid_q; i++) d.ws[i] = (m >> i) & 1u ? w[i] * d.wsc : 0.0;
+    } else if (p.j0 < 0) {
         for (int i = 0; i < p.fluid_q; i++) d.ws[i] = w[i];
         d.wsc = 1.0;
         d.cs2s = 1.0 / 3.0;
@@ -228,6 +245,8 @@ static DomDev dom_record(const DomHost &h, bool fp64) {
     // TRT: the second rate of each lattice from the magic parameter 3/16,
     // (tau+ - 1/2)(tau- - 1/2) = 3/16; BGK: both rates equal
     D.trt = p.collision == LBM_TRT;
+    D.smask = p.solute_q == p.fluid_q ? (1u << p.fluid_q) - 1u
+                                      : (p.fluid_q == 9 ? axis_mask<D2Q9>() : axis_mask<D3Q19>());
     const double tfm = 0.5 + (3.0 / 16.0) / (p.tau_ns - 0.5), tgm = 0.5 + (3.0 / 16.0) / (p.tau_ad - 0.5);
     D.omega_fm = D.trt ? 1.0 / tfm : D.omega_f;
     D.force_fac_m = 1.0 - 0.5 * D.omega_fm;
@@ -253,9 +272,9 @@ static std::string check_batch(const lbm_params *p, int n) {
     for (int d = 0; d < n; d++) {
         std::string m = check_params(p[d]);
         if (!m.empty()) return (n > 1 ? "domain " + std::to_string(d) + ": " : std::string()) + m;
-        if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].precision != p[0].precision ||
-            p[d].collision != p[0].collision)
-            return "all domains of a batch need the same dim, lattice, precision and collision";
+        if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].solute_q != p[0].solute_q ||
+            p[d].precision != p[0].precision || p[d].collision != p[0].collision)
+            return "all domains of a batch need the same dim, lattices, precision and collision";
         if (p[d].phase_change != 0 && n > 1) return "phase_change is not supported in a batch";
         if (p[d].phase_change != 0 && p[d].phase_change != 1) return "phase_change must be 0 or 1";
     }
@@ -829,6 +848,10 @@ static lbm_status adj_check(Ctx *c, int32_t nsteps, int32_t ckpt) {
         c->err = "the adjoint transposes the BGK step (collision = LBM_BGK)";
         return LBM_EINVAL;
     }
+    if (c->red) {
+        c->err = "the adjoint transposes the step with the solute on the fluid's velocity set";
+        return LBM_EINVAL;
+    }
     return LBM_OK;
 }
 
@@ -979,20 +1002,20 @@ lbm_status lbm_get_diag(lbm_ctx *ctx, lbm_diag *out) {
     return LBM_OK;
 }
 
-// state layout: header (64 B) | f | g (Q*N of T each) | phi | kr (N doubles) |
-// nrm (3N doubles) | solid (N bytes)
+// state layout: header (64 B) | f (Q*N of T) | g (QS*N of T) | phi | kr (N
+// doubles) | nrm (3N doubles) | solid (N bytes)
 struct StateHeader {
     uint64_t magic;
     int64_t N, Q, precision, step, n_events;
     double wall_ex;
-    int64_t pad;
+    int64_t QS;
 };
 
 lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes) {
     const Ctx *c = (const Ctx *)ctx;
     if (!c || !bytes) return LBM_EINVAL;
     const size_t ts = c->fp64 ? 8 : 4;
-    *bytes = sizeof(StateHeader) + 2 * ts * c->Q * c->N + 8 * 5 * c->N + c->N;
+    *bytes = sizeof(StateHeader) + ts * (c->Q + c->QS) * c->N + 8 * 5 * c->N + c->N;
     return LBM_OK;
 }
 
@@ -1015,7 +1038,8 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes) {
     StateHeader h;
     memset(&h, 0, sizeof h);
     h.magic = 0x4c424d5242433031ULL;
-    h.N = c->N; h.Q = c->Q; h.precision = c->p.precision; h.step = c->step; h.n_events = c->n_events;
+    h.N = c->N; h.Q = c->Q; h.QS = c->QS; h.precision = c->p.precision; h.step = c->step;
+    h.n_events = c->n_events;
     double wex = 0;
     hipError_t e = launch_fold_exchange(*c);
     if (e == hipSuccess) e = launch_phi_flush(*c);
@@ -1028,7 +1052,7 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes) {
     size_t off = sizeof h;
     for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
         e = hipMemcpyAsync(b + off, (char *)c->f[c->cur] + i * ts * c->S, pb, hipMemcpyDeviceToDevice, c->stream);
-    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
+    for (int i = 0; i < c->QS && e == hipSuccess; i++, off += pb)
         e = hipMemcpyAsync(b + off, (char *)c->g[c->cur] + i * ts * c->S, pb, hipMemcpyDeviceToDevice, c->stream);
     if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->phi, 8 * c->N, hipMemcpyDeviceToDevice, c->stream);
     off += 8 * c->N;
@@ -1057,14 +1081,14 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
     hipError_t e = hipMemcpyAsync(&h, b, sizeof h, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_err(c, e, "load_state");
-    if (h.magic != 0x4c424d5242433031ULL || h.N != c->N || h.Q != c->Q ||
+    if (h.magic != 0x4c424d5242433031ULL || h.N != c->N || h.Q != c->Q || h.QS != c->QS ||
         h.precision != c->p.precision) {
         c->err = "state buffer does not match this context";
         return LBM_EINVAL;
     }
     const size_t ts = c->fp64 ? 8 : 4;
     const size_t pb = ts * c->N;
-    const size_t pops = sizeof h, phio = pops + 2 * c->Q * pb;
+    const size_t pops = sizeof h, phio = pops + (c->Q + c->QS) * pb;
     // geometry first (rebuilds links from solid, normals and k_r), then state
     const double *phi_src = (const double *)(b + phio);
     const double *kr_src = (const double *)(b + phio + 8 * c->N);
@@ -1087,7 +1111,7 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
     size_t off = pops;
     for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
         e = hipMemcpyAsync((char *)c->f[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
-    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
+    for (int i = 0; i < c->QS && e == hipSuccess; i++, off += pb)
         e = hipMemcpyAsync((char *)c->g[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
     double wex = h.wall_ex;
     if (e == hipSuccess) e = hipMemcpyAsync(c->dacc, &wex, sizeof(double), hipMemcpyHostToDevice, c->stream);

@@ -59,6 +59,30 @@ __host__ __device__ constexpr uint32_t dir_mask(int a, int s) {
     return m;
 }
 
+// Solute velocity sets.  The solute runs on the fluid's own set, or on the
+// paper's reduced D2Q5 / D3Q7 (appendix, velocity sets): the rest vector and
+// the unit vectors along the axes, a subset of D2Q9 / D3Q19.  A set is a bit
+// mask over the fluid directions.  Solute populations are stored for the
+// set's directions only: slot s holds the s-th direction of the mask (for
+// D2Q5 the paper's order, for D3Q7 rest, +x, +y, +z, -x, -y, -z).
+template <class L>
+__host__ __device__ constexpr uint32_t axis_mask() {
+    uint32_t m = 0u;
+    for (int i = 0; i < L::Q; i++)
+        if (L::ex[i] * L::ex[i] + L::ey[i] * L::ey[i] + L::ez[i] * L::ez[i] <= 1) m |= 1u << i;
+    return m;
+}
+
+template <class L, bool RED>
+__host__ __device__ constexpr uint32_t sol_mask() {
+    return RED ? axis_mask<L>() : (1u << L::Q) - 1u;
+}
+
+// storage slot of fluid direction i in the solute set m
+__host__ __device__ constexpr int sol_slot(uint32_t m, int i) {
+    return __builtin_popcount(m & ((1u << i) - 1u));
+}
+
 // Node flags of the geometry pass (dense, uint32 per node; not read per step)
 //   bits 0..Q-1 : fluid view, upstream site x - e_i is solid or outside a
 //                 non-periodic face
@@ -104,10 +128,12 @@ struct DomDev {
     // scaled by force_fac_m; solute even parts relax with omega_gs (odd ones
     // with omega_g).  BGK: omega_fm = omega_f, omega_gs = omega_g
     int trt;
+    uint32_t smask;            // solute velocity set (bit i: fluid direction i)
     double omega_fm, force_fac_m, omega_gs;
     double F[3];
-    double ws[19];             // solute weights (rest fraction)
-    double wsc;                // ws[i] = w[i] * wsc for every moving direction
+    double ws[19];             // solute weights by fluid direction (rest fraction;
+                               // 0 outside the solute set)
+    double wsc;                // ws[i] = w[i] * wsc for every moving direction of the set
     double inv_cs2s, cs2s, gamma;
     double rho0, c_ref;        // deviation references (0 in FP64 storage)
     double ceq_dev;            // C_eq - C_ref

@@ -73,14 +73,17 @@ __global__ __launch_bounds__(BLK) void k_copy_i32(const int32_t *src, int32_t *d
 }
 
 // C and rho of the fluid node at compact index ko of the state before this
-// pass (FP64 sums in direction order)
-template <class L, typename T>
+// pass (FP64 sums in direction order; the solute set is a compile-time mask,
+// so all loads issue together)
+template <class L, typename T, bool RED>
 __device__ __forceinline__ void pop_moments(const DomDev &D, int ko, const T *f, const T *g, long S,
                                             double *C, double *rho) {
+    constexpr uint32_t SM = sol_mask<L, RED>();
     double c = 0.0, r = 0.0;
+#pragma unroll
     for (int i = 0; i < L::Q; i++) {
         r += (double)f[(long)i * S + ko] + L::w[i] * D.rho0;
-        c += (double)g[(long)i * S + ko] + sol_w<L>(D, i) * D.c_ref;
+        if ((SM >> i) & 1u) c += (double)g[(long)sol_slot(SM, i) * S + ko] + sol_w<L>(D, i) * D.c_ref;
     }
     *C = c;
     *rho = r;
@@ -93,7 +96,7 @@ __device__ __forceinline__ void rec_moments(const DomDev &D, const EvRec &e, dou
     double c = 0.0, r = 0.0;
     for (int i = 0; i < L::Q; i++) {
         r += L::w[i] * e.rho;
-        c += sol_w<L>(D, i) * e.C;
+        c += D.ws[i] * e.C;   // 0 outside the solute set
     }
     *C = c;
     *rho = r;
@@ -140,7 +143,7 @@ __device__ __forceinline__ int32_t heap_pop(int32_t *h, int &n) {
 // pass recomputes); the next node is the smaller of the list head and the
 // heap top.  out[0] = events, out[1] = 1 if the records or the heap
 // overflowed (the pass stops there).
-template <class L, typename T>
+template <class L, typename T, bool RED>
 __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t *list, long nlist,
                                                uint8_t *solid, double *phi, const double *kr,
                                                const int32_t *kof, int32_t *kof_old, const T *f,
@@ -195,7 +198,7 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                 // of a node that became fluid in it
                 const int ko = kof_old[y];
                 if (ko <= -2) rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
-                else if (ko >= 0) pop_moments<L, T>(D, ko, f, g, S, &Cy, &Ry);
+                else if (ko >= 0) pop_moments<L, T, RED>(D, ko, f, g, S, &Cy, &Ry);
             }
         }
         // lane 0: the node's own state, read alongside its neighbours'
@@ -207,7 +210,7 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
             krn = kr[n];
             if (!sol_n && phn >= 1.0) {
                 const int ko = kof_old[n];
-                if (ko >= 0) pop_moments<L, T>(D, ko, f, g, S, &Cx, &Rx);
+                if (ko >= 0) pop_moments<L, T, RED>(D, ko, f, g, S, &Cx, &Rx);
                 else rec_moments<L>(D, rec[-2 - ko], &Cx, &Rx);
             }
         }
@@ -366,15 +369,14 @@ __global__ __launch_bounds__(BLK) void k_relayout(const DomDev *doms, long nf, c
     const long n = nodeof[k];
     const int ko = kof_old[n];
     if (ko >= 0) {
-        for (int i = 0; i < L::Q; i++) {
-            fn[(long)i * S + k] = fo[(long)i * S + ko];
-            gn[(long)i * S + k] = go[(long)i * S + ko];
-        }
+        for (int i = 0; i < L::Q; i++) fn[(long)i * S + k] = fo[(long)i * S + ko];
+        for (int s = 0; s < __builtin_popcount(D.smask); s++) gn[(long)s * S + k] = go[(long)s * S + ko];
     } else {
         const EvRec &e = rec[-2 - ko];
         for (int i = 0; i < L::Q; i++) {
             fn[(long)i * S + k] = (T)(L::w[i] * e.rho - L::w[i] * D.rho0);
-            gn[(long)i * S + k] = (T)(sol_w<L>(D, i) * e.C - sol_w<L>(D, i) * D.c_ref);
+            if ((D.smask >> i) & 1u)
+                gn[(long)sol_slot(D.smask, i) * S + k] = (T)(D.ws[i] * e.C - D.ws[i] * D.c_ref);
         }
     }
 }
@@ -437,9 +439,14 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     const long nlist = h[0] < c.ev_cap ? h[0] : c.ev_cap;
     if (h[0] > c.ev_cap) *overflow = true;
-    hipLaunchKernelGGL((k_events<L, T>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
-                       c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
-                       c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, c.evheap, cnt2);
+    if (c.red)
+        hipLaunchKernelGGL((k_events<L, T, true>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
+                           c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
+                           c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, c.evheap, cnt2);
+    else
+        hipLaunchKernelGGL((k_events<L, T, false>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
+                           c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
+                           c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, c.evheap, cnt2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(h, cnt2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;

@@ -127,8 +127,9 @@ __global__ __launch_bounds__(BLK) void k_flags(Geo g, long N, const uint8_t *sol
         int fc;
         const long y = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], false, &fc);
         if (y < 0 || solid[base + y]) fl |= 1u << i;
+        // a reactive link needs a direction of the solute set
         const long ys = site(box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
-        if (ys >= 0 && solid[base + ys]) rm |= 1u << i;
+        if (ys >= 0 && solid[base + ys] && ((g.doms[d].smask >> i) & 1u)) rm |= 1u << i;
     }
     if (rm) fl |= F_LINK;
     flags[n] = fl;

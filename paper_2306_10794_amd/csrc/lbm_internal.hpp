@@ -57,6 +57,9 @@ struct Ctx {
     lbm_launch_config cfg;   // tile / schedule of the step launches
     hipStream_t stream;
     int Q, dim;
+    int QS;                  // solute directions (Q, or 5 / 7 on D2Q5 / D3Q7)
+    bool red;                // the solute runs on the reduced set (QS < Q)
+    uint32_t smask;          // solute set as a mask over the fluid directions
     int ndom;
     std::vector<DomHost> dom;
     long N;                  // nodes of all domains
@@ -67,7 +70,7 @@ struct Ctx {
     bool fp64;
     int64_t max_links;
     // device arrays carved from the caller workspace
-    void *f[2], *g[2];       // populations, [Q][S] each (T = double or float), compact
+    void *f[2], *g[2];       // populations, f [Q][S], g [QS][S] (T = double or float), compact
     DomDev *doms;            // [ndom]
     long *dnode_off;         // [ndom + 1] dense node offsets
     long *dword_off;         // [ndom + 1] row-word offsets

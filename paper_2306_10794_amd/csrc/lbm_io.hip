@@ -22,11 +22,13 @@ __global__ __launch_bounds__(BLK) void k_init(long N, long S, const DomDev *doms
     for (int i = 0; i < L::Q; i++) {
         const double eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
         const double feq = L::w[i] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        const double geq = D.ws[i] * C * (1.0 + eu / D.cs2s);
         f0[i * S + k] = T(feq - L::w[i] * D.rho0);
-        g0[i * S + k] = T(geq - D.ws[i] * D.c_ref);
         f1[i * S + k] = T(0);
-        g1[i * S + k] = T(0);
+        if (!((D.smask >> i) & 1u)) continue;
+        const long s = sol_slot(D.smask, i);
+        const double geq = D.ws[i] * C * (1.0 + eu / D.cs2s);
+        g0[s * S + k] = T(geq - D.ws[i] * D.c_ref);
+        g1[s * S + k] = T(0);
     }
 }
 
@@ -49,7 +51,7 @@ __global__ __launch_bounds__(BLK) void k_fields(long N, long S, const DomDev *do
             jx += L::ex[i] * fi;
             jy += L::ey[i] * fi;
             jz += L::ez[i] * fi;
-            dc += (double)g[i * S + k];
+            if ((D.smask >> i) & 1u) dc += (double)g[sol_slot(D.smask, i) * S + k];
         }
         r = D.rho0 + dr;
         C = D.c_ref + dc;
@@ -75,7 +77,9 @@ __global__ __launch_bounds__(BLK) void k_pops(long N, long S, const DomDev *doms
     const DomDev &D = doms[find_dom(noff, ndom, n)];
     for (int i = 0; i < L::Q; i++) {
         if (fo) fo[i * N + n] = k < 0 ? 0.0 : (double)f[i * S + k] + L::w[i] * D.rho0;
-        if (go) go[i * N + n] = k < 0 ? 0.0 : (double)g[i * S + k] + D.ws[i] * D.c_ref;
+        if (!go || !((D.smask >> i) & 1u)) continue;
+        const long s = sol_slot(D.smask, i);
+        go[s * N + n] = k < 0 ? 0.0 : (double)g[s * S + k] + D.ws[i] * D.c_ref;
     }
 }
 
@@ -109,8 +113,11 @@ __global__ __launch_bounds__(BLK) void k_diag(long N, long S, const DomDev *doms
             const DomDev &D = doms[find_dom(noff, ndom, n)];
             double dc = 0.0;
             for (int i = 0; i < L::Q; i++) {
-                const double fi = (double)f[i * S + k], gi = (double)g[i * S + k];
-                if (!isfinite(fi) || !isfinite(gi)) bad = 1;
+                const double fi = (double)f[i * S + k];
+                if (!isfinite(fi)) bad = 1;
+                if (!((D.smask >> i) & 1u)) continue;
+                const double gi = (double)g[sol_slot(D.smask, i) * S + k];
+                if (!isfinite(gi)) bad = 1;
                 dc += gi;
             }
             cs = D.c_ref + dc;

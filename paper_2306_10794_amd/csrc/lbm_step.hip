@@ -6,7 +6,9 @@
 //                moments, Guo-forced BGK.  Solute: pull-stream, inlet/outlet
 //                planes, the general reactive boundary condition on every link
 //                that enters from a solid node, advection-diffusion BGK with
-//                the rest-fraction weights; writes the exchange q of each
+//                the rest-fraction weights (on the fluid's velocity set, or on
+//                D2Q5 / D3Q7 when RED: the solute loops then visit the set's
+//                directions only, at compile time); writes the exchange q of each
 //                reactive link and credits precipitation (q < 0) to the fluid
 //                node's phi.  The task's links are one range (by direction,
 //                then lane): their betas are fetched into LDS in one pass
@@ -34,11 +36,14 @@ namespace lbm {
 // tiles on one XCD.  FP32 storage asks for 4 waves per SIMD (at most 128
 // VGPRs, a few spilled): the extra wave hides more memory latency than the
 // spills cost (256^3 sphere packing: 732 -> 660 us).
-template <class L, typename T, int WV, bool TRT>
+template <class L, typename T, int WV, bool TRT, bool RED>
 __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepArgs<T> a, long nblocks,
                                                                          int remap) {
     using R = double;
     constexpr int Q = L::Q;
+    // the solute set, and the storage slot of each of its directions
+    constexpr uint32_t SM = sol_mask<L, RED>();
+    constexpr int QS = __builtin_popcount(SM);
     const long tile = remap ? xcd_tile(blockIdx.x, nblocks) : (long)blockIdx.x;
     const int t = __builtin_amdgcn_readfirstlane((int)(tile * WV) + (int)(threadIdx.x >> 6));
     if (t >= a.ntasks) return;
@@ -156,7 +161,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         }
         if (kk[i] == -1) solidnb |= 1u << i;
     }
-    const uint32_t rbc = active ? (solidnb & ~cross) : 0u;
+    const uint32_t rbc = active ? (solidnb & ~cross & SM) : 0u;
 
     // ---- the task's reactive links: one range from lbase of its first node,
     // ordered by direction, then by lane (a link's index is the task's base,
@@ -166,13 +171,14 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // link's exchange later replaces its coefficient there, and the whole
     // range is stored at once at the end ----
     constexpr int NW = (int)(sizeof(T) / 4);
-    __shared__ uint32_t slink[WV][NW][64 * (Q - 1)];
+    __shared__ uint32_t slink[WV][NW][64 * (QS - 1)];
     const int wv = threadIdx.x >> 6;
     const int lt = __builtin_amdgcn_readfirstlane(lb);
     const unsigned long long below = (1ull << lane) - 1ull;
     int nlt = 0;
 #pragma unroll
-    for (int i = 1; i < Q; i++) nlt += __popcll(__ballot((rbc >> i) & 1u));
+    for (int i = 1; i < Q; i++)
+        if ((SM >> i) & 1u) nlt += __popcll(__ballot((rbc >> i) & 1u));
     for (int c = 0; c < nlt; c += 64) {
         if (c + lane < nlt) {
             const uint32_t *p = (const uint32_t *)(a.lbeta + lt + c + lane);
@@ -188,7 +194,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // hides behind the population loads (updated at the end)
     const double phi_in = rbc ? a.phif[k] : 0.0;
 
-    // ---- loads: Q fluid + Q solute values per node ----
+    // ---- loads: Q fluid + QS solute values per node ----
     T fv[Q], gv[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
@@ -197,6 +203,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
+        if (!((SM >> i) & 1u)) continue;
         int e = kk[i];
         if (cross & (1u << i)) {
             if (cross_hi & (1u << i)) {
@@ -209,7 +216,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             }
         }
         // fluid neighbour: pull; solid or box face: own value along opp(i)
-        gv[i] = e >= 0 ? a.gin[(long)i * S + e] : a.gin[(long)L::opp[i] * S + k];
+        gv[i] = e >= 0 ? a.gin[(long)sol_slot(SM, i) * S + e] : a.gin[(long)sol_slot(SM, L::opp[i]) * S + k];
     }
 
     // ---- fluid: moments and Guo-forced BGK ----
@@ -265,7 +272,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     if (cross & ~cross_hi) {
 #pragma unroll
         for (int i = 0; i < Q; i++) {
-            if ((cross & ~cross_hi) & (1u << i)) {
+            if ((SM >> i) & 1u && ((cross & ~cross_hi) & (1u << i))) {
                 const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
                 gv[i] = (T)(sol_w<L>(D, i) * (D.c_in - D.c_ref) + sol_w<L>(D, i) * D.c_in * eu * D.inv_cs2s);
             }
@@ -284,6 +291,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         int off = 0;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
+            if (!((SM >> i) & 1u)) continue;
             const unsigned long long bal = __ballot((rbc >> i) & 1u);
             const int pos = off + __popcll(bal & below);   // position in the task's range
             off += __popcll(bal);
@@ -326,7 +334,8 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     }
     R dC = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; i++) dC += (R)gv[i];
+    for (int i = 0; i < Q; i++)
+        if ((SM >> i) & 1u) dC += (R)gv[i];
     const R C = D.c_ref + dC;
     // g* = g + omg (g_eq - g), g_eq = ws (dC + C e.u / c_s^2): in pairs as
     // above, (1 - omg) g + As +- Bs with As = omg ws dC, Bs = omg ws C e.u / c_s^2
@@ -335,8 +344,9 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     a.gout[k] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
-        if (L::opp[i] < i) continue;
+        if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
         const int o = L::opp[i];
+        const long si = (long)sol_slot(SM, i) * S + k, so = (long)sol_slot(SM, o) * S + k;
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
         const R ws = sol_w<L>(D, i);
         const R Bs = ws * Cu * eu;
@@ -344,12 +354,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             const R As = oms * ws * dC;
             const R gi = (R)gv[i], go = (R)gv[o];
             const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * omg * (gi - go);
-            a.gout[(long)i * S + k] = (T)(gi - hs - ha + (As + Bs));
-            a.gout[(long)o * S + k] = (T)(go - hs + ha + (As - Bs));
+            a.gout[si] = (T)(gi - hs - ha + (As + Bs));
+            a.gout[so] = (T)(go - hs + ha + (As - Bs));
         } else {
             const R As = omg * ws * dC;
-            a.gout[(long)i * S + k] = (T)(omg1 * (R)gv[i] + (As + Bs));
-            a.gout[(long)o * S + k] = (T)(omg1 * (R)gv[o] + (As - Bs));
+            a.gout[si] = (T)(omg1 * (R)gv[i] + (As + Bs));
+            a.gout[so] = (T)(omg1 * (R)gv[o] + (As - Bs));
         }
     }
 }
@@ -357,17 +367,17 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
 // dissolution side of the solid fraction, per solid interface node, links in
 // ascending direction order; also the step's total exchange, added to this
 // workgroup's own slot xpart[blockIdx.x] (no atomics: the slots are folded
-// into the running total when it is read).  A solid node has at most Q - 1
-// links: all their indices, then all their exchanges, are loaded before the
-// ordered sum.
-template <class L, typename T>
+// into the running total when it is read).  A solid node has at most QS - 1
+// links (one per moving direction of the solute set): all their indices,
+// then all their exchanges, are loaded before the ordered sum.
+template <class L, typename T, bool RED>
 __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ soff,
                                                    const int32_t *__restrict__ slinks,
                                                    const int32_t *__restrict__ sdom,
                                                    const DomDev *__restrict__ doms,
                                                    const T *__restrict__ lq, double *__restrict__ phis,
                                                    long nsif, double *__restrict__ xpart, int ndom) {
-    constexpr int M = L::Q - 1;
+    constexpr int M = __builtin_popcount(sol_mask<L, RED>()) - 1;
     const long j = (long)blockIdx.x * BLK + threadIdx.x;
     double tot = 0.0;
     if (j < nsif) {
@@ -412,6 +422,16 @@ static StepArgs<T> step_args(Ctx &c) {
     return a;
 }
 
+template <class L, typename T, bool TRT, bool RED>
+static void launch_k_step(int wv, long nb, hipStream_t st, const StepArgs<T> &args, int rm) {
+    switch (wv) {
+    case 1: hipLaunchKernelGGL((k_step<L, T, 1, TRT, RED>), dim3(nb), dim3(64), 0, st, args, nb, rm); break;
+    case 2: hipLaunchKernelGGL((k_step<L, T, 2, TRT, RED>), dim3(nb), dim3(128), 0, st, args, nb, rm); break;
+    case 8: hipLaunchKernelGGL((k_step<L, T, 8, TRT, RED>), dim3(nb), dim3(512), 0, st, args, nb, rm); break;
+    default: hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED>), dim3(nb), dim3(256), 0, st, args, nb, rm); break;
+    }
+}
+
 // One step.  The exchanges alternate between two buffers, so that with
 // `overlap` the solid-side kernel of this step runs on the side stream while
 // the next step's fused kernel (which writes the other buffer) runs on the
@@ -434,23 +454,14 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
         const int wv = c.cfg.wg_waves;
         const long nb = (c.n_tasks + wv - 1) / wv;
         const int rm = c.cfg.xcd_remap;
-        // TRT is a separate instantiation: its extra terms would cost the
-        // BGK kernel registers (every domain of a context shares the choice)
-        if (c.p.collision == LBM_TRT) {
-            switch (wv) {
-            case 1: hipLaunchKernelGGL((k_step<L, T, 1, true>), dim3(nb), dim3(64), 0, c.stream, args, nb, rm); break;
-            case 2: hipLaunchKernelGGL((k_step<L, T, 2, true>), dim3(nb), dim3(128), 0, c.stream, args, nb, rm); break;
-            case 8: hipLaunchKernelGGL((k_step<L, T, 8, true>), dim3(nb), dim3(512), 0, c.stream, args, nb, rm); break;
-            default: hipLaunchKernelGGL((k_step<L, T, 4, true>), dim3(nb), dim3(256), 0, c.stream, args, nb, rm); break;
-            }
-        } else {
-            switch (wv) {
-            case 1: hipLaunchKernelGGL((k_step<L, T, 1, false>), dim3(nb), dim3(64), 0, c.stream, args, nb, rm); break;
-            case 2: hipLaunchKernelGGL((k_step<L, T, 2, false>), dim3(nb), dim3(128), 0, c.stream, args, nb, rm); break;
-            case 8: hipLaunchKernelGGL((k_step<L, T, 8, false>), dim3(nb), dim3(512), 0, c.stream, args, nb, rm); break;
-            default: hipLaunchKernelGGL((k_step<L, T, 4, false>), dim3(nb), dim3(256), 0, c.stream, args, nb, rm); break;
-            }
-        }
+        // TRT and the reduced solute set are separate instantiations: TRT's
+        // extra terms would cost the BGK kernel registers (every domain of a
+        // context shares both choices)
+        const bool trt = c.p.collision == LBM_TRT;
+        if (trt && c.red) launch_k_step<L, T, true, true>(wv, nb, c.stream, args, rm);
+        else if (trt) launch_k_step<L, T, true, false>(wv, nb, c.stream, args, rm);
+        else if (c.red) launch_k_step<L, T, false, true>(wv, nb, c.stream, args, rm);
+        else launch_k_step<L, T, false, false>(wv, nb, c.stream, args, rm);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[1], c.stream);
@@ -464,8 +475,12 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
     if (ev) (void)hipEventRecord(ev[2], ps);
     if (c.n_sif > 0) {
         const long nb2 = (c.n_sif + BLK - 1) / BLK;
-        hipLaunchKernelGGL((k_phi_solid<L, T>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
-                           c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom);
+        if (c.red)
+            hipLaunchKernelGGL((k_phi_solid<L, T, true>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
+                               c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom);
+        else
+            hipLaunchKernelGGL((k_phi_solid<L, T, false>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
+                               c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[3], ps);

@@ -17,7 +17,8 @@ def params_from_case(case, precision: int = L.LBM_FP32_DEV, max_links: int = 0) 
     """lbm_params of an ``lbm_inputs.Case`` (plain field copy)."""
     p = L.lbm_params()
     p.dim, p.nx, p.ny, p.nz = case.dim, case.nx, case.ny, case.nz
-    p.fluid_q = p.solute_q = case.q
+    p.fluid_q = case.q
+    p.solute_q = getattr(case, "qs", 0) or case.q
     p.precision = precision
     p.rbc_mechanics, p.rbc_scheme = case.mechanics, case.scheme
     p.tau_ns, p.tau_ad, p.j0 = case.tau_ns, case.tau_ad, case.j0
@@ -55,6 +56,7 @@ class Simulation:
         self.workspace = torch.empty(self.nbytes, dtype=torch.uint8, device=self.device)
         self.ctx = L.lbm_create(self.params, self.workspace, self.nbytes, self.stream)
         self.N, self.Q = case.n, case.q
+        self.QS = self.params.solute_q
         self._geom = dict(
             solid=_dev(case.solid_flat(), torch.uint8, self.device),
             normals=_dev(case.normals_flat(), torch.float64, self.device),
@@ -83,7 +85,7 @@ class Simulation:
 
     def pops(self):
         f = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
-        g = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
+        g = torch.empty((self.QS, self.N), dtype=torch.float64, device=self.device)
         L.lbm_get_pops(self.ctx, f, g)
         return f, g
 
@@ -181,6 +183,7 @@ class BatchSimulation:
         self.ctx = L.lbm_create_batch(self.params, self.workspace, self.nbytes, self.stream)
         self.offsets = L.lbm_batch_offsets(self.ctx, len(self.cases))
         self.N, self.Q = self.offsets[-1], self.cases[0].q
+        self.QS = getattr(self.cases[0], "qs", 0) or self.Q
 
         def cat(get, dtype, width=None):
             parts = [get(c) for c in self.cases]
@@ -224,7 +227,7 @@ class BatchSimulation:
 
     def pops(self):
         f = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
-        g = torch.empty((self.Q, self.N), dtype=torch.float64, device=self.device)
+        g = torch.empty((self.QS, self.N), dtype=torch.float64, device=self.device)
         L.lbm_get_pops(self.ctx, f, g)
         return f, g
 

@@ -61,11 +61,22 @@ def test_workspace_bytes_scales_with_lattice():
     assert a >= 4 * 9 * 64 * 32 * 8
 
 
+def test_reduced_solute_set_shrinks_the_workspace():
+    """D2Q5 solute storage: two buffers of 5 instead of 9 directions."""
+    L = _L()
+    full = L.lbm_workspace_bytes(_good_params())
+    red = L.lbm_workspace_bytes(_good_params(solute_q=5))
+    S = (64 * 32 + 63) // 64 * 64
+    S += 64 if (S // 64) % 2 == 0 else 0
+    assert full - red >= 2 * 4 * S * 8 - 2 * 256
+
+
 @pytest.mark.parametrize("kw,frag", [
     (dict(dim=4), "dim"),
     (dict(nz=2), "nz = 1"),
     (dict(fluid_q=19), "fluid_q"),
-    (dict(solute_q=5), "solute_q"),
+    (dict(solute_q=7), "solute_q"),
+    (dict(solute_q=19), "solute_q"),
     (dict(precision=7), "precision"),
     (dict(rbc_mechanics=3), "rbc_mechanics"),
     (dict(rbc_scheme=9), "rbc_scheme"),
