@@ -79,7 +79,8 @@ typedef enum {
 #define LBM_SNEW 0       /* c_s^-2 gamma k_r (e.n)   -- the paper's new scheme  */
 #define LBM_SV 1         /* c_s^-2 k_r (e.n)         -- Verhaeghe              */
 #define LBM_SPJ 2        /* c_s^-2 gamma k_r / (e.n) -- Patel / Ju             */
-#define LBM_ABB 3        /* k_i = infinity: anti-bounce-back with C_eq         */
+#define LBM_ABB 3        /* k_i = infinity: anti-bounce-back with C_eq at solid
+                            nodes with k_r > 0 (k_r = 0: bounce-back)          */
 
 typedef struct {
     int32_t dim;              /* 2 or 3                                            */

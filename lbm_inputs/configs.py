@@ -65,6 +65,40 @@ def robin_1d(ny_fluid=24, nx=3, tau_ad=0.8, k_r=2e-2, c_eq=1.0, c_in=0.25,
 
 
 # --------------------------------------------------------------------------
+# the paper's 2D reaction-diffusion verification, configuration A
+# --------------------------------------------------------------------------
+def reaction_diffusion_2d(peda=1.0, scheme=SCHEME_SNEW, a=100, b=80, pe=1.0, U=1e-3, c0=1.0,
+                          c_eq=0.0, j0=-1.0, qs=5, collision=0, mechanics=MECH_PRE,
+                          c_init=None) -> Case:
+    """Configuration A of the paper's analytic reaction-diffusion case (its
+    default parameter table): pure diffusion in an a x b box aligned with the
+    grid; fixed concentration C0 on the left (the solute inlet plane at x = 0),
+    zero gradient on the right (the outlet plane at x = a - 1) and at the
+    bottom (a solid row with k_r = 0, i.e. bounce-back), the first-order
+    reaction with C_eq on the top (a solid row with k_r).  D = U b / Pe, the
+    solute on D2Q5 by default; tau_AD from D and c_s^2 = (1 - J0)/2 (J0 = 1/3
+    when j0 < 0), k_r = PeDa D / b.  Fluid rows y = 1..b; solid rows 0 and
+    b + 1."""
+    D = U * b / pe
+    if qs == 5:
+        cs2 = (1.0 - (1.0 / 3.0 if j0 < 0 else j0)) / 2.0
+    else:   # the solute on D2Q9
+        cs2 = 1.0 / 3.0 if j0 < 0 else 3.0 * (1.0 - j0) / 5.0
+    tau_ad = 0.5 + D / cs2
+    k_r = peda * D / b
+    ny = b + 2
+    solid, normals = geometry.plane_channel(a, ny, (0, ny - 1))
+    kr = np.zeros((1, ny, a))
+    kr[0, ny - 1, :] = k_r
+    return Case(name=f"rd2d_A_peda{peda:g}_s{scheme}", dim=2, nx=a, ny=ny, nz=1, q=9,
+                qs=qs if qs != 9 else 0, solid=solid, normals=normals, tau_ns=1.0, tau_ad=tau_ad,
+                j0=j0, c_eq=c_eq, k_r=0.0, k_r_field=kr.reshape(-1), v_m=0.0,
+                periodic=(1, 0, 1), inlet_axis=0, c_in=c0, c0=c0, c_init=c_init,
+                mechanics=mechanics, scheme=scheme, collision=collision,
+                info=dict(D=D, k_r=k_r, cs2=cs2, a=a, b=b, peda=peda))
+
+
+# --------------------------------------------------------------------------
 # workload 1: 512 x 512 tilted channel, Poiseuille flow + solute, Pe x Da sweep
 # --------------------------------------------------------------------------
 def channel_flow_params(pe: float, da: float, L: float, tau_ns: float, q: int = 9,

@@ -29,7 +29,8 @@
  *     eqs. k_i_S_Ve, k_i_S2, k_i_S_New; gamma of eq. gammaAppendix):
  *        g_out = k/(1+k) 2 w C_eq + (1-k)/(1+k) g_src
  *     with the anti-bounce-back limit for k -> infinity and plain bounce-back
- *     for k = 0 (Sec. 2.3, limits).
+ *     for k = 0 (Sec. 2.3, limits); the anti-bounce-back scheme applies at
+ *     solid nodes with k_r > 0 (a non-reactive wall stays bounce-back).
  *   - solid fraction (Sec. 2.4, eq. solidFractionUpdate) fed by the mass
  *     actually exchanged over each reactive link; dissolution is charged to
  *     the solid node, precipitation credited to the fluid node.
@@ -318,7 +319,10 @@ static double link_k(const orc *o, long s, int i)
     switch (o->p.scheme) {
     case ORC_SV:   return en > 0 ? kr * en / o->cs2s : 0.0;
     case ORC_SPJ:  return en > 0 ? o->gamma * kr / (o->cs2s * en) : 0.0;
-    case ORC_ABB:  return INFINITY;
+    /* anti-bounce-back is the limit k -> infinity of the rate condition (Sec.
+     * 3.1, extended PeDa range); a solid node without reaction (k_r = 0)
+     * keeps plain bounce-back */
+    case ORC_ABB:  return kr > 0 ? INFINITY : 0.0;
     default:       return en > 0 ? o->gamma * kr * en / o->cs2s : 0.0;
     }
 }

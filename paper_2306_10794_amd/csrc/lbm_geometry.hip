@@ -419,7 +419,9 @@ __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *no
         // pre-collision source with both neighbours solid: fall back to the
         // node's own post-collision population, whose effective rate is gamma k
         if (D.mech == LBM_PRECOLL && (rm & (1u << L::opp[i]))) kap = kap / D.gamma;
-        const double beta = D.scheme == LBM_ABB ? -1.0 : (1.0 - kap) / (1.0 + kap);
+        // anti-bounce-back (the k -> infinity limit) at reactive solid nodes;
+        // a solid node with k_r = 0 keeps plain bounce-back (kap = 0)
+        const double beta = (D.scheme == LBM_ABB && kv > 0.0) ? -1.0 : (1.0 - kap) / (1.0 + kap);
         const int l = lmap[base + r];
         lbeta[l] = (T)beta;
         lnode[l] = (int32_t)n;

@@ -15,7 +15,7 @@ from lbm_inputs import (Case, configs, geometry, MECH_PRE, MECH_POST, SCHEME_SNE
                         SCHEME_SPJ, SCHEME_ABB)
 from oracle import Oracle
 
-from analytic import linear_robin_steady, plane_wall_robin
+from analytic import linear_robin_steady, paper_2d_verification, plane_wall_robin
 
 GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
 
@@ -569,6 +569,70 @@ def test_infinite_rate_is_anti_bounce_back():
     a.step(500)
     b.step(500)
     assert np.abs(a.pops()[1] - b.pops()[1]).max() < 1e-12
+
+
+def test_anti_bounce_back_spares_non_reactive_walls():
+    """Anti-bounce-back is the k -> infinity limit of the rate condition (paper,
+    extended PeDa range): at a solid node with k_r = 0 it leaves plain
+    bounce-back, so a channel whose walls both have k_r = 0 runs bit for bit
+    as under the new scheme with k_r = 0."""
+    case = configs.robin_channel(k_r=0.0, steps=300)
+    rng = np.random.default_rng(8)
+    case = case.replace(c_init=rng.uniform(0.0, 1.0, size=case.n))
+    a = Oracle(case.replace(scheme=SCHEME_ABB))
+    b = Oracle(case)
+    a.step(300)
+    b.step(300)
+    assert np.array_equal(a.pops()[1], b.pops()[1])
+
+
+def _config_a_small(scheme, peda, kfac=1.0):
+    """The paper's configuration A (2D reaction-diffusion, D2Q5, tau_AD =
+    0.74) scaled to a = 25, b = 20 at the same D = 0.08, started from the
+    analytic field (with the rate k_r kfac) and run to its steady state."""
+    a, b, U = 25, 20, 0.004
+    D = U * b
+    kr = peda * D / b
+    an = _config_a_analytic(a, b, D, kr * kfac)
+    init = np.ones((b + 2, a))
+    init[1:b + 1] = an
+    case = configs.reaction_diffusion_2d(peda, scheme, a=a, b=b, U=U, c_init=init.reshape(-1))
+    o = Oracle(case)
+    o.step(16000)
+    return o.fields()["c"].reshape(b + 2, a)[1:b + 1], (a, b, D, kr)
+
+
+def _config_a_analytic(a, b, D, kr):
+    """The paper's analytic field (eq. analytical2Dverification) on the fluid
+    nodes x = 0..a-1, rows 1..b: the fixed-concentration plane at the inlet's
+    virtual node x = -1, the zero-gradient plane half a node past the last
+    column, the bottom zero-flux plane halfway to the solid row, the reactive
+    plane on the top fluid row (the pre-collision source with the new scheme
+    puts the wall on the node; see test_linear_steady_robin)."""
+    x = np.arange(a) + 1.0
+    y = np.arange(1, b + 1) - 0.5
+    X, Y = np.meshgrid(x, y)
+    return paper_2d_verification(X, Y, a + 0.5, b - 0.5, D, kr, 1.0, 0.0)
+
+
+def test_configuration_a_scheme_trends():
+    """Configuration A against the paper's analytic solution (Sec. 3.1): on
+    grid-aligned walls S.P.J. and the new scheme coincide exactly (e.n = 1 on
+    every D2Q5 link); the new scheme matches the analytic field; S.V. is far
+    off at PeDa = 1 and matches once its rate is divided by gamma (the PeDa
+    shift the paper reports)."""
+    C_new, (a, b, D, kr) = _config_a_small(SCHEME_SNEW, 1.0)
+    C_spj, _ = _config_a_small(SCHEME_SPJ, 1.0)
+    gamma = 0.74 / 0.24
+    C_sv, _ = _config_a_small(SCHEME_SV, 1.0, kfac=1 / gamma)
+    assert np.array_equal(C_new, C_spj)
+    an = _config_a_analytic(a, b, D, kr)
+    mae_new = np.abs(C_new - an).mean()
+    mae_sv = np.abs(C_sv - an).mean()
+    mae_sv_shift = np.abs(C_sv - _config_a_analytic(a, b, D, kr / gamma)).mean()
+    assert mae_new < 1e-2
+    assert mae_sv > 10 * mae_new
+    assert mae_sv_shift < 2 * mae_new
 
 
 def test_gradient_normals_of_straight_walls():
