@@ -56,6 +56,29 @@ def tilted_band(nx: int, ny: int, shift: int, width: float, s0: float = 0.37):
     return solid, normals, info
 
 
+def diagonal_band(n: int, width: float, s0: float = 0.37):
+    """Fluid band at 45 degrees on the plain n x n torus: s = (x + y)/sqrt(2)
+    grows by the period P = n/sqrt(2) under either translation, so
+    ``(s - s0) mod P`` is well defined; nodes with that value in [0, width)
+    are fluid.  Normals of solid nodes are -+m, m = (1, 1)/sqrt(2), toward the
+    nearer band surface.  Returns (solid, normals, info) like tilted_band."""
+    r = 1.0 / math.sqrt(2.0)
+    m = np.array([r, r, 0.0])
+    P = n * r
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    d = np.mod(m[0] * x + m[1] * y - s0, P)
+    fluid = d < width
+    solid = (~fluid).astype(np.uint8)[None]
+    normals = np.zeros((1, n, n, 3), np.float64)
+    upper = (d - width) < (P - d)
+    sol = ~fluid
+    for k in range(2):
+        normals[0, :, :, k] = np.where(sol & upper, -m[k], np.where(sol, m[k], 0.0))
+    info = dict(t=np.array([r, -r, 0.0]), m=m, period=P, d=d[None], angle_deg=-45.0,
+                wall_length=2.0 * n * math.sqrt(2.0))
+    return solid, normals, info
+
+
 def _wrap_delta(d, n):
     return d - n * np.round(d / n)
 

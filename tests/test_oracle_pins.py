@@ -593,26 +593,28 @@ def _config_a_small(scheme, peda, kfac=1.0):
     a, b, U = 25, 20, 0.004
     D = U * b
     kr = peda * D / b
-    an = _config_a_analytic(a, b, D, kr * kfac)
+    an = _config_a_analytic(a, b, D, kr * kfac, 0.74)
     init = np.ones((b + 2, a))
     init[1:b + 1] = an
     case = configs.reaction_diffusion_2d(peda, scheme, a=a, b=b, U=U, c_init=init.reshape(-1))
+    assert abs(case.tau_ad - 0.74) < 1e-12
     o = Oracle(case)
     o.step(16000)
     return o.fields()["c"].reshape(b + 2, a)[1:b + 1], (a, b, D, kr)
 
 
-def _config_a_analytic(a, b, D, kr):
+def _config_a_analytic(a, b, D, kr, tau):
     """The paper's analytic field (eq. analytical2Dverification) on the fluid
-    nodes x = 0..a-1, rows 1..b: the fixed-concentration plane at the inlet's
-    virtual node x = -1, the zero-gradient plane half a node past the last
-    column, the bottom zero-flux plane halfway to the solid row, the reactive
-    plane on the top fluid row (the pre-collision source with the new scheme
-    puts the wall on the node; see test_linear_steady_robin)."""
-    x = np.arange(a) + 1.0
+    nodes x = 0..a-1, rows 1..b, with each boundary plane where the lattice
+    puts it for a linear profile: the equilibrium inlet fixes C at x = -tau
+    (see analytic.linear_robin_steady), the zero-gradient outlet copy mirrors
+    about x = a - 1/2, bounce-back at the bottom is halfway to the solid row,
+    and the pre-collision source with the new scheme puts the reactive wall on
+    the top fluid row (test_linear_steady_robin)."""
+    x = np.arange(a) + tau
     y = np.arange(1, b + 1) - 0.5
     X, Y = np.meshgrid(x, y)
-    return paper_2d_verification(X, Y, a + 0.5, b - 0.5, D, kr, 1.0, 0.0)
+    return paper_2d_verification(X, Y, a - 0.5 + tau, b - 0.5, D, kr, 1.0, 0.0)
 
 
 def test_configuration_a_scheme_trends():
@@ -626,10 +628,10 @@ def test_configuration_a_scheme_trends():
     gamma = 0.74 / 0.24
     C_sv, _ = _config_a_small(SCHEME_SV, 1.0, kfac=1 / gamma)
     assert np.array_equal(C_new, C_spj)
-    an = _config_a_analytic(a, b, D, kr)
+    an = _config_a_analytic(a, b, D, kr, 0.74)
     mae_new = np.abs(C_new - an).mean()
     mae_sv = np.abs(C_sv - an).mean()
-    mae_sv_shift = np.abs(C_sv - _config_a_analytic(a, b, D, kr / gamma)).mean()
+    mae_sv_shift = np.abs(C_sv - _config_a_analytic(a, b, D, kr / gamma, 0.74)).mean()
     assert mae_new < 1e-2
     assert mae_sv > 10 * mae_new
     assert mae_sv_shift < 2 * mae_new
