@@ -52,6 +52,9 @@ class Case:
     phase_change: int = 0
     collision: int = 0          # 0 BGK, 1 TRT (magic parameter 3/16 for both lattices)
     qs: int = 0                 # solute lattice: 0 (the fluid's), 5 (D2Q5) or 7 (D3Q7)
+    fluid_open: int = 0         # 1: plug inflow u_in at the inlet face, density rho_out
+    u_in: float = 0.0           #    at the outlet face (inlet axis not periodic)
+    rho_out: float = 1.0
     normals: Optional[np.ndarray] = None   # float64 [N, 3], unit normal solid -> fluid
     k_r_field: Optional[np.ndarray] = None  # float64 [N]
     phi0: Optional[np.ndarray] = None       # float64 [N]

@@ -35,7 +35,8 @@ class _Params(C.Structure):
                 ("force", C.c_double * 3), ("c_eq", C.c_double), ("k_r", C.c_double),
                 ("v_m", C.c_double), ("a_m", C.c_double), ("periodic", C.c_int * 3),
                 ("xwrap_shift_y", C.c_int), ("inlet_axis", C.c_int), ("c_in", C.c_double),
-                ("phase_change", C.c_int), ("collision", C.c_int), ("qs", C.c_int)]
+                ("phase_change", C.c_int), ("collision", C.c_int), ("qs", C.c_int),
+                ("fluid_open", C.c_int), ("u_in", C.c_double), ("rho_out", C.c_double)]
 
 
 _lib = None
@@ -94,6 +95,8 @@ class Oracle:
         p.phase_change = case.phase_change
         p.collision = getattr(case, "collision", 0)
         p.qs = getattr(case, "qs", 0)
+        p.fluid_open = getattr(case, "fluid_open", 0)
+        p.u_in, p.rho_out = getattr(case, "u_in", 0.0), getattr(case, "rho_out", 1.0)
         self._solid = case.solid_flat()
         self._normals = case.normals_flat()
         self._kr = None if case.k_r_field is None else np.ascontiguousarray(case.k_r_field, np.float64)

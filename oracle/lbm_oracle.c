@@ -31,6 +31,13 @@
  *     with the anti-bounce-back limit for k -> infinity and plain bounce-back
  *     for k = 0 (Sec. 2.3, limits); the anti-bounce-back scheme applies at
  *     solid nodes with k_r > 0 (a non-reactive wall stays bounce-back).
+ *   - open channel (Sec. 3.3, reactive object in a channel flow: plug velocity
+ *     at the inlet, fixed density at the outlet; the paper names no scheme):
+ *     at the inlet face an incoming population is the node's own opposite one
+ *     plus 2 w_i rho_out (e_i.u_in)/c_s^2 (bounce-back from a wall moving with
+ *     u_in, which carries exactly rho_out u_in per inlet node), at the outlet
+ *     face minus the node's own opposite one plus 2 w_i rho_out
+ *     (anti-bounce-back at density rho_out, dropping O(u^2) terms).
  *   - solid fraction (Sec. 2.4, eq. solidFractionUpdate) fed by the mass
  *     actually exchanged over each reactive link; dissolution is charged to
  *     the solid node, precipitation credited to the fluid node.
@@ -68,6 +75,10 @@ typedef struct {
     int collision;          /* ORC_BGK | ORC_TRT */
     int qs;                 /* solute lattice: 0 or q (the fluid's), 5 (D2Q5 with
                                D2Q9) or 7 (D3Q7 with D3Q19) */
+    int fluid_open;         /* 1: the fluid enters at the inlet face with the plug
+                               velocity u_in and leaves at the outlet face at
+                               density rho_out (inlet axis not periodic) */
+    double u_in, rho_out;
 } orc_params;
 
 typedef struct {
@@ -335,12 +346,20 @@ static void update_node(orc *o, long x)
     coords(o, x, &X, &Y, &Z);
     double *fo = o->f, *go = o->g;
 
-    /* fluid: pull with halfway bounce-back */
+    /* fluid: pull with halfway bounce-back; an open channel's inlet and
+     * outlet faces instead impose the plug velocity and the outlet density */
     double fp[ORC_QMAX];
     for (int i = 0; i < Q; i++) {
         long y = site(o, X, Y, Z, -o->e[i][0], -o->e[i][1], -o->e[i][2], 0, &face);
         if (y >= 0 && !o->solid[y]) fp[i] = fo[y * Q + i];
         else fp[i] = fo[x * Q + o->opp[i]];
+        if (y < 0 && p->fluid_open && p->inlet_axis >= 0) {
+            const int a = p->inlet_axis;
+            if (face == 2 * a)
+                fp[i] += 2.0 * o->wf[i] * p->rho_out * (o->e[i][a] * p->u_in) / o->cs2f;
+            else if (face == 2 * a + 1)
+                fp[i] = -fp[i] + 2.0 * o->wf[i] * p->rho_out;
+        }
     }
     double rho = 0, j[3] = {0, 0, 0};
     for (int i = 0; i < Q; i++) {

@@ -637,6 +637,46 @@ def test_configuration_a_scheme_trends():
     assert mae_sv_shift < 2 * mae_new
 
 
+def _open_channel(coll, tau, u_in=0.01, nx=60, ny=14, steps=30000):
+    solid, normals = geometry.plane_channel(nx, ny, (0, ny - 1))
+    case = Case(name="open", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=tau, tau_ad=0.8, periodic=(0, 1, 1), inlet_axis=0, c_in=1.0, c0=1.0,
+                fluid_open=1, u_in=u_in, rho_out=1.0, collision=coll)
+    o = Oracle(case)
+    o.step(steps)
+    f = o.fields()
+    rho = f["rho"].reshape(ny, nx)[1:-1]
+    ux = f["u"].reshape(ny, nx, 3)[1:-1, :, 0]
+    return rho, ux
+
+
+@pytest.mark.parametrize("coll,tau", [(COLL_BGK, 0.8), (COLL_TRT, 0.8), (COLL_TRT, 1.7)])
+def test_open_channel_carries_the_inlet_flux(coll, tau):
+    """Open channel (plug inflow, fixed outlet density; Sec. 3.3's channel
+    boundary conditions): each inlet link adds exactly 2 w_i rho_out
+    (e_i.u_in)/c_s^2, i.e. rho_out u_in per inlet node, so at steady state
+    every cross-section carries rho_out u_in H.  The developed flow is
+    Poiseuille's: the pressure gradient is 12 nu rho u_in / H^2 (within 1 %),
+    and with TRT (walls exactly halfway) the profile across the walls at
+    y = 0 and H is a parabola; the density extrapolated to the outlet plane is
+    rho_out up to the dropped O(u^2) terms."""
+    H, u_in = 12, 0.01
+    rho, ux = _open_channel(coll, tau)
+    flux = (rho * ux).sum(0)
+    assert np.abs(flux / (u_in * H) - 1).max() < 1e-10
+    nu = (tau - 0.5) / 3
+    rc = rho.mean(0)
+    grad = np.polyfit(np.arange(20, 40), rc[20:40], 1)[0] / 3.0
+    assert grad / (-12 * nu * u_in / H ** 2) == pytest.approx(1.0, abs=0.01)
+    assert abs(rc[-1] + 0.5 * (rc[-1] - rc[-2]) - 1.0) < 1e-3
+    if coll == COLL_TRT:
+        prof = (rho * ux)[:, 30]
+        y = np.arange(H) + 0.5
+        par = 1 - (2 * (y - H / 2) / H) ** 2
+        par *= u_in * H / par.sum()        # the exact discrete flux fixes the amplitude
+        assert np.abs(prof - par).max() < 1e-4 * par.max()
+
+
 def test_gradient_normals_of_straight_walls():
     """Without given normals the oracle uses the isotropic lattice gradient of
     the solid indicator.  On a straight wall that gradient is exactly normal to
