@@ -123,6 +123,18 @@ typedef struct {
     int32_t collision;        /* LBM_BGK | LBM_TRT                                 */
     int64_t max_links;        /* capacity for reactive links; <= 0 selects
                                  max(4096, N*(Q-1)/4)                              */
+    int32_t fluid_open;       /* 1: open channel along inlet_axis (Sec. 3.3's
+                                 channel flow; needs inlet_axis >= 0 and that axis
+                                 not periodic): at the inlet face an incoming
+                                 fluid population is the node's own opposite one
+                                 plus 2 w_i rho_out (e_i.u_in)/c_s^2 (a wall
+                                 moving with the plug velocity), at the outlet
+                                 face minus that one plus 2 w_i rho_out (density
+                                 rho_out, O(u^2) terms dropped).  0: the box faces
+                                 of that axis are bounce-back walls            */
+    int32_t reserved1;
+    double u_in;              /* plug velocity along +inlet_axis                   */
+    double rho_out;           /* outlet density (> 0)                              */
 } lbm_params;
 
 typedef struct {

@@ -99,6 +99,61 @@ def reaction_diffusion_2d(peda=1.0, scheme=SCHEME_SNEW, a=100, b=80, pe=1.0, U=1
 
 
 # --------------------------------------------------------------------------
+# the paper's reactive object in a channel flow (Molins et al.'s benchmark)
+# --------------------------------------------------------------------------
+MOLINS_CASES = {1: (600.0, 178.0), 2: (600.0, 17800.0), 3: (6.0, 178.0), 4: (6.0, 0.178)}
+
+
+def reactive_cylinder(case=4, scheme=SCHEME_SNEW, scale=4, re=0.6, collision=1, c_in=0.0,
+                      c_eq=1.0) -> Case:
+    """The paper's channel-flow case: a 600 x 1200 channel (H = 0.05 cm,
+    W = 0.1 cm) with a reactive cylinder of diameter 240 (0.02 cm) in its
+    middle, plug inflow and fixed outlet density, Re = 0.6, Pe and Da of the
+    paper's four cases with the channel height as the length (Re = U H / nu,
+    Pe = U H / D, Da = k_r / U: with H = 0.05 cm and u_in = 0.12 cm/s these
+    give water's viscosity and D = 1e-5 cm^2/s at Pe = 600), J0 = 0.99 at
+    Pe = 600 and 1/3 at Pe = 6 on a D2Q5 solute, TRT.  Lengths
+    are divided by ``scale`` and the lattice velocity 0.001 multiplied by it,
+    which keeps both relaxation times.  Walls: solid rows below and above the
+    H fluid rows (k_r = 0); the cylinder's solid nodes carry k_r."""
+    pe, da = MOLINS_CASES[case]
+    H, W, d = 600 // scale, 1200 // scale, 240.0 / scale
+    U = 0.001 * scale
+    nu = U * H / re
+    Dm = U * H / pe
+    j0 = 0.99 if pe > 100 else 1.0 / 3.0
+    cs2 = (1.0 - j0) / 2.0
+    ny = H + 2
+    y, x = np.mgrid[0:ny, 0:W].astype(np.float64)
+    cx, cy = W / 2.0 - 0.5, ny / 2.0 - 0.5
+    r = np.hypot(x - cx, y - cy)
+    cyl = r <= d / 2.0
+    solid = np.zeros((1, ny, W), np.uint8)
+    solid[0, 0, :] = solid[0, ny - 1, :] = 1
+    solid[0][cyl] = 1
+    normals = np.zeros((1, ny, W, 3))
+    normals[0, 0, :, 1], normals[0, ny - 1, :, 1] = 1.0, -1.0
+    rr = np.maximum(r, 1e-12)
+    normals[0, :, :, 0] = np.where(cyl, (x - cx) / rr, normals[0, :, :, 0])
+    normals[0, :, :, 1] = np.where(cyl, (y - cy) / rr, normals[0, :, :, 1])
+    kr = np.where(cyl, da * U, 0.0)[None]
+    return Case(name=f"molins_case{case}_s{scheme}_1over{scale}", dim=2, nx=W, ny=ny, nz=1, q=9,
+                qs=5, solid=solid, normals=normals, tau_ns=0.5 + 3.0 * nu, tau_ad=0.5 + Dm / cs2,
+                j0=j0, c_eq=c_eq, k_r=0.0, k_r_field=kr.reshape(-1), v_m=0.0, periodic=(0, 1, 1),
+                inlet_axis=0, c_in=c_in, c0=c_in, scheme=scheme, collision=collision,
+                fluid_open=1, u_in=U, rho_out=1.0,
+                info=dict(pe=pe, da=da, H=H, W=W, d=d, U=U, case=case))
+
+
+def reactive_cylinder_rate(case, c, ux):
+    """R_avg of the paper's channel case in lattice units: (outlet flux of C
+    minus inlet flux) / (pi d), from the concentration and velocity fields of
+    the fluid rows [ny, nx] (the outlet column is the last one)."""
+    inf = case.info
+    return ((c[1:-1, -1] * ux[1:-1, -1]).sum() - case.c_in * inf["U"] * inf["H"]) / (math.pi * inf["d"])
+
+
+# --------------------------------------------------------------------------
 # workload 1: 512 x 512 tilted channel, Poiseuille flow + solute, Pe x Da sweep
 # --------------------------------------------------------------------------
 def channel_flow_params(pe: float, da: float, L: float, tau_ns: float, q: int = 9,

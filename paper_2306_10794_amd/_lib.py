@@ -40,7 +40,9 @@ class lbm_params(C.Structure):
                 ("c_eq", C.c_double), ("k_r", C.c_double), ("v_m", C.c_double),
                 ("a_m", C.c_double), ("periodic", C.c_int32 * 3), ("xwrap_shift_y", C.c_int32),
                 ("inlet_axis", C.c_int32), ("c_in", C.c_double), ("phase_change", C.c_int32),
-                ("collision", C.c_int32), ("max_links", C.c_int64)]
+                ("collision", C.c_int32), ("max_links", C.c_int64),
+                ("fluid_open", C.c_int32), ("reserved1", C.c_int32), ("u_in", C.c_double),
+                ("rho_out", C.c_double)]
 
 
 class lbm_diag(C.Structure):

@@ -50,6 +50,11 @@ std::string check_params(const lbm_params &p) {
     }
     if (p.phase_change != 0 && p.phase_change != 1) return "phase_change must be 0 or 1";
     if (p.collision != LBM_BGK && p.collision != LBM_TRT) return "collision must be LBM_BGK or LBM_TRT";
+    if (p.fluid_open != 0 && p.fluid_open != 1) return "fluid_open must be 0 or 1";
+    if (p.fluid_open) {
+        if (p.inlet_axis < 0 || p.periodic[p.inlet_axis]) return "fluid_open needs inlet_axis >= 0 and that axis not periodic";
+        if (!(p.rho_out > 0.0) || !(fabs(p.u_in) < 0.3)) return "fluid_open needs rho_out > 0 and |u_in| < 0.3";
+    }
     return "";
 }
 
@@ -245,6 +250,9 @@ static DomDev dom_record(const DomHost &h, bool fp64) {
     // TRT: the second rate of each lattice from the magic parameter 3/16,
     // (tau+ - 1/2)(tau- - 1/2) = 3/16; BGK: both rates equal
     D.trt = p.collision == LBM_TRT;
+    D.fopen = p.fluid_open;
+    D.u_in = p.u_in;
+    D.rho_out = p.rho_out;
     D.smask = p.solute_q == p.fluid_q ? (1u << p.fluid_q) - 1u
                                       : (p.fluid_q == 9 ? axis_mask<D2Q9>() : axis_mask<D3Q19>());
     const double tfm = 0.5 + (3.0 / 16.0) / (p.tau_ns - 0.5), tgm = 0.5 + (3.0 / 16.0) / (p.tau_ad - 0.5);

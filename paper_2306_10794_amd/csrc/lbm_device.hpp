@@ -129,6 +129,8 @@ struct DomDev {
     // with omega_g).  BGK: omega_fm = omega_f, omega_gs = omega_g
     int trt;
     uint32_t smask;            // solute velocity set (bit i: fluid direction i)
+    int fopen;                 // open channel along the inlet axis (plug inflow u_in,
+    double u_in, rho_out;      // outlet density rho_out)
     double omega_fm, force_fac_m, omega_gs;
     double F[3];
     double ws[19];             // solute weights by fluid direction (rest fraction;

@@ -201,6 +201,18 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         // fluid neighbour: pull along i; solid or box face: own value along opp(i)
         fv[i] = kk[i] >= 0 ? a.fin[(long)i * S + kk[i]] : a.fin[(long)L::opp[i] * S + k];
     }
+    // open channel: the box faces of the inlet axis carry the plug inflow
+    // (bounce-back from a wall moving with u_in) and the outlet density
+    // (anti-bounce-back at rho_out); values are deviations from w rho0
+    if (D.fopen && cross) {
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (!(cross & (1u << i))) continue;
+            const R ea = R(ax == 0 ? L::ex[i] : (ax == 1 ? L::ey[i] : L::ez[i]));
+            if (cross_hi & (1u << i)) fv[i] = (T)(-(R)fv[i] + R(2) * R(L::w[i]) * (D.rho_out - D.rho0));
+            else fv[i] = (T)((R)fv[i] + R(6) * R(L::w[i]) * D.rho_out * (ea * D.u_in));
+        }
+    }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         if (!((SM >> i) & 1u)) continue;

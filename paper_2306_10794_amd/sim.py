@@ -30,6 +30,8 @@ def params_from_case(case, precision: int = L.LBM_FP32_DEV, max_links: int = 0) 
     p.phase_change = case.phase_change
     p.collision = getattr(case, "collision", 0)
     p.max_links = max_links
+    p.fluid_open = getattr(case, "fluid_open", 0)
+    p.u_in, p.rho_out = getattr(case, "u_in", 0.0), getattr(case, "rho_out", 1.0)
     return p
 
 
