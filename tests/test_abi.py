@@ -1,6 +1,7 @@
 """C-ABI contract checks that need no GPU: the library loads, exports every
 function the header declares, and rejects bad parameters on the host."""
 import ctypes as C
+import os
 import subprocess
 
 import pytest
@@ -42,13 +43,30 @@ def test_library_exports_every_header_symbol():
         assert getattr(L.lib, n) is not None
 
 
-def test_struct_layout_matches_header():
-    """The ctypes mirror has the header's field order; sizes are multiples of 8."""
+def test_struct_layout_matches_header(tmp_path):
+    """The ctypes mirrors have the header's layout: a C program compiled
+    against include/lbmrbc.h prints every field's offset and each struct's
+    size, and they must equal ctypes'."""
     L = _L()
-    assert C.sizeof(L.lbm_params) % 8 == 0
-    assert L.lbm_params.max_links.offset == C.sizeof(L.lbm_params) - 8
-    assert C.sizeof(L.lbm_diag) == 6 * 8 + 3 * 8 + 8
-    assert C.sizeof(L.lbm_launch_config) == 16
+    root = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+    structs = {"lbm_params": L.lbm_params, "lbm_diag": L.lbm_diag,
+               "lbm_launch_config": L.lbm_launch_config}
+    lines = ['#include <stdio.h>', '#include <stddef.h>', '#include "lbmrbc.h"', "int main(void) {"]
+    for sname, cls in structs.items():
+        lines.append(f'printf("{sname} size %zu\\n", sizeof({sname}));')
+        for fname, _ in cls._fields_:
+            lines.append(f'printf("{sname}.{fname} %zu\\n", offsetof({sname}, {fname}));')
+    lines += ["return 0;", "}"]
+    src = tmp_path / "layout.c"
+    src.write_text("\n".join(lines) + "\n")
+    exe = tmp_path / "layout"
+    subprocess.run(["gcc", "-I", os.path.join(root, "include"), "-o", str(exe), str(src)], check=True)
+    got = dict(line.rsplit(" ", 1) for line in subprocess.run(
+        [str(exe)], capture_output=True, text=True, check=True).stdout.splitlines())
+    for sname, cls in structs.items():
+        assert int(got[f"{sname} size"]) == C.sizeof(cls), sname
+        for fname, _ in cls._fields_:
+            assert int(got[f"{sname}.{fname}"]) == getattr(cls, fname).offset, (sname, fname)
 
 
 def test_workspace_bytes_scales_with_lattice():
