@@ -281,8 +281,9 @@ static std::string check_batch(const lbm_params *p, int n) {
         std::string m = check_params(p[d]);
         if (!m.empty()) return (n > 1 ? "domain " + std::to_string(d) + ": " : std::string()) + m;
         if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].solute_q != p[0].solute_q ||
-            p[d].precision != p[0].precision || p[d].collision != p[0].collision)
-            return "all domains of a batch need the same dim, lattices, precision and collision";
+            p[d].precision != p[0].precision || p[d].collision != p[0].collision ||
+            p[d].fluid_open != p[0].fluid_open)
+            return "all domains of a batch need the same dim, lattices, precision, collision and fluid_open";
         if (p[d].phase_change != 0 && n > 1) return "phase_change is not supported in a batch";
         if (p[d].phase_change != 0 && p[d].phase_change != 1) return "phase_change must be 0 or 1";
     }

@@ -36,7 +36,7 @@ namespace lbm {
 // tiles on one XCD.  FP32 storage asks for 4 waves per SIMD (at most 128
 // VGPRs, a few spilled): the extra wave hides more memory latency than the
 // spills cost (256^3 sphere packing: 732 -> 660 us).
-template <class L, typename T, int WV, bool TRT, bool RED>
+template <class L, typename T, int WV, bool TRT, bool RED, bool OPEN>
 __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepArgs<T> a, long nblocks,
                                                                          int remap) {
     using R = double;
@@ -201,18 +201,6 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         // fluid neighbour: pull along i; solid or box face: own value along opp(i)
         fv[i] = kk[i] >= 0 ? a.fin[(long)i * S + kk[i]] : a.fin[(long)L::opp[i] * S + k];
     }
-    // open channel: the box faces of the inlet axis carry the plug inflow
-    // (bounce-back from a wall moving with u_in) and the outlet density
-    // (anti-bounce-back at rho_out); values are deviations from w rho0
-    if (D.fopen && cross) {
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            if (!(cross & (1u << i))) continue;
-            const R ea = R(ax == 0 ? L::ex[i] : (ax == 1 ? L::ey[i] : L::ez[i]));
-            if (cross_hi & (1u << i)) fv[i] = (T)(-(R)fv[i] + R(2) * R(L::w[i]) * (D.rho_out - D.rho0));
-            else fv[i] = (T)((R)fv[i] + R(6) * R(L::w[i]) * D.rho_out * (ea * D.u_in));
-        }
-    }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         if (!((SM >> i) & 1u)) continue;
@@ -235,6 +223,19 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     R fp[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) fp[i] = (R)fv[i];
+    // open channel: the box faces of the inlet axis carry the plug inflow
+    // (bounce-back from a wall moving with u_in) and the outlet density
+    // (anti-bounce-back at rho_out); values are deviations from w rho0.  A
+    // separate instantiation: in the others it would cost registers (spills)
+    if (OPEN && D.fopen && cross) {
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (!(cross & (1u << i))) continue;
+            const R ea = R(ax == 0 ? L::ex[i] : (ax == 1 ? L::ey[i] : L::ez[i]));
+            if (cross_hi & (1u << i)) fp[i] = -fp[i] + R(2) * R(L::w[i]) * (D.rho_out - D.rho0);
+            else fp[i] = fp[i] + R(6) * R(L::w[i]) * D.rho_out * (ea * D.u_in);
+        }
+    }
     R drho = R(0), jx = R(0), jy = R(0), jz = R(0);
 #pragma unroll
     for (int i = 0; i < Q; i++) {
@@ -434,13 +435,18 @@ static StepArgs<T> step_args(Ctx &c) {
     return a;
 }
 
+// An open channel runs the 4-wave tile only (its launch uses that grid).
 template <class L, typename T, bool TRT, bool RED>
-static void launch_k_step(int wv, long nb, hipStream_t st, const StepArgs<T> &args, int rm) {
+static void launch_k_step(int wv, long nb, hipStream_t st, const StepArgs<T> &args, int rm, bool open) {
+    if (open) {
+        hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, true>), dim3(nb), dim3(256), 0, st, args, nb, rm);
+        return;
+    }
     switch (wv) {
-    case 1: hipLaunchKernelGGL((k_step<L, T, 1, TRT, RED>), dim3(nb), dim3(64), 0, st, args, nb, rm); break;
-    case 2: hipLaunchKernelGGL((k_step<L, T, 2, TRT, RED>), dim3(nb), dim3(128), 0, st, args, nb, rm); break;
-    case 8: hipLaunchKernelGGL((k_step<L, T, 8, TRT, RED>), dim3(nb), dim3(512), 0, st, args, nb, rm); break;
-    default: hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED>), dim3(nb), dim3(256), 0, st, args, nb, rm); break;
+    case 1: hipLaunchKernelGGL((k_step<L, T, 1, TRT, RED, false>), dim3(nb), dim3(64), 0, st, args, nb, rm); break;
+    case 2: hipLaunchKernelGGL((k_step<L, T, 2, TRT, RED, false>), dim3(nb), dim3(128), 0, st, args, nb, rm); break;
+    case 8: hipLaunchKernelGGL((k_step<L, T, 8, TRT, RED, false>), dim3(nb), dim3(512), 0, st, args, nb, rm); break;
+    default: hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, false>), dim3(nb), dim3(256), 0, st, args, nb, rm); break;
     }
 }
 
@@ -463,17 +469,19 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
     const StepArgs<T> args = step_args<T>(c);
     if (ev) (void)hipEventRecord(ev[0], c.stream);
     if (c.n_tasks > 0) {
-        const int wv = c.cfg.wg_waves;
+        // an open channel (any domain) takes the 4-wave tile
+        const bool open = c.p.fluid_open != 0;
+        const int wv = open ? 4 : c.cfg.wg_waves;
         const long nb = (c.n_tasks + wv - 1) / wv;
         const int rm = c.cfg.xcd_remap;
         // TRT and the reduced solute set are separate instantiations: TRT's
         // extra terms would cost the BGK kernel registers (every domain of a
         // context shares both choices)
         const bool trt = c.p.collision == LBM_TRT;
-        if (trt && c.red) launch_k_step<L, T, true, true>(wv, nb, c.stream, args, rm);
-        else if (trt) launch_k_step<L, T, true, false>(wv, nb, c.stream, args, rm);
-        else if (c.red) launch_k_step<L, T, false, true>(wv, nb, c.stream, args, rm);
-        else launch_k_step<L, T, false, false>(wv, nb, c.stream, args, rm);
+        if (trt && c.red) launch_k_step<L, T, true, true>(wv, nb, c.stream, args, rm, open);
+        else if (trt) launch_k_step<L, T, true, false>(wv, nb, c.stream, args, rm, open);
+        else if (c.red) launch_k_step<L, T, false, true>(wv, nb, c.stream, args, rm, open);
+        else launch_k_step<L, T, false, false>(wv, nb, c.stream, args, rm, open);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[1], c.stream);

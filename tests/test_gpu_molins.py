@@ -84,3 +84,18 @@ def test_reactive_cylinder_table():
     assert abs(abb31 / p31 - 1) < 0.05
     # anti-BB does not depend on the rate constant
     assert R[2, 3] == R[3, 3]
+
+
+def test_open_channel_limits():
+    """Every domain of a batch shares fluid_open; an open channel needs its
+    inlet axis non-periodic."""
+    import torch
+    from paper_2306_10794_amd import BatchSimulation, Simulation, LbmError, LBM_EINVAL
+    c = configs.reactive_cylinder(4, SCHEME_SNEW, scale=20)
+    with pytest.raises(LbmError) as ei:
+        BatchSimulation([c, c.replace(fluid_open=0)], precision=FP32)
+    assert ei.value.status == LBM_EINVAL
+    with pytest.raises(LbmError) as ei:
+        Simulation(c.replace(periodic=(1, 1, 1)), precision=FP32)
+    assert ei.value.status == LBM_EINVAL
+    torch.cuda.synchronize()
