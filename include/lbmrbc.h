@@ -132,7 +132,10 @@ typedef struct {
                                  face minus that one plus 2 w_i rho_out (density
                                  rho_out, O(u^2) terms dropped).  0: the box faces
                                  of that axis are bounce-back walls            */
-    int32_t reserved1;
+    int32_t ceq_field;        /* 1: the equilibrium concentration of the reaction
+                                 varies per solid node, given by lbm_set_ceq
+                                 (8 B per node and ts per link of workspace);
+                                 0: c_eq everywhere                              */
     double u_in;              /* plug velocity along +inlet_axis                   */
     double rho_out;           /* outlet density (> 0)                              */
 } lbm_params;
@@ -187,6 +190,15 @@ lbm_status lbm_batch_offsets(const lbm_ctx *ctx, int64_t *node_off);
  *   phi0    [N]    FP64 initial solid fraction (NULL: 1 at solid, 0 at fluid)
  * Synchronises the stream.  ECAPACITY if the links exceed max_links (the
  * message gives the count needed). */
+/* Per-node equilibrium concentration of the reaction (contexts created with
+ * ceq_field = 1; EINVAL otherwise): c_eq [N] FP64 device, the value at each
+ * solid node is the C_eq of eq. general_RBC on that node's reactive links
+ * (fluid entries are ignored).  Copied into the workspace; takes effect at the
+ * next lbm_set_geometry (call it first) and in every relink after phase
+ * change.  Until it is called, params.c_eq holds everywhere.  Not with
+ * lbm_record / lbm_adjoint. */
+lbm_status lbm_set_ceq(lbm_ctx *ctx, const double *c_eq);
+
 lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *normals,
                             const double *k_r, const double *phi0);
 

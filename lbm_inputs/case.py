@@ -55,6 +55,7 @@ class Case:
     fluid_open: int = 0         # 1: plug inflow u_in at the inlet face, density rho_out
     u_in: float = 0.0           #    at the outlet face (inlet axis not periodic)
     rho_out: float = 1.0
+    c_eq_field: Optional[np.ndarray] = None  # float64 [N]: per-node C_eq at solid nodes
     normals: Optional[np.ndarray] = None   # float64 [N, 3], unit normal solid -> fluid
     k_r_field: Optional[np.ndarray] = None  # float64 [N]
     phi0: Optional[np.ndarray] = None       # float64 [N]

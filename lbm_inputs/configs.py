@@ -154,6 +154,33 @@ def reactive_cylinder_rate(case, c, ux):
 
 
 # --------------------------------------------------------------------------
+# the paper's pattern formation during precipitation
+# --------------------------------------------------------------------------
+def grain_growth(rot_deg=0.0, scheme=SCHEME_SNEW, n=300, v_m=0.2, k_r=0.0014, c0=1.0) -> Case:
+    """The paper's precipitation case: a circular domain of diameter n whose
+    rim holds C = 1 (solid nodes outside the circle reacting toward C_eq = 1
+    with a rate so large that the rim is anti-bounce-back), and a seed in the
+    centre with the boundary r(theta) = n (0.1 + 0.02 cos 4 theta), turned
+    clockwise by rot_deg, reacting toward C_eq = 0 with k_r = 0.0014; pure
+    diffusion on D2Q5 (tau_AD = 1), precipitation with phase change, wall
+    normals from the isotropic lattice gradient (none given).  The solute
+    starts at c0.  V_m (not given by the paper) sets the growth speed."""
+    y, x = np.mgrid[0:n, 0:n].astype(np.float64)
+    c = (n - 1) / 2.0
+    r = np.hypot(x - c, y - c)
+    th = np.arctan2(y - c, x - c) + math.radians(rot_deg)
+    seed = r <= n * (0.1 + 0.02 * np.cos(4.0 * th))
+    rim = r > n / 2.0 - 1.0
+    solid = (seed | rim).astype(np.uint8)[None]
+    kr = np.where(rim, 1e3, k_r)
+    ceq = np.where(rim, 1.0, 0.0)
+    return Case(name=f"grain_s{scheme}_{rot_deg:g}deg", dim=2, nx=n, ny=n, nz=1, q=9, qs=5,
+                solid=solid, tau_ns=1.0, tau_ad=1.0, c_eq=0.0, k_r=0.0, k_r_field=kr.reshape(-1),
+                c_eq_field=ceq.reshape(-1), v_m=v_m, periodic=(1, 1, 1), c0=c0, phase_change=1,
+                scheme=scheme, info=dict(seed=seed, rim=rim, rot=rot_deg))
+
+
+# --------------------------------------------------------------------------
 # workload 1: 512 x 512 tilted channel, Poiseuille flow + solute, Pe x Da sweep
 # --------------------------------------------------------------------------
 def channel_flow_params(pe: float, da: float, L: float, tau_ns: float, q: int = 9,

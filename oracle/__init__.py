@@ -64,6 +64,7 @@ def _load():
         lib.orc_adjoint.restype = C.c_int
         lib.orc_adjoint.argtypes = [P, C.c_int, P, P, P]
         lib.orc_threads.restype = C.c_int
+        lib.orc_set_ceq.argtypes = [P, P]
         lib.orc_get_solute_set.restype = C.c_int
         lib.orc_get_solute_set.argtypes = [P, P]
         _lib = lib
@@ -109,6 +110,10 @@ class Oracle:
         sd = np.empty(19, np.int32)
         self.QS = int(lib.orc_get_solute_set(self._h, _ptr(sd)))
         self.sdirs = sd[:self.QS].copy()
+        ceq = getattr(case, "c_eq_field", None)
+        if ceq is not None:
+            self._ceq = np.ascontiguousarray(ceq, np.float64).reshape(-1)
+            lib.orc_set_ceq(self._h, _ptr(self._ceq))
         if init:
             self.init(case.rho_flat(), case.u_flat(), case.c_flat())
 

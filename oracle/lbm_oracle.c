@@ -96,6 +96,7 @@ typedef struct {
     double gamma;          /* tau_AD / (tau_AD - 1/2)                     */
     uint8_t *solid;
     double *nrm;           /* [N][3] */
+    double *ceq;           /* [N] per-node C_eq of the reaction, or NULL (c_eq) */
     double *kr;            /* [N]    */
     double *phi;           /* [N]    */
     double *f, *fn, *g, *gn; /* [N][Q] post-collision populations       */
@@ -276,7 +277,7 @@ orc *orc_create(const orc_params *p, const uint8_t *solid, const double *normals
 void orc_destroy(orc *o)
 {
     if (!o) return;
-    free(o->solid); free(o->nrm); free(o->kr); free(o->phi);
+    free(o->solid); free(o->nrm); free(o->kr); free(o->phi); free(o->ceq);
     free(o->f); free(o->fn); free(o->g); free(o->gn); free(o->qx); free(o->kind);
     free(o);
 }
@@ -452,9 +453,11 @@ static void update_node(orc *o, long x)
              * post-collision source, whose effective rate is gamma times larger */
             if (p->mechanics == ORC_MECH_PRE) k = k / o->gamma;
         }
+        /* the equilibrium concentration of the solid node's reaction */
+        const double ceq = o->ceq ? o->ceq[sol[i]] : p->c_eq;
         double gout;
-        if (isinf(k)) gout = 2.0 * o->ws[i] * p->c_eq - src;
-        else gout = k / (1.0 + k) * 2.0 * o->ws[i] * p->c_eq + (1.0 - k) / (1.0 + k) * src;
+        if (isinf(k)) gout = 2.0 * o->ws[i] * ceq - src;
+        else gout = k / (1.0 + k) * 2.0 * o->ws[i] * ceq + (1.0 - k) / (1.0 + k) * src;
         gp[i] = gout;
         o->qx[x * Q + i] = gout - go[x * Q + ob];
     }
@@ -799,6 +802,7 @@ int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *la
     if (o->p.phase_change) return -2;
     if (o->p.collision != ORC_BGK) return -3;   /* the transposed step below is BGK's */
     if (o->QS != Q) return -4;                  /* ... on the fluid's velocity set */
+    if (o->ceq) return -5;                      /* ... with a uniform C_eq */
     double *G = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * Q);
     double *U = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * 3);
     double *lam = (double *)calloc((size_t)N * Q, sizeof(double));
@@ -877,6 +881,17 @@ void orc_set_pops(orc *o, const double *f, const double *g)
         for (int s = 0; s < o->QS; s++)
             if (g) o->g[n * Q + o->sd[s]] = g[(long)s * o->N + n];
     }
+}
+
+/* per-node equilibrium concentration of the reaction at solid nodes [N]
+ * (NULL: the uniform c_eq) */
+void orc_set_ceq(orc *o, const double *ceq)
+{
+    free(o->ceq);
+    o->ceq = NULL;
+    if (!ceq) return;
+    o->ceq = (double *)malloc(sizeof(double) * o->N);
+    memcpy(o->ceq, ceq, sizeof(double) * o->N);
 }
 
 /* the solute set: its size, and the fluid direction of each solute direction */

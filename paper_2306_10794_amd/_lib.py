@@ -41,7 +41,7 @@ class lbm_params(C.Structure):
                 ("a_m", C.c_double), ("periodic", C.c_int32 * 3), ("xwrap_shift_y", C.c_int32),
                 ("inlet_axis", C.c_int32), ("c_in", C.c_double), ("phase_change", C.c_int32),
                 ("collision", C.c_int32), ("max_links", C.c_int64),
-                ("fluid_open", C.c_int32), ("reserved1", C.c_int32), ("u_in", C.c_double),
+                ("fluid_open", C.c_int32), ("ceq_field", C.c_int32), ("u_in", C.c_double),
                 ("rho_out", C.c_double)]
 
 
@@ -79,6 +79,7 @@ _SIGS = {
     "lbm_create_batch": [C.POINTER(lbm_params), C.c_int32, _P, C.c_size_t, _P, C.POINTER(_P)],
     "lbm_batch_offsets": [_P, C.POINTER(C.c_int64)],
     "lbm_set_geometry": [_P, _P, _P, _P, _P],
+    "lbm_set_ceq": [_P, _P],
     "lbm_init_fields": [_P, _P, _P, _P],
     "lbm_step": [_P, C.c_int32],
     "lbm_step_timed": [_P, C.c_int32, C.POINTER(C.c_double)],
@@ -177,6 +178,10 @@ def lbm_batch_offsets(ctx, n: int) -> list:
 def lbm_set_geometry(ctx, solid, normals=None, k_r=None, phi0=None):
     _check(lib.lbm_set_geometry(ctx, _ptr(solid), _ptr(normals), _ptr(k_r), _ptr(phi0)),
            "lbm_set_geometry", ctx)
+
+
+def lbm_set_ceq(ctx, c_eq):
+    _check(lib.lbm_set_ceq(ctx, _ptr(c_eq)), "lbm_set_ceq", ctx)
 
 
 def lbm_init_fields(ctx, rho=None, u=None, c=None):

@@ -51,6 +51,7 @@ std::string check_params(const lbm_params &p) {
     if (p.phase_change != 0 && p.phase_change != 1) return "phase_change must be 0 or 1";
     if (p.collision != LBM_BGK && p.collision != LBM_TRT) return "collision must be LBM_BGK or LBM_TRT";
     if (p.fluid_open != 0 && p.fluid_open != 1) return "fluid_open must be 0 or 1";
+    if (p.ceq_field != 0 && p.ceq_field != 1) return "ceq_field must be 0 or 1";
     if (p.fluid_open) {
         if (p.inlet_axis < 0 || p.periodic[p.inlet_axis]) return "fluid_open needs inlet_axis >= 0 and that axis not periodic";
         if (!(p.rho_out > 0.0) || !(fabs(p.u_in) < 0.3)) return "fluid_open needs rho_out > 0 and |u_in| < 0.3";
@@ -109,6 +110,8 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *flags = take(4 * N), *rmask = take(4 * N), *cnt = take(4 * N), *sidx = take(4 * N);
     char *phi = take(8 * N), *kr = take(8 * N), *nrm = take(24 * N), *solid = take(N);
     char *phif = take(8 * S), *phis = take(8 * L);
+    const bool ceqf = p[0].ceq_field != 0;
+    char *ceq = take(ceqf ? 8 * N : 0), *lceq = take(ceqf ? ts * L : 0);
     char *lbeta = take(ts * L), *lq = take(ts * L), *lq2 = take(ts * L), *lnode = take(4 * L),
          *lsolid = take(4 * L), *lmap = take(4 * L),
          *ldir = take(L);
@@ -135,6 +138,9 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->R = R;
         c->RW = RW;
         c->Q = Q;
+        c->ceq = ceqf ? (double *)ceq : nullptr;
+        c->lceq = ceqf ? (void *)lceq : nullptr;
+        c->ceq_set = false;
         c->QS = QS;
         c->red = QS != Q;
         c->smask = Q == 9 ? (c->red ? axis_mask<D2Q9>() : sol_mask<D2Q9, false>())
@@ -282,8 +288,9 @@ static std::string check_batch(const lbm_params *p, int n) {
         if (!m.empty()) return (n > 1 ? "domain " + std::to_string(d) + ": " : std::string()) + m;
         if (p[d].dim != p[0].dim || p[d].fluid_q != p[0].fluid_q || p[d].solute_q != p[0].solute_q ||
             p[d].precision != p[0].precision || p[d].collision != p[0].collision ||
-            p[d].fluid_open != p[0].fluid_open)
-            return "all domains of a batch need the same dim, lattices, precision, collision and fluid_open";
+            p[d].fluid_open != p[0].fluid_open || p[d].ceq_field != p[0].ceq_field)
+            return "all domains of a batch need the same dim, lattices, precision, collision, fluid_open "
+                   "and ceq_field";
         if (p[d].phase_change != 0 && n > 1) return "phase_change is not supported in a batch";
         if (p[d].phase_change != 0 && p[d].phase_change != 1) return "phase_change must be 0 or 1";
     }
@@ -590,6 +597,24 @@ const char *lbm_last_error(const lbm_ctx *ctx) {
     return ((const Ctx *)ctx)->err.c_str();
 }
 
+lbm_status lbm_set_ceq(lbm_ctx *ctx, const double *c_eq) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    if (!c->ceq) {
+        c->err = "lbm_set_ceq needs a context created with ceq_field = 1";
+        return LBM_EINVAL;
+    }
+    if (!c_eq) {
+        c->err = "c_eq is required";
+        return LBM_EINVAL;
+    }
+    if (!dev_ptr_ok(c_eq)) return bad_ptr(c, "c_eq");
+    hipError_t e = hipMemcpyAsync(c->ceq, c_eq, sizeof(double) * c->N, hipMemcpyDeviceToDevice, c->stream);
+    if (e != hipSuccess) return dev_err(c, e, "lbm_set_ceq");
+    c->ceq_set = true;
+    return LBM_OK;
+}
+
 lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *normals,
                             const double *k_r, const double *phi0) {
     Ctx *c = (Ctx *)ctx;
@@ -859,6 +884,10 @@ static lbm_status adj_check(Ctx *c, int32_t nsteps, int32_t ckpt) {
     }
     if (c->red) {
         c->err = "the adjoint transposes the step with the solute on the fluid's velocity set";
+        return LBM_EINVAL;
+    }
+    if (c->ceq) {
+        c->err = "the adjoint takes a uniform c_eq (ceq_field = 0)";
         return LBM_EINVAL;
     }
     return LBM_OK;

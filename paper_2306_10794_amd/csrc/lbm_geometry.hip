@@ -393,7 +393,8 @@ __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *no
                                                const uint32_t *rmask, const int32_t *lbase,
                                                const int32_t *lmap,
                                                const double *nrm, const double *kr, T *lbeta,
-                                               int32_t *lnode, int32_t *lsolid, uint8_t *ldir) {
+                                               int32_t *lnode, int32_t *lsolid, uint8_t *ldir,
+                                               const double *ceq, T *lceq) {
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
     if (k >= nf) return;
     const long n = nodeof[k];
@@ -424,6 +425,8 @@ __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *no
         const double beta = (D.scheme == LBM_ABB && kv > 0.0) ? -1.0 : (1.0 - kap) / (1.0 + kap);
         const int l = lmap[base + r];
         lbeta[l] = (T)beta;
+        // per-node C_eq (deviation form); the uniform value until one is given
+        if (lceq) lceq[l] = (T)((ceq ? ceq[s] : D.ceq_dev + D.c_ref) - D.c_ref);
         lnode[l] = (int32_t)n;
         lsolid[l] = (int32_t)s;
         ldir[l] = (uint8_t)i;
@@ -611,7 +614,8 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
         hipLaunchKernelGGL((k_link_map<L>), dim3((c.n_tasks + BLK / 64 - 1) / (BLK / 64)), dim3(BLK), 0, st,
                            c.tasks, (long)c.n_tasks, c.nodeof, c.rmask, c.lbase, c.lmap);
     hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, g, (long)nf, c.nodeof,
-                       c.rmask, c.lbase, c.lmap, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir);
+                       c.rmask, c.lbase, c.lmap, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir,
+                       c.ceq_set ? c.ceq : nullptr, (T *)c.lceq);
     // solid side: per solid interface node, its links in direction order
     hipLaunchKernelGGL((k_solid_count<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rmask,
                        c.cnt, c.sidx);

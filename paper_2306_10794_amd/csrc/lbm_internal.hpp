@@ -27,6 +27,7 @@ struct StepArgs {
     const T *__restrict__ lbeta;         // per link: (1 - k)/(1 + k)
     T *__restrict__ lq;                  // per link: mass exchanged in this step
     double *__restrict__ phif;           // [S] solid fraction of fluid nodes, compact order
+    const T *__restrict__ lceq;          // per link: C_eq - C_ref of its solid node (per-node C_eq)
     long ntasks;
     long S;                              // stride between directions
     int ndom;                            // domains of the context
@@ -92,6 +93,9 @@ struct Ctx {
     double *phif, *phis;     // [S], [max_links]
     bool phi_stale;          // phi[] lags the working copies
     uint8_t *solid;          // [N]
+    double *ceq;             // [N] per-node C_eq (ceq_field contexts), else null
+    void *lceq;              // [max_links] of T: C_eq - C_ref per link, else null
+    bool ceq_set;            // lbm_set_ceq has filled ceq
     void *lbeta, *lq;        // [max_links] of T; lq: exchanges of the last step
     void *lqb[2];            // the two exchange buffers lq alternates between
     int lq_next;             // buffer the next step writes

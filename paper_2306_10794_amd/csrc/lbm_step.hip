@@ -36,7 +36,7 @@ namespace lbm {
 // tiles on one XCD.  FP32 storage asks for 4 waves per SIMD (at most 128
 // VGPRs, a few spilled): the extra wave hides more memory latency than the
 // spills cost (256^3 sphere packing: 732 -> 660 us).
-template <class L, typename T, int WV, bool TRT, bool RED, bool OPEN>
+template <class L, typename T, int WV, bool TRT, bool RED, bool OPEN, bool CEQ>
 __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepArgs<T> a, long nblocks,
                                                                          int remap) {
     using R = double;
@@ -320,8 +320,11 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
                     bt = __builtin_bit_cast(T, lo | (hi << 32));
                 }
                 const R beta = (R)bt;
+                // the link's C_eq: per solid node (a separate instantiation), or uniform
+                R ceqd = D.ceq_dev;
+                if constexpr (CEQ) ceqd = (R)a.lceq[lt + pos];
                 // (1 - beta) w C_eq + beta g_src: exactly g_src at beta = 1
-                const R g = (R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv;
+                const R g = (R(1) - beta) * (sol_w<L>(D, i) * ceqd) + beta * srcv;
                 const T qv = (T)(g - own);
                 if constexpr (NW == 1) {
                     slink[wv][0][pos] = __builtin_bit_cast(uint32_t, qv);
@@ -429,24 +432,32 @@ static StepArgs<T> step_args(Ctx &c) {
     a.lbeta = (const T *)c.lbeta;
     a.lq = (T *)c.lq;
     a.phif = c.phif;
+    a.lceq = (const T *)c.lceq;
     a.ntasks = c.n_tasks;
     a.ndom = c.ndom;
     a.S = c.S;
     return a;
 }
 
-// An open channel runs the 4-wave tile only (its launch uses that grid).
+// An open channel or a per-node C_eq runs the 4-wave tile only (its launch
+// uses that grid).
 template <class L, typename T, bool TRT, bool RED>
-static void launch_k_step(int wv, long nb, hipStream_t st, const StepArgs<T> &args, int rm, bool open) {
-    if (open) {
-        hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, true>), dim3(nb), dim3(256), 0, st, args, nb, rm);
+static void launch_k_step(int wv, long nb, hipStream_t st, const StepArgs<T> &args, int rm, bool open,
+                          bool ceq) {
+    if (open || ceq) {
+        if (open && ceq)
+            hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, true, true>), dim3(nb), dim3(256), 0, st, args, nb, rm);
+        else if (open)
+            hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, true, false>), dim3(nb), dim3(256), 0, st, args, nb, rm);
+        else
+            hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, false, true>), dim3(nb), dim3(256), 0, st, args, nb, rm);
         return;
     }
     switch (wv) {
-    case 1: hipLaunchKernelGGL((k_step<L, T, 1, TRT, RED, false>), dim3(nb), dim3(64), 0, st, args, nb, rm); break;
-    case 2: hipLaunchKernelGGL((k_step<L, T, 2, TRT, RED, false>), dim3(nb), dim3(128), 0, st, args, nb, rm); break;
-    case 8: hipLaunchKernelGGL((k_step<L, T, 8, TRT, RED, false>), dim3(nb), dim3(512), 0, st, args, nb, rm); break;
-    default: hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, false>), dim3(nb), dim3(256), 0, st, args, nb, rm); break;
+    case 1: hipLaunchKernelGGL((k_step<L, T, 1, TRT, RED, false, false>), dim3(nb), dim3(64), 0, st, args, nb, rm); break;
+    case 2: hipLaunchKernelGGL((k_step<L, T, 2, TRT, RED, false, false>), dim3(nb), dim3(128), 0, st, args, nb, rm); break;
+    case 8: hipLaunchKernelGGL((k_step<L, T, 8, TRT, RED, false, false>), dim3(nb), dim3(512), 0, st, args, nb, rm); break;
+    default: hipLaunchKernelGGL((k_step<L, T, 4, TRT, RED, false, false>), dim3(nb), dim3(256), 0, st, args, nb, rm); break;
     }
 }
 
@@ -469,19 +480,19 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
     const StepArgs<T> args = step_args<T>(c);
     if (ev) (void)hipEventRecord(ev[0], c.stream);
     if (c.n_tasks > 0) {
-        // an open channel (any domain) takes the 4-wave tile
-        const bool open = c.p.fluid_open != 0;
-        const int wv = open ? 4 : c.cfg.wg_waves;
+        // an open channel or a per-node C_eq (all domains alike) takes the 4-wave tile
+        const bool open = c.p.fluid_open != 0, ceq = c.lceq != nullptr;
+        const int wv = (open || ceq) ? 4 : c.cfg.wg_waves;
         const long nb = (c.n_tasks + wv - 1) / wv;
         const int rm = c.cfg.xcd_remap;
         // TRT and the reduced solute set are separate instantiations: TRT's
         // extra terms would cost the BGK kernel registers (every domain of a
         // context shares both choices)
         const bool trt = c.p.collision == LBM_TRT;
-        if (trt && c.red) launch_k_step<L, T, true, true>(wv, nb, c.stream, args, rm, open);
-        else if (trt) launch_k_step<L, T, true, false>(wv, nb, c.stream, args, rm, open);
-        else if (c.red) launch_k_step<L, T, false, true>(wv, nb, c.stream, args, rm, open);
-        else launch_k_step<L, T, false, false>(wv, nb, c.stream, args, rm, open);
+        if (trt && c.red) launch_k_step<L, T, true, true>(wv, nb, c.stream, args, rm, open, ceq);
+        else if (trt) launch_k_step<L, T, true, false>(wv, nb, c.stream, args, rm, open, ceq);
+        else if (c.red) launch_k_step<L, T, false, true>(wv, nb, c.stream, args, rm, open, ceq);
+        else launch_k_step<L, T, false, false>(wv, nb, c.stream, args, rm, open, ceq);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[1], c.stream);

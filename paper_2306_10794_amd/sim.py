@@ -32,6 +32,7 @@ def params_from_case(case, precision: int = L.LBM_FP32_DEV, max_links: int = 0) 
     p.max_links = max_links
     p.fluid_open = getattr(case, "fluid_open", 0)
     p.u_in, p.rho_out = getattr(case, "u_in", 0.0), getattr(case, "rho_out", 1.0)
+    p.ceq_field = 0 if getattr(case, "c_eq_field", None) is None else 1
     return p
 
 
@@ -64,6 +65,9 @@ class Simulation:
             normals=_dev(case.normals_flat(), torch.float64, self.device),
             k_r=_dev(case.k_r_field, torch.float64, self.device),
             phi0=_dev(case.phi0, torch.float64, self.device))
+        if getattr(case, "c_eq_field", None) is not None:
+            self._ceq = _dev(np.asarray(case.c_eq_field).reshape(-1), torch.float64, self.device)
+            L.lbm_set_ceq(self.ctx, self._ceq)
         L.lbm_set_geometry(self.ctx, **self._geom)
         if init:
             self.init_fields(case.rho_flat(), case.u_flat(), case.c_flat())
@@ -203,6 +207,9 @@ class BatchSimulation:
                           normals=cat(lambda c: c.normals_flat(), torch.float64, 3),
                           k_r=cat(lambda c: c.k_r_field, torch.float64),
                           phi0=cat(lambda c: c.phi0, torch.float64))
+        self._ceq = cat(lambda c: getattr(c, "c_eq_field", None), torch.float64)
+        if self._ceq is not None:
+            L.lbm_set_ceq(self.ctx, self._ceq)
         L.lbm_set_geometry(self.ctx, **self._geom)
         if init:
             self._init = [cat(lambda c: c.rho_flat(), torch.float64),

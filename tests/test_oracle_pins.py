@@ -677,6 +677,37 @@ def test_open_channel_carries_the_inlet_flux(coll, tau):
         assert np.abs(prof - par).max() < 1e-4 * par.max()
 
 
+@pytest.mark.parametrize("qs", [0, 5])
+def test_per_node_equilibrium_concentration(qs):
+    """A per-node C_eq (eq. general_RBC with C_eq taken at each link's solid
+    node): a field equal to c_eq everywhere runs bit for bit as the uniform
+    value; with C_eq = a on the bottom wall and b on the top wall of a
+    pure-diffusion channel the steady profile is the exact linear one, each
+    wall on its boundary node with flux k (C_eq - C_wall) (pre-collision
+    source, new scheme; see test_linear_steady_robin):
+    slope = (b - a) / (n - 1 + 2 D / k)."""
+    nx, ny, tau, k_r = 3, 22, 0.8, 0.02
+    solid, normals = geometry.plane_channel(nx, ny, (0, ny - 1))
+    a, b = 0.3, 1.7
+    base = dict(name="ceq", dim=2, nx=nx, ny=ny, nz=1, q=9, qs=qs, solid=solid, normals=normals,
+                tau_ad=tau, k_r=k_r, c_eq=a, c0=1.0)
+    u1 = Oracle(Case(**base))
+    u2 = Oracle(Case(**base, c_eq_field=np.full(nx * ny, a)))
+    u1.step(200)
+    u2.step(200)
+    assert np.array_equal(u1.pops()[1], u2.pops()[1])
+    field = np.full((ny, nx), a)
+    field[ny - 1, :] = b
+    o = Oracle(Case(**base, c_eq_field=field.reshape(-1)))
+    o.step(60000)
+    c = o.fields()["c"].reshape(ny, nx)[1:ny - 1, 0]
+    D = (tau - 0.5) / 3.0          # c_s^2 = 1/3 on D2Q9 and on the standard D2Q5
+    n = ny - 2
+    slope = (b - a) / (n - 1 + 2 * D / k_r)
+    exact = a + D * slope / k_r + slope * np.arange(n)
+    assert np.abs(c - exact).max() < 1e-11
+
+
 def test_gradient_normals_of_straight_walls():
     """Without given normals the oracle uses the isotropic lattice gradient of
     the solid indicator.  On a straight wall that gradient is exactly normal to
