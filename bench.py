@@ -31,10 +31,10 @@ HBM_PEAK_GBS = 8000.0
 CSRC = os.path.join(ROOT, "paper_2306_10794_amd", "csrc")
 # sources that determine the step kernel's code
 KERNEL_SRCS = [os.path.join(CSRC, f) for f in ("lbm_step.hip", "lbm_device.hpp", "lbm_internal.hpp")]
-STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4, false, false, false>"
+STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4, false, false, false, false>"
 PHI_KERNEL = "lbm::k_phi_solid<lbm::D3Q19, float, false>"
 # the same workload with the solute on D3Q7
-RED_STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4, false, true, false>"
+RED_STEP_KERNEL = "lbm::k_step<lbm::D3Q19, float, 4, false, true, false, false>"
 RED_PHI_KERNEL = "lbm::k_phi_solid<lbm::D3Q19, float, true>"
 COPY_KERNEL = "neg_kernel"   # torch elementwise negation: one read, one write per element
 # the rocprofv3 runs whose summaries are committed (run from the repository
