@@ -49,6 +49,11 @@ PROFILE_CMDS = {
     "fetch": f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch -o run -- python3 bench.py {PMC_ARGS}",
     "write": f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/write -o run -- python3 bench.py {PMC_ARGS}",
     "summary": "python3 bench.py --summarize-profiles gpurun_out/prof",
+    # every leg of the default run, for the per-kernel durations of the batch,
+    # adjoint, phase-change and reduced-solute legs
+    "legs": "rocprofv3 --kernel-trace --stats -d gpurun_out/prof/legs -o run -- "
+            "python3 bench.py --steps 50 --warmup 5 --no-cpu-baseline --batch-steps 200 "
+            "--adjoint-steps 400 --phase-change-steps 100 --reduced-steps 50",
 }
 
 
@@ -364,6 +369,31 @@ def summarize_profiles(prof_dir, workload="spheres256", calib_mib=1024):
     print(json.dumps(rec), flush=True)
 
 
+def summarize_legs(prof_dir):
+    """Per-kernel durations of the run PROFILE_CMDS['legs'] (its trace under
+    prof_dir/legs), written to prof_dir/summary/kernels_all_legs_trace.md."""
+    out_dir = os.path.join(prof_dir, "summary")
+    os.makedirs(out_dir, exist_ok=True)
+    tr = _db(os.path.join(prof_dir, "legs"))
+    rows = tr.execute("select name, count(*), avg(end - start), min(end - start), max(end - start), "
+                      "sum(end - start) from kernels group by name order by sum(end - start) desc"
+                      ).fetchall()
+    total = sum(r[5] for r in rows) or 1
+    lines = ["# Kernel durations, every leg of bench.py (rocprofv3 --kernel-trace --stats)", "",
+             "Legs: the 256^3 sphere packing (D3Q19 and D3Q7 solute), the 1024-domain batch, the",
+             "phase-change burst and the 128^3 adjoint (record + adjoint).", "",
+             "Command (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
+             f"    {PROFILE_CMDS['legs']}", "",
+             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+    for name, n, avg, mn, mx, tot in rows[:30]:
+        short = name.split("(")[0].replace("void ", "")
+        lines.append(f"| `{short}` | {n} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
+                     f"{100.0 * tot / total:.1f} |")
+    path = os.path.join(out_dir, "kernels_all_legs_trace.md")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print(path, flush=True)
+
+
 def calibration_copies(mib):
     """Three copy-like passes of a known size (counter calibration): an
     elementwise negation reads and writes every element once."""
@@ -404,9 +434,14 @@ def main():
                     help="after the measurement, copy this many MiB three times (counter calibration)")
     ap.add_argument("--summarize-profiles", metavar="DIR",
                     help="summarise rocprofv3 runs under DIR/{trace,fetch,write} and exit")
+    ap.add_argument("--summarize-legs", metavar="DIR",
+                    help="summarise the all-legs kernel trace under DIR/legs and exit")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
+        return
+    if args.summarize_legs:
+        summarize_legs(args.summarize_legs)
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
