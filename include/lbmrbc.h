@@ -221,7 +221,8 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms);
 /* Launch configuration of the step (a performance choice only: every
  * configuration gives bit-identical populations and solid fractions).
  *   wg_waves    tasks (wavefronts of up to 64 fluid nodes) per workgroup:
- *               1, 2, 4 or 8 (default 4)
+ *               1, 2, 4 or 8 (default 4); contexts with fluid_open or
+ *               ceq_field always run 4 (the autotuner tries no other)
  *   xcd_remap   1: consecutive tiles of tasks run on one XCD, so that the rows
  *               they share stay in one L2 (default 1); 0: plain order
  *   graph_steps 0: lbm_step issues two kernel launches per step (default);

@@ -746,8 +746,11 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
     lbm_launch_config bc = keep;
     double bms = 1e300;
     const int waves[4] = {1, 2, 4, 8};
+    // an open channel or a per-node C_eq always runs the 4-wave tile
+    const bool fixed_tile = c->p.fluid_open != 0 || c->lceq != nullptr;
     for (int wi = 0; wi < 4 && e == hipSuccess; wi++)
         for (int rm = 0; rm < 2 && e == hipSuccess; rm++) {
+            if (fixed_tile && waves[wi] != 4) continue;
             lbm_launch_config g = {waves[wi], rm, 0, 0};
             double ms = 0.0;
             e = trial(g, 2, trial_steps, &ms);

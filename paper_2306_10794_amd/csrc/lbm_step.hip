@@ -3,7 +3,7 @@
 // One time step is two launches on the context stream:
 //   k_step       one wavefront per task (up to 64 consecutive fluid nodes of
 //                one x-row).  Fluid: pull-stream with halfway bounce-back,
-//                moments, Guo-forced BGK.  Solute: pull-stream, inlet/outlet
+//                moments, Guo-forced BGK or TRT.  Solute: pull-stream, inlet/outlet
 //                planes, the general reactive boundary condition on every link
 //                that enters from a solid node, advection-diffusion BGK with
 //                the rest-fraction weights (on the fluid's velocity set, or on
@@ -14,6 +14,11 @@
 //                then lane): their betas are fetched into LDS in one pass
 //                ahead of the loads, each link's q replaces its beta there,
 //                and the range is stored in one pass.
+//                Compile-time variants: TRT collision, the reduced solute set
+//                (RED), the open channel's inflow/outflow faces (OPEN) and a
+//                per-node C_eq read per link (CEQ); the rarely used ones only
+//                at four waves per workgroup, so that the common kernel keeps
+//                its registers.
 //
 // The neighbour classification is written out here rather than taken from
 // classify() (lbm_task.hpp, used by the adjoint kernels): the compiler
@@ -34,8 +39,8 @@ namespace lbm {
 
 // WV wavefronts (tasks) per workgroup; remap != 0 keeps runs of consecutive
 // tiles on one XCD.  FP32 storage asks for 4 waves per SIMD (at most 128
-// VGPRs, a few spilled): the extra wave hides more memory latency than the
-// spills cost (256^3 sphere packing: 732 -> 660 us).
+// VGPRs): the extra wave hides more memory latency than a spill would cost
+// (256^3 sphere packing: 732 -> 660 us when it was first tried).
 template <class L, typename T, int WV, bool TRT, bool RED, bool OPEN, bool CEQ>
 __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepArgs<T> a, long nblocks,
                                                                          int remap) {
