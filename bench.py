@@ -82,9 +82,10 @@ def kernel_sha256():
     return h.hexdigest()
 
 
-def traffic_from_profile(workload):
+def traffic_from_profile(workload, key="bytes_per_launch"):
     """HBM bytes per launch from committed rocprofv3 counter summaries, if they
-    were taken on the current kernel source."""
+    were taken on the current kernel source (key: bytes_per_launch for the
+    step kernel, reduced_bytes_per_launch for its D3Q7-solute variant)."""
     path = os.path.join(ROOT, "profiles", f"k_step_{workload}_pmc.json")
     if not os.path.exists(path):
         return None
@@ -92,7 +93,7 @@ def traffic_from_profile(workload):
         rec = json.load(open(path))
         if rec.get("kernel_sha256") != kernel_sha256():
             return None
-        return rec.get("bytes_per_launch")
+        return rec.get(key)
     except Exception:
         return None
 
@@ -269,6 +270,7 @@ def reduced_run(case, steps, warmup):
             "steps": steps, "reactive_links": int(d["n_links"]), "bytes_per_launch": int(kb),
             "avg_kernel_us": round(k_s * 1e6, 2), "phi_kernel_us": round(phi_ms / steps * 1e3, 2),
             "achieved_gbs": round(kb / k_s / 1e9, 1), "frac": round(kb / k_s / 1e9 / HBM_PEAK_GBS, 4),
+            "traffic": traffic_from_profile("spheres256", "reduced_bytes_per_launch"),
             "status": d["status"]}
 
 
@@ -364,6 +366,8 @@ def summarize_profiles(prof_dir, workload="spheres256", calib_mib=1024):
                          f"{rb + wb:.4g} |")
             if k == STEP_KERNEL:
                 rec.update(read_bytes=rb, write_bytes=wb, bytes_per_launch=rb + wb)
+            if k == RED_STEP_KERNEL:
+                rec.update(reduced_bytes_per_launch=rb + wb)
     open(os.path.join(out_dir, f"k_step_{workload}_pmc.md"), "w").write("\n".join(lines) + "\n")
     json.dump(rec, open(os.path.join(out_dir, f"k_step_{workload}_pmc.json"), "w"), indent=1)
     print(json.dumps(rec), flush=True)
