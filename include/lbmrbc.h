@@ -193,9 +193,12 @@ lbm_status lbm_batch_offsets(const lbm_ctx *ctx, int64_t *node_off);
 /* Per-node equilibrium concentration of the reaction (contexts created with
  * ceq_field = 1; EINVAL otherwise): c_eq [N] FP64 device, the value at each
  * solid node is the C_eq of eq. general_RBC on that node's reactive links
- * (fluid entries are ignored).  Copied into the workspace; takes effect at the
- * next lbm_set_geometry (call it first) and in every relink after phase
- * change.  Until it is called, params.c_eq holds everywhere.  Not with
+ * (fluid entries are ignored).  Copied into the workspace by an asynchronous
+ * copy on the context stream (c_eq must stay valid until the stream reaches
+ * it; lbm_set_geometry, which synchronises, is the next call in the usual
+ * order); takes effect at the next lbm_set_geometry (call it first) and in
+ * every relink after phase change.  Until it is called, params.c_eq holds
+ * everywhere.  The per-node field is not part of a saved state.  Not with
  * lbm_record / lbm_adjoint. */
 lbm_status lbm_set_ceq(lbm_ctx *ctx, const double *c_eq);
 
