@@ -97,3 +97,41 @@ def test_tilted_sweep_orientation_full_size():
         log(f"[fullsize] {ct.name}: uptake per wall length {ft:.6e} (30 deg) {fa:.6e} (0 deg) "
             f"rel {rel:.2e}")
     assert worst <= 0.01
+
+
+def test_sphere_packing_256_full_length():
+    """The 256^3 precipitation workload over its full 10,000 steps with the
+    phase-change thresholds on, in the launch configuration bench.py times:
+    the state stays finite and C within a band around [C_eq, C_in] (the
+    advection-diffusion lattice is not monotone: at D = nu/1000 the grid
+    Peclet number is about 60 and fronts overshoot by up to ~10 %, measured
+    C in [0.83, 2.18] with C_eq = 1, C_in = 2), and every change of the
+    solid fraction is the mass that crossed the reactive links (Sec. 2.4:
+    sum(phi) - sum(phi_0) = -V_m a_m * (total exchange into the fluid)) as
+    long as no event has moved mass between the phases."""
+    import torch
+    from paper_2306_10794_amd import Simulation
+    case = configs.sphere_precipitation(n=256, seed=3, phase_change=1)
+    assert case.steps == 10000
+    sim = Simulation(case, precision=FP32)
+    d0 = sim.diag()
+    done, chunk = 0, 2000
+    while done < case.steps:
+        sim.step(chunk)
+        done += chunk
+        d = sim.diag()
+        log(f"[fullsize] {case.name} step {done}: events {d['n_events']} status {d['status']} "
+            f"wall exchange {d['wall_exchange']:.6e} phi sum {d['phi_sum']:.9e}")
+        assert d["status"] == 0 and d["nan_flag"] == 0
+    c = sim.fields()["c"]
+    fl = torch.from_numpy(case.solid_flat() == 0).to(c.device)
+    cmin, cmax = float(c[fl].min()), float(c[fl].max())
+    sim.close()
+    torch.cuda.synchronize()
+    log(f"[fullsize] C in [{cmin:.6f}, {cmax:.6f}]")
+    assert 0.0 < cmin and cmax < 1.25 * case.c_in
+    if d["n_events"] == 0:
+        dphi = d["phi_sum"] - d0["phi_sum"]
+        expect = -case.v_m * case.a_m * (d["wall_exchange"] - d0["wall_exchange"])
+        log(f"[fullsize] phi change {dphi:.9e} expected {expect:.9e}")
+        assert abs(dphi - expect) <= 1e-9 * abs(expect) + 1e-6
