@@ -274,17 +274,49 @@ def reduced_run(case, steps, warmup):
             "status": d["status"]}
 
 
-def cpu_baseline(case, steps):
+def _oracle_rate(case, steps, threads=None):
     import oracle
-    o = oracle.Oracle(case)
-    o.step(1)
-    t0 = time.perf_counter()
-    o.step(steps)
-    dt = time.perf_counter() - t0
-    return dict(value=case.n_fluid * steps / dt / 1e6, unit="MLUPS", cores=oracle.threads(),
-                kind="oracle",
-                sample=f"full {case.nx}x{case.ny}x{case.nz} workload, FP64, {steps} steps after "
-                       f"1 warm-up step ({dt:.1f} s)")
+    n_all = oracle.threads() if threads is None else None
+    if threads is not None:
+        oracle.set_threads(threads)
+    try:
+        o = oracle.Oracle(case)
+        o.step(1)
+        t0 = time.perf_counter()
+        o.step(steps)
+        dt = time.perf_counter() - t0
+    finally:
+        if threads is not None:
+            oracle.set_threads(_ORACLE_ALL_THREADS)
+    return case.n_fluid * steps / dt / 1e6, dt, (threads or n_all)
+
+
+_ORACLE_ALL_THREADS = 0
+
+
+def cpu_baseline(case, steps):
+    """The oracle timed on this host: all cores on the full workload (the
+    reported value), one core on the same recipe at 128^3, and all / one core
+    on the 512^2 tilted channel."""
+    global _ORACLE_ALL_THREADS
+    import oracle
+    from lbm_inputs import configs
+    _ORACLE_ALL_THREADS = oracle.threads()
+    v, dt, cores = _oracle_rate(case, steps)
+    out = dict(value=v, unit="MLUPS", cores=cores, kind="oracle",
+               sample=f"full {case.nx}x{case.ny}x{case.nz} workload, FP64, {steps} steps after "
+                      f"1 warm-up step ({dt:.1f} s)")
+    small = configs.sphere_precipitation(n=128, seed=3, phase_change=0)
+    v1, dt1, _ = _oracle_rate(small, 1, threads=1)
+    out["single_thread"] = dict(value=v1, unit="MLUPS", cores=1,
+                                sample=f"the same recipe at 128^3, 1 step after 1 warm-up step ({dt1:.1f} s)")
+    tc = configs.tilted_channel(pe=10.0, da=1.0, steps=0)
+    v2, dt2, c2 = _oracle_rate(tc, 20)
+    v3, dt3, _ = _oracle_rate(tc, 5, threads=1)
+    out["tilted_512"] = dict(all_cores=v2, cores=c2, single_thread=v3, unit="MLUPS",
+                             sample=f"512^2 tilted channel D2Q9 + D2Q9, 20 steps ({dt2:.1f} s) and "
+                                    f"5 steps on one core ({dt3:.1f} s)")
+    return out
 
 
 def _db(d):

@@ -64,6 +64,7 @@ def _load():
         lib.orc_adjoint.restype = C.c_int
         lib.orc_adjoint.argtypes = [P, C.c_int, P, P, P]
         lib.orc_threads.restype = C.c_int
+        lib.orc_set_threads.argtypes = [C.c_int]
         lib.orc_set_ceq.argtypes = [P, P]
         lib.orc_get_solute_set.restype = C.c_int
         lib.orc_get_solute_set.argtypes = [P, P]
@@ -77,6 +78,11 @@ def _ptr(a):
 
 def threads() -> int:
     return int(_load().orc_threads())
+
+
+def set_threads(n: int):
+    """Threads of the oracle's node loop from now on (CPU-baseline timing)."""
+    _load().orc_set_threads(int(n))
 
 
 class Oracle:

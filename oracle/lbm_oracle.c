@@ -962,6 +962,16 @@ void orc_diag(const orc *o, double *d)
     d[6] = (double)o->n_events;
 }
 
+/* threads of the node loop (timing of the CPU baseline) */
+void orc_set_threads(int n)
+{
+#ifdef _OPENMP
+    if (n > 0) omp_set_num_threads(n);
+#else
+    (void)n;
+#endif
+}
+
 int orc_threads(void)
 {
 #ifdef _OPENMP

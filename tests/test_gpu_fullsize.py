@@ -135,3 +135,44 @@ def test_sphere_packing_256_full_length():
         expect = -case.v_m * case.a_m * (d["wall_exchange"] - d0["wall_exchange"])
         log(f"[fullsize] phi change {dphi:.9e} expected {expect:.9e}")
         assert abs(dphi - expect) <= 1e-9 * abs(expect) + 1e-6
+
+
+@pytest.mark.parametrize("precision,tol", [(0, 1e-12), (FP32, 1e-5)])
+def test_spheres32_full_length_against_oracle(precision, tol):
+    """The precipitation workload's recipe at 32^3 over the full 10,000 steps
+    against the FP64 oracle's run (tests/golden/spheres32_10k.npz, written by
+    make_spheres32_10k.py, which calls only the oracle): fields at 256 seeded
+    fluid nodes and the solid fraction at 64 solid interface nodes, to 1e-12
+    (FP64) and 1e-5 (FP32 deviation storage) of their scales, and the FP64
+    sums.  In FP64 the solid fraction is a running sum of 10,000 updates of
+    a value near 1, each rounded to the last bit on either side, so its bound
+    is absolute: 2 eps per step."""
+    import os
+    import torch
+    from paper_2306_10794_amd import Simulation
+    gold = np.load(os.path.join(os.path.dirname(__file__), "golden", "spheres32_10k.npz"))
+    case = configs.sphere_precipitation(n=32, seed=3, r_min=2.0, r_max=4.0, phase_change=0)
+    assert int(gold["steps"]) == case.steps == 10000
+    sim = Simulation(case, precision=precision)
+    sim.step(case.steps)
+    torch.cuda.synchronize()
+    f = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    d = sim.diag()
+    sim.close()
+    idx, sidx = gold["idx"], gold["sidx"]
+    us = max(np.abs(gold["u"]).max(), 3 ** -0.5 if precision == 0 else 0.0)
+    cs = max(np.abs(gold["c"]).max(), case.c_eq)
+    dphi = max(np.abs(gold["phi"]).max(), np.abs(gold["sphi"] - 1.0).max())
+    phi_abs = max(np.abs(f["phi"][idx] - gold["phi"]).max(), np.abs(f["phi"][sidx] - gold["sphi"]).max())
+    if precision == 0:
+        log(f"[fullsize] 32^3 x 10k FP64 phi {phi_abs:.2e} (bound {case.steps * 2 * 2.2e-16:.2e})")
+        assert phi_abs <= case.steps * 2 * 2.2e-16
+    err = dict(rho=np.abs(f["rho"][idx] - gold["rho"]).max(),
+               u=np.abs(f["u"][idx] - gold["u"]).max() / us,
+               c=np.abs(f["c"][idx] - gold["c"]).max() / cs,
+               phi=phi_abs / dphi if precision != 0 else 0.0,
+               mass=abs(d["mass_c"] - float(gold["mass_c"])) / abs(float(gold["mass_c"])),
+               wall=abs(d["wall_exchange"] - float(gold["wall_exchange"])) / abs(float(gold["wall_exchange"])))
+    log(f"[fullsize] 32^3 x 10k precision={precision} errors {err}")
+    for k, v in err.items():
+        assert v <= tol, (k, v)
