@@ -4,7 +4,7 @@ The compute lives in ``liblbmrbc.so`` (hand-written HIP for gfx950) behind the C
 ABI of ``include/lbmrbc.h``; this package is its thin Python binding.
 """
 from . import _lib
-from ._lib import (LbmError, lbm_params, lbm_workspace_bytes, lbm_create, lbm_set_geometry,
+from ._lib import (LbmError, lbm_params, lbm_workspace_bytes, lbm_create, lbm_set_geometry, lbm_set_ceq,
                    lbm_batch_workspace_bytes, lbm_create_batch, lbm_batch_offsets,
                    lbm_init_fields, lbm_step, lbm_step_timed, lbm_set_launch_config,
                    lbm_get_launch_config, lbm_autotune, lbm_adjoint_workspace_bytes,
