@@ -104,6 +104,25 @@ def test_fp32_long_run_steady_channel(dim):
     _assert_parity(case, FP32, 12000)
 
 
+@pytest.mark.parametrize("dim,collision,qs", [(2, 1, 5), (3, 1, 0), (3, 0, 7)])
+def test_fp32_long_run_steady_channel_variants(dim, collision, qs):
+    """The same 12,000-step bias check for the TRT collision and the reduced
+    solute sets (D2Q5 / D3Q7), each a separate kernel instantiation with its
+    own arithmetic."""
+    h = 62
+    nx, ny, nz, q = (4, h + 2, 1, 9) if dim == 2 else (4, h + 2, 4, 19)
+    solid = np.zeros((nz, ny, nx), np.uint8)
+    solid[:, 0, :] = 1
+    solid[:, -1, :] = 1
+    nu = (1.0 - 0.5) / 3.0
+    force = 0.04 * 8.0 * nu / h ** 2
+    case = Case(name=f"long channel {dim}D collision {collision} qs {qs}", dim=dim, nx=nx, ny=ny,
+                nz=nz, q=q, qs=qs, solid=solid, tau_ns=1.0, tau_ad=0.9, j0=0.3,
+                force=(force, 0.0, 0.0), c_eq=1.0, k_r=2e-3, v_m=0.05, c0=0.2, c_ref=0.5,
+                collision=collision)
+    _assert_parity(case, FP32, 12000)
+
+
 @pytest.mark.parametrize("precision", [FP64, FP32])
 def test_spheres_3d_inlet_outlet(precision):
     """3D D3Q19 sphere pack with an inlet and a zero-gradient outlet on z,
