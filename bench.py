@@ -101,7 +101,7 @@ def traffic_from_profile(workload, key="bytes_per_launch"):
 def make_case(workload):
     from lbm_inputs import configs
     if workload == "spheres256":
-        # the event thresholds are not part of this build's timed step
+        # the event thresholds are not part of the timed step (a separate leg times them)
         return configs.sphere_precipitation(n=256, seed=3, phase_change=0)
     if workload == "spheres128":
         return configs.sphere_precipitation(n=128, seed=3, phase_change=0)
