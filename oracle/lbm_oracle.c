@@ -86,6 +86,7 @@ typedef struct {
     int Q;
     int QS;                /* solute directions                           */
     int sd[ORC_QMAX];      /* solute direction s is fluid direction sd[s] */
+    uint8_t ins[ORC_QMAX]; /* fluid direction i belongs to the solute set */
     long N;
     int e[ORC_QMAX][3];
     int opp[ORC_QMAX];
@@ -188,6 +189,8 @@ static void set_lattice(orc *o)
             o->cs2s = (1.0 / 3.0) * sc;
         }
     }
+    for (int i = 0; i < Q; i++) o->ins[i] = 0;
+    for (int s = 0; s < o->QS; s++) o->ins[o->sd[s]] = 1;
     o->gamma = o->p.tau_ad / (o->p.tau_ad - 0.5);
 }
 
@@ -729,8 +732,15 @@ static void adjoint_node(const orc *o, long x, const double *go, const double *u
     int src_d[ORC_QMAX], kd[ORC_QMAX];
     double gp[ORC_QMAX];
     for (int i = 0; i < Q; i++) {
-        long y = site(o, X, Y, Z, -o->e[i][0], -o->e[i][1], -o->e[i][2], 1, &face);
         sol[i] = -1;
+        if (!o->ins[i]) {
+            /* outside the solute set: no population, no link */
+            kd[i] = K_KNOWN;
+            src_n[i] = -1;
+            gp[i] = 0.0;
+            continue;
+        }
+        long y = site(o, X, Y, Z, -o->e[i][0], -o->e[i][1], -o->e[i][2], 1, &face);
         src_n[i] = x;
         src_d[i] = o->opp[i];
         if (y >= 0) {
@@ -793,7 +803,7 @@ static void adjoint_node(const orc *o, long x, const double *go, const double *u
  * velocity, then the adjoint of the loss whose gradient with respect to the
  * final concentrations C_T = sum_i g*_i(T) is dLdC [N].  Writes dL/dk_r into
  * grad [N] (zero away from solid interface nodes) and, if lam0 is not NULL,
- * dL/dg*(0) into lam0 [N][Q].  Leaves the state at step T.  Returns 0, or -1
+ * dL/dg*(0) into lam0 [N][Q] (zero outside the solute set).  Leaves the state at step T.  Returns 0, or -1
  * (out of memory), -2 (phase change enabled). */
 int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *lam0)
 {
@@ -801,7 +811,6 @@ int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *la
     const int Q = o->Q;
     if (o->p.phase_change) return -2;
     if (o->p.collision != ORC_BGK) return -3;   /* the transposed step below is BGK's */
-    if (o->QS != Q) return -4;                  /* ... on the fluid's velocity set */
     if (o->ceq) return -5;                      /* ... with a uniform C_eq */
     double *G = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * Q);
     double *U = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * 3);
@@ -821,7 +830,7 @@ int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *la
     for (long n = 0; n < N; n++) {
         grad[n] = 0.0;
         if (o->solid[n]) continue;
-        for (int i = 0; i < Q; i++) lam[n * Q + i] = dLdC[n];
+        for (int i = 0; i < Q; i++) lam[n * Q + i] = o->ins[i] ? dLdC[n] : 0.0;
     }
     for (int t = nsteps - 1; t >= 0; t--) {
         memset(lnew, 0, sizeof(double) * N * Q);

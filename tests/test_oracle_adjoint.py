@@ -77,6 +77,9 @@ CASES = [
     ("disks R2 anti-BB", lambda: _disk_case(MECH_POST, SCHEME_ABB)),
     ("spheres inlet/outlet", lambda: _sphere_case(inlet=True)),
     ("spheres walls", lambda: _sphere_case(inlet=False, walls=True)),
+    ("disks D2Q5 R1 S.New flow", lambda: _disk_case(MECH_PRE, SCHEME_SNEW).replace(qs=5)),
+    ("disks D2Q5 R2 S.P.J.", lambda: _disk_case(MECH_POST, SCHEME_SPJ, flow=False).replace(qs=5)),
+    ("spheres D3Q7 inlet/outlet", lambda: _sphere_case(inlet=True).replace(qs=7)),
 ]
 
 
@@ -87,9 +90,13 @@ def test_adjoint_is_the_transpose_of_the_step(name, make):
     rng = np.random.default_rng(1)
     fl = case.solid_flat() == 0
     w = np.where(fl, rng.normal(size=case.n), 0.0)
-    v = np.where(fl[None, :], rng.normal(size=(case.q, case.n)), 0.0) * 1e-2
     base = Oracle(case)
+    qs = base.QS
+    v = np.where(fl[None, :], rng.normal(size=(qs, case.n)), 0.0) * 1e-2
     _, lam0 = base.adjoint(steps, w, want_lam0=True)
+    # lambda_0 by fluid direction; the solute set's rows carry the populations
+    assert np.all(np.delete(lam0, base.sdirs, axis=0) == 0.0)
+    lam0 = lam0[base.sdirs]
     c_base = base.fields()["c"]
     pert = Oracle(case)
     f0, g0 = pert.pops()

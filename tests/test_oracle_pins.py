@@ -457,15 +457,11 @@ def test_reduced_solute_plus_solid_mass_invariant(q, qs):
 
 
 def test_reduced_refusals():
-    """The oracle takes D2Q5 only with D2Q9 and D3Q7 only with D3Q19, and the
-    hand-written adjoint transposes the full-lattice step only."""
+    """The oracle takes D2Q5 only with D2Q9 and D3Q7 only with D3Q19."""
     with pytest.raises(ValueError):
         Oracle(_small_case(qs=7))
     with pytest.raises(ValueError):
         Oracle(_box3(qs=5))
-    o = Oracle(_small_case(qs=5, k_r=0.01))
-    with pytest.raises(RuntimeError):
-        o.adjoint(2, np.zeros(o.N))
 
 
 # --------------------------------------------------------------------------
