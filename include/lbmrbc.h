@@ -93,8 +93,7 @@ typedef struct {
                                  +x, +y, +z, -x, -y, -z.  On these sets w_0 = J0,
                                  w_i = c_s^2/2, c_s^2 = (1 - J0)/dim (J0 = 1/3
                                  resp. 1/4 when j0 < 0), and reactive links exist
-                                 along their directions only.  Not with
-                                 lbm_record / lbm_adjoint.                    */
+                                 along their directions only.                   */
     int32_t precision;        /* LBM_FP64 | LBM_FP32_DEV                           */
     int32_t rbc_mechanics;    /* LBM_PRECOLL | LBM_POSTCOLL                        */
     int32_t rbc_scheme;       /* LBM_SNEW | LBM_SV | LBM_SPJ | LBM_ABB             */
@@ -268,8 +267,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
  * every reactive link through eqs. k_i_S_Ve, k_i_S2, k_i_S_New and
  * eq. general_RBC).  The fluid does not depend on k_r; the adjoint covers a
  * fluid at rest (pure reaction-diffusion): single-lattice contexts with no
- * body force, inlet_axis = -1, phase_change = 0, collision = LBM_BGK and
- * solute_q = fluid_q (EINVAL otherwise, and
+ * body force, inlet_axis = -1, phase_change = 0, collision = LBM_BGK and a
+ * uniform c_eq (EINVAL otherwise, and
  * lbm_record checks that no fluid node carries momentum).
  *
  * lbm_adjoint_workspace_bytes: device bytes that lbm_record needs for nsteps

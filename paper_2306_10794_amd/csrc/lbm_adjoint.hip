@@ -88,19 +88,23 @@ __device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c
 // One solute step with the fluid at rest, from gin to gout: the arithmetic of
 // the fused step's solute half with u = 0 (no exchange or solid fraction is
 // written).
-template <class L, typename T>
+template <class L, typename T, bool RED>
 __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     using R = double;
     constexpr int Q = L::Q;
+    constexpr uint32_t SM = sol_mask<L, RED>();   // the solute set (D2Q5 / D3Q7 when RED)
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c) || !c.active) return;
     const DomDev &D = c.D;
     const long S = a.S;
-    const uint32_t rbc = c.solidnb;
+    const uint32_t rbc = c.solidnb & SM;
     T gv[Q];
 #pragma unroll
-    for (int i = 0; i < Q; i++)
-        gv[i] = c.kk[i] >= 0 ? a.gin[(long)i * S + c.kk[i]] : a.gin[(long)L::opp[i] * S + c.k];
+    for (int i = 0; i < Q; i++) {
+        if (!((SM >> i) & 1u)) continue;
+        gv[i] = c.kk[i] >= 0 ? a.gin[(long)sol_slot(SM, i) * S + c.kk[i]]
+                             : a.gin[(long)sol_slot(SM, L::opp[i]) * S + c.k];
+    }
     // link index: the task's base (lbase of its first node, lane 0, which is
     // active), then by direction, then by lane
     const int lt = __builtin_amdgcn_readfirstlane(c.lb);
@@ -110,6 +114,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
         int loff = lt;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
+            if (!((SM >> i) & 1u)) continue;
             const unsigned long long bal = __ballot((rbc >> i) & 1u);
             const int l = loff + __popcll(bal & below);
             loff += __popcll(bal);
@@ -124,47 +129,54 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     }
     R dC = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; i++) dC += (R)gv[i];
+    for (int i = 0; i < Q; i++)
+        if ((SM >> i) & 1u) dC += (R)gv[i];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
+        if (!((SM >> i) & 1u)) continue;
         const R gi = (R)gv[i];
         const R geq = sol_w<L>(D, i) * dC;
-        a.gout[(long)i * S + c.k] = (T)(gi + D.omega_g * (geq - gi));
+        a.gout[(long)sol_slot(SM, i) * S + c.k] = (T)(gi + D.omega_g * (geq - gi));
     }
 }
 
 // lambda(T)_i(x) = dL/dC_T(x) for every i, written in the P layout
-template <class L, typename T>
+template <class L, typename T, bool RED>
 __global__ __launch_bounds__(BLK) void k_adj_init(AdjArgs<T> a) {
     constexpr int Q = L::Q;
+    constexpr uint32_t SM = sol_mask<L, RED>();
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c) || !c.active) return;
     const long S = a.S;
     const double own = a.dldc[c.n];
 #pragma unroll
     for (int j = 0; j < Q; j++)
-        a.pout[(long)j * S + c.k] = (T)(c.kk[j] >= 0 ? a.dldc[a.nodeof[c.kk[j]]] : own);
+        if ((SM >> j) & 1u)
+            a.pout[(long)sol_slot(SM, j) * S + c.k] = (T)(c.kk[j] >= 0 ? a.dldc[a.nodeof[c.kk[j]]] : own);
 }
 
-template <class L, typename T>
+template <class L, typename T, bool RED>
 __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     using R = double;
     constexpr int Q = L::Q;
+    constexpr uint32_t SM = sol_mask<L, RED>();
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c) || !c.active) return;
     const DomDev &D = c.D;
     const long S = a.S;
-    const uint32_t rbc = c.solidnb;
+    const uint32_t rbc = c.solidnb & SM;
     // lambda(t+1) at this node: the forward pull with directions reversed
     T mu[Q];
 #pragma unroll
     for (int d = 0; d < Q; d++) {
+        if (!((SM >> d) & 1u)) continue;
         const int kd = c.kk[L::opp[d]];
-        mu[d] = kd >= 0 ? a.pin[(long)d * S + kd] : a.pin[(long)L::opp[d] * S + c.k];
+        mu[d] = kd >= 0 ? a.pin[(long)sol_slot(SM, d) * S + kd] : a.pin[(long)sol_slot(SM, L::opp[d]) * S + c.k];
     }
     R m = R(0);
 #pragma unroll
-    for (int i = 0; i < Q; i++) m += sol_w<L>(D, i) * (R)mu[i];
+    for (int i = 0; i < Q; i++)
+        if ((SM >> i) & 1u) m += sol_w<L>(D, i) * (R)mu[i];
     const R om = D.omega_g, om1 = R(1) - om;
     a.pout[c.k] = (T)(om1 * (R)mu[0] + om * m);
     // link index: the task's base (lbase of its first node, lane 0, which is
@@ -177,6 +189,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
         int off = lt;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
+            if (!((SM >> i) & 1u)) continue;
             const unsigned long long bal = __ballot((rbc >> i) & 1u);
             lpos[i] = off + __popcll(bal & below);
             off += __popcll(bal);
@@ -189,8 +202,9 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     // its dL/dbeta.
 #pragma unroll
     for (int i = 1; i < Q; i++) {
-        if (L::opp[i] < i) continue;
+        if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
         const int o = L::opp[i];
+        const long si = (long)sol_slot(SM, i) * S, so = (long)sol_slot(SM, o) * S;
         const R nui = om1 * (R)mu[i] + om * m, nuo = om1 * (R)mu[o] + om * m;
         R outi = nui, outo = nuo;
         const bool li = (rbc >> i) & 1u, lo = (rbc >> o) & 1u;
@@ -198,8 +212,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const int l = lpos[i];
             const R beta = (R)a.lbeta[l];
             const bool pulled = D.mech == LBM_PRECOLL && !lo;
-            const R src = pulled ? (R)(c.kk[o] >= 0 ? a.gin[(long)o * S + c.kk[o]] : a.gin[(long)i * S + c.k])
-                                 : (R)a.gin[(long)o * S + c.k];
+            const R src = pulled ? (R)(c.kk[o] >= 0 ? a.gin[so + c.kk[o]] : a.gin[si + c.k])
+                                 : (R)a.gin[so + c.k];
             a.gbeta[l] += nui * (src - sol_w<L>(D, i) * D.ceq_dev);
             if (pulled) {
                 outo += beta * nui;
@@ -212,8 +226,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const int l = lpos[o];
             const R beta = (R)a.lbeta[l];
             const bool pulled = D.mech == LBM_PRECOLL && !li;
-            const R src = pulled ? (R)(c.kk[i] >= 0 ? a.gin[(long)i * S + c.kk[i]] : a.gin[(long)o * S + c.k])
-                                 : (R)a.gin[(long)i * S + c.k];
+            const R src = pulled ? (R)(c.kk[i] >= 0 ? a.gin[si + c.kk[i]] : a.gin[so + c.k])
+                                 : (R)a.gin[si + c.k];
             a.gbeta[l] += nuo * (src - sol_w<L>(D, o) * D.ceq_dev);
             if (pulled) {
                 outi += beta * nuo;
@@ -222,8 +236,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
                 outo = beta * nuo;
             }
         }
-        a.pout[(long)i * S + c.k] = (T)outi;
-        a.pout[(long)o * S + c.k] = (T)outo;
+        a.pout[si + c.k] = (T)outi;
+        a.pout[so + c.k] = (T)outo;
     }
 }
 
@@ -321,11 +335,11 @@ static hipError_t rest_check_impl(Ctx &c, bool *at_rest) {
     return e;
 }
 
-template <class L, typename T>
+template <class L, typename T, bool RED>
 static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
     const AdjState &r = c.adj;
     const long nb = (c.n_tasks + BLK / 64 - 1) / (BLK / 64);
-    const size_t slot = (size_t)c.Q * c.S;
+    const size_t slot = (size_t)c.QS * c.S;
     AdjArgs<T> a = adj_args<T>(c);
     T *P[2] = {(T *)r.p[0], (T *)r.p[1]};
     const T *ck = (const T *)r.ckpt;
@@ -335,7 +349,7 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
                        r.gbeta, (long)c.n_links);
     a.dldc = dldc;
     a.pout = P[0];
-    if (nb > 0) hipLaunchKernelGGL((k_adj_init<L, T>), dim3(nb), dim3(BLK), 0, c.stream, a);
+    if (nb > 0) hipLaunchKernelGGL((k_adj_init<L, T, RED>), dim3(nb), dim3(BLK), 0, c.stream, a);
     int cur = 0;
     const int nseg = (int)((r.nsteps + r.ckpt_every - 1) / r.ckpt_every);
     for (int sgi = nseg - 1; sgi >= 0; sgi--) {
@@ -348,13 +362,13 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
         for (int j = 1; j < len; j++) {
             a.gin = state(j - 1);
             a.gout = state(j);
-            if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T, RED>), dim3(nb), dim3(BLK), 0, c.stream, a);
         }
         for (int j = len - 1; j >= 0; j--) {
             a.gin = state(j);
             a.pin = P[cur];
             a.pout = P[1 - cur];
-            if (nb > 0) hipLaunchKernelGGL((k_adj_step<L, T>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            if (nb > 0) hipLaunchKernelGGL((k_adj_step<L, T, RED>), dim3(nb), dim3(BLK), 0, c.stream, a);
             cur = 1 - cur;
         }
         hipError_t e = hipGetLastError();
@@ -373,9 +387,14 @@ hipError_t launch_rest_check(Ctx &c, bool *at_rest) {
     return c.fp64 ? rest_check_impl<D3Q19, double>(c, at_rest) : rest_check_impl<D3Q19, float>(c, at_rest);
 }
 
+template <class L, typename T>
+static hipError_t adjoint_set(Ctx &c, const double *dldc, double *grad) {
+    return c.red ? adjoint_impl<L, T, true>(c, dldc, grad) : adjoint_impl<L, T, false>(c, dldc, grad);
+}
+
 hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad) {
-    if (c.Q == 9) return c.fp64 ? adjoint_impl<D2Q9, double>(c, dldc, grad) : adjoint_impl<D2Q9, float>(c, dldc, grad);
-    return c.fp64 ? adjoint_impl<D3Q19, double>(c, dldc, grad) : adjoint_impl<D3Q19, float>(c, dldc, grad);
+    if (c.Q == 9) return c.fp64 ? adjoint_set<D2Q9, double>(c, dldc, grad) : adjoint_set<D2Q9, float>(c, dldc, grad);
+    return c.fp64 ? adjoint_set<D3Q19, double>(c, dldc, grad) : adjoint_set<D3Q19, float>(c, dldc, grad);
 }
 
 }  // namespace lbm

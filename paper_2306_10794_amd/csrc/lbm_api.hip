@@ -842,7 +842,7 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms) {
 
 static size_t adj_layout(const Ctx *c, int64_t nsteps, int64_t ckpt, AdjState *st, char *base) {
     const size_t ts = c->fp64 ? 8 : 4;
-    const size_t slot = (size_t)c->Q * (size_t)c->S * ts;
+    const size_t slot = (size_t)c->QS * (size_t)c->S * ts;
     const size_t ncp = (size_t)((nsteps + ckpt - 1) / ckpt);
     size_t off = 0;
     auto take = [&](size_t n) -> char * {
@@ -883,10 +883,6 @@ static lbm_status adj_check(Ctx *c, int32_t nsteps, int32_t ckpt) {
     }
     if (c->p.collision != LBM_BGK) {
         c->err = "the adjoint transposes the BGK step (collision = LBM_BGK)";
-        return LBM_EINVAL;
-    }
-    if (c->red) {
-        c->err = "the adjoint transposes the step with the solute on the fluid's velocity set";
         return LBM_EINVAL;
     }
     if (c->ceq) {
@@ -935,7 +931,7 @@ lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *de
     }
     c->adj.valid = false;
     adj_layout(c, nsteps, ckpt_every, &c->adj, (char *)dev_workspace);
-    const size_t slot = (size_t)c->Q * (size_t)c->S * (c->fp64 ? 8 : 4);
+    const size_t slot = (size_t)c->QS * (size_t)c->S * (c->fp64 ? 8 : 4);
     for (int32_t t = 0; t < nsteps; t += ckpt_every) {
         e = hipMemcpyAsync((char *)c->adj.ckpt + (size_t)(t / ckpt_every) * slot, c->g[c->cur], slot,
                            hipMemcpyDeviceToDevice, c->stream);

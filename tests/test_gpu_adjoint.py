@@ -68,12 +68,17 @@ def _oracle_grad(case, steps, target):
 
 @pytest.mark.parametrize("precision,name", [(FP64, "spheres32"), (FP32, "spheres32"),
                                             (FP64, "disks R2 S.V."), (FP64, "disks R1 S.P.J."),
-                                            (FP32, "disks R1 S.New")])
+                                            (FP32, "disks R1 S.New"), (FP64, "spheres32 D3Q7"),
+                                            (FP32, "spheres32 D3Q7"), (FP64, "disks D2Q5 R1 S.New"),
+                                            (FP64, "disks D2Q5 R2 S.V.")])
 def test_adjoint_matches_oracle(precision, name):
     case = {"spheres32": lambda: _spheres32(),
             "disks R2 S.V.": lambda: _disks(MECH_POST, SCHEME_SV),
             "disks R1 S.P.J.": lambda: _disks(MECH_PRE, SCHEME_SPJ),
-            "disks R1 S.New": lambda: _disks(MECH_PRE, SCHEME_SNEW)}[name]()
+            "disks R1 S.New": lambda: _disks(MECH_PRE, SCHEME_SNEW),
+            "spheres32 D3Q7": lambda: _spheres32().replace(qs=7),
+            "disks D2Q5 R1 S.New": lambda: _disks(MECH_PRE, SCHEME_SNEW).replace(qs=5),
+            "disks D2Q5 R2 S.V.": lambda: _disks(MECH_POST, SCHEME_SV).replace(qs=5)}[name]()
     steps, ckpt = 100, 30     # segments 30, 30, 30, 10
     target = _target(case)
     log(f"[adjoint] {name} precision={precision} shape=({case.nx},{case.ny},{case.nz}) "
