@@ -764,15 +764,22 @@ static void adjoint_node(const orc *o, long x, const double *go, const double *u
         else if (kd[i] == K_RBC) gp[i] = 0.0;
         else gp[i] = go[src_n[i] * Q + src_d[i]];
     }
-    /* collision g*_i = (1 - 1/tau) p_i + (1/tau) w_i C (1 + e_i.u/c_s^2),
-     * C = sum_j p_j: its transpose */
+    /* collision, BGK: g*_i = (1 - 1/tau) p_i + (1/tau) w_i C (1 + e_i.u/c_s^2),
+     * C = sum_j p_j.  TRT (Sec. 2.1, eqs. solute_TRT, solute_TRT_terms) with
+     * the even rate we = 1/tau- and the odd rate wo = 1/tau_AD:
+     *   g*_i = (1 - (we + wo)/2) p_i + ((wo - we)/2) p_opp(i)
+     *          + w_i C (we + wo e_i.u/c_s^2),
+     * which is the BGK form when we = wo.  Its transpose: */
+    double we = 1.0 / p->tau_ad, wo = 1.0 / p->tau_ad;
+    if (p->collision == ORC_TRT) we = 1.0 / (0.5 + ORC_MAGIC / (p->tau_ad - 0.5));
     double m = 0.0;
     for (int i = 0; i < Q; i++) {
         double eu = o->e[i][0] * u[0] + o->e[i][1] * u[1] + o->e[i][2] * u[2];
-        m += mu[i] * o->ws[i] * (1.0 + eu / o->cs2s);
+        m += mu[i] * o->ws[i] * (we + wo * eu / o->cs2s);
     }
     double nu[ORC_QMAX];
-    for (int i = 0; i < Q; i++) nu[i] = (1.0 - 1.0 / p->tau_ad) * mu[i] + m / p->tau_ad;
+    for (int i = 0; i < Q; i++)
+        nu[i] = (1.0 - 0.5 * (we + wo)) * mu[i] + 0.5 * (wo - we) * mu[o->opp[i]] + m;
     /* reactive links: p_i = k/(1+k) 2 w_i C_eq + (1-k)/(1+k) src */
     for (int i = 0; i < Q; i++) {
         if (kd[i] != K_RBC) continue;
@@ -810,7 +817,6 @@ int orc_adjoint(orc *o, int nsteps, const double *dLdC, double *grad, double *la
     const long N = o->N;
     const int Q = o->Q;
     if (o->p.phase_change) return -2;
-    if (o->p.collision != ORC_BGK) return -3;   /* the transposed step below is BGK's */
     if (o->ceq) return -5;                      /* ... with a uniform C_eq */
     double *G = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * Q);
     double *U = (double *)malloc(sizeof(double) * (size_t)(nsteps > 0 ? nsteps : 1) * N * 3);

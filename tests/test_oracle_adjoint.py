@@ -80,6 +80,9 @@ CASES = [
     ("disks D2Q5 R1 S.New flow", lambda: _disk_case(MECH_PRE, SCHEME_SNEW).replace(qs=5)),
     ("disks D2Q5 R2 S.P.J.", lambda: _disk_case(MECH_POST, SCHEME_SPJ, flow=False).replace(qs=5)),
     ("spheres D3Q7 inlet/outlet", lambda: _sphere_case(inlet=True).replace(qs=7)),
+    ("disks TRT R1 S.New flow", lambda: _disk_case(MECH_PRE, SCHEME_SNEW).replace(collision=1, tau_ad=1.3)),
+    ("disks TRT D2Q5 R2 S.V.", lambda: _disk_case(MECH_POST, SCHEME_SV).replace(collision=1, qs=5)),
+    ("spheres TRT inlet/outlet", lambda: _sphere_case(inlet=True).replace(collision=1)),
 ]
 
 

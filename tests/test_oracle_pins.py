@@ -242,13 +242,6 @@ def test_trt_diffusion_from_the_odd_rate(tau):
     assert amp / 0.1 == pytest.approx(math.exp(-D * k * k * steps), rel=2e-3)
 
 
-def test_trt_adjoint_is_refused():
-    """The hand-written adjoint transposes the BGK step only."""
-    o = Oracle(_small_case(collision=COLL_TRT, k_r=0.01))
-    with pytest.raises(RuntimeError):
-        o.adjoint(2, np.zeros(o.N))
-
-
 # --------------------------------------------------------------------------
 # reduced solute lattices D2Q5 / D3Q7 (the paper's solute lattices)
 # --------------------------------------------------------------------------
