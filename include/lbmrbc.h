@@ -72,8 +72,8 @@ typedef enum {
                             (Sec. 2.1, eqs. fluid_TRT, solute_TRT): fluid even
                             parts relax with tau_ns, odd parts with tau-; the
                             solute's odd parts with tau_ad, even parts with
-                            tau-; the Guo force term is split the same way.
-                            Not with lbm_record / lbm_adjoint.               */
+                            tau-; the Guo force term is split the same way
+                            (the adjoint transposes either operator).      */
 
 /* k_i of the reactive boundary condition */
 #define LBM_SNEW 0       /* c_s^-2 gamma k_r (e.n)   -- the paper's new scheme  */
@@ -267,8 +267,8 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
  * every reactive link through eqs. k_i_S_Ve, k_i_S2, k_i_S_New and
  * eq. general_RBC).  The fluid does not depend on k_r; the adjoint covers a
  * fluid at rest (pure reaction-diffusion): single-lattice contexts with no
- * body force, inlet_axis = -1, phase_change = 0, collision = LBM_BGK and a
- * uniform c_eq (EINVAL otherwise, and
+ * body force, inlet_axis = -1, phase_change = 0 and a uniform c_eq (EINVAL
+ * otherwise, and
  * lbm_record checks that no fluid node carries momentum).
  *
  * lbm_adjoint_workspace_bytes: device bytes that lbm_record needs for nsteps

@@ -131,6 +131,23 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < Q; i++)
         if ((SM >> i) & 1u) dC += (R)gv[i];
+    if (D.trt) {
+        // TRT at rest: even parts relax with omega_gs toward w C, odd parts
+        // with omega_g toward 0 (as the fused step with u = 0)
+        const R oms = D.omega_gs, oma = D.omega_g;
+        a.gout[c.k] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
+            const int o = L::opp[i];
+            const R gi = (R)gv[i], go = (R)gv[o];
+            const R As = oms * sol_w<L>(D, i) * dC;
+            const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * oma * (gi - go);
+            a.gout[(long)sol_slot(SM, i) * S + c.k] = (T)(gi - hs - ha + As);
+            a.gout[(long)sol_slot(SM, o) * S + c.k] = (T)(go - hs + ha + As);
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         if (!((SM >> i) & 1u)) continue;
@@ -177,8 +194,12 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < Q; i++)
         if ((SM >> i) & 1u) m += sol_w<L>(D, i) * (R)mu[i];
-    const R om = D.omega_g, om1 = R(1) - om;
-    a.pout[c.k] = (T)(om1 * (R)mu[0] + om * m);
+    // transposed collision.  BGK: nu_j = (1 - om) mu_j + om m.  TRT (even rate
+    // oms, odd rate om): nu_j = (1 - (oms + om)/2) mu_j + ((om - oms)/2)
+    // mu_opp(j) + oms m, which is BGK's when oms = om
+    const R om = D.omega_g, om1 = R(1) - om, oms = D.omega_gs;
+    const R ta = R(1) - R(0.5) * (oms + om), tb = R(0.5) * (om - oms);
+    a.pout[c.k] = (T)(D.trt ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
     // link index: the task's base (lbase of its first node, lane 0, which is
     // active), then by direction, then by lane
     const int lt = __builtin_amdgcn_readfirstlane(c.lb);
@@ -205,7 +226,11 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
         if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
         const int o = L::opp[i];
         const long si = (long)sol_slot(SM, i) * S, so = (long)sol_slot(SM, o) * S;
-        const R nui = om1 * (R)mu[i] + om * m, nuo = om1 * (R)mu[o] + om * m;
+        R nui = om1 * (R)mu[i] + om * m, nuo = om1 * (R)mu[o] + om * m;
+        if (D.trt) {
+            nui = ta * (R)mu[i] + tb * (R)mu[o] + oms * m;
+            nuo = ta * (R)mu[o] + tb * (R)mu[i] + oms * m;
+        }
         R outi = nui, outo = nuo;
         const bool li = (rbc >> i) & 1u, lo = (rbc >> o) & 1u;
         if (li) {

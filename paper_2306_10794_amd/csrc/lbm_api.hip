@@ -881,10 +881,6 @@ static lbm_status adj_check(Ctx *c, int32_t nsteps, int32_t ckpt) {
         c->err = "the adjoint needs the fluid at rest (no body force)";
         return LBM_EINVAL;
     }
-    if (c->p.collision != LBM_BGK) {
-        c->err = "the adjoint transposes the BGK step (collision = LBM_BGK)";
-        return LBM_EINVAL;
-    }
     if (c->ceq) {
         c->err = "the adjoint takes a uniform c_eq (ceq_field = 0)";
         return LBM_EINVAL;

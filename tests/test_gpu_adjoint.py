@@ -70,7 +70,8 @@ def _oracle_grad(case, steps, target):
                                             (FP64, "disks R2 S.V."), (FP64, "disks R1 S.P.J."),
                                             (FP32, "disks R1 S.New"), (FP64, "spheres32 D3Q7"),
                                             (FP32, "spheres32 D3Q7"), (FP64, "disks D2Q5 R1 S.New"),
-                                            (FP64, "disks D2Q5 R2 S.V.")])
+                                            (FP64, "disks D2Q5 R2 S.V."), (FP64, "spheres32 TRT"),
+                                            (FP32, "spheres32 TRT"), (FP64, "disks TRT D2Q5 R1 S.P.J.")])
 def test_adjoint_matches_oracle(precision, name):
     case = {"spheres32": lambda: _spheres32(),
             "disks R2 S.V.": lambda: _disks(MECH_POST, SCHEME_SV),
@@ -78,7 +79,9 @@ def test_adjoint_matches_oracle(precision, name):
             "disks R1 S.New": lambda: _disks(MECH_PRE, SCHEME_SNEW),
             "spheres32 D3Q7": lambda: _spheres32().replace(qs=7),
             "disks D2Q5 R1 S.New": lambda: _disks(MECH_PRE, SCHEME_SNEW).replace(qs=5),
-            "disks D2Q5 R2 S.V.": lambda: _disks(MECH_POST, SCHEME_SV).replace(qs=5)}[name]()
+            "disks D2Q5 R2 S.V.": lambda: _disks(MECH_POST, SCHEME_SV).replace(qs=5),
+            "spheres32 TRT": lambda: _spheres32().replace(collision=1, tau_ad=1.4),
+            "disks TRT D2Q5 R1 S.P.J.": lambda: _disks(MECH_PRE, SCHEME_SPJ).replace(collision=1, qs=5)}[name]()
     steps, ckpt = 100, 30     # segments 30, 30, 30, 10
     target = _target(case)
     log(f"[adjoint] {name} precision={precision} shape=({case.nx},{case.ny},{case.nz}) "
