@@ -88,7 +88,7 @@ __device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c
 // One solute step with the fluid at rest, from gin to gout: the arithmetic of
 // the fused step's solute half with u = 0 (no exchange or solid fraction is
 // written).
-template <class L, typename T, bool RED>
+template <class L, typename T, bool RED, bool TRT>
 __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     using R = double;
     constexpr int Q = L::Q;
@@ -131,7 +131,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < Q; i++)
         if ((SM >> i) & 1u) dC += (R)gv[i];
-    if (D.trt) {
+    if constexpr (TRT) {
         // TRT at rest: even parts relax with omega_gs toward w C, odd parts
         // with omega_g toward 0 (as the fused step with u = 0)
         const R oms = D.omega_gs, oma = D.omega_g;
@@ -172,7 +172,7 @@ __global__ __launch_bounds__(BLK) void k_adj_init(AdjArgs<T> a) {
             a.pout[(long)sol_slot(SM, j) * S + c.k] = (T)(c.kk[j] >= 0 ? a.dldc[a.nodeof[c.kk[j]]] : own);
 }
 
-template <class L, typename T, bool RED>
+template <class L, typename T, bool RED, bool TRT>
 __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     using R = double;
     constexpr int Q = L::Q;
@@ -199,7 +199,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     // mu_opp(j) + oms m, which is BGK's when oms = om
     const R om = D.omega_g, om1 = R(1) - om, oms = D.omega_gs;
     const R ta = R(1) - R(0.5) * (oms + om), tb = R(0.5) * (om - oms);
-    a.pout[c.k] = (T)(D.trt ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
+    a.pout[c.k] = (T)(TRT ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
     // link index: the task's base (lbase of its first node, lane 0, which is
     // active), then by direction, then by lane
     const int lt = __builtin_amdgcn_readfirstlane(c.lb);
@@ -226,10 +226,13 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
         if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
         const int o = L::opp[i];
         const long si = (long)sol_slot(SM, i) * S, so = (long)sol_slot(SM, o) * S;
-        R nui = om1 * (R)mu[i] + om * m, nuo = om1 * (R)mu[o] + om * m;
-        if (D.trt) {
+        R nui, nuo;
+        if constexpr (TRT) {
             nui = ta * (R)mu[i] + tb * (R)mu[o] + oms * m;
             nuo = ta * (R)mu[o] + tb * (R)mu[i] + oms * m;
+        } else {
+            nui = om1 * (R)mu[i] + om * m;
+            nuo = om1 * (R)mu[o] + om * m;
         }
         R outi = nui, outo = nuo;
         const bool li = (rbc >> i) & 1u, lo = (rbc >> o) & 1u;
@@ -360,7 +363,7 @@ static hipError_t rest_check_impl(Ctx &c, bool *at_rest) {
     return e;
 }
 
-template <class L, typename T, bool RED>
+template <class L, typename T, bool RED, bool TRT>
 static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
     const AdjState &r = c.adj;
     const long nb = (c.n_tasks + BLK / 64 - 1) / (BLK / 64);
@@ -387,13 +390,13 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
         for (int j = 1; j < len; j++) {
             a.gin = state(j - 1);
             a.gout = state(j);
-            if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T, RED>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T, RED, TRT>), dim3(nb), dim3(BLK), 0, c.stream, a);
         }
         for (int j = len - 1; j >= 0; j--) {
             a.gin = state(j);
             a.pin = P[cur];
             a.pout = P[1 - cur];
-            if (nb > 0) hipLaunchKernelGGL((k_adj_step<L, T, RED>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            if (nb > 0) hipLaunchKernelGGL((k_adj_step<L, T, RED, TRT>), dim3(nb), dim3(BLK), 0, c.stream, a);
             cur = 1 - cur;
         }
         hipError_t e = hipGetLastError();
@@ -414,7 +417,11 @@ hipError_t launch_rest_check(Ctx &c, bool *at_rest) {
 
 template <class L, typename T>
 static hipError_t adjoint_set(Ctx &c, const double *dldc, double *grad) {
-    return c.red ? adjoint_impl<L, T, true>(c, dldc, grad) : adjoint_impl<L, T, false>(c, dldc, grad);
+    // the collision and the solute set are compile-time variants: a runtime
+    // TRT branch costs the BGK transpose a wave of occupancy
+    const bool trt = c.p.collision == LBM_TRT;
+    if (trt) return c.red ? adjoint_impl<L, T, true, true>(c, dldc, grad) : adjoint_impl<L, T, false, true>(c, dldc, grad);
+    return c.red ? adjoint_impl<L, T, true, false>(c, dldc, grad) : adjoint_impl<L, T, false, false>(c, dldc, grad);
 }
 
 hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad) {
