@@ -316,7 +316,40 @@ def cpu_baseline(case, steps):
     out["tilted_512"] = dict(all_cores=v2, cores=c2, single_thread=v3, unit="MLUPS",
                              sample=f"512^2 tilted channel D2Q9 + D2Q9, 20 steps ({dt2:.1f} s) and "
                                     f"5 steps on one core ({dt3:.1f} s)")
+    out["batch_1024"] = _oracle_batch_rate(_ORACLE_ALL_THREADS)
     return out
+
+
+def _oracle_batch_rate(cores, every=16, steps=50, steps1=10):
+    """The oracle on the 1024-domain sweep: every 16th domain (64 domains, the
+    size mix of the whole set), domains stepped in parallel on a pool of host
+    threads, one oracle instance each (the library call releases the GIL; a
+    domain this small runs its own step on one thread), and the same domains
+    one after another on one core."""
+    from concurrent.futures import ThreadPoolExecutor
+    import oracle
+    from lbm_inputs import configs
+    cases = configs.batch_domains(count=1024, seed=4)[::every]
+    nf = sum(c.n_fluid for c in cases)
+    oracle.set_threads(1)
+    try:
+        oras = [oracle.Oracle(c) for c in cases]
+        for o in oras:
+            o.step(1)
+        t0 = time.perf_counter()
+        with ThreadPoolExecutor(max_workers=cores) as ex:
+            list(ex.map(lambda o: o.step(steps), oras))
+        dt = time.perf_counter() - t0
+        t0 = time.perf_counter()
+        for o in oras:
+            o.step(steps1)
+        dt1 = time.perf_counter() - t0
+    finally:
+        oracle.set_threads(_ORACLE_ALL_THREADS)
+    return dict(all_cores=nf * steps / dt / 1e6, cores=cores, single_thread=nf * steps1 / dt1 / 1e6,
+                unit="MLUPS", sample=f"{len(cases)} of the 1024 domains (every {every}th, "
+                                     f"{nf} fluid nodes), {steps} steps in parallel over domains "
+                                     f"({dt:.1f} s) and {steps1} steps on one core ({dt1:.1f} s)")
 
 
 def _db(d):
