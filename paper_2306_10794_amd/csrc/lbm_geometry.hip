@@ -80,8 +80,15 @@ __global__ __launch_bounds__(BLK) void k_scan_down(const int32_t *in, int32_t *o
     }
 }
 
+__global__ void k_zero_total(int32_t *p) { *p = 0; }
+
 hipError_t scan_excl(Ctx &c, const int32_t *in, int32_t *out, long n, int32_t *total_dev) {
-    if (n <= 0) n = 1;
+    if (n <= 0) {
+        // nothing to scan (a lattice without fluid nodes): the total is 0, and
+        // no element of in, which the caller has not written, is read
+        hipLaunchKernelGGL(k_zero_total, dim3(1), dim3(1), 0, c.stream, total_dev);
+        return hipGetLastError();
+    }
     const long nb = (n + SCAN_TILE - 1) / SCAN_TILE;
     hipLaunchKernelGGL(k_scan_reduce, dim3(nb), dim3(BLK), 0, c.stream, in, n, c.bsum);
     hipLaunchKernelGGL(k_scan_blocks, dim3(1), dim3(1024), 0, c.stream, c.bsum, nb, total_dev);

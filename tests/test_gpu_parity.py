@@ -178,6 +178,50 @@ def test_all_fluid_periodic_and_column():
     _assert_parity(col, FP64, 40)
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_all_solid_lattice_and_zero_steps(precision):
+    """The degenerate lattices: no fluid node at all (no task, link or solid
+    interface node; every field as the oracle's), and a step count of zero
+    (the populations unchanged bit for bit)."""
+    import torch
+    from oracle import Oracle
+    from paper_2306_10794_amd import Simulation
+    solid = np.ones((1, 10, 12), np.uint8)
+    rock = Case(name="rock", dim=2, nx=12, ny=10, nz=1, q=9, solid=solid, tau_ad=0.8,
+                k_r=0.01, c_eq=1.0, v_m=0.1)
+    log(f"[parity] all-solid 12x10 precision={precision}")
+    sim = Simulation(rock, precision=precision)
+    sim.step(5)
+    torch.cuda.synchronize()
+    d = sim.diag()
+    assert d["status"] == 0 and d["n_links"] == 0
+    fg = {k: v.cpu().numpy() for k, v in sim.fields().items()}
+    qg = sim.exchange().cpu().numpy()
+    sim.close()
+    ora = Oracle(rock)
+    ora.step(5)
+    fo = ora.fields()
+    for k in ("phi", "type"):   # the fields a solid node carries
+        assert np.array_equal(np.asarray(fg[k], np.float64).reshape(fo[k].shape), fo[k]), k
+    for k in ("rho", "u", "c"):
+        assert np.isfinite(fg[k]).all(), k
+    assert not qg.any()
+    rng = np.random.default_rng(12)
+    solid2 = np.zeros((1, 16, 20), np.uint8)
+    solid2[0, 5:9, 6:11] = 1
+    case = Case(name="zero steps", dim=2, nx=20, ny=16, nz=1, q=9, solid=solid2, tau_ad=0.9,
+                k_r=0.02, c_eq=1.0, c_init=rng.uniform(0, 1, solid2.size))
+    sim = Simulation(case, precision=precision)
+    sim.step(3)
+    f0, g0 = (t.cpu().numpy().copy() for t in sim.pops())
+    sim.step(0)
+    f1, g1 = (t.cpu().numpy() for t in sim.pops())
+    torch.cuda.synchronize()
+    assert np.array_equal(f0, f1) and np.array_equal(g0, g1)
+    assert sim.diag()["status"] == 0
+    sim.close()
+
+
 def test_linear_robin_steady_on_gpu():
     """The exact linear steady state (inlet + reactive wall) reproduced by the
     library itself in FP64."""
