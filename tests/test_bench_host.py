@@ -1,0 +1,39 @@
+"""bench.py's host-side contract, without a GPU: one GPU only (any other
+count exits with a message), and the algorithmic bytes of one fused step
+launch as the per-unit figures state them."""
+import os
+import subprocess
+import sys
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+sys.path.insert(0, ROOT)
+
+
+def test_more_than_one_gpu_exits_with_a_message():
+    r = subprocess.run([sys.executable, os.path.join(ROOT, "bench.py"), "--gpus", "2"],
+                       capture_output=True, text=True, timeout=120, cwd=ROOT)
+    assert r.returncode == 2
+    assert "one GPU only" in r.stdout + r.stderr
+
+
+def test_step_bytes_per_launch():
+    import bench
+    nf, nl, nif = 6_695_295, 12_829_908, 2_791_773     # the 256^3 sphere packing
+    # per fluid node: Q read + Q written for each lattice (FP32), a 4 B
+    # solid-neighbour mask; per link: coefficient read, exchange written; per
+    # fluid interface node: solid fraction read and written (FP64)
+    per_node = (19 + 19) * 4 * 2 + 4
+    expect = nf * per_node + nl * (4 + 4) + nif * 16
+    assert bench.kernel_bytes(19, 4, nf, nl, nif) == expect == 2_209_458_492
+    # the solute on D3Q7: 7 populations instead of 19
+    per_node7 = (19 + 7) * 4 * 2 + 4
+    assert bench.kernel_bytes(19, 4, nf, 3_397_116, 1_000_000, qs=7) == \
+        nf * per_node7 + 3_397_116 * 8 + 1_000_000 * 16
+    # FP64 storage doubles the population and link terms
+    assert bench.kernel_bytes(9, 8, 100, 10, 5) == 100 * ((9 + 9) * 8 * 2 + 4) + 10 * 16 + 5 * 16
+
+
+if __name__ == "__main__":
+    sys.exit(pytest.main([__file__, "-q"]))
