@@ -18,14 +18,14 @@ SRC = os.path.join(HERE, "lbm_oracle.c")
 LIB = os.path.join(HERE, "liblbm_oracle.so")
 
 
-def build(force: bool = False) -> str:
+def build(force: bool = False, src: str = SRC, lib: str = LIB) -> str:
     """Compile the oracle with gcc (plain -O3, no fast-math, no FMA contraction)."""
-    if force or not os.path.exists(LIB) or os.path.getmtime(LIB) < os.path.getmtime(SRC):
-        tmp = LIB + ".tmp"
+    if force or not os.path.exists(lib) or os.path.getmtime(lib) < os.path.getmtime(src):
+        tmp = lib + ".tmp"
         subprocess.check_call(["gcc", "-O3", "-std=gnu11", "-ffp-contract=off", "-fopenmp",
-                               "-fPIC", "-shared", "-Wall", "-o", tmp, SRC, "-lm"])
-        os.replace(tmp, LIB)
-    return LIB
+                               "-fPIC", "-shared", "-Wall", "-o", tmp, src, "-lm"])
+        os.replace(tmp, lib)
+    return lib
 
 
 class _Params(C.Structure):
@@ -42,34 +42,48 @@ class _Params(C.Structure):
 _lib = None
 
 
+def _bind(lib):
+    P = C.c_void_p
+    dp = C.POINTER(C.c_double)
+    lib.orc_create.restype = P
+    lib.orc_create.argtypes = [C.POINTER(_Params), P, P, P, P]
+    lib.orc_destroy.argtypes = [P]
+    lib.orc_init.argtypes = [P, P, P, P]
+    lib.orc_step.argtypes = [P, C.c_int]
+    lib.orc_get_fields.argtypes = [P, P, P, P, P, P]
+    lib.orc_get_pops.argtypes = [P, P, P]
+    lib.orc_set_pops.argtypes = [P, P, P]
+    lib.orc_get_exchange.argtypes = [P, P, P]
+    lib.orc_get_link_k.argtypes = [P, P]
+    lib.orc_get_lattice.argtypes = [P, P, P, P, P]
+    lib.orc_get_normals.argtypes = [P, P]
+    lib.orc_diag.argtypes = [P, dp]
+    lib.orc_adjoint.restype = C.c_int
+    lib.orc_adjoint.argtypes = [P, C.c_int, P, P, P]
+    lib.orc_threads.restype = C.c_int
+    lib.orc_set_threads.argtypes = [C.c_int]
+    lib.orc_set_ceq.argtypes = [P, P]
+    lib.orc_get_solute_set.restype = C.c_int
+    lib.orc_get_solute_set.argtypes = [P, P]
+    return lib
+
+
 def _load():
     global _lib
     if _lib is None:
-        lib = C.CDLL(build())
-        P = C.c_void_p
-        dp = C.POINTER(C.c_double)
-        lib.orc_create.restype = P
-        lib.orc_create.argtypes = [C.POINTER(_Params), P, P, P, P]
-        lib.orc_destroy.argtypes = [P]
-        lib.orc_init.argtypes = [P, P, P, P]
-        lib.orc_step.argtypes = [P, C.c_int]
-        lib.orc_get_fields.argtypes = [P, P, P, P, P, P]
-        lib.orc_get_pops.argtypes = [P, P, P]
-        lib.orc_set_pops.argtypes = [P, P, P]
-        lib.orc_get_exchange.argtypes = [P, P, P]
-        lib.orc_get_link_k.argtypes = [P, P]
-        lib.orc_get_lattice.argtypes = [P, P, P, P, P]
-        lib.orc_get_normals.argtypes = [P, P]
-        lib.orc_diag.argtypes = [P, dp]
-        lib.orc_adjoint.restype = C.c_int
-        lib.orc_adjoint.argtypes = [P, C.c_int, P, P, P]
-        lib.orc_threads.restype = C.c_int
-        lib.orc_set_threads.argtypes = [C.c_int]
-        lib.orc_set_ceq.argtypes = [P, P]
-        lib.orc_get_solute_set.restype = C.c_int
-        lib.orc_get_solute_set.argtypes = [P, P]
-        _lib = lib
+        _lib = _bind(C.CDLL(build()))
     return _lib
+
+
+def load_variant(source: str, directory: str):
+    """Compile ``source`` (a modified copy of lbm_oracle.c) into ``directory``
+    and return the loaded library, for ``Oracle(case, lib=...)``.  The test
+    suite uses this to check that its pins reject planted mistakes."""
+    src = os.path.join(directory, "lbm_oracle_variant.c")
+    with open(src, "w") as fh:
+        fh.write(source)
+    return _bind(C.CDLL(build(force=True, src=src,
+                              lib=os.path.join(directory, "liblbm_oracle_variant.so"))))
 
 
 def _ptr(a):
@@ -88,8 +102,9 @@ def set_threads(n: int):
 class Oracle:
     """Stateful FP64 reference run of one ``lbm_inputs.Case``."""
 
-    def __init__(self, case, init: bool = True):
-        lib = _load()
+    def __init__(self, case, init: bool = True, lib=None):
+        lib = _load() if lib is None else lib
+        self._lib = lib
         self.case = case
         p = _Params()
         p.dim, p.nx, p.ny, p.nz, p.q = case.dim, case.nx, case.ny, case.nz, case.q
@@ -126,58 +141,58 @@ class Oracle:
     def __del__(self):
         h = getattr(self, "_h", None)
         if h:
-            _load().orc_destroy(h)
+            self._lib.orc_destroy(h)
             self._h = None
 
     def init(self, rho=None, u=None, c=None):
         rho = None if rho is None else np.ascontiguousarray(rho, np.float64)
         u = None if u is None else np.ascontiguousarray(u, np.float64)
         c = None if c is None else np.ascontiguousarray(c, np.float64)
-        _load().orc_init(self._h, _ptr(rho), _ptr(u), _ptr(c))
+        self._lib.orc_init(self._h, _ptr(rho), _ptr(u), _ptr(c))
 
     def step(self, n: int = 1):
-        _load().orc_step(self._h, int(n))
+        self._lib.orc_step(self._h, int(n))
 
     def fields(self) -> dict:
         N = self.N
         rho, u, c, phi = (np.empty(N), np.empty((N, 3)), np.empty(N), np.empty(N))
         typ = np.empty(N, np.uint8)
-        _load().orc_get_fields(self._h, _ptr(rho), _ptr(u), _ptr(c), _ptr(phi), _ptr(typ))
+        self._lib.orc_get_fields(self._h, _ptr(rho), _ptr(u), _ptr(c), _ptr(phi), _ptr(typ))
         return dict(rho=rho, u=u, c=c, phi=phi, type=typ)
 
     def pops(self):
         """(f [Q, N], g [QS, N]); g in the solute set's order."""
         f = np.empty((self.Q, self.N))
         g = np.empty((self.QS, self.N))
-        _load().orc_get_pops(self._h, _ptr(f), _ptr(g))
+        self._lib.orc_get_pops(self._h, _ptr(f), _ptr(g))
         return f, g
 
     def set_pops(self, f=None, g=None):
         f = None if f is None else np.ascontiguousarray(f, np.float64)
         g = None if g is None else np.ascontiguousarray(g, np.float64)
-        _load().orc_set_pops(self._h, _ptr(f), _ptr(g))
+        self._lib.orc_set_pops(self._h, _ptr(f), _ptr(g))
 
     def exchange(self):
         """(q [N,Q], kind [N,Q]) of the last step; kind 1 marks reactive links."""
         q = np.empty((self.N, self.Q))
         kind = np.empty((self.N, self.Q), np.uint8)
-        _load().orc_get_exchange(self._h, _ptr(q), _ptr(kind))
+        self._lib.orc_get_exchange(self._h, _ptr(q), _ptr(kind))
         return q, kind
 
     def link_k(self):
         k = np.empty((self.N, self.Q))
-        _load().orc_get_link_k(self._h, _ptr(k))
+        self._lib.orc_get_link_k(self._h, _ptr(k))
         return k
 
     def normals(self):
         n = np.empty((self.N, 3))
-        _load().orc_get_normals(self._h, _ptr(n))
+        self._lib.orc_get_normals(self._h, _ptr(n))
         return n
 
     def lattice(self):
         e = np.empty((self.Q, 3), np.int32)
         wf, ws, cs2 = np.empty(self.Q), np.empty(self.Q), np.empty(2)
-        _load().orc_get_lattice(self._h, _ptr(e), _ptr(wf), _ptr(ws), _ptr(cs2))
+        self._lib.orc_get_lattice(self._h, _ptr(e), _ptr(wf), _ptr(ws), _ptr(cs2))
         # ws by fluid direction (0 outside the solute set); sd: the fluid
         # direction of each solute direction
         return dict(e=e, wf=wf, ws=ws, cs2f=cs2[0], cs2s=cs2[1], sd=self.sdirs.copy())
@@ -189,13 +204,13 @@ class Oracle:
         dLdC = np.ascontiguousarray(dLdC, np.float64)
         grad = np.zeros(self.N)
         lam0 = np.zeros((self.N, self.Q)) if want_lam0 else None
-        rc = _load().orc_adjoint(self._h, int(nsteps), _ptr(dLdC), _ptr(grad), _ptr(lam0))
+        rc = self._lib.orc_adjoint(self._h, int(nsteps), _ptr(dLdC), _ptr(grad), _ptr(lam0))
         if rc != 0:
             raise RuntimeError(f"orc_adjoint failed ({rc})")
         return grad, (None if lam0 is None else np.ascontiguousarray(lam0.T))
 
     def diag(self) -> dict:
         d = (C.c_double * 7)()
-        _load().orc_diag(self._h, d)
+        self._lib.orc_diag(self._h, d)
         return dict(mass_c=d[0], phi_sum=d[1], wall_exchange=d[2], inlet_exchange=d[3],
                     outlet_exchange=d[4], step=int(d[5]), n_events=int(d[6]))

@@ -551,14 +551,20 @@ void orc_step(orc *o, int nsteps)
 
 /* ------------------------------------------------------------------------- */
 /* Phase change (Sec. 2.4: thresholds phi = 0 for dissolution and phi = 1 for
- * precipitation, redistribution of the excess weighted by the reaction rate).
- * The paper states the rules in words only.  Reading taken here: a dissolving
- * solid node becomes fluid with C = mean C of its fluid neighbours and
- * equilibrium populations, and V_m C - phi is taken from its solid neighbours
- * in proportion to their link k (equal shares if all k are 0); a precipitating
- * fluid node becomes solid, adds V_m C to phi and passes phi - 1 to its fluid
- * neighbours in proportion to their link k.  Both keep the solute plus solid
- * mass.  Events are taken in node-index order. */
+ * precipitation; the local concentration is turned into phi, the excess goes
+ * to the surrounding fluid cells, and a dissolved cell starts at the mean
+ * concentration of its fluid neighbours, paid for by the surrounding solid
+ * cells).  The paper states the rules in words only.  Reading taken here: a
+ * dissolving solid node (with at least one fluid neighbour) becomes fluid
+ * with C and rho the means over its fluid neighbours and equilibrium
+ * populations at rest, and V_m C - phi is taken from its solid neighbours in
+ * proportion to their rate constants k_r (equal shares if all are 0; kept by
+ * the node as a negative phi if it has no solid neighbour); a precipitating
+ * fluid node becomes solid, adds V_m C to phi and passes phi - 1 in equal
+ * shares to its fluid neighbours (the rate that weights the shares is the
+ * precipitating cell's own, the same for every share).  Both keep the solute
+ * plus solid mass.  Events are taken in node-index order; a node pushed over
+ * its threshold by an earlier event is taken when the loop reaches it. */
 
 static double node_C(const orc *o, long n)
 {
@@ -649,20 +655,16 @@ static void apply_phase_change(orc *o)
             o->phi[n] += vm * Cx;
             double excess = o->phi[n] - 1.0;
             long nb[ORC_QMAX];
-            double wt[ORC_QMAX], wsum = 0;
             int nn = 0;
             for (int i = 1; i < Q; i++) {
                 long y = site(o, X, Y, Z, o->e[i][0], o->e[i][1], o->e[i][2], 1, &face);
                 if (y < 0 || o->solid[y]) continue;
-                /* weight: the rate constant this node will present to y */
-                nb[nn] = y;
-                wt[nn] = o->kr[n];
-                wsum += wt[nn];
-                nn++;
+                nb[nn++] = y;
             }
+            /* the weight is the precipitating cell's own rate, one value for
+             * every share: the shares are equal */
             if (nn > 0) {
-                for (int k = 0; k < nn; k++)
-                    o->phi[nb[k]] += excess * (wsum > 0 ? wt[k] / wsum : 1.0 / nn);
+                for (int k = 0; k < nn; k++) o->phi[nb[k]] += excess / nn;
                 o->phi[n] = 1.0;
             }
             o->solid[n] = 1;

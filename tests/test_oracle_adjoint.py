@@ -18,6 +18,7 @@ import pytest
 from lbm_inputs import (Case, configs, geometry, MECH_PRE, MECH_POST, SCHEME_SNEW, SCHEME_SV,
                         SCHEME_SPJ, SCHEME_ABB)
 from oracle import Oracle
+from test_oracle_events import _slit_case
 
 
 def _disk_case(mech, scheme, flow=True, seed=3):
@@ -51,18 +52,18 @@ def _sphere_case(inlet=True, walls=False, seed=9):
                 c_in=2.0, c0=0.5)
 
 
-def _loss(case, steps, target):
-    o = Oracle(case)
+def _loss(case, steps, target, lib=None):
+    o = Oracle(case, lib=lib)
     o.step(steps)
     c = o.fields()["c"]
     fl = case.solid_flat() == 0
     return float(((c - target)[fl] ** 2).sum()), c
 
 
-def _grad(case, steps, target):
-    o = Oracle(case)
+def _grad(case, steps, target, lib=None):
+    o = Oracle(case, lib=lib)
     fl = case.solid_flat() == 0
-    o2 = Oracle(case)
+    o2 = Oracle(case, lib=lib)
     o2.step(steps)
     c = o2.fields()["c"]
     dLdC = np.where(fl, 2.0 * (c - target), 0.0)
@@ -154,3 +155,27 @@ def test_zero_loss_gradient_is_zero():
     o = Oracle(case)
     grad, lam0 = o.adjoint(20, np.zeros(case.n), want_lam0=True)
     assert np.all(grad == 0.0) and np.all(lam0 == 0.0)
+
+
+def check_gap_adjoint(lib=None, steps=50):
+    """A layer one node thick (every reactive link has solid at both ends):
+    the pre-collision reading falls back to the post-collision source with
+    k / gamma, and its rate gradient must carry the same 1/gamma (central
+    differences of the forward run)."""
+    case = _slit_case(9, 0, MECH_PRE, SCHEME_SNEW)
+    rng = np.random.default_rng(5)
+    fl = case.solid_flat() == 0
+    target = np.where(fl, rng.uniform(0.0, 1.5, case.n), 0.0)
+    grad = _grad(case, steps, target, lib)
+    k0 = case.k_r_field.copy()
+    d = np.where(case.solid_flat() == 1, rng.normal(size=case.n), 0.0) * k0
+    h = 1e-4
+    fd = (_loss(case.replace(k_r_field=k0 + h * d), steps, target, lib)[0] -
+          _loss(case.replace(k_r_field=k0 - h * d), steps, target, lib)[0]) / (2 * h)
+    ad = float(grad @ d)
+    assert abs(ad) > 0
+    assert abs(fd - ad) <= 1e-6 * abs(ad), (fd, ad)
+
+
+def test_rate_gradient_across_a_one_node_gap():
+    check_gap_adjoint()
