@@ -203,11 +203,10 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
         }
         // lane 0: the node's own state, read alongside its neighbours'
         bool sol_n = false;
-        double phn = 0.0, krn = 0.0, Cx = 0.0, Rx = 0.0;
+        double phn = 0.0, Cx = 0.0, Rx = 0.0;
         if (lane == 0) {
             sol_n = solid[n] != 0;
             phn = phi[n];
-            krn = kr[n];
             if (!sol_n && phn >= 1.0) {
                 const int ko = kof_old[n];
                 if (ko >= 0) pop_moments<L, T, RED>(D, ko, f, g, S, &Cx, &Rx);
@@ -292,14 +291,13 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                     phi[n] = phx;
                     const double excess = phx - 1.0;
                     int nn = 0;
-                    double wsum = 0.0;
                     for (int i = 1; i < L::Q; i++)
-                        if (ys[i] >= 0 && !(fs[i] & 1)) { wsum += krn; nn++; }
+                        if (ys[i] >= 0 && !(fs[i] & 1)) nn++;
                     if (nn > 0) {
                         for (int i = 1; i < L::Q; i++) {
                             const long s = ys[i];
                             if (s < 0 || (fs[i] & 1)) continue;
-                            const double pnew = (distinct ? ps[i] : phi[s]) + excess * (wsum > 0 ? krn / wsum : 1.0 / nn);
+                            const double pnew = (distinct ? ps[i] : phi[s]) + excess / nn;
                             phi[s] = pnew;
                             if (s > n && !(fs[i] & 2) && pnew >= 1.0)
                                 push(s, (fs[i] & 4) != 0);
