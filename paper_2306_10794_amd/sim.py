@@ -108,6 +108,7 @@ class Simulation:
         initialised afterwards)."""
         self._geom["k_r"] = _dev(k_r, torch.float64, self.device)
         L.lbm_set_geometry(self.ctx, **self._geom)
+        self.records = getattr(self, "records", 0) + 1
 
     def record(self, nsteps: int, ckpt_every: int):
         """Run nsteps steps keeping the checkpoints the adjoint needs."""
@@ -116,6 +117,9 @@ class Simulation:
             self._adj_ws = None
             self._adj_ws = torch.empty(n, dtype=torch.uint8, device=self.device)
         L.lbm_record(self.ctx, nsteps, ckpt_every, self._adj_ws, self._adj_ws.numel())
+        # a recorded run is identified by this counter: a later record (or a
+        # new geometry) makes the gradients of earlier ones unavailable
+        self.records = getattr(self, "records", 0) + 1
 
     def adjoint(self, dL_dC) -> torch.Tensor:
         """dL/dk_r [N] of the recorded run for dL/dC_T = dL_dC [N]."""
@@ -157,10 +161,15 @@ class RateToConcentration(torch.autograd.Function):
         sim.init_fields(None, None, c0)
         sim.record(int(nsteps), int(ckpt_every))
         ctx.sim = sim
+        ctx.record = sim.records
         return sim.fields()["c"]
 
     @staticmethod
     def backward(ctx, grad_c):
+        if ctx.sim.records != ctx.record:
+            raise RuntimeError("the simulation has recorded another run since this forward "
+                               "call; its gradient is no longer available (use one Simulation "
+                               "per live forward call)")
         return ctx.sim.adjoint(grad_c.contiguous()), None, None, None, None
 
 

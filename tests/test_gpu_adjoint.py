@@ -3,10 +3,13 @@ adjoint, against central differences of the GPU forward run, and through
 torch.autograd.
 
 Tolerances: FP64 gradients agree with the oracle to 1e-11 of the largest
-component (summation order differs); FP32 deviation storage to 1e-4 (the
-adjoint populations are stored in FP32 as well).  Central differences
-(h = 1e-3 k) carry an O(h^2) truncation error: 1e-5 of the largest
-component.
+component (summation order differs); FP32 deviation storage to 1e-5 (the
+stated FP32 field tolerance; the adjoint populations are stored in FP32 as
+well, the link sums in FP64).  Central differences (h = 1e-3 k) carry an
+O(h^2) truncation error: 1e-5 of the largest component.  At the full size of
+the rate-recovery workload (128^3, 2000 steps, a checkpoint every 100) the
+FP32 gradient is held to 1e-5 of the FP64 GPU gradient of the same run (the
+FP64 path is the one matched to the oracle above).
 """
 import math
 
@@ -92,8 +95,8 @@ def test_adjoint_matches_oracle(precision, name):
     err = np.abs(g - go).max() / scale
     log(f"[adjoint] max |grad| {scale:.3e}, rel err {err:.3e}, nonzero {(go != 0).sum()}")
     assert scale > 0
-    assert np.array_equal(g != 0, go != 0) or precision == FP32
-    assert err <= (1e-11 if precision == FP64 else 1e-4)
+    assert np.array_equal(g != 0, go != 0)
+    assert err <= (1e-11 if precision == FP64 else 1e-5)
 
 
 def test_adjoint_matches_central_differences_fp64():
@@ -183,3 +186,63 @@ def test_adjoint_state_errors():
         flow.record(10, 5)
     assert ei.value.status == LBM_EINVAL
     flow.close()
+
+
+def test_fp32_adjoint_at_full_size():
+    """The rate-recovery workload as specified: 128^3 sphere packing (porosity
+    0.45), log-normal k_r, 2000 steps with a checkpoint every 100; the FP32
+    gradient against the FP64 gradient of the same run."""
+    case = configs.rate_recovery(n=128, seed=5, steps=2000)
+    steps, ckpt = 2000, 100
+    target = _target(case, seed=8)
+    log(f"[adjoint] 128^3 rate recovery, {steps} steps, checkpoint every {ckpt}")
+    g64, l64 = _gpu_grad(case, FP64, steps, ckpt, target)
+    g32, l32 = _gpu_grad(case, FP32, steps, ckpt, target)
+    scale = np.abs(g64).max()
+    err = np.abs(g32 - g64).max() / scale
+    log(f"[adjoint] 128^3: max |grad| {scale:.3e}, FP32 vs FP64 rel err {err:.3e}, "
+        f"loss {l64:.6e} / {l32:.6e}, nonzero {(g64 != 0).sum()}")
+    assert scale > 0 and np.isfinite(g32).all()
+    assert np.array_equal(g32 != 0, g64 != 0)
+    assert err <= 1e-5
+    assert l32 == pytest.approx(l64, rel=1e-5)
+
+
+def test_record_refuses_a_fluid_not_at_rest():
+    """A non-uniform density at zero velocity has no momentum yet drives a flow
+    in later steps; the adjoint recomputes with the fluid at rest, so the
+    record is refused."""
+    import torch
+    from paper_2306_10794_amd import Simulation, LbmError, LBM_EINVAL
+    case = _disks(MECH_PRE, SCHEME_SNEW)
+    for prec in (FP64, FP32):
+        sim = Simulation(case, precision=prec)
+        rho = 1.0 + 1e-3 * np.random.default_rng(1).uniform(size=case.n)
+        sim.init_fields(rho, None, case.c_flat())
+        with pytest.raises(LbmError) as ei:
+            sim.record(10, 5)
+        assert ei.value.status == LBM_EINVAL
+        # a uniform density other than the reference is at rest
+        sim.init_fields(np.full(case.n, 1.002), None, case.c_flat())
+        sim.record(10, 5)
+        sim.close()
+
+
+def test_autograd_refuses_a_stale_record():
+    """Two forward calls on one Simulation, then the backward of the first:
+    the first run's checkpoints are gone, so backward raises instead of
+    returning the second run's gradient."""
+    import torch
+    from paper_2306_10794_amd import Simulation, final_concentration
+    case = _disks(MECH_PRE, SCHEME_SNEW)
+    fl = torch.as_tensor(case.solid_flat() == 0, device="cuda")
+    sim = Simulation(case, precision=FP64)
+    k1 = torch.as_tensor(case.k_r_field, device="cuda").requires_grad_(True)
+    k2 = (1.5 * torch.as_tensor(case.k_r_field, device="cuda")).requires_grad_(True)
+    l1 = final_concentration(k1, sim, 30, 10, case.c_flat())[fl].sum()
+    l2 = final_concentration(k2, sim, 30, 10, case.c_flat())[fl].sum()
+    with pytest.raises(RuntimeError, match="recorded another run"):
+        l1.backward()
+    l2.backward()
+    assert torch.isfinite(k2.grad).all() and k2.grad.abs().max() > 0
+    sim.close()
