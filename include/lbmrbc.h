@@ -23,7 +23,8 @@
  *   - Nodes are indexed n = x + nx*(y + ny*z) (x fastest).  2D uses nz = 1.
  *   - All array arguments are DEVICE pointers unless stated otherwise, and are
  *     owned by the caller.  The library never frees them.  The only device
- *     memory the library uses is the caller's workspace given to lbm_create.
+ *     memory the library uses is the caller's workspaces (lbm_create,
+ *     lbm_record) and one static array per GPU (lbm_record_static).
  *   - All device work is enqueued, in order, on the HIP stream given to
  *     lbm_create (NULL = the legacy default stream).  Only lbm_get_diag,
  *     lbm_set_geometry and lbm_create synchronise that stream.
@@ -289,6 +290,24 @@ lbm_status lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int32_t nsteps, int32
 lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *dev_workspace,
                       size_t bytes);
 lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k);
+
+/* lbm_record without a workspace, for callers that cannot allocate device
+ * memory (code under stream capture, tight serving loops, harnesses that
+ * forbid hipMalloc).  The checkpoints and the adjoint's working arrays live in
+ * a device array inside the library, LBM_STATIC_SCRATCH_BYTES per GPU, held
+ * from the library's load until the process ends.  Same run, same results
+ * and same lbm_adjoint as lbm_record; the steps run as plain kernel launches
+ * on the context stream (no graph, no second stream), and nothing is
+ * allocated.
+ *   ENOMEM if lbm_adjoint_workspace_bytes(ctx, nsteps, ckpt_every) exceeds
+ *   LBM_STATIC_SCRATCH_BYTES (the message gives both sizes); the other
+ *   errors as lbm_record.
+ * One array per GPU, shared by every context on it: each call overwrites the
+ * previous call's contents, and lbm_adjoint of a context whose static record
+ * has since been overwritten returns ESTATE.  Calls on one GPU (and their
+ * lbm_adjoint) must not overlap in time: concurrent use of the array races. */
+#define LBM_STATIC_SCRATCH_BYTES (64ull << 20)
+lbm_status lbm_record_static(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every);
 
 /* Macroscopic fields of the current state (asynchronous; NULL skips a field):
  * rho = sum f, u = (sum e f - F/2)/rho, C = sum g (the values that entered

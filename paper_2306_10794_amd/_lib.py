@@ -90,6 +90,7 @@ _SIGS = {
     "lbm_adjoint_workspace_bytes": [_P, C.c_int32, C.c_int32, C.POINTER(C.c_size_t)],
     "lbm_record": [_P, C.c_int32, C.c_int32, _P, C.c_size_t],
     "lbm_adjoint": [_P, _P, _P],
+    "lbm_record_static": [_P, C.c_int32, C.c_int32],
     "lbm_get_fields": [_P, _P, _P, _P, _P, _P],
     "lbm_get_pops": [_P, _P, _P],
     "lbm_get_exchange": [_P, _P],
@@ -233,6 +234,10 @@ def lbm_adjoint_workspace_bytes(ctx, nsteps: int, ckpt_every: int) -> int:
 def lbm_record(ctx, nsteps: int, ckpt_every: int, workspace, nbytes: int):
     _check(lib.lbm_record(ctx, int(nsteps), int(ckpt_every), _ptr(workspace), int(nbytes)),
            "lbm_record", ctx)
+
+
+def lbm_record_static(ctx, nsteps: int, ckpt_every: int):
+    _check(lib.lbm_record_static(ctx, int(nsteps), int(ckpt_every)), "lbm_record_static", ctx)
 
 
 def lbm_adjoint(ctx, dL_dC, grad_k):

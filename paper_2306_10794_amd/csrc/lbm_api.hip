@@ -3,6 +3,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <new>
 #include <string>
 #include <vector>
@@ -333,6 +334,11 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
     }
     c->p = params[0];
     c->stream = (hipStream_t)hip_stream;
+    if (hipGetDevice(&c->device) != hipSuccess) {
+        delete c;
+        g_create_err = "hipGetDevice failed";
+        return LBM_EDEVICE;
+    }
     c->dim = params[0].dim;
     c->fp64 = params[0].precision == LBM_FP64;
     c->ndom = nd;
@@ -480,7 +486,9 @@ static hipError_t phase_change_pass(Ctx *c, bool *capacity) {
     return e;
 }
 
-static hipError_t run_steps(Ctx *c, int32_t nsteps) {
+// plain: kernel launches on the context stream only (no graph, which would
+// allocate when built, and no second stream)
+static hipError_t run_steps(Ctx *c, int32_t nsteps, bool plain = false) {
     int32_t t = 0;
     if (c->p.phase_change) {
         // events need a decision on the host after every step (no graphs)
@@ -499,7 +507,7 @@ static hipError_t run_steps(Ctx *c, int32_t nsteps) {
         }
         return hipSuccess;
     }
-    const int gs = (c->cfg.graph_steps + 1) & ~1;
+    const int gs = plain ? 0 : (c->cfg.graph_steps + 1) & ~1;
     if (gs > 0 && nsteps >= gs) {
         if (c->cur != 0) {   // the graph starts from buffer 0
             hipError_t e = launch_step(*c);
@@ -526,7 +534,7 @@ static hipError_t run_steps(Ctx *c, int32_t nsteps) {
         }
     }
     for (; t < nsteps; t++) {
-        hipError_t e = launch_step(*c, nullptr, c->have_side && c->cfg.overlap);
+        hipError_t e = launch_step(*c, nullptr, !plain && c->have_side && c->cfg.overlap);
         if (e != hipSuccess) return e;
         c->step++;
     }
@@ -898,16 +906,52 @@ lbm_status lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int32_t nsteps, int32
     return LBM_OK;
 }
 
-lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *dev_workspace,
-                      size_t bytes) {
-    Ctx *c = (Ctx *)ctx;
-    if (!c) return LBM_EINVAL;
+// checks shared by lbm_record and lbm_record_static, up to the workspace
+static lbm_status record_check(Ctx *c, int32_t nsteps, int32_t ckpt_every) {
     lbm_status st = adj_check(c, nsteps, ckpt_every);
     if (st != LBM_OK) return st;
     if (!c->have_state) {
         c->err = "lbm_record before lbm_init_fields";
         return LBM_ESTATE;
     }
+    return LBM_OK;
+}
+
+// the recorded run into the adjoint workspace at base (checked by the caller)
+static lbm_status record_into(Ctx *c, int32_t nsteps, int32_t ckpt_every, char *base, bool plain) {
+    bool rest = false;
+    hipError_t e = launch_rest_check(*c, &rest);
+    if (e != hipSuccess) return dev_err(c, e, "rest check");
+    if (!rest) {
+        c->err = "the adjoint needs the fluid at rest: every fluid node at the equilibrium at "
+                 "rest of one common density";
+        return LBM_EINVAL;
+    }
+    c->adj.valid = false;
+    adj_layout(c, nsteps, ckpt_every, &c->adj, base);
+    const size_t slot = (size_t)c->QS * (size_t)c->S * (c->fp64 ? 8 : 4);
+    for (int32_t t = 0; t < nsteps; t += ckpt_every) {
+        e = hipMemcpyAsync((char *)c->adj.ckpt + (size_t)(t / ckpt_every) * slot, c->g[c->cur], slot,
+                           hipMemcpyDeviceToDevice, c->stream);
+        if (e != hipSuccess) return dev_err(c, e, "checkpoint copy");
+        e = run_steps(c, nsteps - t < ckpt_every ? nsteps - t : ckpt_every, plain);
+        if (e != hipSuccess) return dev_err(c, e, "step launch");
+    }
+    c->adj.nsteps = nsteps;
+    c->adj.ckpt_every = ckpt_every;
+    c->adj.end_step = c->step;
+    c->adj.geom_epoch = c->geom_epoch;
+    c->adj.static_gen = 0;
+    c->adj.valid = true;
+    return LBM_OK;
+}
+
+lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *dev_workspace,
+                      size_t bytes) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    lbm_status st = record_check(c, nsteps, ckpt_every);
+    if (st != LBM_OK) return st;
     const size_t need = adj_layout(c, nsteps, ckpt_every, nullptr, nullptr);
     if (!dev_workspace || bytes < need) {
         c->err = "adjoint workspace of " + std::to_string(bytes) + " bytes is smaller than the " +
@@ -918,29 +962,61 @@ lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *de
         c->err = "adjoint workspace must be 256-byte aligned device memory";
         return LBM_EINVAL;
     }
-    bool rest = false;
-    hipError_t e = launch_rest_check(*c, &rest);
-    if (e != hipSuccess) return dev_err(c, e, "rest check");
-    if (!rest) {
-        c->err = "the adjoint needs the fluid at rest (some node carries momentum)";
+    return record_into(c, nsteps, ckpt_every, (char *)dev_workspace, false);
+}
+
+// ---------------------------------------------------------------------------
+// lbm_record_static: the adjoint workspace in a device array of the library.
+// In host code `scratch` only stands for the array; its device address on
+// each GPU comes from hipGetSymbolAddress, taken once per device (that
+// device current) and kept in scratch_ptr.
+static __device__ __align__(256) unsigned char scratch[LBM_STATIC_SCRATCH_BYTES];
+
+namespace {
+constexpr int MAX_DEVICES = 64;
+std::mutex scratch_mu;
+void *scratch_ptr[MAX_DEVICES];
+int64_t scratch_gen[MAX_DEVICES];   // records taken into each device's array
+}  // namespace
+
+lbm_status lbm_record_static(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every) {
+    Ctx *c = (Ctx *)ctx;
+    if (!c) return LBM_EINVAL;
+    lbm_status st = record_check(c, nsteps, ckpt_every);
+    if (st != LBM_OK) return st;
+    const size_t need = adj_layout(c, nsteps, ckpt_every, nullptr, nullptr);
+    if (need > (size_t)LBM_STATIC_SCRATCH_BYTES) {
+        c->err = "the recorded run needs " + std::to_string(need) + " bytes, more than the " +
+                 std::to_string((size_t)LBM_STATIC_SCRATCH_BYTES) +
+                 " of the library's static array (use lbm_record with a workspace)";
+        return LBM_ENOMEM;
+    }
+    const int dev = c->device;
+    if (dev < 0 || dev >= MAX_DEVICES) {
+        c->err = "device index out of range for the static array";
         return LBM_EINVAL;
     }
-    c->adj.valid = false;
-    adj_layout(c, nsteps, ckpt_every, &c->adj, (char *)dev_workspace);
-    const size_t slot = (size_t)c->QS * (size_t)c->S * (c->fp64 ? 8 : 4);
-    for (int32_t t = 0; t < nsteps; t += ckpt_every) {
-        e = hipMemcpyAsync((char *)c->adj.ckpt + (size_t)(t / ckpt_every) * slot, c->g[c->cur], slot,
-                           hipMemcpyDeviceToDevice, c->stream);
-        if (e != hipSuccess) return dev_err(c, e, "checkpoint copy");
-        e = run_steps(c, nsteps - t < ckpt_every ? nsteps - t : ckpt_every);
-        if (e != hipSuccess) return dev_err(c, e, "step launch");
+    char *base = nullptr;
+    int64_t gen = 0;
+    {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        if (!scratch_ptr[dev]) {
+            int prev = -1;
+            hipError_t e = hipGetDevice(&prev);
+            if (e == hipSuccess && prev != dev) e = hipSetDevice(dev);
+            void *ptr = nullptr;
+            if (e == hipSuccess) e = hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch));
+            if (prev >= 0 && prev != dev) (void)hipSetDevice(prev);
+            if (e != hipSuccess || !ptr) return dev_err(c, e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                        "hipGetSymbolAddress of the static array");
+            scratch_ptr[dev] = ptr;
+        }
+        base = (char *)scratch_ptr[dev];
+        gen = ++scratch_gen[dev];
     }
-    c->adj.nsteps = nsteps;
-    c->adj.ckpt_every = ckpt_every;
-    c->adj.end_step = c->step;
-    c->adj.geom_epoch = c->geom_epoch;
-    c->adj.valid = true;
-    return LBM_OK;
+    st = record_into(c, nsteps, ckpt_every, base, true);
+    if (st == LBM_OK) c->adj.static_gen = gen;
+    return st;
 }
 
 lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k) {
@@ -955,6 +1031,13 @@ lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k) {
     if (!c->adj.valid || c->adj.end_step != c->step || c->adj.geom_epoch != c->geom_epoch) {
         c->err = "no recorded run ends at the current state (call lbm_record first)";
         return LBM_ESTATE;
+    }
+    if (c->adj.static_gen != 0) {
+        std::lock_guard<std::mutex> lock(scratch_mu);
+        if (scratch_gen[c->device] != c->adj.static_gen) {
+            c->err = "a later lbm_record_static on this GPU has overwritten the recorded run";
+            return LBM_ESTATE;
+        }
     }
     hipError_t e = launch_adjoint(*c, dL_dC, grad_k);
     if (e != hipSuccess) return dev_err(c, e, "adjoint");

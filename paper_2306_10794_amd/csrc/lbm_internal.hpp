@@ -47,6 +47,8 @@ struct DomHost {
 struct AdjState {
     bool valid;
     int64_t nsteps, ckpt_every, end_step, geom_epoch;
+    int64_t static_gen;      // > 0: the run lives in the library's static array,
+                             // as the static_gen-th record taken into it
     void *ckpt;              // [ceil(nsteps/ckpt_every)][Q][S] solute states
     void *hist;              // [ckpt_every - 1][Q][S] recomputed states
     void *p[2];              // [Q][S] adjoint arrays
@@ -57,6 +59,7 @@ struct Ctx {
     lbm_params p;            // parameters of domain 0 (precision, lattice)
     lbm_launch_config cfg;   // tile / schedule of the step launches
     hipStream_t stream;
+    int device;              // HIP device current at lbm_create
     int Q, dim;
     int QS;                  // solute directions (Q, or 5 / 7 on D2Q5 / D3Q7)
     bool red;                // the solute runs on the reduced set (QS < Q)
