@@ -153,6 +153,18 @@ typedef struct {
                                  links since lbm_init_fields (FP64)               */
     int32_t nan_flag;         /* 1 if any population is non-finite                 */
     int32_t reserved0;
+    double inlet_exchange;    /* cumulative mass entering the fluid across the
+                                 inlet plane since lbm_init_fields: per step and
+                                 inlet link the incoming equilibrium value minus
+                                 the node's own population leaving along the
+                                 opposite direction (FP64; 0 without an inlet) */
+    double outlet_exchange;   /* the same across the outlet plane (the
+                                 zero-gradient copy minus the population leaving);
+                                 negative when mass leaves.  With no events,
+                                 sum C + sum phi / (V_m a_m) changes by exactly
+                                 inlet_exchange + outlet_exchange (Sec. 2.4,
+                                 eq. solidFractionUpdate); a batch reports the
+                                 totals over its domains                      */
 } lbm_diag;
 
 /* Workspace size in bytes for these parameters (host call, no device work).

@@ -49,7 +49,8 @@ class lbm_diag(C.Structure):
     _fields_ = [("step", C.c_int64), ("n_events", C.c_int64), ("n_links", C.c_int64),
                 ("n_solid_iface", C.c_int64), ("n_fluid", C.c_int64),
                 ("n_fluid_iface", C.c_int64), ("mass_c", C.c_double), ("phi_sum", C.c_double),
-                ("wall_exchange", C.c_double), ("nan_flag", C.c_int32), ("reserved0", C.c_int32)]
+                ("wall_exchange", C.c_double), ("nan_flag", C.c_int32), ("reserved0", C.c_int32),
+                ("inlet_exchange", C.c_double), ("outlet_exchange", C.c_double)]
 
 
 class lbm_launch_config(C.Structure):

@@ -121,7 +121,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *dpart = take(16 * ((N + 255) / 256 + 1));
     char *dacc = take(8 * 64), *iacc = take(4 * 64);
     const long nxp = (N + 255) / 256 + 1;
-    char *xpart = take(8 * nxp);
+    char *xpart = take(8 * nxp), *xio = take(16 * task_cap);
     // phase change (single lattice): old compact map, candidates, records
     const bool pc = nd == 1 && p[0].phase_change != 0;
     const long ev_cap = pc ? (N < 65536 ? N : 65536) : 0;
@@ -169,6 +169,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->dpart = (double *)dpart;
         c->dacc = (double *)dacc; c->iacc = (int32_t *)iacc;
         c->xpart = (double *)xpart; c->n_xpart = nxp;
+        c->xio = (double *)xio;
     }
     return off;
 }
@@ -359,6 +360,7 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
         woff += h.R * h.W;
         roff += h.R;
         hd[d] = dom_record(h, c->fp64);
+        if (params[d].inlet_axis >= 0) c->any_planes = true;
     }
     hn[nd] = noff;
     hw[nd] = woff;
@@ -1096,7 +1098,7 @@ lbm_status lbm_get_diag(lbm_ctx *ctx, lbm_diag *out) {
         c->err = "no state: call lbm_init_fields first";
         return LBM_ESTATE;
     }
-    double sums[3] = {0, 0, 0};
+    double sums[5] = {0, 0, 0, 0, 0};
     int32_t nan_flag = 0;
     hipError_t e = launch_diag(*c, sums, &nan_flag);
     if (e != hipSuccess) return dev_err(c, e, "diag");
@@ -1110,6 +1112,8 @@ lbm_status lbm_get_diag(lbm_ctx *ctx, lbm_diag *out) {
     out->wall_exchange = sums[0];
     out->mass_c = sums[1];
     out->phi_sum = sums[2];
+    out->inlet_exchange = sums[3];
+    out->outlet_exchange = sums[4];
     out->nan_flag = nan_flag;
     if (nan_flag) {
         c->err = "non-finite population";
@@ -1125,6 +1129,7 @@ struct StateHeader {
     int64_t N, Q, precision, step, n_events;
     double wall_ex;
     int64_t QS;
+    double inlet_ex, outlet_ex;
 };
 
 lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes) {
@@ -1153,16 +1158,18 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes) {
     const size_t pb = ts * c->N;
     StateHeader h;
     memset(&h, 0, sizeof h);
-    h.magic = 0x4c424d5242433031ULL;
+    h.magic = 0x4c424d5242433032ULL;
     h.N = c->N; h.Q = c->Q; h.QS = c->QS; h.precision = c->p.precision; h.step = c->step;
     h.n_events = c->n_events;
-    double wex = 0;
+    double acc[5] = {0, 0, 0, 0, 0};
     hipError_t e = launch_fold_exchange(*c);
     if (e == hipSuccess) e = launch_phi_flush(*c);
-    if (e == hipSuccess) e = hipMemcpyAsync(&wex, c->dacc, sizeof(double), hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(acc, c->dacc, sizeof acc, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_err(c, e, "save_state");
-    h.wall_ex = wex;
+    h.wall_ex = acc[0];
+    h.inlet_ex = acc[3];
+    h.outlet_ex = acc[4];
     char *b = (char *)dev_buf;
     e = hipMemcpyAsync(b, &h, sizeof h, hipMemcpyHostToDevice, c->stream);
     size_t off = sizeof h;
@@ -1197,7 +1204,7 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
     hipError_t e = hipMemcpyAsync(&h, b, sizeof h, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_err(c, e, "load_state");
-    if (h.magic != 0x4c424d5242433031ULL || h.N != c->N || h.Q != c->Q || h.QS != c->QS ||
+    if (h.magic != 0x4c424d5242433032ULL || h.N != c->N || h.Q != c->Q || h.QS != c->QS ||
         h.precision != c->p.precision) {
         c->err = "state buffer does not match this context";
         return LBM_EINVAL;
@@ -1229,8 +1236,9 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
         e = hipMemcpyAsync((char *)c->f[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
     for (int i = 0; i < c->QS && e == hipSuccess; i++, off += pb)
         e = hipMemcpyAsync((char *)c->g[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
-    double wex = h.wall_ex;
-    if (e == hipSuccess) e = hipMemcpyAsync(c->dacc, &wex, sizeof(double), hipMemcpyHostToDevice, c->stream);
+    // the cumulative exchanges (the diag sums in between are recomputed)
+    double acc[5] = {h.wall_ex, 0.0, 0.0, h.inlet_ex, h.outlet_ex};
+    if (e == hipSuccess) e = hipMemcpyAsync(c->dacc, acc, sizeof acc, hipMemcpyHostToDevice, c->stream);
     if (e == hipSuccess) e = launch_zero_exchange(*c);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_err(c, e, "load_state");

@@ -28,6 +28,8 @@ struct StepArgs {
     T *__restrict__ lq;                  // per link: mass exchanged in this step
     double *__restrict__ phif;           // [S] solid fraction of fluid nodes, compact order
     const T *__restrict__ lceq;          // per link: C_eq - C_ref of its solid node (per-node C_eq)
+    double *__restrict__ xio;            // [2][task_cap] per task: inlet, outlet exchange (cumulative)
+    long task_cap;
     long ntasks;
     long S;                              // stride between directions
     int ndom;                            // domains of the context
@@ -123,6 +125,9 @@ struct Ctx {
     bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions
     double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums
+    bool any_planes;         // some domain has an inlet and an outlet plane
+    double *xio;             // [2][task_cap] inlet / outlet exchange of the tasks on those
+                             // planes, one slot per task, folded into dacc[3..4] when read
     double *xpart;           // [n_xpart] wall exchange of the solid-side workgroups, one
                              // slot per workgroup, folded into dacc[0] when read
     long n_xpart;

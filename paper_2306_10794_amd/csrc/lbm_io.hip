@@ -163,12 +163,19 @@ __global__ __launch_bounds__(BLK) void k_fold_exchange(double *part, long n, dou
 
 hipError_t launch_fold_exchange(Ctx &c) {
     hipLaunchKernelGGL(k_fold_exchange, dim3(1), dim3(BLK), 0, c.stream, c.xpart, c.n_xpart, c.dacc);
+    if (c.any_planes) {
+        hipLaunchKernelGGL(k_fold_exchange, dim3(1), dim3(BLK), 0, c.stream, c.xio, c.task_cap, c.dacc + 3);
+        hipLaunchKernelGGL(k_fold_exchange, dim3(1), dim3(BLK), 0, c.stream, c.xio + c.task_cap, c.task_cap,
+                           c.dacc + 4);
+    }
     return hipGetLastError();
 }
 
 hipError_t launch_zero_exchange(Ctx &c) {
     hipLaunchKernelGGL(k_zero_f64, dim3((c.n_xpart + BLK - 1) / BLK), dim3(BLK), 0, c.stream, c.xpart,
                        c.n_xpart);
+    hipLaunchKernelGGL(k_zero_f64, dim3((2 * c.task_cap + BLK - 1) / BLK), dim3(BLK), 0, c.stream, c.xio,
+                       2 * c.task_cap);
     return hipGetLastError();
 }
 
@@ -245,7 +252,7 @@ static hipError_t diag_impl(Ctx &c, double *sums, int32_t *nan_flag) {
     hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(BLK), 0, c.stream, c.dpart, nb, c.dacc + 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
-    e = hipMemcpyAsync(sums, c.dacc, 3 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
+    e = hipMemcpyAsync(sums, c.dacc, 5 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(nan_flag, c.iacc + 4, sizeof(int32_t), hipMemcpyDeviceToHost, c.stream);
     if (e != hipSuccess) return e;

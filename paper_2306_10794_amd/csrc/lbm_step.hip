@@ -217,7 +217,8 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
                 e = nb_compact(rows, W, b, x - L::ex[i] - (ax == 0),
                                y - L::ey[i] - (ax == 1), z - L::ez[i] - (ax == 2));
             } else {
-                e = k;  // inlet: value set below
+                e = -1;  // inlet: the node's own value along opp(i) (the
+                         // population leaving there); the incoming one is set below
             }
         }
         // fluid neighbour: pull; solid or box face: own value along opp(i)
@@ -287,12 +288,34 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     }
 
     // ---- solute: plane faces, reactive links, collision ----
-    if (cross & ~cross_hi) {
+    // Inlet: the equilibrium at C_in for the populations entering across the
+    // plane.  The mass a plane link brings in is the incoming value minus the
+    // node's own value leaving along the opposite direction (at the inlet
+    // that one was loaded into gv; at the outlet gv holds the zero-gradient
+    // copy, and the own value is read here: outlet nodes only).  Each wavefront
+    // with plane nodes adds its sums (fixed shuffle order) to its task's slots.
+    if (ax >= 0) {
+        R xin = R(0), xout = R(0);
+        if (cross) {
 #pragma unroll
-        for (int i = 0; i < Q; i++) {
-            if ((SM >> i) & 1u && ((cross & ~cross_hi) & (1u << i))) {
-                const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
-                gv[i] = (T)(sol_w<L>(D, i) * (D.c_in - D.c_ref) + sol_w<L>(D, i) * D.c_in * eu * D.inv_cs2s);
+            for (int i = 1; i < Q; i++) {
+                if (!((SM >> i) & 1u) || !(cross & (1u << i))) continue;
+                if (cross_hi & (1u << i)) {
+                    xout += (R)gv[i] - (R)a.gin[(long)sol_slot(SM, L::opp[i]) * S + k];
+                } else {
+                    const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
+                    const R gin = sol_w<L>(D, i) * (D.c_in - D.c_ref) + sol_w<L>(D, i) * D.c_in * eu * D.inv_cs2s;
+                    xin += gin - (R)gv[i];
+                    gv[i] = (T)gin;
+                }
+            }
+        }
+        if (__ballot(cross != 0u)) {
+            xin = wave_sum(xin);
+            xout = wave_sum(xout);
+            if (lane == 0) {
+                a.xio[t] += xin;
+                a.xio[a.task_cap + t] += xout;
             }
         }
     }
@@ -438,6 +461,8 @@ static StepArgs<T> step_args(Ctx &c) {
     a.lq = (T *)c.lq;
     a.phif = c.phif;
     a.lceq = (const T *)c.lceq;
+    a.xio = c.xio;
+    a.task_cap = c.task_cap;
     a.ntasks = c.n_tasks;
     a.ndom = c.ndom;
     a.S = c.S;

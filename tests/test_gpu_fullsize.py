@@ -108,7 +108,10 @@ def test_sphere_packing_256_full_length():
     C in [0.83, 2.18] with C_eq = 1, C_in = 2), and every change of the
     solid fraction is the mass that crossed the reactive links (Sec. 2.4:
     sum(phi) - sum(phi_0) = -V_m a_m * (total exchange into the fluid)) as
-    long as no event has moved mass between the phases."""
+    long as no event has moved mass between the phases; solute plus solid
+    mass, sum C + sum phi / (V_m a_m), changes by exactly the inlet plus the
+    outlet exchange (events move mass between the phases without changing
+    that sum)."""
     import torch
     from paper_2306_10794_amd import Simulation
     case = configs.sphere_precipitation(n=256, seed=3, phase_change=1)
@@ -121,8 +124,14 @@ def test_sphere_packing_256_full_length():
         done += chunk
         d = sim.diag()
         log(f"[fullsize] {case.name} step {done}: events {d['n_events']} status {d['status']} "
-            f"wall exchange {d['wall_exchange']:.6e} phi sum {d['phi_sum']:.9e}")
+            f"wall exchange {d['wall_exchange']:.6e} phi sum {d['phi_sum']:.9e} inlet "
+            f"{d['inlet_exchange']:.9e} outlet {d['outlet_exchange']:.9e}")
         assert d["status"] == 0 and d["nan_flag"] == 0
+        tot = lambda x: x["mass_c"] + x["phi_sum"] / (case.v_m * case.a_m)
+        budget = d["inlet_exchange"] + d["outlet_exchange"]
+        log(f"[fullsize] solute + solid mass change {tot(d) - tot(d0):.9e}, inlet + outlet "
+            f"{budget:.9e}")
+        assert abs(tot(d) - tot(d0) - budget) <= 1e-9 * abs(tot(d0))
     c = sim.fields()["c"]
     fl = torch.from_numpy(case.solid_flat() == 0).to(c.device)
     cmin, cmax = float(c[fl].min()), float(c[fl].max())

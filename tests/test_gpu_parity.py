@@ -252,6 +252,55 @@ def test_mass_invariant_and_diag_fp64():
     assert d["wall_exchange"] == pytest.approx(do["wall_exchange"], rel=1e-10, abs=1e-13)
 
 
+def _plane_case(axis):
+    """A 2D disk medium with an inlet and an outlet along x (axis 0: every
+    task mixes plane and interior nodes) or y (axis 1: tasks span rows, some
+    on the planes), or the 3D sphere pack along z (whole tasks on a plane)."""
+    if axis == 2:
+        return _spheres()
+    solid, normals, _ = geometry.disk_medium(45, 38, 0.7, 2.5, 5.0, seed=31 + axis)
+    if axis == 1:
+        # the channel turned by 90 degrees: walls at x = 0 and x = nx - 1
+        solid = np.ascontiguousarray(solid[0].T[None])
+        nt = np.zeros((1, 45, 38, 3))
+        nt[0, :, :, 0] = normals[0, :, :, 1].T
+        nt[0, :, :, 1] = normals[0, :, :, 0].T
+        normals = nt
+    nx, ny = (45, 38) if axis == 0 else (38, 45)
+    rng = np.random.default_rng(40 + axis)
+    force = (1e-5, 0, 0) if axis == 0 else (0, 1e-5, 0)
+    per = (0, 1, 1) if axis == 0 else (1, 0, 1)
+    return Case(name=f"planes{axis}", dim=2, nx=nx, ny=ny, nz=1, q=9, solid=solid,
+                normals=normals, tau_ns=0.8, tau_ad=0.7, j0=0.3, force=force, periodic=per,
+                c_eq=1.0, k_r=0.02, v_m=0.2, inlet_axis=axis, c_in=1.7,
+                c_init=rng.uniform(0.5, 1.5, solid.size))
+
+
+@pytest.mark.parametrize("axis,precision", [(0, FP64), (1, FP64), (2, FP64), (2, FP32), (0, FP32)])
+def test_inlet_outlet_exchange_matches_oracle(axis, precision):
+    """lbm_get_diag's cumulative inlet and outlet exchange against the
+    oracle's, and the mass budget they close (Sec. 2.4, eq.
+    solidFractionUpdate): sum C + sum phi / V_m changes by exactly the
+    inlet plus the outlet exchange."""
+    case = _plane_case(axis)
+    res = _assert_parity(case, precision, 150, name=f"planes axis {axis}")
+    d, do = res["gpu"]["diag"], res["ora"]["diag"]
+    from oracle import Oracle
+    d0 = Oracle(case).diag()
+    log(f"[parity] inlet {d['inlet_exchange']:.15e} / {do['inlet_exchange']:.15e}, outlet "
+        f"{d['outlet_exchange']:.15e} / {do['outlet_exchange']:.15e}")
+    # scale: the mass that entered (the outlet's net is a small difference of
+    # the populations crossing it, whose FP32 rounding the inlet's size sets)
+    tol = 1e-12 if precision == FP64 else 1e-5
+    scale = abs(do["inlet_exchange"])
+    for k in ("inlet_exchange", "outlet_exchange"):
+        assert abs(do[k]) > 1e-3
+        assert abs(d[k] - do[k]) <= tol * scale, k
+    tot = lambda x: x["mass_c"] + x["phi_sum"] / case.v_m
+    budget = d["inlet_exchange"] + d["outlet_exchange"]
+    assert tot(d) - tot(d0) == pytest.approx(budget, rel=1e-12 if precision == FP64 else 1e-5)
+
+
 def test_fp32_phi_accumulation_is_fp64():
     """In FP32 storage the solid fraction is still accumulated in FP64: the
     device phi equals a host FP64 re-accumulation of the exported per-link
