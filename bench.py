@@ -55,6 +55,27 @@ PROFILE_CMDS = {
             "python3 bench.py --steps 50 --warmup 5 --no-cpu-baseline --batch-steps 200 "
             "--adjoint-steps 400 --phase-change-steps 100 --reduced-steps 50",
 }
+# instruction-level counters of the step and adjoint kernels, one pass per group
+# (at most 8 SQ counters per pass); the adjoint leg runs 20 steps
+SQ_GROUPS = {
+    "sq1": "SQ_WAVES SQ_INSTS_VALU SQ_INSTS_SALU SQ_INSTS_LDS SQ_INSTS_VMEM_RD SQ_INSTS_VMEM_WR "
+           "SQ_INSTS_SMEM SQ_INSTS_BRANCH",
+    "sq2": "SQ_INSTS_VALU_INT32 SQ_INSTS_VALU_INT64 SQ_INSTS_VALU_FMA_F64 SQ_INSTS_VALU_MUL_F64 "
+           "SQ_INSTS_VALU_ADD_F64 SQ_INSTS_VALU_CVT SQ_INSTS_VALU_ADD_F32 SQ_INSTS_VALU_MUL_F32",
+    "sq3": "SQ_WAVE_CYCLES SQ_BUSY_CYCLES SQ_ACTIVE_INST_VALU SQ_ACTIVE_INST_SCA SQ_ACTIVE_INST_LDS "
+           "SQ_ACTIVE_INST_VMEM SQ_WAIT_INST_ANY SQ_WAIT_ANY",
+    "sq4": "SQ_INST_CYCLES_VMEM_RD SQ_INST_CYCLES_VMEM_WR SQ_INST_CYCLES_SALU SQ_THREAD_CYCLES_VALU "
+           "SQ_INSTS_VALU_TRANS_F32 SQ_INSTS_VALU_FMA_F32 SQ_LDS_BANK_CONFLICT SQ_WAIT_INST_LDS",
+}
+SQ_ARGS = ("--steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-phase-change --no-reduced "
+           "--adjoint-steps 20 --adjoint-ckpt 10")
+for _g, _c in SQ_GROUPS.items():
+    PROFILE_CMDS[_g] = f"rocprofv3 --pmc {_c} -d gpurun_out/prof/{_g} -o run -- python3 bench.py {SQ_ARGS}"
+# HBM bytes of every kernel of the step and adjoint legs
+PROFILE_CMDS["fetch_all"] = (f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch_all -o run -- "
+                             f"python3 bench.py {SQ_ARGS} --calib-copy-mib 1024")
+PROFILE_CMDS["write_all"] = (f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/write_all -o run -- "
+                             f"python3 bench.py {SQ_ARGS} --calib-copy-mib 1024")
 
 
 def log(msg):
@@ -463,6 +484,36 @@ def summarize_legs(prof_dir):
     print(path, flush=True)
 
 
+def summarize_counters(prof_dir, runs):
+    """Average per-dispatch value of every counter of the rocprofv3 --pmc runs
+    prof_dir/<run> (one directory per pass), per kernel; written to
+    prof_dir/summary/sq_counters.md with the commands of PROFILE_CMDS."""
+    out_dir = os.path.join(prof_dir, "summary")
+    os.makedirs(out_dir, exist_ok=True)
+    table = {}
+    for r in runs:
+        db = _db(os.path.join(prof_dir, r))
+        for name, cname, val in db.execute("select kernel_name, counter_name, value from "
+                                           "counters_collection"):
+            k = name.split("(")[0].replace("void ", "")
+            table.setdefault(k, {}).setdefault(cname, []).append(float(val))
+    keep = [k for k in table if k.startswith("lbm::")]
+    cnames = sorted({c for k in keep for c in table[k]})
+    lines = ["# SQ counters per dispatch (rocprofv3 --pmc, one pass per counter group)", "",
+             "Commands (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -"]
+    lines += [f"    {PROFILE_CMDS[r]}" for r in runs if r in PROFILE_CMDS]
+    lines += ["", "| kernel | dispatches | " + " | ".join(cnames) + " |",
+              "|---|---|" + "---|" * len(cnames)]
+    for k in sorted(keep, key=lambda k: -max(len(v) for v in table[k].values())):
+        vals = table[k]
+        n = max(len(v) for v in vals.values())
+        cells = [f"{sum(vals[c]) / len(vals[c]):.4g}" if c in vals else "" for c in cnames]
+        lines.append(f"| `{k}` | {n} | " + " | ".join(cells) + " |")
+    path = os.path.join(out_dir, "sq_counters.md")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print(path, flush=True)
+
+
 def calibration_copies(mib):
     """Three copy-like passes of a known size (counter calibration): an
     elementwise negation reads and writes every element once."""
@@ -505,12 +556,19 @@ def main():
                     help="summarise rocprofv3 runs under DIR/{trace,fetch,write} and exit")
     ap.add_argument("--summarize-legs", metavar="DIR",
                     help="summarise the all-legs kernel trace under DIR/legs and exit")
+    ap.add_argument("--summarize-counters", metavar="DIR",
+                    help="summarise the counter passes DIR/<run> named by --runs and exit")
+    ap.add_argument("--runs", default="sq1,sq2,sq3,sq4",
+                    help="comma-separated pass directories for --summarize-counters")
     args = ap.parse_args()
     if args.summarize_profiles:
         summarize_profiles(args.summarize_profiles, args.workload)
         return
     if args.summarize_legs:
         summarize_legs(args.summarize_legs)
+        return
+    if args.summarize_counters:
+        summarize_counters(args.summarize_counters, args.runs.split(","))
         return
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

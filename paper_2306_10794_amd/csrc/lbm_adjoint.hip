@@ -93,6 +93,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     using R = double;
     constexpr int Q = L::Q;
     constexpr uint32_t SM = sol_mask<L, RED>();   // the solute set (D2Q5 / D3Q7 when RED)
+    constexpr int QS = __builtin_popcount(SM);
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c) || !c.active) return;
     const DomDev &D = c.D;
@@ -102,8 +103,8 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         if (!((SM >> i) & 1u)) continue;
-        gv[i] = c.kk[i] >= 0 ? a.gin[(long)sol_slot(SM, i) * S + c.kk[i]]
-                             : a.gin[(long)sol_slot(SM, L::opp[i]) * S + c.k];
+        gv[i] = c.kk[i] >= 0 ? a.gin[pidx(sol_slot(SM, i), c.kk[i], QS)]
+                             : a.gin[pidx(sol_slot(SM, L::opp[i]), c.k, QS)];
     }
     // link index: the task's base (lbase of its first node, lane 0, which is
     // active), then by direction, then by lane
@@ -135,7 +136,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
         // TRT at rest: even parts relax with omega_gs toward w C, odd parts
         // with omega_g toward 0 (as the fused step with u = 0)
         const R oms = D.omega_gs, oma = D.omega_g;
-        a.gout[c.k] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
+        a.gout[pidx(0, c.k, QS)] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
@@ -143,8 +144,8 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
             const R gi = (R)gv[i], go = (R)gv[o];
             const R As = oms * sol_w<L>(D, i) * dC;
             const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * oma * (gi - go);
-            a.gout[(long)sol_slot(SM, i) * S + c.k] = (T)(gi - hs - ha + As);
-            a.gout[(long)sol_slot(SM, o) * S + c.k] = (T)(go - hs + ha + As);
+            a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi - hs - ha + As);
+            a.gout[pidx(sol_slot(SM, o), c.k, QS)] = (T)(go - hs + ha + As);
         }
         return;
     }
@@ -153,7 +154,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
         if (!((SM >> i) & 1u)) continue;
         const R gi = (R)gv[i];
         const R geq = sol_w<L>(D, i) * dC;
-        a.gout[(long)sol_slot(SM, i) * S + c.k] = (T)(gi + D.omega_g * (geq - gi));
+        a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi + D.omega_g * (geq - gi));
     }
 }
 
@@ -162,6 +163,7 @@ template <class L, typename T, bool RED>
 __global__ __launch_bounds__(BLK) void k_adj_init(AdjArgs<T> a) {
     constexpr int Q = L::Q;
     constexpr uint32_t SM = sol_mask<L, RED>();
+    constexpr int QS = __builtin_popcount(SM);
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c) || !c.active) return;
     const long S = a.S;
@@ -169,7 +171,7 @@ __global__ __launch_bounds__(BLK) void k_adj_init(AdjArgs<T> a) {
 #pragma unroll
     for (int j = 0; j < Q; j++)
         if ((SM >> j) & 1u)
-            a.pout[(long)sol_slot(SM, j) * S + c.k] = (T)(c.kk[j] >= 0 ? a.dldc[a.nodeof[c.kk[j]]] : own);
+            a.pout[pidx(sol_slot(SM, j), c.k, QS)] = (T)(c.kk[j] >= 0 ? a.dldc[a.nodeof[c.kk[j]]] : own);
 }
 
 template <class L, typename T, bool RED, bool TRT>
@@ -177,6 +179,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     using R = double;
     constexpr int Q = L::Q;
     constexpr uint32_t SM = sol_mask<L, RED>();
+    constexpr int QS = __builtin_popcount(SM);
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c) || !c.active) return;
     const DomDev &D = c.D;
@@ -188,7 +191,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     for (int d = 0; d < Q; d++) {
         if (!((SM >> d) & 1u)) continue;
         const int kd = c.kk[L::opp[d]];
-        mu[d] = kd >= 0 ? a.pin[(long)sol_slot(SM, d) * S + kd] : a.pin[(long)sol_slot(SM, L::opp[d]) * S + c.k];
+        mu[d] = kd >= 0 ? a.pin[pidx(sol_slot(SM, d), kd, QS)] : a.pin[pidx(sol_slot(SM, L::opp[d]), c.k, QS)];
     }
     R m = R(0);
 #pragma unroll
@@ -199,7 +202,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     // mu_opp(j) + oms m, which is BGK's when oms = om
     const R om = D.omega_g, om1 = R(1) - om, oms = D.omega_gs;
     const R ta = R(1) - R(0.5) * (oms + om), tb = R(0.5) * (om - oms);
-    a.pout[c.k] = (T)(TRT ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
+    a.pout[pidx(0, c.k, QS)] = (T)(TRT ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
     // link index: the task's base (lbase of its first node, lane 0, which is
     // active), then by direction, then by lane
     const int lt = __builtin_amdgcn_readfirstlane(c.lb);
@@ -225,7 +228,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
         const int o = L::opp[i];
-        const long si = (long)sol_slot(SM, i) * S, so = (long)sol_slot(SM, o) * S;
+        const int si = sol_slot(SM, i), so = sol_slot(SM, o);
         R nui, nuo;
         if constexpr (TRT) {
             nui = ta * (R)mu[i] + tb * (R)mu[o] + oms * m;
@@ -240,8 +243,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const int l = lpos[i];
             const R beta = (R)a.lbeta[l];
             const bool pulled = D.mech == LBM_PRECOLL && !lo;
-            const R src = pulled ? (R)(c.kk[o] >= 0 ? a.gin[so + c.kk[o]] : a.gin[si + c.k])
-                                 : (R)a.gin[so + c.k];
+            const R src = pulled ? (R)(c.kk[o] >= 0 ? a.gin[pidx(so, c.kk[o], QS)] : a.gin[pidx(si, c.k, QS)])
+                                 : (R)a.gin[pidx(so, c.k, QS)];
             a.gbeta[l] += nui * (src - sol_w<L>(D, i) * D.ceq_dev);
             if (pulled) {
                 outo += beta * nui;
@@ -254,8 +257,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const int l = lpos[o];
             const R beta = (R)a.lbeta[l];
             const bool pulled = D.mech == LBM_PRECOLL && !li;
-            const R src = pulled ? (R)(c.kk[i] >= 0 ? a.gin[si + c.kk[i]] : a.gin[so + c.k])
-                                 : (R)a.gin[si + c.k];
+            const R src = pulled ? (R)(c.kk[i] >= 0 ? a.gin[pidx(si, c.kk[i], QS)] : a.gin[pidx(so, c.k, QS)])
+                                 : (R)a.gin[pidx(si, c.k, QS)];
             a.gbeta[l] += nuo * (src - sol_w<L>(D, o) * D.ceq_dev);
             if (pulled) {
                 outi += beta * nuo;
@@ -264,8 +267,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
                 outo = beta * nuo;
             }
         }
-        a.pout[si + c.k] = (T)outi;
-        a.pout[so + c.k] = (T)outo;
+        a.pout[pidx(si, c.k, QS)] = (T)outi;
+        a.pout[pidx(so, c.k, QS)] = (T)outo;
     }
 }
 
@@ -322,10 +325,10 @@ __global__ __launch_bounds__(BLK) void k_rest_check(long nf, long S, const T *__
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
     if (k >= nf) return;
     double rref = 0.0;
-    for (int i = 0; i < L::Q; i++) rref += (double)f[(long)i * S] + L::w[i] * rho0;
+    for (int i = 0; i < L::Q; i++) rref += (double)f[pidx(i, 0, L::Q)] + L::w[i] * rho0;
     bool off = false;
     for (int i = 0; i < L::Q; i++) {
-        const double v = (double)f[(long)i * S + k] + L::w[i] * rho0;
+        const double v = (double)f[pidx(i, k, L::Q)] + L::w[i] * rho0;
         off |= !(fabs(v - L::w[i] * rref) <= 1e-9 * fabs(rref));
     }
     if (off) atomicOr(flag, 1);

@@ -1122,8 +1122,8 @@ lbm_status lbm_get_diag(lbm_ctx *ctx, lbm_diag *out) {
     return LBM_OK;
 }
 
-// state layout: header (64 B) | f (Q*N of T) | g (QS*N of T) | phi | kr (N
-// doubles) | nrm (3N doubles) | solid (N bytes)
+// state layout: header | f (Q*S of T) | g (QS*S of T), both in the blocked
+// population layout | phi | kr (N doubles) | nrm (3N doubles) | solid (N bytes)
 struct StateHeader {
     uint64_t magic;
     int64_t N, Q, precision, step, n_events;
@@ -1136,7 +1136,7 @@ lbm_status lbm_state_bytes(const lbm_ctx *ctx, size_t *bytes) {
     const Ctx *c = (const Ctx *)ctx;
     if (!c || !bytes) return LBM_EINVAL;
     const size_t ts = c->fp64 ? 8 : 4;
-    *bytes = sizeof(StateHeader) + ts * (c->Q + c->QS) * c->N + 8 * 5 * c->N + c->N;
+    *bytes = sizeof(StateHeader) + ts * (c->Q + c->QS) * c->S + 8 * 5 * c->N + c->N;
     return LBM_OK;
 }
 
@@ -1155,10 +1155,9 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes) {
     }
     if (!dev_ptr_ok(dev_buf)) return bad_ptr(c, "state buffer");
     const size_t ts = c->fp64 ? 8 : 4;
-    const size_t pb = ts * c->N;
     StateHeader h;
     memset(&h, 0, sizeof h);
-    h.magic = 0x4c424d5242433032ULL;
+    h.magic = 0x4c424d5242433033ULL;
     h.N = c->N; h.Q = c->Q; h.QS = c->QS; h.precision = c->p.precision; h.step = c->step;
     h.n_events = c->n_events;
     double acc[5] = {0, 0, 0, 0, 0};
@@ -1173,10 +1172,11 @@ lbm_status lbm_save_state(lbm_ctx *ctx, void *dev_buf, size_t bytes) {
     char *b = (char *)dev_buf;
     e = hipMemcpyAsync(b, &h, sizeof h, hipMemcpyHostToDevice, c->stream);
     size_t off = sizeof h;
-    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
-        e = hipMemcpyAsync(b + off, (char *)c->f[c->cur] + i * ts * c->S, pb, hipMemcpyDeviceToDevice, c->stream);
-    for (int i = 0; i < c->QS && e == hipSuccess; i++, off += pb)
-        e = hipMemcpyAsync(b + off, (char *)c->g[c->cur] + i * ts * c->S, pb, hipMemcpyDeviceToDevice, c->stream);
+    const size_t fb = ts * c->Q * c->S, gb = ts * c->QS * c->S;
+    if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->f[c->cur], fb, hipMemcpyDeviceToDevice, c->stream);
+    off += fb;
+    if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->g[c->cur], gb, hipMemcpyDeviceToDevice, c->stream);
+    off += gb;
     if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->phi, 8 * c->N, hipMemcpyDeviceToDevice, c->stream);
     off += 8 * c->N;
     if (e == hipSuccess) e = hipMemcpyAsync(b + off, c->kr, 8 * c->N, hipMemcpyDeviceToDevice, c->stream);
@@ -1204,14 +1204,14 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
     hipError_t e = hipMemcpyAsync(&h, b, sizeof h, hipMemcpyDeviceToHost, c->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
     if (e != hipSuccess) return dev_err(c, e, "load_state");
-    if (h.magic != 0x4c424d5242433032ULL || h.N != c->N || h.Q != c->Q || h.QS != c->QS ||
+    if (h.magic != 0x4c424d5242433033ULL || h.N != c->N || h.Q != c->Q || h.QS != c->QS ||
         h.precision != c->p.precision) {
         c->err = "state buffer does not match this context";
         return LBM_EINVAL;
     }
     const size_t ts = c->fp64 ? 8 : 4;
-    const size_t pb = ts * c->N;
-    const size_t pops = sizeof h, phio = pops + (c->Q + c->QS) * pb;
+    const size_t fb = ts * c->Q * c->S, gb = ts * c->QS * c->S;
+    const size_t pops = sizeof h, phio = pops + fb + gb;
     // geometry first (rebuilds links from solid, normals and k_r), then state
     const double *phi_src = (const double *)(b + phio);
     const double *kr_src = (const double *)(b + phio + 8 * c->N);
@@ -1231,11 +1231,8 @@ lbm_status lbm_load_state(lbm_ctx *ctx, const void *dev_buf, size_t bytes) {
     c->n_sif = ns;
     c->have_geom = true;
     c->cur = 0;
-    size_t off = pops;
-    for (int i = 0; i < c->Q && e == hipSuccess; i++, off += pb)
-        e = hipMemcpyAsync((char *)c->f[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
-    for (int i = 0; i < c->QS && e == hipSuccess; i++, off += pb)
-        e = hipMemcpyAsync((char *)c->g[0] + i * ts * c->S, b + off, pb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->f[0], b + pops, fb, hipMemcpyDeviceToDevice, c->stream);
+    if (e == hipSuccess) e = hipMemcpyAsync(c->g[0], b + pops + fb, gb, hipMemcpyDeviceToDevice, c->stream);
     // the cumulative exchanges (the diag sums in between are recomputed)
     double acc[5] = {h.wall_ex, 0.0, 0.0, h.inlet_ex, h.outlet_ex};
     if (e == hipSuccess) e = hipMemcpyAsync(c->dacc, acc, sizeof acc, hipMemcpyHostToDevice, c->stream);

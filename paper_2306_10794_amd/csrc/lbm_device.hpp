@@ -83,6 +83,15 @@ __host__ __device__ constexpr int sol_slot(uint32_t m, int i) {
     return __builtin_popcount(m & ((1u << i) - 1u));
 }
 
+// Population arrays are blocked by 64 fluid nodes: [k / 64][slot][k % 64]
+// for nq slots per node (Q for the fluid, QS for the solute and the adjoint).
+// A wavefront's 64 consecutive nodes find every direction of theirs in one
+// contiguous stretch of nq * 256 B (FP32), instead of nq streams a full
+// array apart.  The arrays hold nq * S elements (S a multiple of 64).
+__host__ __device__ __forceinline__ long pidx(int slot, long k, int nq) {
+    return ((k >> 6) * nq + slot) * 64 + (k & 63);
+}
+
 // Node flags of the geometry pass (dense, uint32 per node; not read per step)
 //   bits 0..Q-1 : fluid view, upstream site x - e_i is solid or outside a
 //                 non-periodic face

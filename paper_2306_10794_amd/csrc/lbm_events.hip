@@ -82,8 +82,8 @@ __device__ __forceinline__ void pop_moments(const DomDev &D, int ko, const T *f,
     double c = 0.0, r = 0.0;
 #pragma unroll
     for (int i = 0; i < L::Q; i++) {
-        r += (double)f[(long)i * S + ko] + L::w[i] * D.rho0;
-        if ((SM >> i) & 1u) c += (double)g[(long)sol_slot(SM, i) * S + ko] + sol_w<L>(D, i) * D.c_ref;
+        r += (double)f[pidx(i, ko, L::Q)] + L::w[i] * D.rho0;
+        if ((SM >> i) & 1u) c += (double)g[pidx(sol_slot(SM, i), ko, __builtin_popcount(SM))] + sol_w<L>(D, i) * D.c_ref;
     }
     *C = c;
     *rho = r;
@@ -367,14 +367,15 @@ __global__ __launch_bounds__(BLK) void k_relayout(const DomDev *doms, long nf, c
     const long n = nodeof[k];
     const int ko = kof_old[n];
     if (ko >= 0) {
-        for (int i = 0; i < L::Q; i++) fn[(long)i * S + k] = fo[(long)i * S + ko];
-        for (int s = 0; s < __builtin_popcount(D.smask); s++) gn[(long)s * S + k] = go[(long)s * S + ko];
+        const int qs = __builtin_popcount(D.smask);
+        for (int i = 0; i < L::Q; i++) fn[pidx(i, k, L::Q)] = fo[pidx(i, ko, L::Q)];
+        for (int s = 0; s < qs; s++) gn[pidx(s, k, qs)] = go[pidx(s, ko, qs)];
     } else {
         const EvRec &e = rec[-2 - ko];
         for (int i = 0; i < L::Q; i++) {
-            fn[(long)i * S + k] = (T)(L::w[i] * e.rho - L::w[i] * D.rho0);
+            fn[pidx(i, k, L::Q)] = (T)(L::w[i] * e.rho - L::w[i] * D.rho0);
             if ((D.smask >> i) & 1u)
-                gn[(long)sol_slot(D.smask, i) * S + k] = (T)(D.ws[i] * e.C - D.ws[i] * D.c_ref);
+                gn[pidx(sol_slot(D.smask, i), k, __builtin_popcount(D.smask))] = (T)(D.ws[i] * e.C - D.ws[i] * D.c_ref);
         }
     }
 }

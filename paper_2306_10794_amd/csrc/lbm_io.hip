@@ -22,13 +22,14 @@ __global__ __launch_bounds__(BLK) void k_init(long N, long S, const DomDev *doms
     for (int i = 0; i < L::Q; i++) {
         const double eu = L::ex[i] * ux + L::ey[i] * uy + L::ez[i] * uz;
         const double feq = L::w[i] * r * (1.0 + 3.0 * eu + 4.5 * eu * eu - 1.5 * uu);
-        f0[i * S + k] = T(feq - L::w[i] * D.rho0);
-        f1[i * S + k] = T(0);
+        f0[pidx(i, k, L::Q)] = T(feq - L::w[i] * D.rho0);
+        f1[pidx(i, k, L::Q)] = T(0);
         if (!((D.smask >> i) & 1u)) continue;
         const long s = sol_slot(D.smask, i);
         const double geq = D.ws[i] * C * (1.0 + eu / D.cs2s);
-        g0[s * S + k] = T(geq - D.ws[i] * D.c_ref);
-        g1[s * S + k] = T(0);
+        const int qs = __builtin_popcount(D.smask);
+        g0[pidx(s, k, qs)] = T(geq - D.ws[i] * D.c_ref);
+        g1[pidx(s, k, qs)] = T(0);
     }
 }
 
@@ -46,12 +47,12 @@ __global__ __launch_bounds__(BLK) void k_fields(long N, long S, const DomDev *do
     if (!sol) {
         double dr = 0, dc = 0;
         for (int i = 0; i < L::Q; i++) {
-            const double fi = (double)f[i * S + k];
+            const double fi = (double)f[pidx(i, k, L::Q)];
             dr += fi;
             jx += L::ex[i] * fi;
             jy += L::ey[i] * fi;
             jz += L::ez[i] * fi;
-            if ((D.smask >> i) & 1u) dc += (double)g[sol_slot(D.smask, i) * S + k];
+            if ((D.smask >> i) & 1u) dc += (double)g[pidx(sol_slot(D.smask, i), k, __builtin_popcount(D.smask))];
         }
         r = D.rho0 + dr;
         C = D.c_ref + dc;
@@ -76,10 +77,10 @@ __global__ __launch_bounds__(BLK) void k_pops(long N, long S, const DomDev *doms
     const int k = kof[n];
     const DomDev &D = doms[find_dom(noff, ndom, n)];
     for (int i = 0; i < L::Q; i++) {
-        if (fo) fo[i * N + n] = k < 0 ? 0.0 : (double)f[i * S + k] + L::w[i] * D.rho0;
+        if (fo) fo[i * N + n] = k < 0 ? 0.0 : (double)f[pidx(i, k, L::Q)] + L::w[i] * D.rho0;
         if (!go || !((D.smask >> i) & 1u)) continue;
         const long s = sol_slot(D.smask, i);
-        go[s * N + n] = k < 0 ? 0.0 : (double)g[s * S + k] + D.ws[i] * D.c_ref;
+        go[s * N + n] = k < 0 ? 0.0 : (double)g[pidx(s, k, __builtin_popcount(D.smask))] + D.ws[i] * D.c_ref;
     }
 }
 
@@ -113,10 +114,10 @@ __global__ __launch_bounds__(BLK) void k_diag(long N, long S, const DomDev *doms
             const DomDev &D = doms[find_dom(noff, ndom, n)];
             double dc = 0.0;
             for (int i = 0; i < L::Q; i++) {
-                const double fi = (double)f[i * S + k];
+                const double fi = (double)f[pidx(i, k, L::Q)];
                 if (!isfinite(fi)) bad = 1;
                 if (!((D.smask >> i) & 1u)) continue;
-                const double gi = (double)g[sol_slot(D.smask, i) * S + k];
+                const double gi = (double)g[pidx(sol_slot(D.smask, i), k, __builtin_popcount(D.smask))];
                 if (!isfinite(gi)) bad = 1;
                 dc += gi;
             }

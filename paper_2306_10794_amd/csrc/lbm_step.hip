@@ -145,26 +145,47 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     int kk[Q];
     uint32_t solidnb = 0u;
     kk[0] = k;
+    // The common case, decided once per wavefront: every pull of every lane
+    // is resolved by the table (no box face, no shifted wrap, all three x
+    // columns inside it).  Then the classification is straight-line selects;
+    // otherwise each direction takes the general path.
+    const bool tab_ok = slots_fit && outm == 0u && shiftm == 0u && tcol[0] >= 0 && tcol[1] >= 0 &&
+                        tcol[2] >= 0;
+    if (__ballot(!tab_ok) == 0ull) {
 #pragma unroll
-    for (int i = 1; i < Q; i++) {
-        const int v = L::ex[i] + 1;
-        const bool in_tab = tcol[v] >= 0;
-        // the shuffles run on every lane: a shuffle reads zero from a lane
-        // that is inactive at that point
-        const int src = in_tab ? ((L::DIM == 3 ? (1 - L::ez[i]) * TY : 0) + 1 - L::ey[i]) * nwd + tcol[v] : 0;
-        const unsigned lo = __shfl((unsigned)(wm & 0xffffffffull), src, 64);
-        const unsigned hi = __shfl((unsigned)(wm >> 32), src, 64);
-        const int pb = __shfl(wpb, src, 64);
-        if (outm & (1u << i)) {
-            kk[i] = -2;
-        } else if (!in_tab || (shiftm & (1u << i))) {
-            kk[i] = nb_compact(rows, W, b, x - L::ex[i], y - L::ey[i], z - L::ez[i]);
-        } else {
+        for (int i = 1; i < Q; i++) {
+            const int v = L::ex[i] + 1;
+            const int src = ((L::DIM == 3 ? (1 - L::ez[i]) * TY : 0) + 1 - L::ey[i]) * nwd + tcol[v];
+            const unsigned lo = __shfl((unsigned)(wm & 0xffffffffull), src, 64);
+            const unsigned hi = __shfl((unsigned)(wm >> 32), src, 64);
+            const int pb = __shfl(wpb, src, 64);
             const unsigned long long m = ((unsigned long long)hi << 32) | lo;
             const unsigned long long bit = tbit[v];
             kk[i] = (m & bit) ? pb + __popcll(m & (bit - 1ull)) : -1;
+            if (kk[i] == -1) solidnb |= 1u << i;
         }
-        if (kk[i] == -1) solidnb |= 1u << i;
+    } else {
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            const int v = L::ex[i] + 1;
+            const bool in_tab = tcol[v] >= 0;
+            // the shuffles run on every lane: a shuffle reads zero from a lane
+            // that is inactive at that point
+            const int src = in_tab ? ((L::DIM == 3 ? (1 - L::ez[i]) * TY : 0) + 1 - L::ey[i]) * nwd + tcol[v] : 0;
+            const unsigned lo = __shfl((unsigned)(wm & 0xffffffffull), src, 64);
+            const unsigned hi = __shfl((unsigned)(wm >> 32), src, 64);
+            const int pb = __shfl(wpb, src, 64);
+            if (outm & (1u << i)) {
+                kk[i] = -2;
+            } else if (!in_tab || (shiftm & (1u << i))) {
+                kk[i] = nb_compact(rows, W, b, x - L::ex[i], y - L::ey[i], z - L::ez[i]);
+            } else {
+                const unsigned long long m = ((unsigned long long)hi << 32) | lo;
+                const unsigned long long bit = tbit[v];
+                kk[i] = (m & bit) ? pb + __popcll(m & (bit - 1ull)) : -1;
+            }
+            if (kk[i] == -1) solidnb |= 1u << i;
+        }
     }
     const uint32_t rbc = active ? (solidnb & ~cross & SM) : 0u;
 
@@ -204,7 +225,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         // fluid neighbour: pull along i; solid or box face: own value along opp(i)
-        fv[i] = kk[i] >= 0 ? a.fin[(long)i * S + kk[i]] : a.fin[(long)L::opp[i] * S + k];
+        fv[i] = kk[i] >= 0 ? a.fin[pidx(i, kk[i], Q)] : a.fin[pidx(L::opp[i], k, Q)];
     }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
@@ -222,7 +243,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             }
         }
         // fluid neighbour: pull; solid or box face: own value along opp(i)
-        gv[i] = e >= 0 ? a.gin[(long)sol_slot(SM, i) * S + e] : a.gin[(long)sol_slot(SM, L::opp[i]) * S + k];
+        gv[i] = e >= 0 ? a.gin[pidx(sol_slot(SM, i), e, QS)] : a.gin[pidx(sol_slot(SM, L::opp[i]), k, QS)];
     }
 
     // ---- fluid: moments and Guo-forced BGK ----
@@ -261,9 +282,14 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // f* = f + om (f_eq - f) + ff S, a direction and its opposite together:
     // e.u, e.m and e.F change sign with e, so f*_(i, opp i) = (1 - om) f + A
     // +- B with the even part A = w (om (drho + rho (9/2 (e.u)^2 - 3/2 u.u))
-    // + ff (9 (e.u)(e.F) - 3 u.F)) and the odd part B = 3 w (om e.m + ff e.F)
+    // + ff (9 (e.u)(e.F) - 3 u.F)) and the odd part B = 3 w (om e.m + ff e.F).
+    // A is evaluated as w (base + e.u (9/2 om rho e.u + 9 ff e.F)) with the
+    // node's base = om (drho - 3/2 rho u.u) - 3 ff u.F: two fused
+    // multiply-adds per pair on top of e.u
     const R om = D.omega_f, ff = D.force_fac, om1 = R(1) - om;
-    a.fout[k] = (T)(om1 * fp[0] + R(L::w[0]) * (om * (drho - R(1.5) * rho * uu) - R(3) * ff * uF));
+    const R base = om * (drho - R(1.5) * rho * uu) - R(3) * ff * uF;
+    const R c45 = R(4.5) * om * rho;
+    a.fout[pidx(0, k, Q)] = (T)(om1 * fp[0] + R(L::w[0]) * base);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i) continue;
@@ -272,18 +298,18 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         const R em = R(L::ex[i]) * mx + R(L::ey[i]) * my + R(L::ez[i]) * mz;
         const R eF = R(L::ex[i]) * D.F[0] + R(L::ey[i]) * D.F[1] + R(L::ez[i]) * D.F[2];
         const R wi = R(L::w[i]);
-        const R A = wi * (om * (drho + rho * (R(4.5) * eu * eu - R(1.5) * uu)) + ff * (R(9) * eu * eF - R(3) * uF));
+        const R A = wi * (base + eu * (c45 * eu + R(9) * ff * eF));
         if constexpr (TRT) {
             // TRT: the odd parts (f_i - f_o)/2, e.m and e.F relax with the
             // second rate, the even ones with om
             const R B = R(3) * wi * (D.omega_fm * em + D.force_fac_m * eF);
             const R hp = R(0.5) * om * (fp[i] + fp[o]), hm = R(0.5) * D.omega_fm * (fp[i] - fp[o]);
-            a.fout[(long)i * S + k] = (T)(fp[i] - hp - hm + (A + B));
-            a.fout[(long)o * S + k] = (T)(fp[o] - hp + hm + (A - B));
+            a.fout[pidx(i, k, Q)] = (T)(fp[i] - hp - hm + (A + B));
+            a.fout[pidx(o, k, Q)] = (T)(fp[o] - hp + hm + (A - B));
         } else {
             const R B = R(3) * wi * (om * em + ff * eF);
-            a.fout[(long)i * S + k] = (T)(om1 * fp[i] + (A + B));
-            a.fout[(long)o * S + k] = (T)(om1 * fp[o] + (A - B));
+            a.fout[pidx(i, k, Q)] = (T)(om1 * fp[i] + (A + B));
+            a.fout[pidx(o, k, Q)] = (T)(om1 * fp[o] + (A - B));
         }
     }
 
@@ -301,7 +327,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             for (int i = 1; i < Q; i++) {
                 if (!((SM >> i) & 1u) || !(cross & (1u << i))) continue;
                 if (cross_hi & (1u << i)) {
-                    xout += (R)gv[i] - (R)a.gin[(long)sol_slot(SM, L::opp[i]) * S + k];
+                    xout += (R)gv[i] - (R)a.gin[pidx(sol_slot(SM, L::opp[i]), k, QS)];
                 } else {
                     const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
                     const R gin = sol_w<L>(D, i) * (D.c_in - D.c_ref) + sol_w<L>(D, i) * D.c_in * eu * D.inv_cs2s;
@@ -384,24 +410,27 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     // g* = g + omg (g_eq - g), g_eq = ws (dC + C e.u / c_s^2): in pairs as
     // above, (1 - omg) g + As +- Bs with As = omg ws dC, Bs = omg ws C e.u / c_s^2
     // TRT: the even parts relax with omega_gs (BGK: omega_gs = omg)
-    const R omg = D.omega_g, omg1 = R(1) - omg, Cu = omg * C * D.inv_cs2s, oms = D.omega_gs;
-    a.gout[k] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
+    // the moving weights are w_i wsc: with the node's Cw = omg C wsc / c_s^2
+    // and Aw = omg wsc dC (oms for TRT), As = w_i Aw and Bs = w_i Cw e.u
+    const R omg = D.omega_g, omg1 = R(1) - omg, oms = D.omega_gs;
+    const R Cw = omg * C * D.inv_cs2s * D.wsc;
+    const R Aw = (TRT ? oms : omg) * D.wsc * dC;
+    a.gout[pidx(0, k, QS)] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
         const int o = L::opp[i];
-        const long si = (long)sol_slot(SM, i) * S + k, so = (long)sol_slot(SM, o) * S + k;
+        const long si = pidx(sol_slot(SM, i), k, QS), so = pidx(sol_slot(SM, o), k, QS);
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
-        const R ws = sol_w<L>(D, i);
-        const R Bs = ws * Cu * eu;
+        const R wi = R(L::w[i]);
+        const R Bs = (wi * Cw) * eu;
+        const R As = wi * Aw;
         if constexpr (TRT) {
-            const R As = oms * ws * dC;
             const R gi = (R)gv[i], go = (R)gv[o];
             const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * omg * (gi - go);
             a.gout[si] = (T)(gi - hs - ha + (As + Bs));
             a.gout[so] = (T)(go - hs + ha + (As - Bs));
         } else {
-            const R As = omg * ws * dC;
             a.gout[si] = (T)(omg1 * (R)gv[i] + (As + Bs));
             a.gout[so] = (T)(omg1 * (R)gv[o] + (As - Bs));
         }
