@@ -321,9 +321,10 @@ __global__ __launch_bounds__(BLK) void k_adj_zero(double *p, long n) {
 // later steps that the adjoint (which recomputes with u = 0) would not see.
 template <class L, typename T>
 __global__ __launch_bounds__(BLK) void k_rest_check(long nf, long S, const T *__restrict__ f,
-                                                    double rho0, int32_t *flag) {
+                                                    const int32_t *__restrict__ nodeof, double rho0,
+                                                    int32_t *flag) {
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
-    if (k >= nf) return;
+    if (k >= nf || nodeof[k] < 0) return;
     double rref = 0.0;
     for (int i = 0; i < L::Q; i++) rref += (double)f[pidx(i, 0, L::Q)] + L::w[i] * rho0;
     bool off = false;
@@ -358,10 +359,10 @@ static AdjArgs<T> adj_args(Ctx &c) {
 template <class L, typename T>
 static hipError_t rest_check_impl(Ctx &c, bool *at_rest) {
     hipLaunchKernelGGL(k_zero_i32_adj, dim3(1), dim3(1), 0, c.stream, c.iacc + 5);
-    const long nf = c.n_fluid;
+    const long nf = c.n_slots;
     if (nf > 0)
         hipLaunchKernelGGL((k_rest_check<L, T>), dim3((nf + BLK - 1) / BLK), dim3(BLK), 0, c.stream,
-                           nf, c.S, (const T *)c.f[c.cur], c.fp64 ? 0.0 : c.p.rho0, c.iacc + 5);
+                           nf, c.S, (const T *)c.f[c.cur], c.nodeof, c.fp64 ? 0.0 : c.p.rho0, c.iacc + 5);
     int32_t flag = 0;
     hipError_t e = hipGetLastError();
     if (e == hipSuccess) e = hipMemcpyAsync(&flag, c.iacc + 5, 4, hipMemcpyDeviceToHost, c.stream);

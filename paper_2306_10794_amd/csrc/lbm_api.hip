@@ -107,8 +107,9 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *doms = take(sizeof(DomDev) * nd);
     char *noff = take(8 * (nd + 1)), *woff = take(8 * (nd + 1)), *roff = take(8 * (nd + 1));
     char *rows = take(sizeof(RowWord) * RW), *tasks = take(sizeof(Task) * task_cap);
-    char *nodeof = take(4 * N), *kof = take(4 * N), *lbase = take(4 * N);
-    char *flags = take(4 * N), *rmask = take(4 * N), *cnt = take(4 * N), *sidx = take(4 * N);
+    // per slot (S >= N entries): nodeof, lbase, and the scan temporaries
+    char *nodeof = take(4 * S), *kof = take(4 * N), *lbase = take(4 * S);
+    char *flags = take(4 * N), *rmask = take(4 * N), *cnt = take(4 * S), *sidx = take(4 * S);
     char *phi = take(8 * N), *kr = take(8 * N), *nrm = take(24 * N), *solid = take(N);
     char *phif = take(8 * S), *phis = take(8 * L);
     const bool ceqf = p[0].ceq_field != 0;

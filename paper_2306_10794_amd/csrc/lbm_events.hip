@@ -365,6 +365,7 @@ __global__ __launch_bounds__(BLK) void k_relayout(const DomDev *doms, long nf, c
     if (k >= nf) return;
     const DomDev D = doms[0];
     const long n = nodeof[k];
+    if (n < 0) return;   // a hole
     const int ko = kof_old[n];
     if (ko >= 0) {
         const int qs = __builtin_popcount(D.smask);
@@ -409,7 +410,7 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     int32_t h[2] = {0, 0};
     hipError_t e = hipSuccess;
     {
-        const long nf = c.n_fluid, ns = c.n_sif, n = nf > ns ? nf : ns;
+        const long nf = c.n_slots, ns = c.n_sif, n = nf > ns ? nf : ns;
         hipLaunchKernelGGL(k_zero2_i32, dim3(1), dim3(1), 0, st, any);
         if (n > 0)
             hipLaunchKernelGGL(k_event_check, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, st, nf, c.phif, ns,
@@ -468,7 +469,7 @@ __global__ __launch_bounds__(BLK) void k_zero_links(T *p, long n) {
 
 template <class L, typename T>
 static hipError_t relayout_impl(Ctx &c) {
-    const long nf = c.n_fluid;
+    const long nf = c.n_slots;
     // the last step's exchanges belong to the old link list
     if (c.n_links > 0)
         hipLaunchKernelGGL((k_zero_links<T>), dim3((c.n_links + BLK - 1) / BLK), dim3(BLK), 0,

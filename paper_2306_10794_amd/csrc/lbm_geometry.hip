@@ -291,7 +291,9 @@ __device__ int plane_tasks(const DomDev &D, int d, const RowWord *rows, long r0,
     return nt;
 }
 
-// Tasks of one wide row r (count; write when `tasks` is given).
+// Tasks of one wide row r (count; write when `tasks` is given).  A task that
+// ends short of 64 nodes ends at a word boundary: the window is checked once
+// per word, for all of the word's nodes (a full task may end inside a word).
 template <class L>
 __device__ int wide_row_tasks(const DomDev &D, int d, const RowWord *rows, long r, Task *tasks) {
     const int W = D.W, maxw = task_max_words<L>();
@@ -306,11 +308,15 @@ __device__ int wide_row_tasks(const DomDev &D, int d, const RowWord *rows, long 
         const RowWord rw = rows[D.word_off + r * W + w];
         unsigned long long m = rw.mask;
         int k = rw.pb;
+        if (m && count > 0) {
+            const int xl = 64 * w + 63 - __clzll((long long)m);
+            if (min(W - 1, (xl + 1) >> 6) - wlo + 1 > maxw) emit();
+        }
         while (m) {
             const int x = 64 * w + __ffsll((long long)m) - 1;
             m &= m - 1ull;
             const int hi = min(W - 1, (x + 1) >> 6);
-            if (count > 0 && (count == 64 || hi - wlo + 1 > maxw)) emit();
+            if (count == 64) emit();
             if (count == 0) {
                 k0 = k;
                 wlo = x == 0 ? 0 : (x - 1) >> 6;
@@ -358,11 +364,71 @@ __global__ __launch_bounds__(BLK) void k_row_tasks(Geo g, long R, const RowWord 
     }
 }
 
-// reactive links per compact node, then the link records
-__global__ __launch_bounds__(BLK) void k_link_count(long nf, const int32_t *nodeof,
+// ---------------------------------------------------------------------------
+// Slots.  Every task gets a block of 64 population slots of its own, the
+// blocks in node order: the nodes of the task of rank r (in node order) take
+// slots 64 r .. 64 r + cnt - 1, so that a wavefront's own loads and stores
+// cover whole 256-byte lines of the blocked population arrays.  A task that
+// ends short of 64 nodes ends at a row-word boundary (a full one may end
+// inside a word, and then its successor's slots follow on without a gap), so
+// the nodes of every row word still have consecutive slots: the row word's pb
+// becomes the slot of its first fluid node.  Slots past a short task's nodes
+// are holes (nodeof = -1) that no kernel reads or writes.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(BLK) void k_task_marks(const Task *tasks, long nt, int32_t *mark) {
+    const long t = (long)blockIdx.x * BLK + threadIdx.x;
+    if (t < nt) mark[tasks[t].k0] = 1;
+}
+
+// tasks: compact k0 -> 64 * rank; tstart[rank] = the compact k0
+__global__ __launch_bounds__(BLK) void k_task_slots(Task *tasks, long nt, const int32_t *rank,
+                                                    int32_t *tstart) {
+    const long t = (long)blockIdx.x * BLK + threadIdx.x;
+    if (t >= nt) return;
+    const int k0 = tasks[t].k0, r = rank[k0];
+    tstart[r] = k0;
+    tasks[t].k0 = 64 * r;
+}
+
+// slot of compact index c (rank: exclusive scan of the task-start marks)
+__device__ __forceinline__ int slot_of(int c, const int32_t *mark, const int32_t *rank,
+                                       const int32_t *tstart) {
+    const int r = rank[c] + mark[c] - 1;
+    return 64 * r + (c - tstart[r]);
+}
+
+__global__ __launch_bounds__(BLK) void k_slot_nodes(long N, int32_t *kof, int32_t *nodeof,
+                                                    const int32_t *mark, const int32_t *rank,
+                                                    const int32_t *tstart) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N || kof[n] < 0) return;
+    const int s = slot_of(kof[n], mark, rank, tstart);
+    kof[n] = s;
+    nodeof[s] = (int32_t)n;
+}
+
+// every word, empty ones too: a word's pb is the slot of the first fluid node
+// at or after it (the kernels find a lane's row by comparing its slot with the
+// pb of each row's first word), ns past the last one
+__global__ __launch_bounds__(BLK) void k_slot_words(long RW, RowWord *rows, long nf, long ns,
+                                                    const int32_t *mark, const int32_t *rank,
+                                                    const int32_t *tstart) {
+    const long j = (long)blockIdx.x * BLK + threadIdx.x;
+    if (j >= RW) return;
+    const int c = rows[j].pb;
+    rows[j].pb = c < nf ? slot_of(c, mark, rank, tstart) : (int32_t)ns;
+}
+
+__global__ void k_fill_i32(int32_t *p, long n, int32_t v) {
+    const long i = (long)blockIdx.x * blockDim.x + threadIdx.x;
+    if (i < n) p[i] = v;
+}
+
+// reactive links per slot (holes have none), then the link records
+__global__ __launch_bounds__(BLK) void k_link_count(long ns, const int32_t *nodeof,
                                                     const uint32_t *rmask, int32_t *cnt) {
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
-    if (k < nf) cnt[k] = __popc(rmask[nodeof[k]]);
+    if (k < ns) cnt[k] = nodeof[k] >= 0 ? __popc(rmask[nodeof[k]]) : 0;
 }
 
 // Link order.  The links of a task's nodes occupy one range (from lbase of
@@ -405,6 +471,7 @@ __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *no
     const long k = (long)blockIdx.x * BLK + threadIdx.x;
     if (k >= nf) return;
     const long n = nodeof[k];
+    if (n < 0) return;   // a hole
     const uint32_t rm = rmask[n];
     if (!rm) return;
     long nl;
@@ -605,12 +672,29 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     int32_t nt = 0;
     if ((e = read_ints(c, c.iacc, &nt, 1)) != hipSuccess) return e;
     c.n_tasks = nt;
+    // slots: a 64-aligned block per task when they fit the arrays, else the
+    // compact indices themselves
+    long ns = nf;
+    if (nt > 0 && 64L * nt <= c.S) {
+        ns = 64L * nt;
+        const long nfl0 = nf > 0 ? nf : 1;
+        hipLaunchKernelGGL(k_fill_i32, blocks(nfl0), dim3(BLK), 0, st, c.cnt, (long)nf, 0);
+        hipLaunchKernelGGL(k_task_marks, blocks(nt), dim3(BLK), 0, st, c.tasks, (long)nt, c.cnt);
+        if ((e = scan_excl(c, c.cnt, c.sidx, nf, c.iacc)) != hipSuccess) return e;
+        hipLaunchKernelGGL(k_task_slots, blocks(nt), dim3(BLK), 0, st, c.tasks, (long)nt, c.sidx, c.lbase);
+        hipLaunchKernelGGL(k_fill_i32, blocks(ns), dim3(BLK), 0, st, c.nodeof, ns, -1);
+        hipLaunchKernelGGL(k_slot_nodes, dim3(nb), dim3(BLK), 0, st, N, c.kof, c.nodeof, c.cnt, c.sidx,
+                           c.lbase);
+        hipLaunchKernelGGL(k_slot_words, blocks(RW), dim3(BLK), 0, st, RW, c.rows, (long)nf, ns, c.cnt,
+                           c.sidx, c.lbase);
+    }
+    c.n_slots = ns;
     // reactive links
-    const long nfl = nf > 0 ? nf : 1;
-    hipLaunchKernelGGL(k_link_count, blocks(nfl), dim3(BLK), 0, st, (long)nf, c.nodeof, c.rmask, c.cnt);
-    if ((e = scan_excl(c, c.cnt, c.lbase, nf, c.iacc)) != hipSuccess) return e;
-    hipLaunchKernelGGL(k_iface_mark, blocks(nfl), dim3(BLK), 0, st, (long)nf, c.cnt, c.sidx);
-    if ((e = scan_excl(c, c.sidx, c.sidx, nf, c.iacc + 2)) != hipSuccess) return e;
+    const long nfl = ns > 0 ? ns : 1;
+    hipLaunchKernelGGL(k_link_count, blocks(nfl), dim3(BLK), 0, st, ns, c.nodeof, c.rmask, c.cnt);
+    if ((e = scan_excl(c, c.cnt, c.lbase, ns, c.iacc)) != hipSuccess) return e;
+    hipLaunchKernelGGL(k_iface_mark, blocks(nfl), dim3(BLK), 0, st, ns, c.cnt, c.sidx);
+    if ((e = scan_excl(c, c.sidx, c.sidx, ns, c.iacc + 2)) != hipSuccess) return e;
     int32_t t4[4] = {0, 0, 0, 0};
     if ((e = read_ints(c, c.iacc, t4, 4)) != hipSuccess) return e;
     const int32_t tot = t4[0];
@@ -620,7 +704,7 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     if (c.n_tasks > 0)
         hipLaunchKernelGGL((k_link_map<L>), dim3((c.n_tasks + BLK / 64 - 1) / (BLK / 64)), dim3(BLK), 0, st,
                            c.tasks, (long)c.n_tasks, c.nodeof, c.rmask, c.lbase, c.lmap);
-    hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, g, (long)nf, c.nodeof,
+    hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, g, ns, c.nodeof,
                        c.rmask, c.lbase, c.lmap, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir,
                        c.ceq_set ? c.ceq : nullptr, (T *)c.lceq);
     // solid side: per solid interface node, its links in direction order
@@ -636,7 +720,7 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, c.soff, (long)t2[0], t2[1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t2[1] != tot) return hipErrorUnknown;  // every link has exactly one solid end
-    if ((e = launch_phi_gather(c, nf, t2[0])) != hipSuccess) return e;
+    if ((e = launch_phi_gather(c, ns, t2[0])) != hipSuccess) return e;
     return hipStreamSynchronize(st);
 }
 

@@ -135,6 +135,9 @@ struct Ctx {
     size_t ws_bytes;
     int cur;                 // buffer holding the current state
     int64_t n_links, n_sif, n_fluid, n_fluid_iface, n_tasks;
+    int64_t n_slots;         // population slots in use: 64 per task (each task's
+                             // nodes in a 64-aligned block of its own), or
+                             // n_fluid when that would not fit S
     int64_t step, n_events;
     bool have_geom, have_state;
     hipEvent_t ev[4];

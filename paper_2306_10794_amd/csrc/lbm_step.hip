@@ -605,7 +605,7 @@ __global__ __launch_bounds__(BLK) void k_phi_gather(long nf, const int32_t *__re
                                                     const double *__restrict__ phi,
                                                     double *__restrict__ phif, double *__restrict__ phis) {
     const long t = (long)blockIdx.x * BLK + threadIdx.x;
-    if (t < nf) phif[t] = phi[nodeof[t]];
+    if (t < nf) phif[t] = nodeof[t] >= 0 ? phi[nodeof[t]] : 0.0;
     if (t < nsif) phis[t] = phi[sif[t]];
 }
 
@@ -615,7 +615,7 @@ __global__ __launch_bounds__(BLK) void k_phi_scatter(long nf, const int32_t *__r
                                                      const double *__restrict__ phis,
                                                      double *__restrict__ phi) {
     const long t = (long)blockIdx.x * BLK + threadIdx.x;
-    if (t < nf) phi[nodeof[t]] = phif[t];
+    if (t < nf && nodeof[t] >= 0) phi[nodeof[t]] = phif[t];
     if (t < nsif) phi[sif[t]] = phis[t];
 }
 
@@ -630,7 +630,7 @@ hipError_t launch_phi_gather(Ctx &c, long nf, long nsif) {
 
 hipError_t launch_phi_flush(Ctx &c) {
     if (!c.phi_stale) return hipSuccess;
-    const long nf = c.n_fluid, nsif = c.n_sif;
+    const long nf = c.n_slots, nsif = c.n_sif;
     const long n = nf > nsif ? nf : nsif;
     if (n > 0)
         hipLaunchKernelGGL(k_phi_scatter, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, c.stream, nf, c.nodeof,
