@@ -82,18 +82,34 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
-def kernel_bytes(q, ts, n_fluid, n_links, n_fluid_iface, qs=None):
+def kernel_bytes(q, ts, n_fluid, n_links, n_fluid_iface, qs=None, n_tasks=0, n_row_words=0):
     """Algorithmic HBM bytes of one launch of the fused step kernel.
 
     Per fluid node: the fluid lattice reads and writes Q populations and the
     solute lattice QS (= Q unless the solute runs on D2Q5 / D3Q7) of ts bytes
     each (a reactive link reads the node's own population toward the wall in
-    place of a pulled one), plus 4 bytes of node metadata.  Per reactive link:
-    the link coefficient read and the exchange written (2 x ts).  Per fluid
-    interface node: its FP64 solid fraction read and written (16 B).
+    place of a pulled one), and 8 bytes of node metadata (its dense index and
+    the base of its links).  Per reactive link: the link coefficient read and
+    the exchange written (2 x ts).  Per fluid interface node: its FP64 solid
+    fraction read and written (16 B).  Per launch: each 32-byte task record
+    and each 16-byte row word once.
     """
     qs = q if qs is None else qs
-    return n_fluid * ((q + qs) * ts * 2 + 4) + n_links * 2 * ts + n_fluid_iface * 16
+    return (n_fluid * ((q + qs) * ts * 2 + 8) + n_links * 2 * ts + n_fluid_iface * 16 +
+            n_tasks * 32 + n_row_words * 16)
+
+
+def adjoint_kernel_bytes(q, ts, n_fluid, n_links, qs=None):
+    """Algorithmic HBM bytes of one launch of the adjoint's two kernels.
+
+    Recomputation (one solute-only step at rest): per fluid node QS values
+    read and QS written; per reactive link its coefficient read.  Transposed
+    step: per fluid node QS adjoint values read and QS written; per reactive
+    link its coefficient and the source value of the forward step read (ts
+    each) and its FP64 dL/dbeta read and written (16 B)."""
+    qs = q if qs is None else qs
+    return (n_fluid * qs * ts * 2 + n_links * ts,
+            n_fluid * qs * ts * 2 + n_links * (2 * ts + 16))
 
 
 def kernel_sha256():
@@ -137,7 +153,7 @@ def batch_vs_plain(batch_steps, plain_steps, tune_steps):
     import torch
     from lbm_inputs import configs
     from paper_2306_10794_amd import (BatchSimulation, Simulation, LBM_FP32_DEV, lbm_step,
-                                      lbm_autotune)
+                                      lbm_autotune, lbm_set_launch_config, lbm_step_timed)
     t0 = time.perf_counter()
     cases = configs.batch_domains(count=1024, seed=4)
     nf = sum(c.n_fluid for c in cases)
@@ -146,12 +162,29 @@ def batch_vs_plain(batch_steps, plain_steps, tune_steps):
     bs = BatchSimulation(cases, precision=LBM_FP32_DEV, device="cuda:0")
     cfg, tune_ms, tune_n = lbm_autotune(bs.ctx, tune_steps)
     log(f"[batch] autotuned {cfg} at {tune_ms:.4f} ms/step ({tune_n} trial steps)")
+
+    def timed(steps):
+        torch.cuda.synchronize()
+        t = time.perf_counter()
+        lbm_step(bs.ctx, steps)
+        torch.cuda.synchronize()
+        return time.perf_counter() - t
+
+    # the same launch configuration with plain launches and with graph replay
+    # of 64 and of 256 steps per graph launch (persistent-launch candidates)
+    modes = {}
+    for gs in (0, 64, 256):
+        lbm_set_launch_config(bs.ctx, cfg["wg_waves"], cfg["xcd_remap"], gs, cfg["overlap"])
+        n = max(batch_steps // max(gs, 1) * max(gs, 1), max(gs, 1))
+        timed(2 * max(gs, 8))
+        modes[gs] = timed(n) / n * 1e3
+        log(f"[batch] graph_steps {gs}: {modes[gs]:.4f} ms/step over {n} steps")
+    # the two kernels' own durations (HIP events around each launch)
+    k_ms, phi_ms = lbm_step_timed(bs.ctx, 200)
+    kern = (k_ms + phi_ms) / 200
+    lbm_set_launch_config(bs.ctx, **cfg)
     lbm_step(bs.ctx, 2 * max(cfg["graph_steps"], 8))
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    lbm_step(bs.ctx, batch_steps)
-    torch.cuda.synchronize()
-    tb = time.perf_counter() - t0
+    tb = timed(batch_steps)
     d = bs.diag()
     bs.close()
     del bs
@@ -186,6 +219,10 @@ def batch_vs_plain(batch_steps, plain_steps, tune_steps):
                     "D2Q9 fluid + D2Q9 solute, FP32 deviation storage",
         "fluid_nodes": int(nf), "unit": "MLUPS",
         "batched": round(mb, 1), "batched_steps": batch_steps, "launch_config": cfg,
+        "ms_per_step_plain_launches": round(modes[0], 4),
+        "ms_per_step_graph_64": round(modes[64], 4), "ms_per_step_graph_256": round(modes[256], 4),
+        "kernels_ms_per_step": round(kern, 4),
+        "launch_gap_ms_per_step": round(modes[0] - kern, 4),
         "plain_1_stream": round(p1, 1), "plain_8_streams": round(p8, 1), "plain_steps": plain_steps,
         "speedup_vs_1_stream": round(mb / p1, 2), "speedup_vs_8_streams": round(mb / p8, 2),
     }
@@ -198,10 +235,11 @@ def adjoint_ratio(steps, ckpt):
     transposed steps), per step, FP32 deviation storage."""
     import torch
     from lbm_inputs import configs
-    from paper_2306_10794_amd import Simulation, LBM_FP32_DEV, lbm_step
+    from paper_2306_10794_amd import Simulation, LBM_FP32_DEV, lbm_step, lbm_adjoint_timed
     case = configs.rate_recovery(n=128, seed=5)
     sim = Simulation(case, precision=LBM_FP32_DEV, device="cuda:0")
-    nf = sim.diag()["n_fluid"]
+    d0 = sim.diag()
+    nf, nl = d0["n_fluid"], d0["n_links"]
     lbm_step(sim.ctx, 20)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
@@ -226,7 +264,16 @@ def adjoint_ratio(steps, ckpt):
     torch.cuda.synchronize()
     t_adj = time.perf_counter() - t0
     ok = bool(torch.isfinite(g).all())
+    # the backward pass's kernels timed one by one (same gradient)
+    grad_t = torch.empty_like(g)
+    sol_ms, adj_ms = lbm_adjoint_timed(sim.ctx, dl, grad_t)
+    torch.cuda.synchronize()
+    same = bool(torch.equal(grad_t, g))
     sim.close()
+    nseg = (steps + ckpt - 1) // ckpt
+    sol_us = sol_ms / max(steps - nseg, 1) * 1e3
+    adj_us = adj_ms / steps * 1e3
+    sol_b, adj_b = adjoint_kernel_bytes(case.q, 4, nf, nl)
     del sim
     torch.cuda.empty_cache()
     return {
@@ -238,6 +285,18 @@ def adjoint_ratio(steps, ckpt):
         "plain_step_ms": round(t_plain / steps * 1e3, 4),
         "adjoint_ms_per_step": round(t_adj / steps * 1e3, 4),
         "ratio": round(t_adj / t_fwd, 3), "finite": ok,
+        # the backward pass against the solute-only step it transposes (the
+        # recomputation kernel is that step): a fairer measure than the
+        # recorded fused step, which also streams the idle fluid lattice
+        "ratio_vs_solute_step": round(t_adj / steps * 1e6 / sol_us, 3),
+        "reactive_links": int(nl),
+        "recompute_kernel": {"kernel": "k_sol_step", "avg_us": round(sol_us, 2), "bytes_per_launch": int(sol_b),
+                             "achieved_gbs": round(sol_b / sol_us / 1e3, 1),
+                             "frac": round(sol_b / sol_us / 1e3 / HBM_PEAK_GBS, 4)},
+        "transposed_kernel": {"kernel": "k_adj_step", "avg_us": round(adj_us, 2), "bytes_per_launch": int(adj_b),
+                              "achieved_gbs": round(adj_b / adj_us / 1e3, 1),
+                              "frac": round(adj_b / adj_us / 1e3 / HBM_PEAK_GBS, 4)},
+        "timed_gradient_identical": same,
     }
 
 
@@ -284,7 +343,8 @@ def reduced_run(case, steps, warmup):
     k_ms, phi_ms = lbm_step_timed(sim.ctx, steps)
     d = sim.diag()
     sim.close()
-    kb = kernel_bytes(rc.q, 4, d["n_fluid"], d["n_links"], d["n_fluid_iface"], qs=rc.qs)
+    kb = kernel_bytes(rc.q, 4, d["n_fluid"], d["n_links"], d["n_fluid_iface"], qs=rc.qs,
+                      n_tasks=d["n_tasks"], n_row_words=d["n_row_words"])
     k_s = k_ms / steps / 1e3
     return {"lattices": f"D3Q19 fluid + D3Q{rc.qs} solute", "j0": round(rc.j0, 6),
             "mlups": round(d["n_fluid"] * steps / wall / 1e6, 1), "ms_per_step": round(wall / steps * 1e3, 4),
@@ -603,7 +663,8 @@ def main():
 
     n_fluid = d["n_fluid"]
     mlups = n_fluid * args.steps / wall / 1e6
-    kb = kernel_bytes(case.q, 4, n_fluid, d["n_links"], d["n_fluid_iface"])
+    kb = kernel_bytes(case.q, 4, n_fluid, d["n_links"], d["n_fluid_iface"], n_tasks=d["n_tasks"],
+                      n_row_words=d["n_row_words"])
     k_avg_s = k_ms / args.steps / 1e3
     achieved = kb / k_avg_s / 1e9
     line = {

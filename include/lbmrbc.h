@@ -165,6 +165,10 @@ typedef struct {
                                  inlet_exchange + outlet_exchange (Sec. 2.4,
                                  eq. solidFractionUpdate); a batch reports the
                                  totals over its domains                      */
+    int64_t n_tasks;          /* wavefront tasks of the fused step (each up to 64
+                                 consecutive fluid nodes)                      */
+    int64_t n_row_words;      /* 64-node row words of the geometry (the step
+                                 reads them to find its neighbours)           */
 } lbm_diag;
 
 /* Workspace size in bytes for these parameters (host call, no device work).
@@ -302,6 +306,13 @@ lbm_status lbm_adjoint_workspace_bytes(const lbm_ctx *ctx, int32_t nsteps, int32
 lbm_status lbm_record(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every, void *dev_workspace,
                       size_t bytes);
 lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k);
+
+/* lbm_adjoint with per-kernel timing, for measurement: the same gradient
+ * (bit for bit), with a HIP event pair around every kernel launch of the
+ * backward pass; synchronises after each.  ms (host array of 2) receives the
+ * summed durations in milliseconds of the segment recomputation (solute-only
+ * forward steps) and of the transposed steps. */
+lbm_status lbm_adjoint_timed(lbm_ctx *ctx, const double *dL_dC, double *grad_k, double *ms);
 
 /* lbm_record without a workspace, for callers that cannot allocate device
  * memory (code under stream capture, tight serving loops, harnesses that

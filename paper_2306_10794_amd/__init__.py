@@ -8,7 +8,7 @@ from ._lib import (LbmError, lbm_params, lbm_workspace_bytes, lbm_create, lbm_se
                    lbm_batch_workspace_bytes, lbm_create_batch, lbm_batch_offsets,
                    lbm_init_fields, lbm_step, lbm_step_timed, lbm_set_launch_config,
                    lbm_get_launch_config, lbm_autotune, lbm_adjoint_workspace_bytes,
-                   lbm_record, lbm_record_static, lbm_adjoint, lbm_get_fields, lbm_get_pops,
+                   lbm_record, lbm_record_static, lbm_adjoint, lbm_adjoint_timed, lbm_get_fields, lbm_get_pops,
                    lbm_get_exchange,
                    lbm_get_diag, lbm_state_bytes, lbm_save_state, lbm_load_state,
                    lbm_last_error, lbm_destroy, LBM_FP64, LBM_FP32_DEV, LBM_PRECOLL,

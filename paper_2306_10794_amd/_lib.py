@@ -50,7 +50,8 @@ class lbm_diag(C.Structure):
                 ("n_solid_iface", C.c_int64), ("n_fluid", C.c_int64),
                 ("n_fluid_iface", C.c_int64), ("mass_c", C.c_double), ("phi_sum", C.c_double),
                 ("wall_exchange", C.c_double), ("nan_flag", C.c_int32), ("reserved0", C.c_int32),
-                ("inlet_exchange", C.c_double), ("outlet_exchange", C.c_double)]
+                ("inlet_exchange", C.c_double), ("outlet_exchange", C.c_double),
+                ("n_tasks", C.c_int64), ("n_row_words", C.c_int64)]
 
 
 class lbm_launch_config(C.Structure):
@@ -92,6 +93,7 @@ _SIGS = {
     "lbm_record": [_P, C.c_int32, C.c_int32, _P, C.c_size_t],
     "lbm_adjoint": [_P, _P, _P],
     "lbm_record_static": [_P, C.c_int32, C.c_int32],
+    "lbm_adjoint_timed": [_P, _P, _P, C.POINTER(C.c_double)],
     "lbm_get_fields": [_P, _P, _P, _P, _P, _P],
     "lbm_get_pops": [_P, _P, _P],
     "lbm_get_exchange": [_P, _P],
@@ -243,6 +245,14 @@ def lbm_record_static(ctx, nsteps: int, ckpt_every: int):
 
 def lbm_adjoint(ctx, dL_dC, grad_k):
     _check(lib.lbm_adjoint(ctx, _ptr(dL_dC), _ptr(grad_k)), "lbm_adjoint", ctx)
+
+
+def lbm_adjoint_timed(ctx, dL_dC, grad_k):
+    """lbm_adjoint; returns (ms of the recomputation kernels, ms of the
+    transposed-step kernels), summed over the backward pass."""
+    ms = (C.c_double * 2)()
+    _check(lib.lbm_adjoint_timed(ctx, _ptr(dL_dC), _ptr(grad_k), ms), "lbm_adjoint_timed", ctx)
+    return ms[0], ms[1]
 
 
 def lbm_get_fields(ctx, rho=None, u=None, c=None, phi=None, type=None):

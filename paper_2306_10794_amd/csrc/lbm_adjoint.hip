@@ -371,8 +371,18 @@ static hipError_t rest_check_impl(Ctx &c, bool *at_rest) {
     return e;
 }
 
+// the kernel durations of one launch bracketed by events ev[0], ev[1] (timed
+// adjoint only): waits for it and adds the milliseconds to *acc
+static hipError_t add_elapsed(Ctx &c, double *acc) {
+    hipError_t e = hipEventSynchronize(c.ev[1]);
+    float t = 0.f;
+    if (e == hipSuccess) e = hipEventElapsedTime(&t, c.ev[0], c.ev[1]);
+    if (e == hipSuccess) *acc += t;
+    return e;
+}
+
 template <class L, typename T, bool RED, bool TRT>
-static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
+static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double *ms) {
     const AdjState &r = c.adj;
     const long nb = (c.n_tasks + BLK / 64 - 1) / (BLK / 64);
     const size_t slot = (size_t)c.QS * c.S;
@@ -398,13 +408,25 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad) {
         for (int j = 1; j < len; j++) {
             a.gin = state(j - 1);
             a.gout = state(j);
+            if (ms) (void)hipEventRecord(c.ev[0], c.stream);
             if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T, RED, TRT>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            if (ms) {
+                (void)hipEventRecord(c.ev[1], c.stream);
+                hipError_t e = add_elapsed(c, &ms[0]);
+                if (e != hipSuccess) return e;
+            }
         }
         for (int j = len - 1; j >= 0; j--) {
             a.gin = state(j);
             a.pin = P[cur];
             a.pout = P[1 - cur];
+            if (ms) (void)hipEventRecord(c.ev[0], c.stream);
             if (nb > 0) hipLaunchKernelGGL((k_adj_step<L, T, RED, TRT>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            if (ms) {
+                (void)hipEventRecord(c.ev[1], c.stream);
+                hipError_t e = add_elapsed(c, &ms[1]);
+                if (e != hipSuccess) return e;
+            }
             cur = 1 - cur;
         }
         hipError_t e = hipGetLastError();
@@ -424,17 +446,17 @@ hipError_t launch_rest_check(Ctx &c, bool *at_rest) {
 }
 
 template <class L, typename T>
-static hipError_t adjoint_set(Ctx &c, const double *dldc, double *grad) {
+static hipError_t adjoint_set(Ctx &c, const double *dldc, double *grad, double *ms) {
     // the collision and the solute set are compile-time variants: a runtime
     // TRT branch costs the BGK transpose a wave of occupancy
     const bool trt = c.p.collision == LBM_TRT;
-    if (trt) return c.red ? adjoint_impl<L, T, true, true>(c, dldc, grad) : adjoint_impl<L, T, false, true>(c, dldc, grad);
-    return c.red ? adjoint_impl<L, T, true, false>(c, dldc, grad) : adjoint_impl<L, T, false, false>(c, dldc, grad);
+    if (trt) return c.red ? adjoint_impl<L, T, true, true>(c, dldc, grad, ms) : adjoint_impl<L, T, false, true>(c, dldc, grad, ms);
+    return c.red ? adjoint_impl<L, T, true, false>(c, dldc, grad, ms) : adjoint_impl<L, T, false, false>(c, dldc, grad, ms);
 }
 
-hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad) {
-    if (c.Q == 9) return c.fp64 ? adjoint_set<D2Q9, double>(c, dldc, grad) : adjoint_set<D2Q9, float>(c, dldc, grad);
-    return c.fp64 ? adjoint_set<D3Q19, double>(c, dldc, grad) : adjoint_set<D3Q19, float>(c, dldc, grad);
+hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad, double *ms) {
+    if (c.Q == 9) return c.fp64 ? adjoint_set<D2Q9, double>(c, dldc, grad, ms) : adjoint_set<D2Q9, float>(c, dldc, grad, ms);
+    return c.fp64 ? adjoint_set<D3Q19, double>(c, dldc, grad, ms) : adjoint_set<D3Q19, float>(c, dldc, grad, ms);
 }
 
 }  // namespace lbm

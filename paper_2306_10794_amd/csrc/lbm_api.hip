@@ -1022,8 +1022,27 @@ lbm_status lbm_record_static(lbm_ctx *ctx, int32_t nsteps, int32_t ckpt_every) {
     return st;
 }
 
+static lbm_status adjoint_common(Ctx *c, const double *dL_dC, double *grad_k, double *ms);
+
 lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k) {
+    return adjoint_common((Ctx *)ctx, dL_dC, grad_k, nullptr);
+}
+
+lbm_status lbm_adjoint_timed(lbm_ctx *ctx, const double *dL_dC, double *grad_k, double *ms) {
     Ctx *c = (Ctx *)ctx;
+    if (!c || !ms) return LBM_EINVAL;
+    if (!c->have_events) {
+        for (int k = 0; k < 4; k++) {
+            hipError_t e = hipEventCreate(&c->ev[k]);
+            if (e != hipSuccess) return dev_err(c, e, "hipEventCreate");
+        }
+        c->have_events = true;
+    }
+    ms[0] = ms[1] = 0.0;
+    return adjoint_common(c, dL_dC, grad_k, ms);
+}
+
+static lbm_status adjoint_common(Ctx *c, const double *dL_dC, double *grad_k, double *ms) {
     if (!c) return LBM_EINVAL;
     if (!dL_dC || !grad_k) {
         c->err = "dL_dC and grad_k are required";
@@ -1042,7 +1061,7 @@ lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k) {
             return LBM_ESTATE;
         }
     }
-    hipError_t e = launch_adjoint(*c, dL_dC, grad_k);
+    hipError_t e = launch_adjoint(*c, dL_dC, grad_k, ms);
     if (e != hipSuccess) return dev_err(c, e, "adjoint");
     return LBM_OK;
 }
@@ -1115,6 +1134,8 @@ lbm_status lbm_get_diag(lbm_ctx *ctx, lbm_diag *out) {
     out->phi_sum = sums[2];
     out->inlet_exchange = sums[3];
     out->outlet_exchange = sums[4];
+    out->n_tasks = c->n_tasks;
+    out->n_row_words = c->RW;
     out->nan_flag = nan_flag;
     if (nan_flag) {
         c->err = "non-finite population";

@@ -173,7 +173,9 @@ hipError_t launch_rest_check(Ctx &c, bool *at_rest);
 hipError_t launch_events(Ctx &c, int64_t *n_events, bool *overflow);
 hipError_t launch_relayout(Ctx &c);
 size_t event_record_bytes();
-hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad);
+// ms (optional, host array of 2): summed durations of the recomputation and of
+// the transposed-step kernels (each launch timed with events; synchronises)
+hipError_t launch_adjoint(Ctx &c, const double *dldc, double *grad, double *ms = nullptr);
 hipError_t scan_excl(Ctx &c, const int32_t *in, int32_t *out, long n, int32_t *total_dev);
 
 }  // namespace lbm

@@ -111,6 +111,25 @@ __device__ __forceinline__ void classify(const RowWord *__restrict__ rows, const
     }
     solidnb = 0u;
     kk[0] = k;
+    // every pull of every lane resolved by the table (decided once per
+    // wavefront): straight-line selects, as in the fused step
+    const bool tab_ok = rs.fit && outm == 0u && shiftm == 0u && tcol[0] >= 0 && tcol[1] >= 0 &&
+                        tcol[2] >= 0;
+    if (__ballot(!tab_ok) == 0ull) {
+#pragma unroll
+        for (int i = 1; i < L::Q; i++) {
+            const int v = L::ex[i] + 1;
+            const int src = ((L::DIM == 3 ? (1 - L::ez[i]) * rs.TY : 0) + 1 - L::ey[i]) * rs.nwd + tcol[v];
+            const unsigned lo = __shfl((unsigned)(rs.wm & 0xffffffffull), src, 64);
+            const unsigned hi = __shfl((unsigned)(rs.wm >> 32), src, 64);
+            const int pb = __shfl(rs.wpb, src, 64);
+            const unsigned long long m = ((unsigned long long)hi << 32) | lo;
+            const unsigned long long bit = tbit[v];
+            kk[i] = (m & bit) ? pb + __popcll(m & (bit - 1ull)) : -1;
+            if (kk[i] == -1) solidnb |= 1u << i;
+        }
+        return;
+    }
 #pragma unroll
     for (int i = 1; i < L::Q; i++) {
         const int v = L::ex[i] + 1;
