@@ -119,7 +119,11 @@ typedef struct {
     double c_in;              /* inlet concentration                                */
     int32_t phase_change;     /* 1: apply the phi thresholds after each step
                                  (Sec. 2.4; single-lattice contexts; lbm_step
-                                 then synchronises once per step)            */
+                                 then synchronises once per step).  One pass
+                                 takes at most 65536 events (and as many nodes
+                                 pushed over a threshold by earlier events of
+                                 the pass); beyond that lbm_step returns
+                                 ECAPACITY                                   */
     int32_t collision;        /* LBM_BGK | LBM_TRT                                 */
     int64_t max_links;        /* capacity for reactive links; <= 0 selects
                                  max(4096, N*(Q-1)/4)                              */

@@ -127,11 +127,13 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     const bool pc = nd == 1 && p[0].phase_change != 0;
     const long ev_cap = pc ? (N < 65536 ? N : 65536) : 0;
     char *kof_old = take(pc ? 4 * N : 0), *evlist = take(4 * ev_cap);
-    char *evrec = take(event_record_bytes() * ev_cap), *evheap = take(4 * ev_cap);
+    char *evrec = take(event_record_bytes() * ev_cap), *evmom = take(pc ? 16 * N : 0);
+    char *evheap = take(4 * ev_cap);
     if (c && base) {
         c->kof_old = (int32_t *)kof_old;
         c->evlist = (int32_t *)evlist;
         c->evrec = evrec;
+        c->evmom = evmom;
         c->evheap = (int32_t *)evheap;
         c->ev_cap = ev_cap;
         c->ev_capacity = false;

@@ -26,6 +26,7 @@
 namespace lbm {
 
 constexpr uint32_t F_PEND = 1u << 29;  // geometry-flag bit: node waits in the heap
+constexpr int EV_HEAP = 38912;         // pending nodes of one pass (LDS heap, 152 KiB)
 
 struct EvRec {
     int64_t node;
@@ -89,6 +90,21 @@ __device__ __forceinline__ void pop_moments(const DomDev &D, int ko, const T *f,
     *rho = r;
 }
 
+// C and rho of every fluid node (dense, by node; 0 at solid nodes) from the
+// populations before the pass, in parallel ahead of it: an event then reads
+// its neighbours' moments in the same round as their state, instead of 2Q
+// population loads behind a map lookup (populations do not change during the
+// pass; a node that becomes fluid in it takes its moments from its record)
+template <class L, typename T, bool RED>
+__global__ __launch_bounds__(BLK) void k_event_moments(const DomDev *doms, long N, const int32_t *kof,
+                                                       const T *f, const T *g, long S, double2 *mom) {
+    const long n = (long)blockIdx.x * BLK + threadIdx.x;
+    if (n >= N) return;
+    double C = 0.0, rho = 0.0;
+    if (kof[n] >= 0) pop_moments<L, T, RED>(doms[0], kof[n], f, g, S, &C, &rho);
+    mom[n] = make_double2(C, rho);
+}
+
 // moments of a node that became fluid earlier in this pass: equilibrium at
 // rest of its record
 template <class L>
@@ -103,7 +119,7 @@ __device__ __forceinline__ void rec_moments(const DomDev &D, const EvRec &e, dou
 }
 
 // min-heap of the nodes that events push over a threshold during a pass
-// (lane 0 only; global memory)
+// (lane 0 only; in LDS)
 __device__ __forceinline__ void heap_push(int32_t *h, int &n, int32_t v) {
     int i = n++;
     while (i > 0) {
@@ -149,24 +165,39 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                                                const int32_t *kof, int32_t *kof_old, const T *f,
                                                const T *g, long S, EvRec *rec, long cap,
                                                const int32_t *cand, uint32_t *gflags,
-                                               int32_t *heap, int32_t *out) {
+                                               const double2 *mom, int32_t *gheap, int32_t *out) {
+    // the heap of pushed nodes and the next 64 list entries live in LDS; a
+    // heap that outgrows the LDS moves to global memory (gheap, cap entries)
+    __shared__ int32_t lheap[EV_HEAP];
+    __shared__ int32_t lbuf[64];
     __shared__ int np_s, ne_s, ovf_s;
-    __shared__ long cur_s;
+    __shared__ long cur_s, pos_s, lpos_s;
     const int lane = threadIdx.x;
     const DomDev D = doms[0];
-    if (lane == 0) { np_s = 0; ne_s = 0; ovf_s = 0; }
+    int32_t *heap = lheap;    // lane 0's view
+    long hcap = cap < EV_HEAP ? cap : EV_HEAP;
+    if (lane == 0) { np_s = 0; ne_s = 0; ovf_s = 0; pos_s = 0; }
     __syncthreads();
-    long pos = 0;
+    long lchunk = -1;   // list position of lbuf[0]
     while (true) {
+        const long pos = pos_s;
+        if ((pos >> 6) != lchunk) {
+            lchunk = pos >> 6;
+            const long q = (lchunk << 6) + lane;
+            lbuf[lane] = q < nlist ? list[q] : -1;
+            __syncthreads();
+        }
         if (lane == 0) {
             // next node: the smaller of the list head and the heap top (a
-            // node is never in both)
-            long nxt = -1;
-            const long a = pos < nlist ? (long)list[pos] : -1;
+            // node is never in both); lpos_s: its list position, -1 if from
+            // the heap
+            long nxt = -1, lp = -1;
+            const long a = pos < nlist ? (long)lbuf[pos & 63] : -1;
             const long b = np_s > 0 ? (long)heap[0] : -1;
             if (a >= 0 && (b < 0 || a < b)) {
                 nxt = a;
-                pos++;
+                lp = pos;
+                pos_s = pos + 1;
             } else if (b >= 0) {
                 int np = np_s;
                 nxt = heap_pop(heap, np);
@@ -174,9 +205,10 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
             }
             if (ovf_s) nxt = -1;
             cur_s = nxt;
+            lpos_s = lp;
         }
         __syncthreads();
-        const long n = cur_s;
+        const long n = cur_s, lp = lpos_s;
         __syncthreads();
         if (n < 0) break;
         int X, Y, Z;
@@ -194,11 +226,16 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
                 fy = (solid[y] ? 1 : 0) | (cand[y] ? 2 : 0) | ((gflags[y] & F_PEND) ? 4 : 0);
                 Py = phi[y];
                 Ky = kr[y];
-                // kof_old: the compact index before the pass, or the record
-                // of a node that became fluid in it
+                // kof_old: the slot before the pass, or the record of a node
+                // that became fluid in it
                 const int ko = kof_old[y];
-                if (ko <= -2) rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
-                else if (ko >= 0) pop_moments<L, T, RED>(D, ko, f, g, S, &Cy, &Ry);
+                const double2 m = mom[y];
+                if (ko <= -2) {
+                    rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
+                } else if (ko >= 0) {
+                    Cy = m.x;
+                    Ry = m.y;
+                }
             }
         }
         // lane 0: the node's own state, read alongside its neighbours'
@@ -207,10 +244,15 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
         if (lane == 0) {
             sol_n = solid[n] != 0;
             phn = phi[n];
+            const int ko = kof_old[n];
+            const double2 m = mom[n];
             if (!sol_n && phn >= 1.0) {
-                const int ko = kof_old[n];
-                if (ko >= 0) pop_moments<L, T, RED>(D, ko, f, g, S, &Cx, &Rx);
-                else rec_moments<L>(D, rec[-2 - ko], &Cx, &Rx);
+                if (ko >= 0) {
+                    Cx = m.x;
+                    Rx = m.y;
+                } else {
+                    rec_moments<L>(D, rec[-2 - ko], &Cx, &Rx);
+                }
             }
         }
         long ys[L::Q];
@@ -232,9 +274,14 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
             const bool distinct = D.box.nx >= 3 && D.box.ny >= 3 && (L::DIM == 2 || D.box.nz >= 3);
             auto push = [&](long v, bool pend) {
                 if (distinct ? pend : (gflags[v] & F_PEND) != 0u) return;
-                if (np_s >= cap) {
-                    ovf_s = 1;
-                    return;
+                if (np_s >= hcap) {
+                    if (heap != lheap || cap <= EV_HEAP) {
+                        ovf_s = 1;
+                        return;
+                    }
+                    for (int j = 0; j < np_s; j++) gheap[j] = lheap[j];
+                    heap = gheap;
+                    hcap = cap;
                 }
                 int np = np_s;
                 heap_push(heap, np, (int32_t)v);
@@ -439,14 +486,21 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;
     const long nlist = h[0] < c.ev_cap ? h[0] : c.ev_cap;
     if (h[0] > c.ev_cap) *overflow = true;
+    double2 *mom = (double2 *)c.evmom;
+    if (c.red)
+        hipLaunchKernelGGL((k_event_moments<L, T, true>), dim3(nb), dim3(BLK), 0, st, c.doms, N, c.kof,
+                           (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.S, mom);
+    else
+        hipLaunchKernelGGL((k_event_moments<L, T, false>), dim3(nb), dim3(BLK), 0, st, c.doms, N, c.kof,
+                           (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.S, mom);
     if (c.red)
         hipLaunchKernelGGL((k_events<L, T, true>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
                            c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
-                           c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, c.evheap, cnt2);
+                           c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, mom, c.evheap, cnt2);
     else
         hipLaunchKernelGGL((k_events<L, T, false>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
                            c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
-                           c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, c.evheap, cnt2);
+                           c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, mom, c.evheap, cnt2);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if ((e = hipMemcpyAsync(h, cnt2, 8, hipMemcpyDeviceToHost, st)) != hipSuccess) return e;
     if ((e = hipStreamSynchronize(st)) != hipSuccess) return e;

@@ -120,7 +120,8 @@ struct Ctx {
     int32_t *kof_old;        // [N] phase change: compact map before the events
     int32_t *evlist;         // [ev_cap] phase-change candidates in node order
     void *evrec;             // [ev_cap] event records
-    int32_t *evheap;         // [ev_cap] pending nodes of an event pass
+    void *evmom;             // [N] moments (C, rho) of every node before an event pass
+    int32_t *evheap;         // [ev_cap] pending nodes of a pass, once they outgrow the LDS
     long ev_cap;
     bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions
