@@ -368,6 +368,256 @@ __global__ __launch_bounds__(64) void k_events(const DomDev *doms, const int32_t
     }
 }
 
+// The same pass with the work of an event spread over the lanes and no
+// workgroup barrier, for boxes at least 3 sites wide along every axis (the
+// Q - 1 neighbours of a node are then distinct sites).  The workgroup is one
+// wavefront, whose memory operations complete in program order: a lane's
+// read in a later event sees what any lane wrote in an earlier one, so the
+// events need only compiler-level ordering between them.
+//   Next node: the smallest of the list head, the far heap top and the first
+// set bit of the pending window.  A node pushed less than EV_WIN sites past
+// the current event goes into the window, a circular bitmap over node indices
+// (every pending node lies within EV_WIN sites after the current one, so bit
+// v mod EV_WIN names one node); a node pushed further goes into the far heap
+// and is marked in the geometry flags.
+//   An event: lanes 1..Q-1 read their neighbour's state and lane 0 the node's
+// own in one round; each lane applies the rule's update to its neighbour
+// (the shares are the same expressions as in the serial rule, so the values
+// are identical); sums over the neighbours are taken in direction order.
+constexpr int EV_WIN = 1 << 19;         // pending window (64 KiB bitmap)
+constexpr int EV_WWORDS = EV_WIN / 64;
+constexpr int EV_FHEAP = 16384;         // far heap entries in LDS (64 KiB)
+
+__device__ __forceinline__ void wave_order() {
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+}
+
+__device__ __forceinline__ double lane_d(double v, int l) {
+    const unsigned long long b = __double_as_longlong(v);
+    const unsigned lo = __builtin_amdgcn_readlane((unsigned)b, l);
+    const unsigned hi = __builtin_amdgcn_readlane((unsigned)(b >> 32), l);
+    return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// first set position in [lo, hi) of the window (hi - lo <= EV_WIN), or -1
+__device__ __forceinline__ long window_first(const unsigned long long *bits, long lo, long hi, int lane) {
+    for (long base = lo & ~63L; base < hi; base += 64L * 64) {
+        const long wp = base + 64L * lane;
+        unsigned long long w = 0ull;
+        if (wp < hi) {
+            w = bits[(wp >> 6) & (EV_WWORDS - 1)];
+            if (wp < lo) w &= ~0ull << (lo - wp);
+            if (hi - wp < 64) w &= (1ull << (hi - wp)) - 1ull;
+        }
+        const unsigned long long m = __ballot(w != 0ull);
+        if (m) {
+            const int l = __builtin_ctzll(m);
+            const unsigned long long wl = ((unsigned long long)__builtin_amdgcn_readlane((unsigned)(w >> 32), l) << 32) |
+                                          (unsigned long long)__builtin_amdgcn_readlane((unsigned)w, l);
+            return base + 64L * l + __builtin_ctzll(wl);
+        }
+    }
+    return -1;
+}
+
+template <class L, typename T, bool RED>
+__global__ __launch_bounds__(64) void k_events_wave(const DomDev *doms, const int32_t *list, long nlist,
+                                                    uint8_t *solid, double *phi, const double *kr,
+                                                    int32_t *kof_old, EvRec *rec, long cap,
+                                                    const int32_t *cand, uint32_t *gflags,
+                                                    const double2 *mom, int32_t *gheap, int32_t *out) {
+    __shared__ unsigned long long bits[EV_WWORDS];
+    __shared__ int32_t lheap[EV_FHEAP];
+    __shared__ int32_t lbuf[64];
+    __shared__ int np_s, inl_s;
+    const int lane = threadIdx.x;
+    const DomDev D = doms[0];
+    for (int w = lane; w < EV_WWORDS; w += 64) bits[w] = 0ull;
+    if (lane == 0) { np_s = 0; inl_s = 1; }
+    wave_order();
+    long pos = 0, lchunk = -1, nbits = 0, ne = 0, last = -1;
+    int ovf = 0;
+    while (!ovf) {
+        if ((pos >> 6) != lchunk) {
+            lchunk = pos >> 6;
+            const long q = (lchunk << 6) + lane;
+            lbuf[lane] = q < nlist ? list[q] : -1;
+            wave_order();
+        }
+        const int np = np_s;
+        const int32_t *heap = inl_s ? lheap : gheap;
+        const long a = pos < nlist ? (long)lbuf[pos & 63] : LONG_MAX;
+        const long b = np > 0 ? (long)heap[0] : LONG_MAX;
+        const long lim = a < b ? a : b;
+        long c = -1;
+        if (nbits > 0) {
+            const long hi = last + 1 + EV_WIN - 1 < lim ? last + EV_WIN : lim;
+            c = window_first(bits, last + 1, hi, lane);
+        }
+        long n;
+        if (c >= 0) {
+            n = c;
+            if (lane == 0) bits[(c >> 6) & (EV_WWORDS - 1)] &= ~(1ull << (c & 63));
+            nbits--;
+        } else if (a < b) {
+            n = a;
+            pos++;
+        } else if (b != LONG_MAX) {
+            n = b;
+            if (lane == 0) {
+                int m = np;
+                heap_pop(inl_s ? lheap : gheap, m);
+                np_s = m;
+            }
+        } else {
+            break;
+        }
+        wave_order();
+        last = n;
+        int X, Y, Z;
+        coords(D.box, n, &X, &Y, &Z);
+        long y = -1;
+        double Cy = 0.0, Ry = 0.0, Py = 0.0, Ky = 0.0;
+        int fy = 0;   // bit 0 solid, bit 1 candidate of the pass, bit 2 in the far heap
+        if (lane >= 1 && lane < L::Q) {
+            int fc;
+            y = site(D.box, X, Y, Z, L::ex[lane], L::ey[lane], L::ez[lane], true, &fc);
+            if (y >= 0) {
+                fy = (solid[y] ? 1 : 0) | (cand[y] ? 2 : 0) | ((gflags[y] & F_PEND) ? 4 : 0);
+                Py = phi[y];
+                Ky = kr[y];
+                const int ko = kof_old[y];
+                const double2 m = mom[y];
+                if (ko <= -2) {
+                    rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
+                } else if (ko >= 0) {
+                    Cy = m.x;
+                    Ry = m.y;
+                }
+            }
+        } else if (lane == 0) {
+            fy = solid[n] ? 1 : 0;
+            Py = phi[n];
+            const int ko = kof_old[n];
+            const double2 m = mom[n];
+            if (!(fy & 1)) {
+                if (ko >= 0) {
+                    Cy = m.x;
+                    Ry = m.y;
+                } else {
+                    rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
+                }
+            }
+        }
+        const bool sol_n = __builtin_amdgcn_readfirstlane(fy) & 1;
+        const double phn = lane_d(Py, 0);
+        const bool nb = lane >= 1 && y >= 0;
+        const unsigned long long fm = __ballot(nb && !(fy & 1)), sm = __ballot(nb && (fy & 1));
+        bool pushme = false;
+        if (sol_n && phn <= 0.0) {
+            const int nf = __builtin_popcountll(fm), nn = __builtin_popcountll(sm);
+            if (nf > 0) {
+                double csum = 0.0, rsum = 0.0, wsum = 0.0;
+#pragma unroll
+                for (int i = 1; i < L::Q; i++) {
+                    if ((fm >> i) & 1ull) {
+                        csum += lane_d(Cy, i);
+                        rsum += lane_d(Ry, i);
+                    }
+                }
+#pragma unroll
+                for (int i = 1; i < L::Q; i++)
+                    if ((sm >> i) & 1ull) wsum += lane_d(Ky, i);
+                const double Cs = csum / nf, Rs = rsum / nf;
+                const double need = D.v_m * Cs - phn;
+                if (ne >= cap) {
+                    ovf = 1;
+                } else {
+                    if (lane == 0) {
+                        solid[n] = 0;
+                        phi[n] = nn > 0 ? 0.0 : 0.0 - need;
+                        rec[ne].node = n;
+                        rec[ne].type = 0;
+                        rec[ne].C = Cs;
+                        rec[ne].rho = Rs;
+                        kof_old[n] = (int32_t)(-2 - ne);
+                    }
+                    ne++;
+                    if (nb && (fy & 1)) {
+                        const double pn = Py - need * (wsum > 0 ? Ky / wsum : 1.0 / nn);
+                        phi[y] = pn;
+                        pushme = y > n && !(fy & 2) && pn <= 0.0;
+                    }
+                }
+            }
+        } else if (!sol_n && phn >= 1.0) {
+            if (ne >= cap) {
+                ovf = 1;
+            } else {
+                const double Cx = lane_d(Cy, 0), Rx = lane_d(Ry, 0);
+                const double phx = phn + D.v_m * Cx;
+                const double excess = phx - 1.0;
+                const int nn = __builtin_popcountll(fm);
+                if (nn > 0 && nb && !(fy & 1)) {
+                    const double pn = Py + excess / nn;
+                    phi[y] = pn;
+                    pushme = y > n && !(fy & 2) && pn >= 1.0;
+                }
+                if (lane == 0) {
+                    phi[n] = nn > 0 ? 1.0 : phx;
+                    solid[n] = 1;
+                    rec[ne].node = n;
+                    rec[ne].type = 1;
+                    rec[ne].C = Cx;
+                    rec[ne].rho = Rx;
+                }
+                ne++;
+            }
+        }
+        // pushes: near ones into the window, far ones into the heap
+        pushme = pushme && !(fy & 4);
+        const bool far = pushme && y - n >= EV_WIN;
+        bool fresh = false;
+        if (pushme && !far) {
+            const unsigned long long bit = 1ull << (y & 63);
+            const unsigned long long old = atomicOr(&bits[(y >> 6) & (EV_WWORDS - 1)], bit);
+            fresh = !(old & bit);
+        }
+        nbits += __builtin_popcountll(__ballot(fresh));
+        unsigned long long fmask = __ballot(far);
+        if (fmask) {
+            if (far) atomicOr(&gflags[y], F_PEND);
+            if (lane == 0) {
+                int m = np_s, inl = inl_s;
+                while (fmask) {
+                    const int l = __builtin_ctzll(fmask);
+                    fmask &= fmask - 1ull;
+                    const long v = (long)__builtin_amdgcn_readlane((unsigned)y, l);
+                    const long hc = inl ? (cap < EV_FHEAP ? cap : EV_FHEAP) : cap;
+                    if (m >= hc) {
+                        if (!inl || cap <= EV_FHEAP) {
+                            ovf = 1;
+                            break;
+                        }
+                        for (int j = 0; j < m; j++) gheap[j] = lheap[j];
+                        inl = 0;
+                    }
+                    heap_push(inl ? lheap : gheap, m, (int32_t)v);
+                }
+                np_s = m;
+                inl_s = inl;
+            }
+            ovf = __builtin_amdgcn_readfirstlane(ovf);
+        }
+        wave_order();
+    }
+    if (lane == 0) {
+        out[0] = (int32_t)ne;
+        out[1] = ovf;
+    }
+}
+
 // wall normals of solid nodes within two sites of every change (fluid view)
 template <class L>
 __global__ __launch_bounds__(BLK) void k_event_normals(const DomDev *doms, const EvRec *rec, long nev,
@@ -493,7 +743,17 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     else
         hipLaunchKernelGGL((k_event_moments<L, T, false>), dim3(nb), dim3(BLK), 0, st, c.doms, N, c.kof,
                            (const T *)c.f[c.cur], (const T *)c.g[c.cur], c.S, mom);
-    if (c.red)
+    const Box &bx = c.dom[0].box;
+    const bool distinct = bx.nx >= 3 && bx.ny >= 3 && (L::DIM == 2 || bx.nz >= 3);
+    if (distinct && c.red)
+        hipLaunchKernelGGL((k_events_wave<L, T, true>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist,
+                           c.solid, c.phi, c.kr, c.kof_old, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags,
+                           mom, c.evheap, cnt2);
+    else if (distinct)
+        hipLaunchKernelGGL((k_events_wave<L, T, false>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist,
+                           c.solid, c.phi, c.kr, c.kof_old, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags,
+                           mom, c.evheap, cnt2);
+    else if (c.red)
         hipLaunchKernelGGL((k_events<L, T, true>), dim3(1), dim3(64), 0, st, c.doms, c.evlist, nlist, c.solid,
                            c.phi, c.kr, c.kof, c.kof_old, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
                            c.S, (EvRec *)c.evrec, (long)c.ev_cap, c.cnt, c.flags, mom, c.evheap, cnt2);
