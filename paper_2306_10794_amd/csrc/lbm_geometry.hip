@@ -508,61 +508,46 @@ __global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *no
     }
 }
 
-template <class L>
-__device__ __forceinline__ int solid_links(const DomDev &D, long nl, const uint8_t *solid,
-                                           const uint32_t *rmask, const int32_t *kof,
-                                           const int32_t *lbase, const int32_t *lmap, int32_t *out) {
-    int X, Y, Z;
-    coords(D.box, nl, &X, &Y, &Z);
-    int cnt = 0;
-    for (int i = 1; i < L::Q; i++) {
-        int fc;
-        const long xl = site(D.box, X, Y, Z, L::ex[i], L::ey[i], L::ez[i], true, &fc);
-        if (xl < 0) continue;
-        const long x = D.node_off + xl;
-        if (solid[x]) continue;
-        const uint32_t rm = rmask[x];
-        if (!(rm & (1u << i))) continue;
-        if (out) out[cnt] = lmap[lbase[kof[x]] + __popc(rm & ((1u << i) - 1u))];
-        cnt++;
-    }
-    return cnt;
+// Solid side of the link list, built from the links themselves: link l joins
+// fluid node lnode[l] to solid node lsolid[l] along direction ldir[l], and a
+// solid node has at most one link per direction, so the set of directions of
+// its links (a bit mask) gives both its link count and each link's rank in
+// direction order.
+__global__ __launch_bounds__(BLK) void k_solid_dirs(long nl, const int32_t *lsolid, const uint8_t *ldir,
+                                                    uint32_t *smask) {
+    const long l = (long)blockIdx.x * BLK + threadIdx.x;
+    if (l < nl) atomicOr(&smask[lsolid[l]], 1u << ldir[l]);
 }
 
-template <class L>
-__global__ __launch_bounds__(BLK) void k_solid_count(Geo g, long N, const uint8_t *solid,
-                                                     const uint32_t *rmask, int32_t *cnt,
-                                                     int32_t *ind) {
+__global__ __launch_bounds__(BLK) void k_solid_mark(long N, const uint32_t *smask, int32_t *ind) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
-    if (n >= N) return;
-    int c = 0;
-    if (solid[n]) {
-        long nl;
-        const int d = dom_of(g, n, &nl);
-        c = solid_links<L>(g.doms[d], nl, solid, rmask, nullptr, nullptr, nullptr, nullptr);
-    }
-    cnt[n] = c;
-    ind[n] = c > 0 ? 1 : 0;
+    if (n < N) ind[n] = smask[n] != 0u ? 1 : 0;
 }
 
-template <class L>
-__global__ __launch_bounds__(BLK) void k_solid_fill(Geo g, long N, const uint8_t *solid,
-                                                    const uint32_t *rmask, const int32_t *kof,
-                                                    const int32_t *lbase, const int32_t *lmap,
-                                                    const int32_t *off,
-                                                    const int32_t *idx, int32_t *sif, int32_t *soff,
-                                                    int32_t *sdom, int32_t *slinks) {
+// per solid interface node (position idx[n] in node order): its node, link
+// count (scanned into offsets afterwards) and domain
+__global__ __launch_bounds__(BLK) void k_solid_nodes(Geo g, long N, const uint32_t *smask, const int32_t *idx,
+                                                     int32_t *sif, int32_t *soff, int32_t *sdom) {
     const long n = (long)blockIdx.x * BLK + threadIdx.x;
     if (n >= N) return;
-    if (!solid[n]) return;
+    const uint32_t m = smask[n];
+    if (!m) return;
     long nl;
-    const int d = dom_of(g, n, &nl);
-    const int c = solid_links<L>(g.doms[d], nl, solid, rmask, kof, lbase, lmap, slinks + off[n]);
-    if (c > 0) {
-        sif[idx[n]] = (int32_t)n;
-        soff[idx[n]] = off[n];
-        sdom[idx[n]] = d;
-    }
+    const int j = idx[n];
+    sif[j] = (int32_t)n;
+    soff[j] = __popc(m);
+    sdom[j] = dom_of(g, n, &nl);
+}
+
+// each link into its solid node's segment, in direction order
+__global__ __launch_bounds__(BLK) void k_solid_links(long nl, const int32_t *lsolid, const uint8_t *ldir,
+                                                     const uint32_t *smask, const int32_t *idx,
+                                                     const int32_t *soff, int32_t *slinks) {
+    const long l = (long)blockIdx.x * BLK + threadIdx.x;
+    if (l >= nl) return;
+    const int32_t s = lsolid[l];
+    const uint32_t m = smask[s];
+    slinks[soff[idx[s]] + __popc(m & ((1u << ldir[l]) - 1u))] = (int32_t)l;
 }
 
 // lattice-gradient normal of the solid indicator (used when no normals are given)
@@ -708,15 +693,21 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
                        c.rmask, c.lbase, c.lmap, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir,
                        c.ceq_set ? c.ceq : nullptr, (T *)c.lceq);
     // solid side: per solid interface node, its links in direction order
-    hipLaunchKernelGGL((k_solid_count<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rmask,
-                       c.cnt, c.sidx);
+    uint32_t *smask = (uint32_t *)c.cnt;
+    hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(BLK), 0, st, c.cnt, N, 0);
+    if (tot > 0)
+        hipLaunchKernelGGL(k_solid_dirs, blocks(tot), dim3(BLK), 0, st, (long)tot, c.lsolid, c.ldir, smask);
+    hipLaunchKernelGGL(k_solid_mark, dim3(nb), dim3(BLK), 0, st, N, smask, c.sidx);
     if ((e = scan_excl(c, c.sidx, c.sidx, N, c.iacc)) != hipSuccess) return e;
-    if ((e = scan_excl(c, c.cnt, c.cnt, N, c.iacc + 1)) != hipSuccess) return e;
     int32_t t2[2] = {0, 0};
-    if ((e = read_ints(c, c.iacc, t2, 2)) != hipSuccess) return e;
+    if ((e = read_ints(c, c.iacc, t2, 1)) != hipSuccess) return e;
     *n_sif = t2[0];
-    hipLaunchKernelGGL((k_solid_fill<L>), dim3(nb), dim3(BLK), 0, st, g, N, c.solid, c.rmask,
-                       c.kof, c.lbase, c.lmap, c.cnt, c.sidx, c.sif, c.soff, c.sdom, c.slinks);
+    hipLaunchKernelGGL(k_solid_nodes, dim3(nb), dim3(BLK), 0, st, g, N, smask, c.sidx, c.sif, c.soff, c.sdom);
+    if ((e = scan_excl(c, c.soff, c.soff, t2[0], c.iacc + 1)) != hipSuccess) return e;
+    if (tot > 0)
+        hipLaunchKernelGGL(k_solid_links, blocks(tot), dim3(BLK), 0, st, (long)tot, c.lsolid, c.ldir, smask,
+                           c.sidx, c.soff, c.slinks);
+    if ((e = read_ints(c, c.iacc + 1, t2 + 1, 1)) != hipSuccess) return e;
     hipLaunchKernelGGL(k_set_last, dim3(1), dim3(1), 0, st, c.soff, (long)t2[0], t2[1]);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (t2[1] != tot) return hipErrorUnknown;  // every link has exactly one solid end
