@@ -118,6 +118,18 @@ __device__ __forceinline__ void rec_moments(const DomDev &D, const EvRec &e, dou
     *rho = r;
 }
 
+// the same with the solute weights read from memory (ws: the domain's)
+template <class L>
+__device__ __forceinline__ void rec_moments_w(const double *ws, const EvRec &e, double *C, double *rho) {
+    double c = 0.0, r = 0.0;
+    for (int i = 0; i < L::Q; i++) {
+        r += L::w[i] * e.rho;
+        c += ws[i] * e.C;
+    }
+    *C = c;
+    *rho = r;
+}
+
 // min-heap of the nodes that events push over a threshold during a pass
 // (lane 0 only; in LDS)
 __device__ __forceinline__ void heap_push(int32_t *h, int &n, int32_t v) {
@@ -430,25 +442,28 @@ __global__ __launch_bounds__(64) void k_events_wave(const DomDev *doms, const in
     __shared__ unsigned long long bits[EV_WWORDS];
     __shared__ int32_t lheap[EV_FHEAP];
     __shared__ int32_t lbuf[64];
-    __shared__ int np_s, inl_s;
     const int lane = threadIdx.x;
-    const DomDev D = doms[0];
+    // only the box and V_m are kept in registers; the solute weights of a
+    // record's moments are read from the domain record
+    const Box bx = doms[0].box;
+    const double v_m = doms[0].v_m;
     for (int w = lane; w < EV_WWORDS; w += 64) bits[w] = 0ull;
-    if (lane == 0) { np_s = 0; inl_s = 1; }
     wave_order();
-    long pos = 0, lchunk = -1, nbits = 0, ne = 0, last = -1;
-    int ovf = 0;
+    // wave-uniform selection state: list position and head a, far heap size
+    // np, place (LDS or gheap) and top b, pending nodes in the window
+    long pos = 0, apos = -1, lchunk = -1, nbits = 0, ne = 0, last = -1, a = LONG_MAX, b = LONG_MAX;
+    int np = 0, inl = 1, ovf = 0;
     while (!ovf) {
-        if ((pos >> 6) != lchunk) {
-            lchunk = pos >> 6;
-            const long q = (lchunk << 6) + lane;
-            lbuf[lane] = q < nlist ? list[q] : -1;
-            wave_order();
+        if (pos != apos) {
+            apos = pos;
+            if (pos < nlist && (pos >> 6) != lchunk) {
+                lchunk = pos >> 6;
+                const long q = (lchunk << 6) + lane;
+                lbuf[lane] = q < nlist ? list[q] : -1;
+                wave_order();
+            }
+            a = pos < nlist ? (long)lbuf[pos & 63] : LONG_MAX;
         }
-        const int np = np_s;
-        const int32_t *heap = inl_s ? lheap : gheap;
-        const long a = pos < nlist ? (long)lbuf[pos & 63] : LONG_MAX;
-        const long b = np > 0 ? (long)heap[0] : LONG_MAX;
         const long lim = a < b ? a : b;
         long c = -1;
         if (nbits > 0) {
@@ -458,57 +473,55 @@ __global__ __launch_bounds__(64) void k_events_wave(const DomDev *doms, const in
         long n;
         if (c >= 0) {
             n = c;
-            if (lane == 0) bits[(c >> 6) & (EV_WWORDS - 1)] &= ~(1ull << (c & 63));
+            if (lane == 0) atomicAnd(&bits[(c >> 6) & (EV_WWORDS - 1)], ~(1ull << (c & 63)));
             nbits--;
         } else if (a < b) {
             n = a;
             pos++;
         } else if (b != LONG_MAX) {
             n = b;
+            int32_t top = 0;
             if (lane == 0) {
-                int m = np;
-                heap_pop(inl_s ? lheap : gheap, m);
-                np_s = m;
+                int32_t *h = inl ? lheap : gheap;
+                heap_pop(h, np);
+                top = np > 0 ? h[0] : -1;
             }
+            np = __builtin_amdgcn_readfirstlane(np);
+            top = __builtin_amdgcn_readfirstlane(top);
+            b = top >= 0 ? (long)top : LONG_MAX;
         } else {
             break;
         }
         wave_order();
         last = n;
         int X, Y, Z;
-        coords(D.box, n, &X, &Y, &Z);
+        coords(bx, n, &X, &Y, &Z);
+        // lanes 1..Q-1: the neighbour along their direction; lane 0: the node.
+        // Every lane loads from a valid node (its own or n), all in one round.
         long y = -1;
-        double Cy = 0.0, Ry = 0.0, Py = 0.0, Ky = 0.0;
-        int fy = 0;   // bit 0 solid, bit 1 candidate of the pass, bit 2 in the far heap
         if (lane >= 1 && lane < L::Q) {
             int fc;
-            y = site(D.box, X, Y, Z, L::ex[lane], L::ey[lane], L::ez[lane], true, &fc);
-            if (y >= 0) {
-                fy = (solid[y] ? 1 : 0) | (cand[y] ? 2 : 0) | ((gflags[y] & F_PEND) ? 4 : 0);
-                Py = phi[y];
-                Ky = kr[y];
-                const int ko = kof_old[y];
-                const double2 m = mom[y];
-                if (ko <= -2) {
-                    rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
-                } else if (ko >= 0) {
-                    Cy = m.x;
-                    Ry = m.y;
-                }
-            }
-        } else if (lane == 0) {
-            fy = solid[n] ? 1 : 0;
-            Py = phi[n];
-            const int ko = kof_old[n];
-            const double2 m = mom[n];
-            if (!(fy & 1)) {
-                if (ko >= 0) {
-                    Cy = m.x;
-                    Ry = m.y;
-                } else {
-                    rec_moments<L>(D, rec[-2 - ko], &Cy, &Ry);
-                }
-            }
+            y = site(bx, X, Y, Z, L::ex[lane], L::ey[lane], L::ez[lane], true, &fc);
+        }
+        const bool have = lane == 0 || y >= 0;
+        const long ya = y >= 0 ? y : n;
+        const int sv = solid[ya];
+        const int cv = cand[ya];
+        const uint32_t gv = gflags[ya];
+        const double pv = phi[ya], kv = kr[ya];
+        const int ko = kof_old[ya];
+        const double2 m = mom[ya];
+        // bit 0 solid, bit 1 candidate of the pass, bit 2 in the far heap
+        const int fy = have ? ((sv ? 1 : 0) | (lane > 0 && cv ? 2 : 0) | (lane > 0 && (gv & F_PEND) ? 4 : 0)) : 0;
+        const double Py = have ? pv : 0.0, Ky = have ? kv : 0.0;
+        // moments: from the populations before the pass, or from the record
+        // of a node that became fluid in it
+        double Cy = 0.0, Ry = 0.0;
+        if (have && ko <= -2) {
+            rec_moments_w<L>(doms[0].ws, rec[-2 - ko], &Cy, &Ry);
+        } else if (have && ko >= 0) {
+            Cy = m.x;
+            Ry = m.y;
         }
         const bool sol_n = __builtin_amdgcn_readfirstlane(fy) & 1;
         const double phn = lane_d(Py, 0);
@@ -530,7 +543,7 @@ __global__ __launch_bounds__(64) void k_events_wave(const DomDev *doms, const in
                 for (int i = 1; i < L::Q; i++)
                     if ((sm >> i) & 1ull) wsum += lane_d(Ky, i);
                 const double Cs = csum / nf, Rs = rsum / nf;
-                const double need = D.v_m * Cs - phn;
+                const double need = v_m * Cs - phn;
                 if (ne >= cap) {
                     ovf = 1;
                 } else {
@@ -556,7 +569,7 @@ __global__ __launch_bounds__(64) void k_events_wave(const DomDev *doms, const in
                 ovf = 1;
             } else {
                 const double Cx = lane_d(Cy, 0), Rx = lane_d(Ry, 0);
-                const double phx = phn + D.v_m * Cx;
+                const double phx = phn + v_m * Cx;
                 const double excess = phx - 1.0;
                 const int nn = __builtin_popcountll(fm);
                 if (nn > 0 && nb && !(fy & 1)) {
@@ -588,27 +601,30 @@ __global__ __launch_bounds__(64) void k_events_wave(const DomDev *doms, const in
         unsigned long long fmask = __ballot(far);
         if (fmask) {
             if (far) atomicOr(&gflags[y], F_PEND);
+            int32_t top = 0;
             if (lane == 0) {
-                int m = np_s, inl = inl_s;
                 while (fmask) {
                     const int l = __builtin_ctzll(fmask);
                     fmask &= fmask - 1ull;
                     const long v = (long)__builtin_amdgcn_readlane((unsigned)y, l);
                     const long hc = inl ? (cap < EV_FHEAP ? cap : EV_FHEAP) : cap;
-                    if (m >= hc) {
+                    if (np >= hc) {
                         if (!inl || cap <= EV_FHEAP) {
                             ovf = 1;
                             break;
                         }
-                        for (int j = 0; j < m; j++) gheap[j] = lheap[j];
+                        for (int j = 0; j < np; j++) gheap[j] = lheap[j];
                         inl = 0;
                     }
-                    heap_push(inl ? lheap : gheap, m, (int32_t)v);
+                    heap_push(inl ? lheap : gheap, np, (int32_t)v);
                 }
-                np_s = m;
-                inl_s = inl;
+                top = np > 0 ? (inl ? lheap : gheap)[0] : -1;
             }
+            np = __builtin_amdgcn_readfirstlane(np);
+            inl = __builtin_amdgcn_readfirstlane(inl);
             ovf = __builtin_amdgcn_readfirstlane(ovf);
+            top = __builtin_amdgcn_readfirstlane(top);
+            b = top >= 0 ? (long)top : LONG_MAX;
         }
         wave_order();
     }
