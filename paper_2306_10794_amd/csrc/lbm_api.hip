@@ -498,6 +498,7 @@ static hipError_t run_steps(Ctx *c, int32_t nsteps, bool plain = false) {
     if (c->p.phase_change) {
         // events need a decision on the host after every step (no graphs)
         for (; t < nsteps; t++) {
+            c->evstamp = c->evstamp == 0x7fffffff ? 1 : c->evstamp + 1;
             hipError_t e = launch_step(*c);
             if (e != hipSuccess) return e;
             c->step++;

@@ -722,7 +722,16 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     int32_t *any = c.iacc + 8, *cnt2 = c.iacc + 10;
     int32_t h[2] = {0, 0};
     hipError_t e = hipSuccess;
-    {
+    if (!c.full_check) {
+        // the step's kernels marked the flag with this step's stamp if an
+        // interface node is past its threshold (only interface nodes' solid
+        // fractions change in a step, and every other node was checked when
+        // its value was last set)
+        e = hipMemcpyAsync(h, c.iacc + 16, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess || h[0] != c.evstamp) return e;
+    } else {
+        c.full_check = false;
         const long nf = c.n_slots, ns = c.n_sif, n = nf > ns ? nf : ns;
         hipLaunchKernelGGL(k_zero2_i32, dim3(1), dim3(1), 0, st, any);
         if (n > 0)

@@ -29,6 +29,8 @@ struct StepArgs {
     double *__restrict__ phif;           // [S] solid fraction of fluid nodes, compact order
     const T *__restrict__ lceq;          // per link: C_eq - C_ref of its solid node (per-node C_eq)
     double *__restrict__ xio;            // [2][task_cap] per task: inlet, outlet exchange (cumulative)
+    int32_t *evflag;                     // phase change: set to evstamp when an interface node's
+    int32_t evstamp;                     // solid fraction is past a threshold (else null)
     long task_cap;
     long ntasks;
     long S;                              // stride between directions
@@ -123,6 +125,8 @@ struct Ctx {
     void *evmom;             // [N] moments (C, rho) of every node before an event pass
     int32_t *evheap;         // [ev_cap] pending nodes of a pass, once they outgrow the LDS
     long ev_cap;
+    bool full_check;         // the next threshold check scans every working copy
+    int32_t evstamp;         // stamp of the current step in the threshold flag
     bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions
     double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums

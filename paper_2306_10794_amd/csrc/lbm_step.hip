@@ -392,6 +392,9 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             }
         }
         if (sneg != 0.0) a.phif[k] = phi_in + D.vma * sneg;
+        // phase change: a node at or past the precipitation threshold marks
+        // the step (every interface node's value is checked, changed or not)
+        if (a.evflag && (sneg != 0.0 ? phi_in + D.vma * sneg : phi_in) >= 1.0) *a.evflag = a.evstamp;
     }
     // the task's exchanges, stored in link order by the active lanes
     for (int j = lane; j < nlt; j += cnt) {
@@ -449,7 +452,8 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
                                                    const int32_t *__restrict__ sdom,
                                                    const DomDev *__restrict__ doms,
                                                    const T *__restrict__ lq, double *__restrict__ phis,
-                                                   long nsif, double *__restrict__ xpart, int ndom) {
+                                                   long nsif, double *__restrict__ xpart, int ndom,
+                                                   int32_t *evflag, int32_t evstamp) {
     constexpr int M = __builtin_popcount(sol_mask<L, RED>()) - 1;
     const long j = (long)blockIdx.x * BLK + threadIdx.x;
     double tot = 0.0;
@@ -468,7 +472,10 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
             tot += v;
             if (v > 0.0) pos += v;
         }
-        phis[j] -= doms[ndom > 1 ? sdom[j] : 0].vma * pos;
+        const double pn = phis[j] - doms[ndom > 1 ? sdom[j] : 0].vma * pos;
+        phis[j] = pn;
+        // phase change: at or past the dissolution threshold
+        if (evflag && pn <= 0.0) *evflag = evstamp;
     }
     tot = block_sum(tot);
     if (threadIdx.x == 0 && tot != 0.0) xpart[blockIdx.x] += tot;
@@ -491,6 +498,8 @@ static StepArgs<T> step_args(Ctx &c) {
     a.phif = c.phif;
     a.lceq = (const T *)c.lceq;
     a.xio = c.xio;
+    a.evflag = c.p.phase_change ? c.iacc + 16 : nullptr;
+    a.evstamp = c.evstamp;
     a.task_cap = c.task_cap;
     a.ntasks = c.n_tasks;
     a.ndom = c.ndom;
@@ -567,10 +576,12 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
         const long nb2 = (c.n_sif + BLK - 1) / BLK;
         if (c.red)
             hipLaunchKernelGGL((k_phi_solid<L, T, true>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
-                               c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom);
+                               c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom,
+                               args.evflag, args.evstamp);
         else
             hipLaunchKernelGGL((k_phi_solid<L, T, false>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
-                               c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom);
+                               c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom,
+                               args.evflag, args.evstamp);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[3], ps);
@@ -625,6 +636,7 @@ hipError_t launch_phi_gather(Ctx &c, long nf, long nsif) {
         hipLaunchKernelGGL(k_phi_gather, dim3((n + BLK - 1) / BLK), dim3(BLK), 0, c.stream, nf, c.nodeof,
                            nsif, c.sif, c.phi, c.phif, c.phis);
     c.phi_stale = false;
+    c.full_check = true;   // values from outside the step: the next check scans them all
     return hipGetLastError();
 }
 
