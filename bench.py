@@ -103,12 +103,13 @@ def adjoint_kernel_bytes(q, ts, n_fluid, n_links, qs=None):
     """Algorithmic HBM bytes of one launch of the adjoint's two kernels.
 
     Recomputation (one solute-only step at rest): per fluid node QS values
-    read and QS written; per reactive link its coefficient read.  Transposed
-    step: per fluid node QS adjoint values read and QS written; per reactive
-    link its coefficient and the source value of the forward step read (ts
-    each) and its FP64 dL/dbeta read and written (16 B)."""
+    read and QS written; per reactive link its coefficient read and the
+    source value of its rate condition written.  Transposed step: per fluid
+    node QS adjoint values read and QS written; per reactive link its
+    coefficient and that source value read (ts each) and its FP64 dL/dbeta
+    read and written (16 B)."""
     qs = q if qs is None else qs
-    return (n_fluid * qs * ts * 2 + n_links * ts,
+    return (n_fluid * qs * ts * 2 + n_links * 2 * ts,
             n_fluid * qs * ts * 2 + n_links * (2 * ts + 16))
 
 

@@ -46,6 +46,8 @@ struct AdjArgs {
     const int32_t *__restrict__ nodeof;
     const int32_t *__restrict__ lbase;
     const T *__restrict__ lbeta;
+    T *__restrict__ lsrc;         // per link: the source value of its rate condition
+                                  // (written by the recomputation, read by the transpose)
     double *__restrict__ gbeta;   // per link dL/dbeta, accumulated
     const double *__restrict__ dldc;  // dense dL/dC_T (init)
     long ntasks, S;
@@ -87,7 +89,8 @@ __device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c
 
 // One solute step with the fluid at rest, from gin to gout: the arithmetic of
 // the fused step's solute half with u = 0 (no exchange or solid fraction is
-// written).
+// written).  Each reactive link's source value goes to lsrc; with gout null
+// only those are written.
 template <class L, typename T, bool RED, bool TRT>
 __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     using R = double;
@@ -124,10 +127,12 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
                 const R own = (R)gv[i];
                 const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
                 const R beta = (R)a.lbeta[l];
+                a.lsrc[l] = (T)srcv;
                 gv[i] = (T)((R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv);
             }
         }
     }
+    if (!a.gout) return;
     R dC = R(0);
 #pragma unroll
     for (int i = 0; i < Q; i++)
@@ -243,8 +248,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const int l = lpos[i];
             const R beta = (R)a.lbeta[l];
             const bool pulled = D.mech == LBM_PRECOLL && !lo;
-            const R src = pulled ? (R)(c.kk[o] >= 0 ? a.gin[pidx(so, c.kk[o], QS)] : a.gin[pidx(si, c.k, QS)])
-                                 : (R)a.gin[pidx(so, c.k, QS)];
+            const R src = (R)a.lsrc[l];
             a.gbeta[l] += nui * (src - sol_w<L>(D, i) * D.ceq_dev);
             if (pulled) {
                 outo += beta * nui;
@@ -257,8 +261,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const int l = lpos[o];
             const R beta = (R)a.lbeta[l];
             const bool pulled = D.mech == LBM_PRECOLL && !li;
-            const R src = pulled ? (R)(c.kk[i] >= 0 ? a.gin[pidx(si, c.kk[i], QS)] : a.gin[pidx(so, c.k, QS)])
-                                 : (R)a.gin[pidx(si, c.k, QS)];
+            const R src = (R)a.lsrc[l];
             a.gbeta[l] += nuo * (src - sol_w<L>(D, o) * D.ceq_dev);
             if (pulled) {
                 outi += beta * nuo;
@@ -349,6 +352,7 @@ static AdjArgs<T> adj_args(Ctx &c) {
     a.nodeof = c.nodeof;
     a.lbase = c.lbase;
     a.lbeta = (const T *)c.lbeta;
+    a.lsrc = nullptr;
     a.gbeta = c.adj.gbeta;
     a.dldc = nullptr;
     a.ntasks = c.n_tasks;
@@ -389,7 +393,8 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double 
     AdjArgs<T> a = adj_args<T>(c);
     T *P[2] = {(T *)r.p[0], (T *)r.p[1]};
     const T *ck = (const T *)r.ckpt;
-    T *hist = (T *)r.hist;
+    T *rs[2] = {(T *)r.rst[0], (T *)r.rst[1]};
+    T *src = (T *)r.lsrc;
     // dL/dbeta := 0, lambda(T) from dL/dC_T
     hipLaunchKernelGGL(k_adj_zero, dim3((c.n_links + BLK - 1) / BLK + 1), dim3(BLK), 0, c.stream,
                        r.gbeta, (long)c.n_links);
@@ -401,13 +406,13 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double 
     for (int sgi = nseg - 1; sgi >= 0; sgi--) {
         const long t0 = (long)sgi * r.ckpt_every;
         const int len = (int)((r.nsteps - t0) < r.ckpt_every ? (r.nsteps - t0) : r.ckpt_every);
-        // state j of the segment: j = 0 the checkpoint, else hist slot j - 1
-        auto state = [&](int j) -> T * {
-            return j == 0 ? (T *)(ck + (size_t)sgi * slot) : hist + (size_t)(j - 1) * slot;
-        };
-        for (int j = 1; j < len; j++) {
-            a.gin = state(j - 1);
-            a.gout = state(j);
+        // recomputation: state 0 of the segment is its checkpoint, state j > 0
+        // lives in rs[(j - 1) & 1]; stepping from state j records the links'
+        // source values of step j (the last state's successor is not needed)
+        for (int j = 0; j < len; j++) {
+            a.gin = j == 0 ? (T *)(ck + (size_t)sgi * slot) : rs[(j - 1) & 1];
+            a.gout = j + 1 < len ? rs[j & 1] : nullptr;
+            a.lsrc = src + (size_t)j * r.src_stride;
             if (ms) (void)hipEventRecord(c.ev[0], c.stream);
             if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T, RED, TRT>), dim3(nb), dim3(BLK), 0, c.stream, a);
             if (ms) {
@@ -416,8 +421,10 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double 
                 if (e != hipSuccess) return e;
             }
         }
+        a.gin = nullptr;
+        a.gout = nullptr;
         for (int j = len - 1; j >= 0; j--) {
-            a.gin = state(j);
+            a.lsrc = src + (size_t)j * r.src_stride;
             a.pin = P[cur];
             a.pout = P[1 - cur];
             if (ms) (void)hipEventRecord(c.ev[0], c.stream);

@@ -864,13 +864,20 @@ static size_t adj_layout(const Ctx *c, int64_t nsteps, int64_t ckpt, AdjState *s
         off += (n + ALIGN - 1) / ALIGN * ALIGN;
         return p;
     };
+    // per step of a segment, one source value per reactive link of the
+    // current geometry (which a recorded run keeps)
+    const size_t stride = ((size_t)c->n_links + 1 + 63) / 64 * 64;
     char *ck = take(ncp * slot);
-    char *hi = take((size_t)(ckpt - 1) * slot);
+    char *r0 = take(slot), *r1 = take(slot);
+    char *ls = take((size_t)ckpt * stride * ts);
     char *p0 = take(slot), *p1 = take(slot);
     char *gb = take(sizeof(double) * (size_t)(c->max_links + 1));
     if (st) {
         st->ckpt = ck;
-        st->hist = hi;
+        st->rst[0] = r0;
+        st->rst[1] = r1;
+        st->lsrc = ls;
+        st->src_stride = (int64_t)stride;
         st->p[0] = p0;
         st->p[1] = p1;
         st->gbeta = (double *)gb;

@@ -54,7 +54,10 @@ struct AdjState {
     int64_t static_gen;      // > 0: the run lives in the library's static array,
                              // as the static_gen-th record taken into it
     void *ckpt;              // [ceil(nsteps/ckpt_every)][Q][S] solute states
-    void *hist;              // [ckpt_every - 1][Q][S] recomputed states
+    void *rst[2];            // [Q][S] recomputed states (alternating)
+    void *lsrc;              // [ckpt_every][n_links + 1] per step and reactive link: the
+                             // source value of its rate condition (recomputed)
+    int64_t src_stride;      // elements between two steps of lsrc
     void *p[2];              // [Q][S] adjoint arrays
     double *gbeta;           // [max_links] dL/dbeta
 };

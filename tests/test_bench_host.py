@@ -40,10 +40,11 @@ def test_step_bytes_per_launch():
 
 def test_adjoint_bytes_per_launch():
     import bench
-    # recomputation: QS read + QS written per node, beta per link; transposed
-    # step: the same per node, beta + source + FP64 dL/dbeta read and written
+    # recomputation: QS read + QS written per node, beta read and the source
+    # value written per link; transposed step: the same per node, beta +
+    # source read and FP64 dL/dbeta read and written per link
     sol, adj = bench.adjoint_kernel_bytes(19, 4, 939_011, 1_000_000)
-    assert sol == 939_011 * 19 * 8 + 1_000_000 * 4
+    assert sol == 939_011 * 19 * 8 + 1_000_000 * 8
     assert adj == 939_011 * 19 * 8 + 1_000_000 * (8 + 16)
 
 
