@@ -113,6 +113,20 @@ def adjoint_kernel_bytes(q, ts, n_fluid, n_links, qs=None):
             n_fluid * qs * ts * 2 + n_links * (2 * ts + 16))
 
 
+def phi_kernel_bytes(ts, n_links, n_solid_iface):
+    """Algorithmic HBM bytes of one launch of the solid-side kernel: per solid
+    interface node its link offset (4 B) and its FP64 solid fraction read and
+    written (16 B); per reactive link its index in the node's list (4 B) and
+    its exchange (ts)."""
+    return n_solid_iface * 20 + n_links * (4 + ts)
+
+
+# kernel names as the profiler reports them, for the per-kernel byte counts
+SOL_KERNEL = "lbm::k_sol_step<lbm::D3Q19, float, false, false>"
+ADJ_KERNEL = "lbm::k_adj_step<lbm::D3Q19, float, false, false>"
+ALGO_BYTES = {}   # kernel -> algorithmic bytes per launch, filled by the legs that run
+
+
 def kernel_sha256():
     h = hashlib.sha256()
     for p in KERNEL_SRCS:
@@ -272,9 +286,13 @@ def adjoint_ratio(steps, ckpt):
     same = bool(torch.equal(grad_t, g))
     sim.close()
     nseg = (steps + ckpt - 1) // ckpt
-    sol_us = sol_ms / max(steps - nseg, 1) * 1e3
+    # one recomputation launch per step (the last of a segment records the
+    # source values only) and one transposed step per step
+    sol_us = sol_ms / steps * 1e3
     adj_us = adj_ms / steps * 1e3
     sol_b, adj_b = adjoint_kernel_bytes(case.q, 4, nf, nl)
+    ALGO_BYTES[SOL_KERNEL] = sol_b
+    ALGO_BYTES[ADJ_KERNEL] = adj_b
     del sim
     torch.cuda.empty_cache()
     return {
@@ -597,6 +615,76 @@ def summarize_counters(prof_dir, runs):
     print(path, flush=True)
 
 
+def summarize_traffic(prof_dir, calib_mib=1024):
+    """HBM bytes per dispatch of every kernel of the runs PROFILE_CMDS
+    ['fetch_all'] and ['write_all'] (FETCH_SIZE and WRITE_SIZE in KiB, scaled
+    by what they read for a copy of calib_mib MiB that reads and writes exactly
+    that many bytes), beside the algorithmic bytes the same run wrote with
+    --dump-bytes; written to prof_dir/summary/kernels_traffic_pmc.md."""
+    out_dir = os.path.join(prof_dir, "summary")
+    os.makedirs(out_dir, exist_ok=True)
+
+    def counter(d, cname):
+        # per (kernel, grid size): the dispatches' values and the first dispatch
+        db = _db(os.path.join(prof_dir, d))
+        res = {}
+        for name, grid, disp, val in db.execute(
+                "select kernel_name, grid_size, dispatch_id, value from counters_collection "
+                "where counter_name = ?", (cname,)):
+            key = (name.split("(")[0].replace("void ", ""), int(grid))
+            e = res.setdefault(key, [[], disp])
+            e[0].append(float(val))
+            e[1] = min(e[1], disp)
+        return res
+
+    fetch, write = counter("fetch_all", "FETCH_SIZE"), counter("write_all", "WRITE_SIZE")
+    algo = {}
+    for d in ("fetch_all", "write_all"):
+        path = os.path.join(prof_dir, d, "algo_bytes.json")
+        if os.path.exists(path):
+            algo.update(json.load(open(path)))
+    calib = calib_mib * 2 ** 20
+
+    def copy_kib(res):
+        vals = [v for (k, _), (vs, _) in res.items() if COPY_KERNEL in k for v in vs]
+        if not vals:
+            raise SystemExit("no calibration dispatches in the counter runs")
+        return sum(vals) / len(vals)
+
+    f_fetch = calib / (copy_kib(fetch) * 1024.0)
+    f_write = calib / (copy_kib(write) * 1024.0)
+    lines = ["# HBM traffic per dispatch of every kernel of the step and adjoint legs (rocprofv3 --pmc)",
+             "", "Commands (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
+             f"    {PROFILE_CMDS['fetch_all']} --dump-bytes gpurun_out/prof/fetch_all/algo_bytes.json",
+             f"    {PROFILE_CMDS['write_all']} --dump-bytes gpurun_out/prof/write_all/algo_bytes.json",
+             "    python3 bench.py --summarize-traffic gpurun_out/prof", "",
+             f"Calibration: an elementwise negation of {calib_mib} MiB (float32) reads and writes "
+             f"{calib} B; FETCH_SIZE reads {copy_kib(fetch):.0f} KiB for it (scale {f_fetch:.3f}) and "
+             f"WRITE_SIZE {copy_kib(write):.0f} KiB (scale {f_write:.3f}).  The step leg (the 256^3 "
+             "sphere packing, D3Q19 + D3Q19, FP32 storage) runs first, then the adjoint leg (the "
+             "128^3 rate-recovery packing, whose recorded forward run also launches the step "
+             "kernels): a kernel appears once per grid size, and the algorithmic bytes belong to "
+             "its first grid (the leg that timed it).", "",
+             "| kernel | grid (work-items) | dispatches | scaled read B | scaled write B | scaled total B | "
+             "algorithmic B | total / algorithmic |", "|---|---|---|---|---|---|---|---|"]
+    keys = [k for k in fetch if k[0].startswith("lbm::") and k in write]
+    first = {}
+    for k in sorted(keys, key=lambda k: fetch[k][1]):
+        first.setdefault(k[0], k)
+    keys.sort(key=lambda k: -sum(fetch[k][0]) / len(fetch[k][0]))
+    for k in keys:
+        fv, wv = fetch[k][0], write[k][0]
+        rb = sum(fv) / len(fv) * 1024 * f_fetch
+        wb = sum(wv) / len(wv) * 1024 * f_write
+        ab = algo.get(k[0]) if first[k[0]] == k else None
+        lines.append(f"| `{k[0]}` | {k[1]} | {len(fv)} | {rb:.4g} | {wb:.4g} | {rb + wb:.4g} | "
+                     f"{'' if ab is None else f'{ab:.4g}'} | "
+                     f"{'' if ab is None else f'{(rb + wb) / ab:.3f}'} |")
+    path = os.path.join(out_dir, "kernels_traffic_pmc.md")
+    open(path, "w").write("\n".join(lines) + "\n")
+    print(path, flush=True)
+
+
 def calibration_copies(mib):
     """Three copy-like passes of a known size (counter calibration): an
     elementwise negation reads and writes every element once."""
@@ -641,6 +729,10 @@ def main():
                     help="summarise the all-legs kernel trace under DIR/legs and exit")
     ap.add_argument("--summarize-counters", metavar="DIR",
                     help="summarise the counter passes DIR/<run> named by --runs and exit")
+    ap.add_argument("--dump-bytes", metavar="PATH",
+                    help="write the algorithmic bytes per launch of the kernels the run timed")
+    ap.add_argument("--summarize-traffic", metavar="DIR",
+                    help="summarise the FETCH_SIZE / WRITE_SIZE passes DIR/fetch_all, DIR/write_all")
     ap.add_argument("--runs", default="sq1,sq2,sq3,sq4",
                     help="comma-separated pass directories for --summarize-counters")
     args = ap.parse_args()
@@ -649,6 +741,9 @@ def main():
         return
     if args.summarize_legs:
         summarize_legs(args.summarize_legs)
+        return
+    if args.summarize_traffic:
+        summarize_traffic(args.summarize_traffic)
         return
     if args.summarize_counters:
         summarize_counters(args.summarize_counters, args.runs.split(","))
@@ -690,6 +785,10 @@ def main():
                       n_row_words=d["n_row_words"])
     k_avg_s = k_ms / args.steps / 1e3
     achieved = kb / k_avg_s / 1e9
+    pb = phi_kernel_bytes(4, d["n_links"], d["n_solid_iface"])
+    phi_avg_s = phi_ms / args.steps / 1e3
+    ALGO_BYTES[STEP_KERNEL] = kb
+    ALGO_BYTES[PHI_KERNEL] = pb
     line = {
         "metric": METRIC,
         "value": round(mlups, 1),
@@ -720,6 +819,9 @@ def main():
             "kernel": "k_step", "bytes_per_launch": int(kb),
             "avg_kernel_us": round(k_avg_s * 1e6, 2),
             "phi_kernel_us": round(phi_ms / args.steps * 1e3, 2),
+            "phi_kernel": {"kernel": "k_phi_solid", "bytes_per_launch": int(pb),
+                           "achieved_gbs": round(pb / phi_avg_s / 1e9, 1),
+                           "frac": round(pb / phi_avg_s / 1e9 / HBM_PEAK_GBS, 4)},
         },
         "cpu_baseline": None,
         "batch": None,
@@ -753,6 +855,8 @@ def main():
         log("[bench] cpu baseline (oracle) ...")
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
         log(f"[bench] cpu baseline {line['cpu_baseline']}")
+    if args.dump_bytes:
+        json.dump(ALGO_BYTES, open(args.dump_bytes, "w"), indent=1)
     print(json.dumps(line), flush=True)
 
 

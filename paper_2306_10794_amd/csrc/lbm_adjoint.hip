@@ -66,7 +66,10 @@ struct TaskCtx {
 
 template <class L, typename T>
 __device__ __forceinline__ bool task_setup(const AdjArgs<T> &a, TaskCtx<L, T> &c) {
-    const int t = __builtin_amdgcn_readfirstlane((int)(blockIdx.x * (BLK / 64)) + (int)(threadIdx.x >> 6));
+    // consecutive workgroups of tasks on one XCD (its L2 then holds the lines
+    // that neighbouring tasks' pulls share), as in the fused step
+    const long tile = xcd_tile(blockIdx.x, gridDim.x);
+    const int t = __builtin_amdgcn_readfirstlane((int)(tile * (BLK / 64)) + (int)(threadIdx.x >> 6));
     if (t >= a.ntasks) return false;
     const int lane = threadIdx.x & 63;
     const Task tk = a.tasks[t];
