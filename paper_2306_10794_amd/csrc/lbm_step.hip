@@ -289,7 +289,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const R om = D.omega_f, ff = D.force_fac, om1 = R(1) - om;
     const R base = om * (drho - R(1.5) * rho * uu) - R(3) * ff * uF;
     const R c45 = R(4.5) * om * rho;
-    a.fout[pidx(0, k, Q)] = (T)(om1 * fp[0] + R(L::w[0]) * base);
+    __builtin_nontemporal_store((T)(om1 * fp[0] + R(L::w[0]) * base), &a.fout[pidx(0, k, Q)]);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i) continue;
@@ -304,12 +304,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             // second rate, the even ones with om
             const R B = R(3) * wi * (D.omega_fm * em + D.force_fac_m * eF);
             const R hp = R(0.5) * om * (fp[i] + fp[o]), hm = R(0.5) * D.omega_fm * (fp[i] - fp[o]);
-            a.fout[pidx(i, k, Q)] = (T)(fp[i] - hp - hm + (A + B));
-            a.fout[pidx(o, k, Q)] = (T)(fp[o] - hp + hm + (A - B));
+            __builtin_nontemporal_store((T)(fp[i] - hp - hm + (A + B)), &a.fout[pidx(i, k, Q)]);
+            __builtin_nontemporal_store((T)(fp[o] - hp + hm + (A - B)), &a.fout[pidx(o, k, Q)]);
         } else {
             const R B = R(3) * wi * (om * em + ff * eF);
-            a.fout[pidx(i, k, Q)] = (T)(om1 * fp[i] + (A + B));
-            a.fout[pidx(o, k, Q)] = (T)(om1 * fp[o] + (A - B));
+            __builtin_nontemporal_store((T)(om1 * fp[i] + (A + B)), &a.fout[pidx(i, k, Q)]);
+            __builtin_nontemporal_store((T)(om1 * fp[o] + (A - B)), &a.fout[pidx(o, k, Q)]);
         }
     }
 
@@ -418,7 +418,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const R omg = D.omega_g, omg1 = R(1) - omg, oms = D.omega_gs;
     const R Cw = omg * C * D.inv_cs2s * D.wsc;
     const R Aw = (TRT ? oms : omg) * D.wsc * dC;
-    a.gout[pidx(0, k, QS)] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
+    __builtin_nontemporal_store((T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC), &a.gout[pidx(0, k, QS)]);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
@@ -431,11 +431,11 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         if constexpr (TRT) {
             const R gi = (R)gv[i], go = (R)gv[o];
             const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * omg * (gi - go);
-            a.gout[si] = (T)(gi - hs - ha + (As + Bs));
-            a.gout[so] = (T)(go - hs + ha + (As - Bs));
+            __builtin_nontemporal_store((T)(gi - hs - ha + (As + Bs)), &a.gout[si]);
+            __builtin_nontemporal_store((T)(go - hs + ha + (As - Bs)), &a.gout[so]);
         } else {
-            a.gout[si] = (T)(omg1 * (R)gv[i] + (As + Bs));
-            a.gout[so] = (T)(omg1 * (R)gv[o] + (As - Bs));
+            __builtin_nontemporal_store((T)(omg1 * (R)gv[i] + (As + Bs)), &a.gout[si]);
+            __builtin_nontemporal_store((T)(omg1 * (R)gv[o] + (As - Bs)), &a.gout[so]);
         }
     }
 }
