@@ -72,10 +72,10 @@ SQ_ARGS = ("--steps 5 --warmup 1 --no-cpu-baseline --no-batch --no-phase-change 
 for _g, _c in SQ_GROUPS.items():
     PROFILE_CMDS[_g] = f"rocprofv3 --pmc {_c} -d gpurun_out/prof/{_g} -o run -- python3 bench.py {SQ_ARGS}"
 # HBM bytes of every kernel of the step and adjoint legs
-PROFILE_CMDS["fetch_all"] = (f"rocprofv3 --pmc FETCH_SIZE -d gpurun_out/prof/fetch_all -o run -- "
-                             f"python3 bench.py {SQ_ARGS} --calib-copy-mib 1024")
-PROFILE_CMDS["write_all"] = (f"rocprofv3 --pmc WRITE_SIZE -d gpurun_out/prof/write_all -o run -- "
-                             f"python3 bench.py {SQ_ARGS} --calib-copy-mib 1024")
+for _c, _d in (("FETCH_SIZE", "fetch_all"), ("WRITE_SIZE", "write_all")):
+    PROFILE_CMDS[_d] = (f"rocprofv3 --pmc {_c} -d gpurun_out/prof/{_d} -o run -- python3 bench.py {SQ_ARGS} "
+                        f"--calib-copy-mib 1024 --dump-bytes gpurun_out/prof/{_d}/algo_bytes.json")
+PROFILE_CMDS["traffic_summary"] = "python3 bench.py --summarize-traffic gpurun_out/prof"
 
 
 def log(msg):
@@ -566,19 +566,23 @@ def summarize_legs(prof_dir):
     out_dir = os.path.join(prof_dir, "summary")
     os.makedirs(out_dir, exist_ok=True)
     tr = _db(os.path.join(prof_dir, "legs"))
-    rows = tr.execute("select name, count(*), avg(end - start), min(end - start), max(end - start), "
-                      "sum(end - start) from kernels group by name order by sum(end - start) desc"
-                      ).fetchall()
-    total = sum(r[5] for r in rows) or 1
+    # one row per kernel and grid size (the legs launch some kernels on
+    # lattices of different sizes)
+    rows = tr.execute("select name, grid_x * grid_y * grid_z, count(*), avg(end - start), min(end - start), "
+                      "max(end - start), sum(end - start) from kernels group by name, grid_x * grid_y * grid_z "
+                      "order by sum(end - start) desc").fetchall()
+    total = sum(r[6] for r in rows) or 1
     lines = ["# Kernel durations, every leg of bench.py (rocprofv3 --kernel-trace --stats)", "",
              "Legs: the 256^3 sphere packing (D3Q19 and D3Q7 solute), the 1024-domain batch, the",
-             "phase-change burst and the 128^3 adjoint (record + adjoint).", "",
+             "phase-change burst and the 128^3 adjoint (record + adjoint).  One row per kernel and",
+             "grid size.", "",
              "Command (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
              f"    {PROFILE_CMDS['legs']}", "",
-             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
-    for name, n, avg, mn, mx, tot in rows[:30]:
+             "| kernel | grid (work-items) | calls | avg us | min us | max us | % of GPU time |",
+             "|---|---|---|---|---|---|---|"]
+    for name, grid, n, avg, mn, mx, tot in rows[:36]:
         short = name.split("(")[0].replace("void ", "")
-        lines.append(f"| `{short}` | {n} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
+        lines.append(f"| `{short}` | {grid} | {n} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
                      f"{100.0 * tot / total:.1f} |")
     path = os.path.join(out_dir, "kernels_all_legs_trace.md")
     open(path, "w").write("\n".join(lines) + "\n")
@@ -594,22 +598,25 @@ def summarize_counters(prof_dir, runs):
     table = {}
     for r in runs:
         db = _db(os.path.join(prof_dir, r))
-        for name, cname, val in db.execute("select kernel_name, counter_name, value from "
-                                           "counters_collection"):
-            k = name.split("(")[0].replace("void ", "")
+        for name, grid, cname, val in db.execute("select kernel_name, grid_size, counter_name, value from "
+                                                 "counters_collection"):
+            k = (name.split("(")[0].replace("void ", ""), int(grid))
             table.setdefault(k, {}).setdefault(cname, []).append(float(val))
-    keep = [k for k in table if k.startswith("lbm::")]
+    keep = [k for k in table if k[0].startswith("lbm::")]
     cnames = sorted({c for k in keep for c in table[k]})
     lines = ["# SQ counters per dispatch (rocprofv3 --pmc, one pass per counter group)", "",
              "Commands (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -"]
     lines += [f"    {PROFILE_CMDS[r]}" for r in runs if r in PROFILE_CMDS]
-    lines += ["", "| kernel | dispatches | " + " | ".join(cnames) + " |",
-              "|---|---|" + "---|" * len(cnames)]
-    for k in sorted(keep, key=lambda k: -max(len(v) for v in table[k].values())):
+    lines += ["", "One row per kernel and grid size: the step leg runs the 256^3 sphere packing, the "
+              "adjoint leg the 128^3 rate-recovery packing (whose recorded forward run launches the "
+              "step kernels too).", "",
+              "| kernel | grid (work-items) | dispatches | " + " | ".join(cnames) + " |",
+              "|---|---|---|" + "---|" * len(cnames)]
+    for k in sorted(keep, key=lambda k: (k[0], -k[1])):
         vals = table[k]
         n = max(len(v) for v in vals.values())
         cells = [f"{sum(vals[c]) / len(vals[c]):.4g}" if c in vals else "" for c in cnames]
-        lines.append(f"| `{k}` | {n} | " + " | ".join(cells) + " |")
+        lines.append(f"| `{k[0]}` | {k[1]} | {n} | " + " | ".join(cells) + " |")
     path = os.path.join(out_dir, "sq_counters.md")
     open(path, "w").write("\n".join(lines) + "\n")
     print(path, flush=True)
@@ -655,9 +662,8 @@ def summarize_traffic(prof_dir, calib_mib=1024):
     f_write = calib / (copy_kib(write) * 1024.0)
     lines = ["# HBM traffic per dispatch of every kernel of the step and adjoint legs (rocprofv3 --pmc)",
              "", "Commands (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
-             f"    {PROFILE_CMDS['fetch_all']} --dump-bytes gpurun_out/prof/fetch_all/algo_bytes.json",
-             f"    {PROFILE_CMDS['write_all']} --dump-bytes gpurun_out/prof/write_all/algo_bytes.json",
-             "    python3 bench.py --summarize-traffic gpurun_out/prof", "",
+             f"    {PROFILE_CMDS['fetch_all']}", f"    {PROFILE_CMDS['write_all']}",
+             f"    {PROFILE_CMDS['traffic_summary']}", "",
              f"Calibration: an elementwise negation of {calib_mib} MiB (float32) reads and writes "
              f"{calib} B; FETCH_SIZE reads {copy_kib(fetch):.0f} KiB for it (scale {f_fetch:.3f}) and "
              f"WRITE_SIZE {copy_kib(write):.0f} KiB (scale {f_write:.3f}).  The step leg (the 256^3 "
@@ -856,6 +862,7 @@ def main():
         line["cpu_baseline"] = cpu_baseline(case, args.cpu_steps)
         log(f"[bench] cpu baseline {line['cpu_baseline']}")
     if args.dump_bytes:
+        os.makedirs(os.path.dirname(os.path.abspath(args.dump_bytes)), exist_ok=True)
         json.dump(ALGO_BYTES, open(args.dump_bytes, "w"), indent=1)
     print(json.dumps(line), flush=True)
 
