@@ -483,6 +483,16 @@ def _db(d):
     return sqlite3.connect(files[-1])
 
 
+def _medians(db, by_grid=False):
+    """Median dispatch duration (ns) per kernel name (and grid size)."""
+    vals = {}
+    q = ("select name, grid_x * grid_y * grid_z, end - start from kernels" if by_grid
+         else "select name, 0, end - start from kernels")
+    for name, grid, d in db.execute(q):
+        vals.setdefault((name, grid) if by_grid else name, []).append(d)
+    return {k: float(np.median(v)) for k, v in vals.items()}
+
+
 def summarize_profiles(prof_dir, workload="spheres256", calib_mib=1024):
     """Per-kernel durations from the kernel-trace run and HBM bytes from the
     FETCH_SIZE / WRITE_SIZE runs (KiB per dispatch), scaled by what the same
@@ -498,14 +508,16 @@ def summarize_profiles(prof_dir, workload="spheres256", calib_mib=1024):
     lines = [f"# Kernel durations, {workload} (rocprofv3 --kernel-trace --stats)", "",
              "Command (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
              f"    {PROFILE_CMDS['trace']}", "",
-             "| kernel | calls | avg us | min us | max us | % of GPU time |", "|---|---|---|---|---|---|"]
+             "| kernel | calls | avg us | median us | min us | max us | % of GPU time |",
+             "|---|---|---|---|---|---|---|"]
+    med = _medians(tr)
     step_avg = None
     for name, n, avg, mn, mx, tot in rows[:14]:
         short = name.split("(")[0].replace("void ", "")
         if short == STEP_KERNEL:
             step_avg = avg
-        lines.append(f"| `{short}` | {n} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
-                     f"{100.0 * tot / total:.1f} |")
+        lines.append(f"| `{short}` | {n} | {avg / 1e3:.1f} | {med[name] / 1e3:.1f} | {mn / 1e3:.1f} | "
+                     f"{mx / 1e3:.1f} | {100.0 * tot / total:.1f} |")
     if step_avg is None:
         for name, n, avg, *_ in rows:
             if name.split("(")[0].replace("void ", "") == STEP_KERNEL:
@@ -578,12 +590,13 @@ def summarize_legs(prof_dir):
              "grid size.", "",
              "Command (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -",
              f"    {PROFILE_CMDS['legs']}", "",
-             "| kernel | grid (work-items) | calls | avg us | min us | max us | % of GPU time |",
-             "|---|---|---|---|---|---|---|"]
+             "| kernel | grid (work-items) | calls | avg us | median us | min us | max us | % of GPU time |",
+             "|---|---|---|---|---|---|---|---|"]
+    med = _medians(tr, by_grid=True)
     for name, grid, n, avg, mn, mx, tot in rows[:36]:
         short = name.split("(")[0].replace("void ", "")
-        lines.append(f"| `{short}` | {grid} | {n} | {avg / 1e3:.1f} | {mn / 1e3:.1f} | {mx / 1e3:.1f} | "
-                     f"{100.0 * tot / total:.1f} |")
+        lines.append(f"| `{short}` | {grid} | {n} | {avg / 1e3:.1f} | {med[(name, grid)] / 1e3:.1f} | "
+                     f"{mn / 1e3:.1f} | {mx / 1e3:.1f} | {100.0 * tot / total:.1f} |")
     path = os.path.join(out_dir, "kernels_all_legs_trace.md")
     open(path, "w").write("\n".join(lines) + "\n")
     print(path, flush=True)
@@ -592,7 +605,7 @@ def summarize_legs(prof_dir):
 def summarize_counters(prof_dir, runs):
     """Average per-dispatch value of every counter of the rocprofv3 --pmc runs
     prof_dir/<run> (one directory per pass), per kernel; written to
-    prof_dir/summary/sq_counters.md with the commands of PROFILE_CMDS."""
+    prof_dir/summary/kernels_step_adjoint_sq_counters.md with the commands of PROFILE_CMDS."""
     out_dir = os.path.join(prof_dir, "summary")
     os.makedirs(out_dir, exist_ok=True)
     table = {}
@@ -602,7 +615,9 @@ def summarize_counters(prof_dir, runs):
                                                  "counters_collection"):
             k = (name.split("(")[0].replace("void ", ""), int(grid))
             table.setdefault(k, {}).setdefault(cname, []).append(float(val))
-    keep = [k for k in table if k[0].startswith("lbm::")]
+    # the kernels the bench legs time
+    timed = (STEP_KERNEL, PHI_KERNEL, RED_STEP_KERNEL, RED_PHI_KERNEL, SOL_KERNEL, ADJ_KERNEL)
+    keep = [k for k in table if k[0] in timed]
     cnames = sorted({c for k in keep for c in table[k]})
     lines = ["# SQ counters per dispatch (rocprofv3 --pmc, one pass per counter group)", "",
              "Commands (repository root):", "", "    cd /tmp && export TMPDIR=/tmp && cd -"]
@@ -617,7 +632,7 @@ def summarize_counters(prof_dir, runs):
         n = max(len(v) for v in vals.values())
         cells = [f"{sum(vals[c]) / len(vals[c]):.4g}" if c in vals else "" for c in cnames]
         lines.append(f"| `{k[0]}` | {k[1]} | {n} | " + " | ".join(cells) + " |")
-    path = os.path.join(out_dir, "sq_counters.md")
+    path = os.path.join(out_dir, "kernels_step_adjoint_sq_counters.md")
     open(path, "w").write("\n".join(lines) + "\n")
     print(path, flush=True)
 
@@ -627,7 +642,7 @@ def summarize_traffic(prof_dir, calib_mib=1024):
     ['fetch_all'] and ['write_all'] (FETCH_SIZE and WRITE_SIZE in KiB, scaled
     by what they read for a copy of calib_mib MiB that reads and writes exactly
     that many bytes), beside the algorithmic bytes the same run wrote with
-    --dump-bytes; written to prof_dir/summary/kernels_traffic_pmc.md."""
+    --dump-bytes; written to prof_dir/summary/kernels_step_adjoint_traffic_pmc.md."""
     out_dir = os.path.join(prof_dir, "summary")
     os.makedirs(out_dir, exist_ok=True)
 
@@ -686,7 +701,7 @@ def summarize_traffic(prof_dir, calib_mib=1024):
         lines.append(f"| `{k[0]}` | {k[1]} | {len(fv)} | {rb:.4g} | {wb:.4g} | {rb + wb:.4g} | "
                      f"{'' if ab is None else f'{ab:.4g}'} | "
                      f"{'' if ab is None else f'{(rb + wb) / ab:.3f}'} |")
-    path = os.path.join(out_dir, "kernels_traffic_pmc.md")
+    path = os.path.join(out_dir, "kernels_step_adjoint_traffic_pmc.md")
     open(path, "w").write("\n".join(lines) + "\n")
     print(path, flush=True)
 

@@ -442,7 +442,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
 
 // dissolution side of the solid fraction, per solid interface node, links in
 // ascending direction order; also the step's total exchange, added to this
-// workgroup's own slot xpart[blockIdx.x] (no atomics: the slots are folded
+// workgroup's own slot xpart[tile] (no atomics: the slots are folded
 // into the running total when it is read).  A solid node has at most QS - 1
 // links (one per moving direction of the solute set): all their indices,
 // then all their exchanges, are loaded before the ordered sum.
@@ -453,9 +453,14 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
                                                    const DomDev *__restrict__ doms,
                                                    const T *__restrict__ lq, double *__restrict__ phis,
                                                    long nsif, double *__restrict__ xpart, int ndom,
-                                                   int32_t *evflag, int32_t evstamp) {
+                                                   int32_t *evflag, int32_t evstamp, int remap) {
     constexpr int M = __builtin_popcount(sol_mask<L, RED>()) - 1;
-    const long j = (long)blockIdx.x * BLK + threadIdx.x;
+    // with remap each XCD takes a contiguous range of solid nodes: the lines
+    // of exchanges that neighbouring solid nodes (and those of the next
+    // planes) gather stay in that XCD's L2, which cuts the kernel's HBM reads
+    // to about its algorithmic bytes
+    const long tile = remap ? xcd_tile(blockIdx.x, gridDim.x) : (long)blockIdx.x;
+    const long j = tile * BLK + threadIdx.x;
     double tot = 0.0;
     if (j < nsif) {
         const int k0 = soff[j], nk = soff[j + 1] - k0;
@@ -478,7 +483,7 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
         if (evflag && pn <= 0.0) *evflag = evstamp;
     }
     tot = block_sum(tot);
-    if (threadIdx.x == 0 && tot != 0.0) xpart[blockIdx.x] += tot;
+    if (threadIdx.x == 0 && tot != 0.0) xpart[tile] += tot;
 }
 
 template <typename T>
@@ -577,11 +582,11 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
         if (c.red)
             hipLaunchKernelGGL((k_phi_solid<L, T, true>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
                                c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom,
-                               args.evflag, args.evstamp);
+                               args.evflag, args.evstamp, c.cfg.xcd_remap);
         else
             hipLaunchKernelGGL((k_phi_solid<L, T, false>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
                                c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom,
-                               args.evflag, args.evstamp);
+                               args.evflag, args.evstamp, c.cfg.xcd_remap);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[3], ps);
