@@ -32,16 +32,19 @@ SCHEMES = (SCHEME_SNEW, SCHEME_SV, SCHEME_SPJ, SCHEME_ABB)
 PEDAS = (0.1, 1.0, 10.0, 100.0, 1e3, 1e4, 1e5)
 
 
-def _analytic(kr, tau=0.74):
+def _analytic(kr, tau=0.74, inlet=None):
     """Analytic field on the fluid nodes (x = 0..A-1, rows 1..B), each
     boundary plane where the lattice puts it for a linear profile: C fixed at
     x = -tau by the equilibrium inlet, the zero-gradient mirror at x = A - 1/2,
     the bottom zero-flux plane halfway to the solid row, the reactive plane
-    on the top fluid row (pre-collision source, new scheme)."""
-    x = np.arange(A) + tau
+    on the top fluid row (pre-collision source, new scheme).  inlet: the
+    distance of the fixed-C plane before the first node column in place of
+    tau (0: the plane on that column)."""
+    x0 = tau if inlet is None else inlet
+    x = np.arange(A) + x0
     y = np.arange(1, B + 1) - 0.5
     X, Y = np.meshgrid(x, y)
-    return paper_2d_verification(X, Y, A - 0.5 + tau, B - 0.5, D, kr, 1.0, 0.0)
+    return paper_2d_verification(X, Y, A - 0.5 + x0, B - 0.5, D, kr, 1.0, 0.0)
 
 
 def _steady(cases, steps=STEADY):
@@ -128,7 +131,11 @@ def test_rest_fraction_table():
     paper's and varies more with J0, and at J0 = 0.9 it is 3.5e-3: the
     equilibrium inlet fixes C at x = -tau, exact only for a linear profile,
     and tau reaches 2.1 there (the paper does not say which Dirichlet
-    condition its code uses).  Values are logged beside the paper's."""
+    condition its code uses).  The same fields against the analytic field
+    with the fixed-C plane half a site before the first column, or on it, lie
+    further off at every J0 (that plane is where the inlet puts C), and none
+    of the three placements gives the paper's J0-independent value.  Values
+    are logged beside the paper's."""
     gold = np.loadtxt(__file__.replace("test_gpu_schemes.py", "golden/restfraction_mae.txt"))
     kr = 1.0 * D / B
     m = {}
@@ -142,6 +149,12 @@ def test_rest_fraction_table():
         paper = gold[:len(j0s), 3 + coll] * 1e-3
         log(f"[schemes] rest fraction, collision {coll}: J0 {list(j0s)} MAE {list(m[coll])} "
             f"paper {list(paper)}")
+        # the same fields against the analytic field with the fixed-C plane
+        # placed elsewhere: on the first node column, half a site before it
+        for x0 in (0.5, 0.0):
+            alt = np.array([np.abs(f - _analytic(kr, c.tau_ad, inlet=x0)).mean() for c, f in zip(cases, fields)])
+            log(f"[schemes] rest fraction, collision {coll}, inlet plane at x = -{x0}: MAE {list(alt)}")
+            assert np.all(alt > m[coll])
     assert np.all(np.abs(m[1][:3] / m[0] - 1) < 0.03)
     assert m[0].max() < 1.5e-3 and m[1][:3].max() < 1.5e-3
     assert np.isfinite(m[1][3]) and m[1][3] < 5e-3
