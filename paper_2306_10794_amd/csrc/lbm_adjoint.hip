@@ -100,69 +100,99 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     constexpr int Q = L::Q;
     constexpr uint32_t SM = sol_mask<L, RED>();   // the solute set (D2Q5 / D3Q7 when RED)
     constexpr int QS = __builtin_popcount(SM);
+    constexpr int LCAP = 256;   // links of a task staged in LDS (more: read in place)
+    __shared__ T sb[BLK / 64][LCAP], ss[BLK / 64][LCAP];
     TaskCtx<L, T> c;
-    if (!task_setup<L, T>(a, c) || !c.active) return;
+    if (!task_setup<L, T>(a, c)) return;
+    const bool act = c.active;
     const DomDev &D = c.D;
     const long S = a.S;
-    const uint32_t rbc = c.solidnb & SM;
-    T gv[Q];
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        if (!((SM >> i) & 1u)) continue;
-        gv[i] = c.kk[i] >= 0 ? a.gin[pidx(sol_slot(SM, i), c.kk[i], QS)]
-                             : a.gin[pidx(sol_slot(SM, L::opp[i]), c.k, QS)];
-    }
+    const uint32_t rbc = act ? (c.solidnb & SM) : 0u;
     // link index: the task's base (lbase of its first node, lane 0, which is
     // active), then by direction, then by lane
     const int lt = __builtin_amdgcn_readfirstlane(c.lb);
-    if (rbc) {
-        const int lane = threadIdx.x & 63;
-        const unsigned long long below = (1ull << lane) - 1ull;
-        int loff = lt;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+    const unsigned long long below = (1ull << lane) - 1ull;
+    int lpos[Q];
+    int nlt = 0;
+#pragma unroll
+    for (int i = 1; i < Q; i++) {
+        if (!((SM >> i) & 1u)) continue;
+        const unsigned long long bal = __ballot((rbc >> i) & 1u);
+        lpos[i] = nlt + __popcll(bal & below);
+        nlt += __popcll(bal);
+    }
+    const bool staged = nlt <= LCAP;
+    if (staged) {
+        T vb[LCAP / 64];
+#pragma unroll
+        for (int r = 0; r < LCAP / 64; r++)
+            if (r * 64 + lane < nlt) vb[r] = a.lbeta[lt + r * 64 + lane];
+#pragma unroll
+        for (int r = 0; r < LCAP / 64; r++)
+            if (r * 64 + lane < nlt) sb[wv][r * 64 + lane] = vb[r];
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+        T gv[Q];
+#pragma unroll
+        for (int i = 0; i < Q; i++) {
+            if (!((SM >> i) & 1u)) continue;
+            gv[i] = c.kk[i] >= 0 ? a.gin[pidx(sol_slot(SM, i), c.kk[i], QS)]
+                                 : a.gin[pidx(sol_slot(SM, L::opp[i]), c.k, QS)];
+        }
+        // a pulled source is a direction without a link, which this loop
+        // leaves unchanged
 #pragma unroll
         for (int i = 1; i < Q; i++) {
-            if (!((SM >> i) & 1u)) continue;
-            const unsigned long long bal = __ballot((rbc >> i) & 1u);
-            const int l = loff + __popcll(bal & below);
-            loff += __popcll(bal);
-            if (rbc & (1u << i)) {
-                const int o = L::opp[i];
-                const R own = (R)gv[i];
-                const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
-                const R beta = (R)a.lbeta[l];
-                a.lsrc[l] = (T)srcv;
-                gv[i] = (T)((R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv);
+            if (!((SM >> i) & 1u) || !(rbc & (1u << i))) continue;
+            const int o = L::opp[i];
+            const int pos = lpos[i];
+            const R own = (R)gv[i];
+            const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
+            const R beta = (R)(staged ? sb[wv][pos] : a.lbeta[lt + pos]);
+            if (staged) ss[wv][pos] = (T)srcv;
+            else a.lsrc[lt + pos] = (T)srcv;
+            gv[i] = (T)((R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv);
+        }
+        if (a.gout) {
+            R dC = R(0);
+#pragma unroll
+            for (int i = 0; i < Q; i++)
+                if ((SM >> i) & 1u) dC += (R)gv[i];
+            if constexpr (TRT) {
+                // TRT at rest: even parts relax with omega_gs toward w C, odd
+                // parts with omega_g toward 0 (as the fused step with u = 0)
+                const R oms = D.omega_gs, oma = D.omega_g;
+                a.gout[pidx(0, c.k, QS)] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
+#pragma unroll
+                for (int i = 1; i < Q; i++) {
+                    if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
+                    const int o = L::opp[i];
+                    const R gi = (R)gv[i], go = (R)gv[o];
+                    const R As = oms * sol_w<L>(D, i) * dC;
+                    const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * oma * (gi - go);
+                    a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi - hs - ha + As);
+                    a.gout[pidx(sol_slot(SM, o), c.k, QS)] = (T)(go - hs + ha + As);
+                }
+            } else {
+#pragma unroll
+                for (int i = 0; i < Q; i++) {
+                    if (!((SM >> i) & 1u)) continue;
+                    const R gi = (R)gv[i];
+                    const R geq = sol_w<L>(D, i) * dC;
+                    a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi + D.omega_g * (geq - gi));
+                }
             }
         }
     }
-    if (!a.gout) return;
-    R dC = R(0);
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (staged) {
 #pragma unroll
-    for (int i = 0; i < Q; i++)
-        if ((SM >> i) & 1u) dC += (R)gv[i];
-    if constexpr (TRT) {
-        // TRT at rest: even parts relax with omega_gs toward w C, odd parts
-        // with omega_g toward 0 (as the fused step with u = 0)
-        const R oms = D.omega_gs, oma = D.omega_g;
-        a.gout[pidx(0, c.k, QS)] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
-            const int o = L::opp[i];
-            const R gi = (R)gv[i], go = (R)gv[o];
-            const R As = oms * sol_w<L>(D, i) * dC;
-            const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * oma * (gi - go);
-            a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi - hs - ha + As);
-            a.gout[pidx(sol_slot(SM, o), c.k, QS)] = (T)(go - hs + ha + As);
-        }
-        return;
-    }
-#pragma unroll
-    for (int i = 0; i < Q; i++) {
-        if (!((SM >> i) & 1u)) continue;
-        const R gi = (R)gv[i];
-        const R geq = sol_w<L>(D, i) * dC;
-        a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi + D.omega_g * (geq - gi));
+        for (int r = 0; r < LCAP / 64; r++)
+            if (r * 64 + lane < nlt) a.lsrc[lt + r * 64 + lane] = ss[wv][r * 64 + lane];
     }
 }
 
@@ -188,93 +218,111 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     constexpr int Q = L::Q;
     constexpr uint32_t SM = sol_mask<L, RED>();
     constexpr int QS = __builtin_popcount(SM);
+    constexpr int LCAP = 256;   // links of a task staged in LDS (more: read in place)
+    __shared__ T sb[BLK / 64][LCAP], ss[BLK / 64][LCAP];
+    __shared__ double sg[BLK / 64][LCAP];
     TaskCtx<L, T> c;
-    if (!task_setup<L, T>(a, c) || !c.active) return;
+    if (!task_setup<L, T>(a, c)) return;
+    const bool act = c.active;
     const DomDev &D = c.D;
     const long S = a.S;
-    const uint32_t rbc = c.solidnb & SM;
-    // lambda(t+1) at this node: the forward pull with directions reversed
-    T mu[Q];
-#pragma unroll
-    for (int d = 0; d < Q; d++) {
-        if (!((SM >> d) & 1u)) continue;
-        const int kd = c.kk[L::opp[d]];
-        mu[d] = kd >= 0 ? a.pin[pidx(sol_slot(SM, d), kd, QS)] : a.pin[pidx(sol_slot(SM, L::opp[d]), c.k, QS)];
-    }
-    R m = R(0);
-#pragma unroll
-    for (int i = 0; i < Q; i++)
-        if ((SM >> i) & 1u) m += sol_w<L>(D, i) * (R)mu[i];
-    // transposed collision.  BGK: nu_j = (1 - om) mu_j + om m.  TRT (even rate
-    // oms, odd rate om): nu_j = (1 - (oms + om)/2) mu_j + ((om - oms)/2)
-    // mu_opp(j) + oms m, which is BGK's when oms = om
-    const R om = D.omega_g, om1 = R(1) - om, oms = D.omega_gs;
-    const R ta = R(1) - R(0.5) * (oms + om), tb = R(0.5) * (om - oms);
-    a.pout[pidx(0, c.k, QS)] = (T)(TRT ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
-    // link index: the task's base (lbase of its first node, lane 0, which is
-    // active), then by direction, then by lane
+    const uint32_t rbc = act ? (c.solidnb & SM) : 0u;
     const int lt = __builtin_amdgcn_readfirstlane(c.lb);
-    const int lane = threadIdx.x & 63;
+    const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
     const unsigned long long below = (1ull << lane) - 1ull;
     int lpos[Q];
-    {
-        int off = lt;
-#pragma unroll
-        for (int i = 1; i < Q; i++) {
-            if (!((SM >> i) & 1u)) continue;
-            const unsigned long long bal = __ballot((rbc >> i) & 1u);
-            lpos[i] = off + __popcll(bal & below);
-            off += __popcll(bal);
-        }
-    }
-    // a direction and its opposite together.  Without links: out = nu.  A
-    // link along i whose source is the value pulled along o (pre-collision
-    // mechanics, o not a link): out_i = 0, out_o = nu_o + beta nu_i; any other
-    // link: out_i = beta nu_i.  Each link also adds nu_i (g_src - w_i C_eq) to
-    // its dL/dbeta.
+    int nlt = 0;
 #pragma unroll
     for (int i = 1; i < Q; i++) {
-        if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
-        const int o = L::opp[i];
-        const int si = sol_slot(SM, i), so = sol_slot(SM, o);
-        R nui, nuo;
-        if constexpr (TRT) {
-            nui = ta * (R)mu[i] + tb * (R)mu[o] + oms * m;
-            nuo = ta * (R)mu[o] + tb * (R)mu[i] + oms * m;
-        } else {
-            nui = om1 * (R)mu[i] + om * m;
-            nuo = om1 * (R)mu[o] + om * m;
-        }
-        R outi = nui, outo = nuo;
-        const bool li = (rbc >> i) & 1u, lo = (rbc >> o) & 1u;
-        if (li) {
-            const int l = lpos[i];
-            const R beta = (R)a.lbeta[l];
-            const bool pulled = D.mech == LBM_PRECOLL && !lo;
-            const R src = (R)a.lsrc[l];
-            a.gbeta[l] += nui * (src - sol_w<L>(D, i) * D.ceq_dev);
-            if (pulled) {
-                outo += beta * nui;
-                outi = R(0);
-            } else {
-                outi = beta * nui;
+        if (!((SM >> i) & 1u)) continue;
+        const unsigned long long bal = __ballot((rbc >> i) & 1u);
+        lpos[i] = nlt + __popcll(bal & below);
+        nlt += __popcll(bal);
+    }
+    const bool staged = nlt <= LCAP;
+    if (staged) {
+        T vb[LCAP / 64], vs[LCAP / 64];
+        double vg[LCAP / 64];
+#pragma unroll
+        for (int r = 0; r < LCAP / 64; r++) {
+            const int j = r * 64 + lane;
+            if (j < nlt) {
+                vb[r] = a.lbeta[lt + j];
+                vs[r] = a.lsrc[lt + j];
+                vg[r] = a.gbeta[lt + j];
             }
         }
-        if (lo) {
-            const int l = lpos[o];
-            const R beta = (R)a.lbeta[l];
-            const bool pulled = D.mech == LBM_PRECOLL && !li;
-            const R src = (R)a.lsrc[l];
-            a.gbeta[l] += nuo * (src - sol_w<L>(D, o) * D.ceq_dev);
-            if (pulled) {
-                outi += beta * nuo;
-                outo = R(0);
-            } else {
-                outo = beta * nuo;
+#pragma unroll
+        for (int r = 0; r < LCAP / 64; r++) {
+            const int j = r * 64 + lane;
+            if (j < nlt) {
+                sb[wv][j] = vb[r];
+                ss[wv][j] = vs[r];
+                sg[wv][j] = vg[r];
             }
         }
-        a.pout[pidx(si, c.k, QS)] = (T)outi;
-        a.pout[pidx(so, c.k, QS)] = (T)outo;
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (act) {
+        // lambda(t+1) at this node: the forward pull with directions reversed
+        T mu[Q];
+#pragma unroll
+        for (int d = 0; d < Q; d++) {
+            if (!((SM >> d) & 1u)) continue;
+            const int kd = c.kk[L::opp[d]];
+            mu[d] = kd >= 0 ? a.pin[pidx(sol_slot(SM, d), kd, QS)] : a.pin[pidx(sol_slot(SM, L::opp[d]), c.k, QS)];
+        }
+        R m = R(0);
+#pragma unroll
+        for (int i = 0; i < Q; i++)
+            if ((SM >> i) & 1u) m += sol_w<L>(D, i) * (R)mu[i];
+        const R om = D.omega_g, om1 = R(1) - om, oms = D.omega_gs;
+        const R ta = R(1) - R(0.5) * (oms + om), tb = R(0.5) * (om - oms);
+        a.pout[pidx(0, c.k, QS)] = (T)(TRT ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
+        auto link = [&](int d, R nu, R *out_d, R *out_other, bool pulled) {
+            const int pos = lpos[d];
+            const R beta = (R)(staged ? sb[wv][pos] : a.lbeta[lt + pos]);
+            const R src = (R)(staged ? ss[wv][pos] : a.lsrc[lt + pos]);
+            const R add = nu * (src - sol_w<L>(D, d) * D.ceq_dev);
+            if (staged) sg[wv][pos] += add;
+            else a.gbeta[lt + pos] += add;
+            if (pulled) {
+                *out_other += beta * nu;
+                *out_d = R(0);
+            } else {
+                *out_d = beta * nu;
+            }
+        };
+#pragma unroll
+        for (int i = 1; i < Q; i++) {
+            if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
+            const int o = L::opp[i];
+            const int si = sol_slot(SM, i), so = sol_slot(SM, o);
+            R nui, nuo;
+            if constexpr (TRT) {
+                nui = ta * (R)mu[i] + tb * (R)mu[o] + oms * m;
+                nuo = ta * (R)mu[o] + tb * (R)mu[i] + oms * m;
+            } else {
+                nui = om1 * (R)mu[i] + om * m;
+                nuo = om1 * (R)mu[o] + om * m;
+            }
+            R outi = nui, outo = nuo;
+            const bool li = (rbc >> i) & 1u, lo = (rbc >> o) & 1u;
+            if (li) link(i, nui, &outi, &outo, D.mech == LBM_PRECOLL && !lo);
+            if (lo) link(o, nuo, &outo, &outi, D.mech == LBM_PRECOLL && !li);
+            a.pout[pidx(si, c.k, QS)] = (T)outi;
+            a.pout[pidx(so, c.k, QS)] = (T)outo;
+        }
+    }
+    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    if (staged) {
+#pragma unroll
+        for (int r = 0; r < LCAP / 64; r++) {
+            const int j = r * 64 + lane;
+            if (j < nlt) a.gbeta[lt + j] = sg[wv][j];
+        }
     }
 }
 
