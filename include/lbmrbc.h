@@ -119,7 +119,10 @@ typedef struct {
     double c_in;              /* inlet concentration                                */
     int32_t phase_change;     /* 1: apply the phi thresholds after each step
                                  (Sec. 2.4; single-lattice contexts; lbm_step
-                                 then synchronises once per step).  One pass
+                                 then synchronises once per step and reads a
+                                 flag the step kernels write into 256 bytes of
+                                 pinned host memory that lbm_create allocates
+                                 and lbm_destroy frees).  One pass
                                  takes at most 65536 events (and as many nodes
                                  pushed over a threshold by earlier events of
                                  the pass); beyond that lbm_step returns
@@ -252,8 +255,9 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms);
  *               > 0: lbm_step replays a HIP graph holding graph_steps steps
  *               (rounded up to even), built on first use and rebuilt after a
  *               geometry or configuration change; remaining steps run as
- *               plain launches.  Graph objects are the only allocation the
- *               library makes; lbm_destroy frees them.
+ *               plain launches.  Graph objects are the only device-side
+ *               allocation the library makes (besides the static array of
+ *               lbm_record_static); lbm_destroy frees them.
  *   overlap     1: the solid-side solid-fraction kernel of a step runs on a
  *               second stream of the library, concurrently with the next
  *               step's fused kernel (two exchange buffers); every lbm_step

@@ -415,6 +415,23 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
         c->have_side = ok;
     }
     c->adj.valid = false;
+    // phase change: the step kernels write the threshold flag straight into
+    // pinned host memory, so the per-step check is a host read after the
+    // stream synchronises (no copy); without it the flag stays on the device
+    c->hflag = c->hflag_dev = nullptr;
+    if (nd == 1 && params[0].phase_change) {
+        void *h = nullptr, *d = nullptr;
+        if (hipHostMalloc(&h, 256, hipHostMallocCoherent) == hipSuccess) {
+            if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
+                c->hflag = (int32_t *)h;
+                c->hflag_dev = (int32_t *)d;
+                *c->hflag = 0;
+            } else {
+                (void)hipHostFree(h);
+            }
+        }
+        (void)hipGetLastError();
+    }
     *out = (lbm_ctx *)c;
     return LBM_OK;
 }
@@ -602,6 +619,10 @@ void lbm_destroy(lbm_ctx *ctx) {
             (void)hipEventDestroy(c->ev_phi[b]);
         }
         (void)hipStreamDestroy(c->side);
+    }
+    if (c->hflag) {
+        (void)hipStreamSynchronize(c->stream);
+        (void)hipHostFree(c->hflag);
     }
     delete c;
 }

@@ -727,8 +727,13 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
         // interface node is past its threshold (only interface nodes' solid
         // fractions change in a step, and every other node was checked when
         // its value was last set)
-        e = hipMemcpyAsync(h, c.iacc + 16, 4, hipMemcpyDeviceToHost, st);
-        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (c.hflag) {
+            e = hipStreamSynchronize(st);
+            h[0] = __atomic_load_n(c.hflag, __ATOMIC_ACQUIRE);
+        } else {
+            e = hipMemcpyAsync(h, c.iacc + 16, 4, hipMemcpyDeviceToHost, st);
+            if (e == hipSuccess) e = hipStreamSynchronize(st);
+        }
         if (e != hipSuccess || h[0] != c.evstamp) return e;
     } else {
         c.full_check = false;

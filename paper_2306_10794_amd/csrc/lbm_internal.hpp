@@ -130,6 +130,8 @@ struct Ctx {
     long ev_cap;
     bool full_check;         // the next threshold check scans every working copy
     int32_t evstamp;         // stamp of the current step in the threshold flag
+    int32_t *hflag;          // the threshold flag in pinned host memory (phase change),
+    int32_t *hflag_dev;      // and its device address; null: the flag is iacc[16]
     bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions
     double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums

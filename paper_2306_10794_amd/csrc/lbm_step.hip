@@ -503,7 +503,7 @@ static StepArgs<T> step_args(Ctx &c) {
     a.phif = c.phif;
     a.lceq = (const T *)c.lceq;
     a.xio = c.xio;
-    a.evflag = c.p.phase_change ? c.iacc + 16 : nullptr;
+    a.evflag = c.p.phase_change ? (c.hflag_dev ? c.hflag_dev : c.iacc + 16) : nullptr;
     a.evstamp = c.evstamp;
     a.task_cap = c.task_cap;
     a.ntasks = c.n_tasks;
