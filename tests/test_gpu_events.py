@@ -91,7 +91,28 @@ def _thin(kind):
                 phase_change=1, phi0=phi0, c_init=rng.uniform(0.5, 1.5, solid.size))
 
 
+def _preset():
+    """Solid fractions past a threshold before the first step, where no step
+    changes them: two fluid nodes away from every wall start above 1, an
+    interface solid node below 0, and a solid node with no fluid neighbour
+    below 0 (not an event until a neighbour dissolves).  The first step's
+    check has to scan every working copy, not only what the step wrote."""
+    solid, normals = geometry.plane_channel(40, 20, (0, 19))
+    solid[0, 1:5, 10:14] = 1
+    normals[0, 1:5, 10:14, 1] = 1.0
+    phi0 = np.where(solid.reshape(-1) == 1, 0.5, 0.0).reshape(1, 20, 40)
+    phi0[0, 10, 5] = 1.05
+    phi0[0, 9, 30] = 1.2
+    phi0[0, 4, 12] = -0.01
+    phi0[0, 2, 11] = -0.1
+    rng = np.random.default_rng(13)
+    return Case(name="preset", dim=2, nx=40, ny=20, nz=1, q=9, solid=solid, normals=normals,
+                tau_ns=0.8, tau_ad=0.8, force=(1e-5, 0.0, 0.0), c_eq=1.0, k_r=0.02, v_m=0.2,
+                phase_change=1, phi0=phi0.reshape(-1), c_init=rng.uniform(0.8, 1.2, solid.size))
+
+
 CASES = {"dissolving": _dissolving, "precipitating": _precipitating, "burst": _burst,
+         "preset": _preset,
          "dissolving R2 S.V.": lambda: _dissolving(MECH_POST, SCHEME_SV),
          "spheres": _spheres_events,
          "thin precipitating": lambda: _thin("precipitating"),
@@ -101,7 +122,8 @@ CASES = {"dissolving": _dissolving, "precipitating": _precipitating, "burst": _b
 @pytest.mark.parametrize("name,precision,steps", [
     ("dissolving", FP64, 300), ("precipitating", FP64, 200), ("dissolving R2 S.V.", FP64, 300),
     ("spheres", FP64, 60), ("burst", FP64, 80), ("dissolving", FP32, 300), ("spheres", FP32, 60),
-    ("thin precipitating", FP64, 200), ("thin dissolving", FP64, 300)])
+    ("thin precipitating", FP64, 200), ("thin dissolving", FP64, 300), ("preset", FP64, 40),
+    ("preset", FP32, 40)])
 def test_events_match_oracle(name, precision, steps):
     case = CASES[name]()
     res = run_pair(case, precision, steps, f"events {name}")
