@@ -120,7 +120,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     char *sif = take(4 * L), *soff = take(4 * (L + 1)), *slinks = take(4 * L), *sdom = take(4 * L);
     char *bsum = take(4 * ((N + 4095) / 4096 + 64));
     char *dpart = take(16 * ((N + 255) / 256 + 1));
-    char *dacc = take(8 * 64), *iacc = take(4 * 64);
+    char *dacc = take(8 * 64), *iacc = take(4 * 64), *fpart = take(8 * 2 * FOLD_G);
     const long nxp = (N + 255) / 256 + 1;
     char *xpart = take(8 * nxp), *xio = take(16 * task_cap);
     // phase change (single lattice): old compact map, candidates, records
@@ -170,7 +170,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->sdom = (int32_t *)sdom;
         c->bsum = (int32_t *)bsum;
         c->dpart = (double *)dpart;
-        c->dacc = (double *)dacc; c->iacc = (int32_t *)iacc;
+        c->dacc = (double *)dacc; c->iacc = (int32_t *)iacc; c->fpart = (double *)fpart;
         c->xpart = (double *)xpart; c->n_xpart = nxp;
         c->xio = (double *)xio;
     }

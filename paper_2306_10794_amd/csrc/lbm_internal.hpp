@@ -62,6 +62,10 @@ struct AdjState {
     double *gbeta;           // [max_links] dL/dbeta
 };
 
+// workgroups of the first level of the fixed-order folds (exchange totals,
+// diagnostics)
+constexpr int FOLD_G = 64;
+
 struct Ctx {
     lbm_params p;            // parameters of domain 0 (precision, lattice)
     lbm_launch_config cfg;   // tile / schedule of the step launches
@@ -121,6 +125,7 @@ struct Ctx {
     uint8_t *ldir;           // [max_links]
     int32_t *sif, *soff, *slinks; // solid interface list [max_links], offsets [max_links+1], [max_links]
     int32_t *sdom;           // [max_links] domain of each solid interface node
+    double *fpart;           // [2 * FOLD_G] first-level sums of the fixed-order folds
     int32_t *bsum;           // scan scratch
     int32_t *kof_old;        // [N] phase change: compact map before the events
     int32_t *evlist;         // [ev_cap] phase-change candidates in node order

@@ -99,7 +99,7 @@ __global__ __launch_bounds__(BLK) void k_scatter_q(long nl, int Q, const T *lq, 
 }
 
 // per-workgroup partial sums of C (fluid) and phi (all nodes), and a
-// non-finite flag; a single workgroup then adds the partials in order
+// non-finite flag; the partials are then added in two fixed-order levels
 template <class L, typename T>
 __global__ __launch_bounds__(BLK) void k_diag(long N, long S, const DomDev *doms, const long *noff,
                                               int ndom, const int32_t *kof, const T *f, const T *g,
@@ -133,6 +133,24 @@ __global__ __launch_bounds__(BLK) void k_diag(long N, long S, const DomDev *doms
     if (bad) atomicOr(nan_flag, 1);
 }
 
+// the per-workgroup (C, phi) pairs of k_diag in two fixed-order levels:
+// workgroup b of FOLD_G sums its contiguous share into bpart[2b], [2b + 1]
+__global__ __launch_bounds__(BLK) void k_sum_pairs(const double *part, long nb, double *bpart) {
+    const long len = (nb + FOLD_G - 1) / FOLD_G;
+    const long lo = (long)blockIdx.x * len, hi = lo + len < nb ? lo + len : nb;
+    double a = 0.0, b = 0.0;
+    for (long j = lo + threadIdx.x; j < hi; j += BLK) {
+        a += part[2 * j];
+        b += part[2 * j + 1];
+    }
+    a = block_sum(a);
+    b = block_sum(b);
+    if (threadIdx.x == 0) {
+        bpart[2 * blockIdx.x] = a;
+        bpart[2 * blockIdx.x + 1] = b;
+    }
+}
+
 __global__ __launch_bounds__(BLK) void k_sum_parts(const double *part, long nb, double *out) {
     double a = 0.0, b = 0.0;
     for (long j = threadIdx.x; j < nb; j += BLK) {
@@ -147,11 +165,15 @@ __global__ __launch_bounds__(BLK) void k_sum_parts(const double *part, long nb, 
     }
 }
 
-// adds the per-workgroup wall-exchange slots to acc[0] (fixed order: lane
-// stride, then the block reduction) and clears them
-__global__ __launch_bounds__(BLK) void k_fold_exchange(double *part, long n, double *acc) {
+// Fixed-order sums in two levels: workgroup b of FOLD_G adds its contiguous
+// share of the slots (lane stride, then the block reduction) into bpart[b];
+// one workgroup then adds the FOLD_G partials in order.  The exchange slots
+// are cleared as they are read.
+__global__ __launch_bounds__(BLK) void k_fold_parts(double *part, long n, double *bpart) {
+    const long len = (n + FOLD_G - 1) / FOLD_G;
+    const long lo = (long)blockIdx.x * len, hi = lo + len < n ? lo + len : n;
     double a = 0.0;
-    for (long j = threadIdx.x; j < n; j += BLK) {
+    for (long j = lo + threadIdx.x; j < hi; j += BLK) {
         const double v = part[j];
         if (v != 0.0) {
             a += v;
@@ -159,15 +181,26 @@ __global__ __launch_bounds__(BLK) void k_fold_exchange(double *part, long n, dou
         }
     }
     a = block_sum(a);
+    if (threadIdx.x == 0) bpart[blockIdx.x] = a;
+}
+
+// acc[0] += the FOLD_G partials, in order
+__global__ __launch_bounds__(BLK) void k_fold_total(const double *bpart, double *acc) {
+    double a = threadIdx.x < FOLD_G ? bpart[threadIdx.x] : 0.0;
+    a = block_sum(a);
     if (threadIdx.x == 0) acc[0] += a;
 }
 
+static void fold_into(Ctx &c, double *part, long n, double *acc) {
+    hipLaunchKernelGGL(k_fold_parts, dim3(FOLD_G), dim3(BLK), 0, c.stream, part, n, c.fpart);
+    hipLaunchKernelGGL(k_fold_total, dim3(1), dim3(BLK), 0, c.stream, (const double *)c.fpart, acc);
+}
+
 hipError_t launch_fold_exchange(Ctx &c) {
-    hipLaunchKernelGGL(k_fold_exchange, dim3(1), dim3(BLK), 0, c.stream, c.xpart, c.n_xpart, c.dacc);
+    fold_into(c, c.xpart, c.n_xpart, c.dacc);
     if (c.any_planes) {
-        hipLaunchKernelGGL(k_fold_exchange, dim3(1), dim3(BLK), 0, c.stream, c.xio, c.task_cap, c.dacc + 3);
-        hipLaunchKernelGGL(k_fold_exchange, dim3(1), dim3(BLK), 0, c.stream, c.xio + c.task_cap, c.task_cap,
-                           c.dacc + 4);
+        fold_into(c, c.xio, c.task_cap, c.dacc + 3);
+        fold_into(c, c.xio + c.task_cap, c.task_cap, c.dacc + 4);
     }
     return hipGetLastError();
 }
@@ -250,7 +283,9 @@ static hipError_t diag_impl(Ctx &c, double *sums, int32_t *nan_flag) {
     hipLaunchKernelGGL((k_diag<L, T>), dim3(nb), dim3(BLK), 0, c.stream, c.N, c.S, c.doms,
                        c.dnode_off, c.ndom, c.kof, (const T *)c.f[c.cur], (const T *)c.g[c.cur],
                        c.phi, c.dpart, c.iacc + 4);
-    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(BLK), 0, c.stream, c.dpart, nb, c.dacc + 1);
+    hipLaunchKernelGGL(k_sum_pairs, dim3(FOLD_G), dim3(BLK), 0, c.stream, (const double *)c.dpart, nb, c.fpart);
+    hipLaunchKernelGGL(k_sum_parts, dim3(1), dim3(BLK), 0, c.stream, (const double *)c.fpart, (long)FOLD_G,
+                       c.dacc + 1);
     e = hipGetLastError();
     if (e != hipSuccess) return e;
     e = hipMemcpyAsync(sums, c.dacc, 5 * sizeof(double), hipMemcpyDeviceToHost, c.stream);
