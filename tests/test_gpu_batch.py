@@ -88,3 +88,68 @@ def test_batch_equals_single_contexts():
         sim.close()
         assert np.array_equal(f, gd["f"]) and np.array_equal(g, gd["g"])
         assert np.array_equal(phi, gd["fields"]["phi"])
+
+
+def test_full_sweep_sampled_against_oracle():
+    """The sweep as specified: 1024 domains, 5000 steps, FP32 deviation
+    storage, one context stepped by 64-step graph replays (every launch
+    configuration gives the same bits).  The four smallest domains and one of
+    median size are run by the oracle alone for the same 5000 steps and
+    compared field by field; every domain keeps its solute plus solid mass
+    (periodic boxes, no inlet: sum C + sum phi / (V_m a_m) is invariant) and
+    stays finite.  The mass bound is the storage rounding: every step rounds
+    each stored solute population's deviation from w_i C_ref (|C - C_ref| <=
+    0.5 here, so the deviations of a node sum to at most about 1) to FP32, at
+    most 2^-24 of it, so a domain's mass moves by at most steps x 2^-24 per
+    fluid node (FP64 storage conserves it to round-off)."""
+    import torch
+    from oracle import Oracle
+    from paper_2306_10794_amd import BatchSimulation
+    from paper_2306_10794_amd import _lib as L
+    steps = 5000
+    cases = configs.batch_domains(count=1024, seed=4, steps=steps)
+    bs = BatchSimulation(cases, precision=FP32)
+    L.lbm_set_launch_config(bs.ctx, 4, 0, 64, 0)
+
+    def masses():
+        fl = bs.fields()
+        cs, ps = bs.split(fl["c"]), bs.split(fl["phi"])
+        return np.array([float(c.sum()) + float(p.sum()) / (case.v_m * case.a_m)
+                         for c, p, case in zip(cs, ps, cases)])
+
+    m0 = masses()
+    bs.step(steps)
+    torch.cuda.synchronize()
+    m1 = masses()
+    diag = bs.diag()
+    fields = bs.fields()
+    f, g = bs.pops()
+    q = bs.exchange()
+    sizes = np.array([c.nx * c.ny for c in cases])
+    order = np.argsort(sizes, kind="stable")
+    sample = list(order[:4]) + [int(order[len(order) // 2])]
+    got = {}
+    for d in sample:
+        fd = {k: bs.split(fields[k])[d].cpu().numpy() for k in fields}
+        got[d] = dict(fields=fd, f=bs.split(f, 1)[d].cpu().numpy(), g=bs.split(g, 1)[d].cpu().numpy(),
+                      q=bs.split(q)[d].cpu().numpy())
+    bs.close()
+    assert diag["status"] == 0 and diag["nan_flag"] == 0
+    nfl = np.array([int((c.solid_flat() == 0).sum()) for c in cases])
+    drift = np.abs(m1 - m0) / (steps * 2.0 ** -24 * nfl)
+    log(f"[batch] full sweep: {len(cases)} domains x {steps} steps, largest mass change "
+        f"{np.abs(m1 - m0).max():.3e}, at most {drift.max():.3f} of the rounding bound")
+    assert drift.max() <= 1.0
+    for d in sample:
+        case = cases[d]
+        ora = Oracle(case)
+        ora.step(steps)
+        qo, kind = ora.exchange()
+        fo, go = ora.pops()
+        res = dict(gpu=got[d], ora=dict(fields=ora.fields(), f=fo, g=go, q=qo, kind=kind))
+        err = rel_errors(res, case, u_floor=0.0)
+        log(f"[batch] full sweep domain {d} ({case.nx}x{case.ny}) errors {err}")
+        assert err["type"] == 0 and err["link_set"] == 0
+        for k in ("rho", "u", "c", "f", "g", "q", "phi"):
+            assert err[k] <= TOL[FP32], (d, k, err[k])
+
