@@ -119,10 +119,10 @@ typedef struct {
     double c_in;              /* inlet concentration                                */
     int32_t phase_change;     /* 1: apply the phi thresholds after each step
                                  (Sec. 2.4; single-lattice contexts; lbm_step
-                                 then synchronises once per step and reads a
-                                 flag the step kernels write into 256 bytes of
-                                 pinned host memory that lbm_create allocates
-                                 and lbm_destroy frees).  One pass
+                                 then queues up to 32 steps at a time, the
+                                 steps after one that crossed a threshold doing
+                                 nothing, and synchronises once per batch and
+                                 after every event pass).  One pass
                                  takes at most 65536 events (and as many nodes
                                  pushed over a threshold by earlier events of
                                  the pass); beyond that lbm_step returns

@@ -415,22 +415,15 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
         c->have_side = ok;
     }
     c->adj.valid = false;
-    // phase change: the step kernels write the threshold flag straight into
-    // pinned host memory, so the per-step check is a host read after the
-    // stream synchronises (no copy); without it the flag stays on the device
-    c->hflag = c->hflag_dev = nullptr;
-    if (nd == 1 && params[0].phase_change) {
-        void *h = nullptr, *d = nullptr;
-        if (hipHostMalloc(&h, 256, hipHostMallocCoherent) == hipSuccess) {
-            if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
-                c->hflag = (int32_t *)h;
-                c->hflag_dev = (int32_t *)d;
-                *c->hflag = 0;
-            } else {
-                (void)hipHostFree(h);
-            }
-        }
+    // the threshold flag of the phase-change steps starts clear (batch 0 is
+    // never used)
+    c->evbatch = c->evidx = 0;
+    if (hipMemsetAsync(c->iacc + 16, 0, 8, c->stream) != hipSuccess ||
+        hipStreamSynchronize(c->stream) != hipSuccess) {
         (void)hipGetLastError();
+        lbm_destroy((lbm_ctx *)c);
+        g_create_err = "could not clear the context's flags";
+        return LBM_EDEVICE;
     }
     *out = (lbm_ctx *)c;
     return LBM_OK;
@@ -483,10 +476,10 @@ static hipError_t build_graph(Ctx *c, int n) {
 
 // Phase change after a step: event pass, then (if anything changed) the
 // geometry rebuilt in place and the populations moved to the new layout.
-static hipError_t phase_change_pass(Ctx *c, bool *capacity) {
+static hipError_t phase_change_pass(Ctx *c, bool flagged, bool *capacity) {
     int64_t nev = 0;
     bool ovf = false;
-    hipError_t e = launch_events(*c, &nev, &ovf);
+    hipError_t e = launch_events(*c, flagged, &nev, &ovf);
     if (e != hipSuccess) return e;
     if (ovf) *capacity = true;
     if (nev == 0) return hipSuccess;
@@ -508,19 +501,51 @@ static hipError_t phase_change_pass(Ctx *c, bool *capacity) {
     return e;
 }
 
+// Phase change: the launches of up to kmax steps are queued as one batch.
+// Every kernel of the batch does nothing once an earlier step of the batch
+// has crossed a threshold (the device flag), so the host waits once per
+// batch; it then counts the steps done (the crossing one included), puts its
+// buffer and exchange parities back to what they were after that step, and
+// the event pass follows.  After values were set from outside a step (all
+// working copies must be checked) the batch is one step.  On return *done
+// steps have run and *flagged says whether the last one crossed.
+static hipError_t phase_change_batch(Ctx *c, int kmax, int *done, bool *flagged, hipEvent_t *ev = nullptr) {
+    const int K = c->full_check ? 1 : kmax;
+    c->evbatch = c->evbatch >= 0x7ffffffe ? 1 : c->evbatch + 1;
+    const int cur0 = c->cur, lq0 = c->lq_next;
+    hipError_t e = hipSuccess;
+    for (int j = 1; j <= K && e == hipSuccess; j++) {
+        c->evidx = j;
+        e = launch_step(*c, ev);
+    }
+    unsigned long long w = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&w, c->iacc + 16, 8, hipMemcpyDeviceToHost, c->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(c->stream);
+    if (e != hipSuccess) return e;
+    *flagged = (int)(w >> 32) == c->evbatch;
+    const int n = *flagged ? (int)(unsigned)w : K;
+    c->cur = (n & 1) ? 1 - cur0 : cur0;
+    c->lq_next = (n & 1) ? 1 - lq0 : lq0;
+    c->lq = c->lqb[(n & 1) ? lq0 : 1 - lq0];
+    c->step += n;
+    *done = n;
+    return hipSuccess;
+}
+
 // plain: kernel launches on the context stream only (no graph, which would
 // allocate when built, and no second stream)
 static hipError_t run_steps(Ctx *c, int32_t nsteps, bool plain = false) {
     int32_t t = 0;
     if (c->p.phase_change) {
-        // events need a decision on the host after every step (no graphs)
-        for (; t < nsteps; t++) {
-            c->evstamp = c->evstamp == 0x7fffffff ? 1 : c->evstamp + 1;
-            hipError_t e = launch_step(*c);
+        // events need a decision on the host (no graphs): batches of steps
+        while (t < nsteps) {
+            int done = 0;
+            bool flagged = false, cap = false;
+            const int kmax = nsteps - t < 32 ? (int)(nsteps - t) : 32;
+            hipError_t e = phase_change_batch(c, kmax, &done, &flagged);
             if (e != hipSuccess) return e;
-            c->step++;
-            bool cap = false;
-            e = phase_change_pass(c, &cap);
+            t += done;
+            e = phase_change_pass(c, flagged, &cap);
             if (e != hipSuccess) return e;
             if (cap) {
                 c->err = "phase change exceeded a capacity (events per step or reactive links)";
@@ -619,10 +644,6 @@ void lbm_destroy(lbm_ctx *ctx) {
             (void)hipEventDestroy(c->ev_phi[b]);
         }
         (void)hipStreamDestroy(c->side);
-    }
-    if (c->hflag) {
-        (void)hipStreamSynchronize(c->stream);
-        (void)hipHostFree(c->hflag);
     }
     delete c;
 }
@@ -851,9 +872,16 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms) {
     }
     ms[0] = ms[1] = 0.0;
     for (int32_t t = 0; t < nsteps; t++) {
-        hipError_t e = launch_step(*c, c->ev);
+        hipError_t e = hipSuccess;
+        bool flagged = false;
+        if (c->p.phase_change) {
+            int done = 0;
+            e = phase_change_batch(c, 1, &done, &flagged, c->ev);
+        } else {
+            e = launch_step(*c, c->ev);
+            c->step++;
+        }
         if (e != hipSuccess) return dev_err(c, e, "step launch");
-        c->step++;
         e = hipEventSynchronize(c->ev[3]);
         if (e != hipSuccess) return dev_err(c, e, "event sync");
         float a = 0.f, b = 0.f;
@@ -864,7 +892,7 @@ lbm_status lbm_step_timed(lbm_ctx *ctx, int32_t nsteps, double *ms) {
         ms[1] += b;
         if (c->p.phase_change) {
             bool cap = false;
-            e = phase_change_pass(c, &cap);
+            e = phase_change_pass(c, flagged, &cap);
             if (e != hipSuccess) return dev_err(c, e, "phase change");
             if (cap) {
                 c->err = "phase change exceeded a capacity (events per step or reactive links)";

@@ -713,7 +713,7 @@ __global__ __launch_bounds__(BLK) void k_event_check(long nf, const double *phif
 }
 
 template <class L, typename T>
-static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
+static hipError_t events_impl(Ctx &c, bool flagged, int64_t *n_events, bool *overflow) {
     hipStream_t st = c.stream;
     const long N = c.N;
     const long nb = (N + BLK - 1) / BLK;
@@ -723,18 +723,11 @@ static hipError_t events_impl(Ctx &c, int64_t *n_events, bool *overflow) {
     int32_t h[2] = {0, 0};
     hipError_t e = hipSuccess;
     if (!c.full_check) {
-        // the step's kernels marked the flag with this step's stamp if an
-        // interface node is past its threshold (only interface nodes' solid
-        // fractions change in a step, and every other node was checked when
-        // its value was last set)
-        if (c.hflag) {
-            e = hipStreamSynchronize(st);
-            h[0] = __atomic_load_n(c.hflag, __ATOMIC_ACQUIRE);
-        } else {
-            e = hipMemcpyAsync(h, c.iacc + 16, 4, hipMemcpyDeviceToHost, st);
-            if (e == hipSuccess) e = hipStreamSynchronize(st);
-        }
-        if (e != hipSuccess || h[0] != c.evstamp) return e;
+        // the step's kernels set the threshold flag if an interface node is
+        // past its threshold (only interface nodes' solid fractions change in
+        // a step, and every other node was checked when its value was last
+        // set); the caller read it
+        if (!flagged) return hipSuccess;
     } else {
         c.full_check = false;
         const long nf = c.n_slots, ns = c.n_sif, n = nf > ns ? nf : ns;
@@ -827,9 +820,12 @@ static hipError_t relayout_impl(Ctx &c) {
     return hipGetLastError();
 }
 
-hipError_t launch_events(Ctx &c, int64_t *n_events, bool *overflow) {
-    if (c.Q == 9) return c.fp64 ? events_impl<D2Q9, double>(c, n_events, overflow) : events_impl<D2Q9, float>(c, n_events, overflow);
-    return c.fp64 ? events_impl<D3Q19, double>(c, n_events, overflow) : events_impl<D3Q19, float>(c, n_events, overflow);
+hipError_t launch_events(Ctx &c, bool flagged, int64_t *n_events, bool *overflow) {
+    if (c.Q == 9)
+        return c.fp64 ? events_impl<D2Q9, double>(c, flagged, n_events, overflow)
+                      : events_impl<D2Q9, float>(c, flagged, n_events, overflow);
+    return c.fp64 ? events_impl<D3Q19, double>(c, flagged, n_events, overflow)
+                  : events_impl<D3Q19, float>(c, flagged, n_events, overflow);
 }
 
 hipError_t launch_relayout(Ctx &c) {

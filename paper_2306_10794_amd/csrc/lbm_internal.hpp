@@ -29,8 +29,12 @@ struct StepArgs {
     double *__restrict__ phif;           // [S] solid fraction of fluid nodes, compact order
     const T *__restrict__ lceq;          // per link: C_eq - C_ref of its solid node (per-node C_eq)
     double *__restrict__ xio;            // [2][task_cap] per task: inlet, outlet exchange (cumulative)
-    int32_t *evflag;                     // phase change: set to evstamp when an interface node's
-    int32_t evstamp;                     // solid fraction is past a threshold (else null)
+    // phase change (else evflag is null): the step's kernels set *evflag to
+    // (evbatch << 32 | evidx) when an interface node's solid fraction is past
+    // a threshold, and do nothing at all once a step of the same batch before
+    // this one (index < evidx) has set it
+    unsigned long long *evflag;
+    int32_t evbatch, evidx;
     long task_cap;
     long ntasks;
     long S;                              // stride between directions
@@ -134,9 +138,7 @@ struct Ctx {
     int32_t *evheap;         // [ev_cap] pending nodes of a pass, once they outgrow the LDS
     long ev_cap;
     bool full_check;         // the next threshold check scans every working copy
-    int32_t evstamp;         // stamp of the current step in the threshold flag
-    int32_t *hflag;          // the threshold flag in pinned host memory (phase change),
-    int32_t *hflag_dev;      // and its device address; null: the flag is iacc[16]
+    int32_t evbatch, evidx;  // current batch of steps and step within it (threshold flag)
     bool ev_capacity;        // the last step ran out of event or link capacity
     double *dpart;           // per-workgroup partial sums of the reductions
     double *dacc;            // device accumulators: [0] wall exchange, [1..2] diag sums
@@ -185,7 +187,7 @@ hipError_t launch_phi_gather(Ctx &c, long nf, long nsif);
 hipError_t launch_phi_flush(Ctx &c);
 hipError_t launch_zero_exchange(Ctx &c);
 hipError_t launch_rest_check(Ctx &c, bool *at_rest);
-hipError_t launch_events(Ctx &c, int64_t *n_events, bool *overflow);
+hipError_t launch_events(Ctx &c, bool flagged, int64_t *n_events, bool *overflow);
 hipError_t launch_relayout(Ctx &c);
 size_t event_record_bytes();
 // ms (optional, host array of 2): summed durations of the recomputation and of

@@ -52,6 +52,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const long tile = remap ? xcd_tile(blockIdx.x, nblocks) : (long)blockIdx.x;
     const int t = __builtin_amdgcn_readfirstlane((int)(tile * WV) + (int)(threadIdx.x >> 6));
     if (t >= a.ntasks) return;
+    // phase change: nothing to do once an earlier step of this batch crossed
+    // a threshold (the host runs the event pass and repeats from there)
+    if (a.evflag) {
+        const unsigned long long w = *a.evflag;
+        if ((int)(w >> 32) == a.evbatch && (int)(unsigned)w < a.evidx) return;
+    }
     const int lane = threadIdx.x & 63;
     const Task tk = a.tasks[t];
     // by value, read before the first store: loads of a uniform address that no
@@ -394,7 +400,8 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         if (sneg != 0.0) a.phif[k] = phi_in + D.vma * sneg;
         // phase change: a node at or past the precipitation threshold marks
         // the step (every interface node's value is checked, changed or not)
-        if (a.evflag && (sneg != 0.0 ? phi_in + D.vma * sneg : phi_in) >= 1.0) *a.evflag = a.evstamp;
+        if (a.evflag && (sneg != 0.0 ? phi_in + D.vma * sneg : phi_in) >= 1.0)
+            *a.evflag = ((unsigned long long)(unsigned)a.evbatch << 32) | (unsigned)a.evidx;
     }
     // the task's exchanges, stored in link order by the active lanes
     for (int j = lane; j < nlt; j += cnt) {
@@ -453,8 +460,13 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
                                                    const DomDev *__restrict__ doms,
                                                    const T *__restrict__ lq, double *__restrict__ phis,
                                                    long nsif, double *__restrict__ xpart, int ndom,
-                                                   int32_t *evflag, int32_t evstamp, int remap) {
+                                                   unsigned long long *evflag, int evbatch, int evidx,
+                                                   int remap) {
     constexpr int M = __builtin_popcount(sol_mask<L, RED>()) - 1;
+    if (evflag) {   // as in the fused kernel (the value is the same for every thread)
+        const unsigned long long w = *evflag;
+        if ((int)(w >> 32) == evbatch && (int)(unsigned)w < evidx) return;
+    }
     // with remap each XCD takes a contiguous range of solid nodes: the lines
     // of exchanges that neighbouring solid nodes (and those of the next
     // planes) gather stay in that XCD's L2, which cuts the kernel's HBM reads
@@ -480,7 +492,7 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
         const double pn = phis[j] - doms[ndom > 1 ? sdom[j] : 0].vma * pos;
         phis[j] = pn;
         // phase change: at or past the dissolution threshold
-        if (evflag && pn <= 0.0) *evflag = evstamp;
+        if (evflag && pn <= 0.0) *evflag = ((unsigned long long)(unsigned)evbatch << 32) | (unsigned)evidx;
     }
     tot = block_sum(tot);
     if (threadIdx.x == 0 && tot != 0.0) xpart[tile] += tot;
@@ -503,8 +515,9 @@ static StepArgs<T> step_args(Ctx &c) {
     a.phif = c.phif;
     a.lceq = (const T *)c.lceq;
     a.xio = c.xio;
-    a.evflag = c.p.phase_change ? (c.hflag_dev ? c.hflag_dev : c.iacc + 16) : nullptr;
-    a.evstamp = c.evstamp;
+    a.evflag = c.p.phase_change ? (unsigned long long *)(c.iacc + 16) : nullptr;
+    a.evbatch = c.evbatch;
+    a.evidx = c.evidx;
     a.task_cap = c.task_cap;
     a.ntasks = c.n_tasks;
     a.ndom = c.ndom;
@@ -582,11 +595,11 @@ static hipError_t step_impl(Ctx &c, hipEvent_t *ev, bool overlap) {
         if (c.red)
             hipLaunchKernelGGL((k_phi_solid<L, T, true>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
                                c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom,
-                               args.evflag, args.evstamp, c.cfg.xcd_remap);
+                               args.evflag, args.evbatch, args.evidx, c.cfg.xcd_remap);
         else
             hipLaunchKernelGGL((k_phi_solid<L, T, false>), dim3(nb2), dim3(BLK), 0, ps, c.soff,
                                c.slinks, c.sdom, c.doms, (const T *)c.lq, c.phis, (long)c.n_sif, c.xpart, c.ndom,
-                               args.evflag, args.evstamp, c.cfg.xcd_remap);
+                               args.evflag, args.evbatch, args.evidx, c.cfg.xcd_remap);
         e = hipGetLastError();
     }
     if (ev) (void)hipEventRecord(ev[3], ps);
