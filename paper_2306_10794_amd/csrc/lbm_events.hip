@@ -15,12 +15,15 @@
 // larger, else at the next step.  Wall normals of solid nodes within two sites
 // of a change are recomputed from the solid indicator.
 //
-// On the GPU: a scan over all nodes marks candidates; one wavefront takes
-// them in node order (lanes gather the neighbours' moments, lane 0 applies
-// the rule and keeps a sorted list of nodes that later events push over a
-// threshold); then the wall normals near the changes are refreshed, the
-// geometry (row words, tasks, links) is rebuilt in place and the populations
-// are moved into the new compact layout.
+// On the GPU: the step kernels flag a crossed threshold; a scan over all
+// nodes then marks the candidates and the C and rho of every node are taken
+// from the populations; one wavefront takes the events in node order (each
+// lane reads and updates one neighbour; nodes that later events push over a
+// threshold wait in an LDS bitmap window or a heap); then the wall normals
+// near the changes are refreshed, the geometry (row words, tasks, links) is
+// rebuilt in place and the populations are moved into the new compact
+// layout.  The rule is serial in node order; the wavefront is used for the
+// neighbourhood of one event at a time.
 #include "lbm_internal.hpp"
 
 namespace lbm {
@@ -160,9 +163,11 @@ __device__ __forceinline__ int32_t heap_pop(int32_t *h, int &n) {
     return top;
 }
 
+// The pass for boxes less than 3 sites wide along some axis (a site can then
+// be reached twice from one node, and lane 0 re-reads it after each update).
 // One wavefront.  Lanes 1..Q-1 read, in parallel, the state of the neighbour
 // along their direction (solid, phi, rate, marks, and its moments from the
-// populations or from its record if it became fluid earlier in the pass);
+// pass's moments or from its record if it became fluid earlier in the pass);
 // lane 0 applies the rule and writes everything an event changes (solid, phi,
 // kof_old, the records, the heap and its marks); the barrier at the end of
 // every event makes those writes visible to the next event's reads.
