@@ -32,19 +32,20 @@ SCHEMES = (SCHEME_SNEW, SCHEME_SV, SCHEME_SPJ, SCHEME_ABB)
 PEDAS = (0.1, 1.0, 10.0, 100.0, 1e3, 1e4, 1e5)
 
 
-def _analytic(kr, tau=0.74, inlet=None):
+def _analytic(kr, tau=0.74, inlet=None, top=B - 0.5):
     """Analytic field on the fluid nodes (x = 0..A-1, rows 1..B), each
     boundary plane where the lattice puts it for a linear profile: C fixed at
     x = -tau by the equilibrium inlet, the zero-gradient mirror at x = A - 1/2,
     the bottom zero-flux plane halfway to the solid row, the reactive plane
     on the top fluid row (pre-collision source, new scheme).  inlet: the
     distance of the fixed-C plane before the first node column in place of
-    tau (0: the plane on that column)."""
+    tau (0: the plane on that column); top: the height of the reactive plane
+    above the zero-flux plane (B - 1/2: on the top fluid row)."""
     x0 = tau if inlet is None else inlet
     x = np.arange(A) + x0
     y = np.arange(1, B + 1) - 0.5
     X, Y = np.meshgrid(x, y)
-    return paper_2d_verification(X, Y, A - 0.5 + x0, B - 0.5, D, kr, 1.0, 0.0)
+    return paper_2d_verification(X, Y, A - 0.5 + x0, top, D, kr, 1.0, 0.0)
 
 
 def _steady(cases, steps=STEADY):
@@ -155,6 +156,12 @@ def test_rest_fraction_table():
             alt = np.array([np.abs(f - _analytic(kr, c.tau_ad, inlet=x0)).mean() for c, f in zip(cases, fields)])
             log(f"[schemes] rest fraction, collision {coll}, inlet plane at x = -{x0}: MAE {list(alt)}")
             assert np.all(alt > m[coll])
+        # and with the reactive plane half a site higher (halfway to the
+        # solid row), for each inlet placement
+        for x0 in (None, 0.5, 0.0):
+            alt = [np.abs(f - _analytic(kr, c.tau_ad, inlet=x0, top=B)).mean() for c, f in zip(cases, fields)]
+            log(f"[schemes] rest fraction, collision {coll}, inlet plane at x = "
+                f"{'-tau' if x0 is None else -x0}, reactive plane at y = B: MAE {alt}")
     assert np.all(np.abs(m[1][:3] / m[0] - 1) < 0.03)
     assert m[0].max() < 1.5e-3 and m[1][:3].max() < 1.5e-3
     assert np.isfinite(m[1][3]) and m[1][3] < 5e-3
