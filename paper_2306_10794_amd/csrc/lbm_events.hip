@@ -417,14 +417,25 @@ __device__ __forceinline__ double lane_d(double v, int l) {
     return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
 }
 
-// first set position in [lo, hi) of the window (hi - lo <= EV_WIN), or -1
+// first set position in [lo, hi) of the window (hi - lo <= EV_WIN), or -1.
+// The word holding lo first, read by every lane alike (the next pending node
+// is usually a few sites on); then 64 words at a time, one per lane.
 __device__ __forceinline__ long window_first(const unsigned long long *bits, long lo, long hi, int lane) {
-    for (long base = lo & ~63L; base < hi; base += 64L * 64) {
+    const long w0 = lo & ~63L;
+    {
+        unsigned long long w = bits[(w0 >> 6) & (EV_WWORDS - 1)];
+        w &= ~0ull << (lo - w0);
+        if (hi - w0 < 64) w &= (1ull << (hi - w0)) - 1ull;
+        const unsigned long long wu = ((unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)(w >> 32)) << 32) |
+                                      (unsigned long long)__builtin_amdgcn_readfirstlane((unsigned)w);
+        if (wu) return w0 + __builtin_ctzll(wu);
+        if (hi <= w0 + 64) return -1;
+    }
+    for (long base = w0 + 64; base < hi; base += 64L * 64) {
         const long wp = base + 64L * lane;
         unsigned long long w = 0ull;
         if (wp < hi) {
             w = bits[(wp >> 6) & (EV_WWORDS - 1)];
-            if (wp < lo) w &= ~0ull << (lo - wp);
             if (hi - wp < 64) w &= (1ull << (hi - wp)) - 1ull;
         }
         const unsigned long long m = __ballot(w != 0ull);
