@@ -234,7 +234,9 @@ lbm_status lbm_set_geometry(lbm_ctx *ctx, const uint8_t *solid, const double *no
 lbm_status lbm_init_fields(lbm_ctx *ctx, const double *rho, const double *u,
                            const double *c);
 
-/* Advance nsteps fused time steps (asynchronous). */
+/* Advance nsteps fused time steps (asynchronous; with phase_change = 1 it
+ * synchronises once per batch of up to 32 steps and after each event pass,
+ * which it runs after the step that crossed a threshold, Sec. 2.4). */
 lbm_status lbm_step(lbm_ctx *ctx, int32_t nsteps);
 
 /* lbm_step with per-kernel timing, for measurement: runs nsteps exactly like
