@@ -92,3 +92,36 @@ def test_bad_launch_config_rejected():
             lbm_set_launch_config(sim.ctx, **bad)
         assert ei.value.status == LBM_EINVAL
     sim.close()
+
+
+@pytest.mark.parametrize("phase_change", [0, 1])
+def test_timed_steps_equal_plain_steps(phase_change):
+    """lbm_step_timed (an event pair around every kernel, one step at a time)
+    gives the state of lbm_step bit for bit, with the phase-change thresholds
+    off and on (in the second case with events during the run, which lbm_step
+    takes in batches of steps and lbm_step_timed one step at a time)."""
+    import torch
+    from paper_2306_10794_amd import Simulation, lbm_step, lbm_step_timed
+    case = configs.sphere_precipitation(n=24, seed=3, phase_change=phase_change, r_min=2.0, r_max=4.0)
+    if phase_change:
+        zi = np.arange(case.n) // (case.nx * case.ny)
+        case = case.replace(phi0=np.where(case.solid_flat() == 1, 1.0, np.where(zi < 2, 0.9999, 0.0)))
+    out = []
+    for timed in (False, True):
+        sim = Simulation(case, precision=FP32)
+        if timed:
+            ms = lbm_step_timed(sim.ctx, 80)
+            assert ms[0] > 0.0 and ms[1] > 0.0
+        else:
+            lbm_step(sim.ctx, 80)
+        torch.cuda.synchronize()
+        st = _state(sim)
+        out.append((st, sim.diag()["n_events"]))
+        sim.close()
+    (a, ea), (b, eb) = out
+    log(f"[launch] timed vs plain, phase change {phase_change}: events {ea} / {eb}")
+    assert a[3] == b[3] == 80 and ea == eb
+    if phase_change:
+        assert ea > 0
+    for x, y in zip(a[:3], b[:3]):
+        assert np.array_equal(x, y)
