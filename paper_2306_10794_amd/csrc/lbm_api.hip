@@ -115,8 +115,7 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
     const bool ceqf = p[0].ceq_field != 0;
     char *ceq = take(ceqf ? 8 * N : 0), *lceq = take(ceqf ? ts * L : 0);
     char *lbeta = take(ts * L), *lq = take(ts * L), *lq2 = take(ts * L), *lnode = take(4 * L),
-         *lsolid = take(4 * L), *lmap = take(4 * L),
-         *ldir = take(L);
+         *lsolid = take(4 * L), *ldir = take(L);
     char *sif = take(4 * L), *soff = take(4 * (L + 1)), *slinks = take(4 * L), *sdom = take(4 * L);
     char *bsum = take(4 * ((N + 4095) / 4096 + 64));
     char *dpart = take(16 * ((N + 255) / 256 + 1));
@@ -163,7 +162,6 @@ size_t workspace_layout(const lbm_params *p, int nd, Ctx *c, char *base) {
         c->phi_stale = false;
         c->solid = (uint8_t *)solid;
         c->lbeta = lbeta; c->lq = lq; c->lnode = (int32_t *)lnode; c->lsolid = (int32_t *)lsolid;
-        c->lmap = (int32_t *)lmap;
         c->lqb[0] = lq; c->lqb[1] = lq2; c->lq_next = 1;
         c->ldir = (uint8_t *)ldir;
         c->sif = (int32_t *)sif; c->soff = (int32_t *)soff; c->slinks = (int32_t *)slinks;

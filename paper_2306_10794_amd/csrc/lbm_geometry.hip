@@ -434,13 +434,17 @@ __global__ __launch_bounds__(BLK) void k_link_count(long ns, const int32_t *node
 // Link order.  The links of a task's nodes occupy one range (from lbase of
 // its first node); within it they are ordered by direction, then by node, so
 // that the lanes of a wavefront holding a link along the same direction read
-// its coefficient and write its exchange at consecutive addresses.  lmap takes
-// a link's slot in node order (lbase[k] + its rank among k's directions) to
-// its index.  One wavefront per task.
-template <class L>
-__global__ __launch_bounds__(BLK) void k_link_map(const Task *tasks, long ntasks, const int32_t *nodeof,
-                                                  const uint32_t *rmask, const int32_t *lbase,
-                                                  int32_t *lmap) {
+// its coefficient and write its exchange at consecutive addresses.  The link
+// records are written in that order, one wavefront per task (lanes = the
+// task's nodes): a link's index is the task's base, the links of the earlier
+// directions and the lanes below holding the same direction (the fused step's
+// numbering).
+template <class L, typename T>
+__global__ __launch_bounds__(BLK) void k_links(Geo g, const Task *tasks, long ntasks, const int32_t *nodeof,
+                                               const uint32_t *rmask, const int32_t *lbase,
+                                               const double *nrm, const double *kr, T *lbeta,
+                                               int32_t *lnode, int32_t *lsolid, uint8_t *ldir,
+                                               const double *ceq, T *lceq) {
     const long t = (long)blockIdx.x * (BLK / 64) + (threadIdx.x >> 6);
     if (t >= ntasks) return;
     const int lane = threadIdx.x & 63;
@@ -448,63 +452,43 @@ __global__ __launch_bounds__(BLK) void k_link_map(const Task *tasks, long ntasks
     const int cnt = tk.cnt & 255;
     const bool active = lane < cnt;
     const int k = tk.k0 + (active ? lane : 0);
-    const uint32_t rm = active ? rmask[nodeof[k]] : 0u;
-    const int ob = lbase[k];
-    const int base = __shfl(ob, 0, 64);   // the task's first link
-    const unsigned long long below = (1ull << lane) - 1ull;
-    int off = 0, m = 0;
-    for (int i = 1; i < L::Q; i++) {
-        const bool has = (rm >> i) & 1u;
-        const unsigned long long bal = __ballot(has);
-        if (has) lmap[ob + m++] = base + off + __popcll(bal & below);
-        off += __popcll(bal);
-    }
-}
-
-template <class L, typename T>
-__global__ __launch_bounds__(BLK) void k_links(Geo g, long nf, const int32_t *nodeof,
-                                               const uint32_t *rmask, const int32_t *lbase,
-                                               const int32_t *lmap,
-                                               const double *nrm, const double *kr, T *lbeta,
-                                               int32_t *lnode, int32_t *lsolid, uint8_t *ldir,
-                                               const double *ceq, T *lceq) {
-    const long k = (long)blockIdx.x * BLK + threadIdx.x;
-    if (k >= nf) return;
     const long n = nodeof[k];
-    if (n < 0) return;   // a hole
-    const uint32_t rm = rmask[n];
-    if (!rm) return;
+    const uint32_t rm = active ? rmask[n] : 0u;
+    const int base = __shfl(lbase[k], 0, 64);   // the task's first link
+    const unsigned long long below = (1ull << lane) - 1ull;
     long nl;
     const int d = dom_of(g, n, &nl);
     const DomDev &D = g.doms[d];
     int X, Y, Z;
     coords(D.box, nl, &X, &Y, &Z);
-    const int base = lbase[k];
-    int r = 0;
+    int off = 0;
     for (int i = 1; i < L::Q; i++) {
-        if (!(rm & (1u << i))) continue;
-        int fc;
-        const long s = D.node_off + site(D.box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
-        const double en = L::ex[i] * nrm[3 * s] + L::ey[i] * nrm[3 * s + 1] + L::ez[i] * nrm[3 * s + 2];
-        const double kv = kr[s];
-        double kap;
-        if (D.scheme == LBM_SV) kap = en > 0 ? kv * en / D.cs2s : 0.0;
-        else if (D.scheme == LBM_SPJ) kap = en > 0 ? D.gamma * kv / (D.cs2s * en) : 0.0;
-        else kap = en > 0 ? D.gamma * kv * en / D.cs2s : 0.0;
-        // pre-collision source with both neighbours solid: fall back to the
-        // node's own post-collision population, whose effective rate is gamma k
-        if (D.mech == LBM_PRECOLL && (rm & (1u << L::opp[i]))) kap = kap / D.gamma;
-        // anti-bounce-back (the k -> infinity limit) at reactive solid nodes;
-        // a solid node with k_r = 0 keeps plain bounce-back (kap = 0)
-        const double beta = (D.scheme == LBM_ABB && kv > 0.0) ? -1.0 : (1.0 - kap) / (1.0 + kap);
-        const int l = lmap[base + r];
-        lbeta[l] = (T)beta;
-        // per-node C_eq (deviation form); the uniform value until one is given
-        if (lceq) lceq[l] = (T)((ceq ? ceq[s] : D.ceq_dev + D.c_ref) - D.c_ref);
-        lnode[l] = (int32_t)n;
-        lsolid[l] = (int32_t)s;
-        ldir[l] = (uint8_t)i;
-        r++;
+        const bool has = (rm >> i) & 1u;
+        const unsigned long long bal = __ballot(has);
+        if (has) {
+            const int l = base + off + __popcll(bal & below);
+            int fc;
+            const long s = D.node_off + site(D.box, X, Y, Z, -L::ex[i], -L::ey[i], -L::ez[i], true, &fc);
+            const double en = L::ex[i] * nrm[3 * s] + L::ey[i] * nrm[3 * s + 1] + L::ez[i] * nrm[3 * s + 2];
+            const double kv = kr[s];
+            double kap;
+            if (D.scheme == LBM_SV) kap = en > 0 ? kv * en / D.cs2s : 0.0;
+            else if (D.scheme == LBM_SPJ) kap = en > 0 ? D.gamma * kv / (D.cs2s * en) : 0.0;
+            else kap = en > 0 ? D.gamma * kv * en / D.cs2s : 0.0;
+            // pre-collision source with both neighbours solid: fall back to the
+            // node's own post-collision population, whose effective rate is gamma k
+            if (D.mech == LBM_PRECOLL && (rm & (1u << L::opp[i]))) kap = kap / D.gamma;
+            // anti-bounce-back (the k -> infinity limit) at reactive solid nodes;
+            // a solid node with k_r = 0 keeps plain bounce-back (kap = 0)
+            const double beta = (D.scheme == LBM_ABB && kv > 0.0) ? -1.0 : (1.0 - kap) / (1.0 + kap);
+            lbeta[l] = (T)beta;
+            // per-node C_eq (deviation form); the uniform value until one is given
+            if (lceq) lceq[l] = (T)((ceq ? ceq[s] : D.ceq_dev + D.c_ref) - D.c_ref);
+            lnode[l] = (int32_t)n;
+            lsolid[l] = (int32_t)s;
+            ldir[l] = (uint8_t)i;
+        }
+        off += __popcll(bal);
     }
 }
 
@@ -687,11 +671,9 @@ static hipError_t geometry_impl(Ctx &c, const uint8_t *solid, const double *norm
     *n_links = tot;
     if (tot > c.max_links) return hipSuccess;  // the caller reports the capacity error
     if (c.n_tasks > 0)
-        hipLaunchKernelGGL((k_link_map<L>), dim3((c.n_tasks + BLK / 64 - 1) / (BLK / 64)), dim3(BLK), 0, st,
-                           c.tasks, (long)c.n_tasks, c.nodeof, c.rmask, c.lbase, c.lmap);
-    hipLaunchKernelGGL((k_links<L, T>), blocks(nfl), dim3(BLK), 0, st, g, ns, c.nodeof,
-                       c.rmask, c.lbase, c.lmap, c.nrm, c.kr, (T *)c.lbeta, c.lnode, c.lsolid, c.ldir,
-                       c.ceq_set ? c.ceq : nullptr, (T *)c.lceq);
+        hipLaunchKernelGGL((k_links<L, T>), dim3((c.n_tasks + BLK / 64 - 1) / (BLK / 64)), dim3(BLK), 0, st, g,
+                           c.tasks, (long)c.n_tasks, c.nodeof, c.rmask, c.lbase, c.nrm, c.kr, (T *)c.lbeta,
+                           c.lnode, c.lsolid, c.ldir, c.ceq_set ? c.ceq : nullptr, (T *)c.lceq);
     // solid side: per solid interface node, its links in direction order
     uint32_t *smask = (uint32_t *)c.cnt;
     hipLaunchKernelGGL(k_fill_i32, dim3(nb), dim3(BLK), 0, st, c.cnt, N, 0);

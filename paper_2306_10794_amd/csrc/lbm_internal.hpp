@@ -125,7 +125,6 @@ struct Ctx {
     bool phi_pending[2];     // ev_phi[b] marks a solid-side kernel still to be waited for
     int last_phi;            // buffer of the last overlapped solid-side kernel, -1 none
     int32_t *lnode, *lsolid; // [max_links]
-    int32_t *lmap;           // [max_links] link slot in node order -> link index
     uint8_t *ldir;           // [max_links]
     int32_t *sif, *soff, *slinks; // solid interface list [max_links], offsets [max_links+1], [max_links]
     int32_t *sdom;           // [max_links] domain of each solid interface node
