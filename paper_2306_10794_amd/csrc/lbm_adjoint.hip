@@ -53,6 +53,49 @@ struct AdjArgs {
     long ntasks, S;
 };
 
+// A task's per-link values staged in LDS as 32-bit words (word w of element
+// j at [w][j]): fetched straight from global memory into LDS, so that no
+// register waits on them and the population loads issue behind them at once.
+template <typename V, int CAP>
+__device__ __forceinline__ void lds_fetch(const V *__restrict__ src, uint32_t (&dst)[sizeof(V) / 4][CAP], int n,
+                                          int lane) {
+    for (int c = 0; c < n; c += 64)
+        if (c + lane < n) {
+            const uint32_t *p = (const uint32_t *)(src + c + lane);
+#pragma unroll
+            for (int w = 0; w < (int)(sizeof(V) / 4); w++)
+                __builtin_amdgcn_global_load_lds((const __attribute__((address_space(1))) void *)(p + w),
+                                                 (__attribute__((address_space(3))) void *)&dst[w][c], 4, 0, 0);
+        }
+}
+
+template <typename V, int CAP>
+__device__ __forceinline__ V lds_get(const uint32_t (&src)[sizeof(V) / 4][CAP], int j) {
+    if constexpr (sizeof(V) == 4) {
+        return __builtin_bit_cast(V, src[0][j]);
+    } else {
+        return __builtin_bit_cast(V, (unsigned long long)src[0][j] | ((unsigned long long)src[1][j] << 32));
+    }
+}
+
+template <typename V, int CAP>
+__device__ __forceinline__ void lds_put(uint32_t (&dst)[sizeof(V) / 4][CAP], int j, V v) {
+    if constexpr (sizeof(V) == 4) {
+        dst[0][j] = __builtin_bit_cast(uint32_t, v);
+    } else {
+        const unsigned long long b = __builtin_bit_cast(unsigned long long, v);
+        dst[0][j] = (uint32_t)b;
+        dst[1][j] = (uint32_t)(b >> 32);
+    }
+}
+
+// Element index of slot 0 of node k in a blocked population array (slot s
+// is 64 s further): pidx() with one 32 x 32 -> 64-bit multiply, for a compact
+// index k >= 0.  The node's own base is formed once and reused by every slot.
+__device__ __forceinline__ long blk0(int k, int nq) {
+    return (long)((unsigned long long)((unsigned)k >> 6) * (unsigned)(nq * 64)) + (k & 63);
+}
+
 // per-wavefront task setup shared by the three kernels; returns false for a
 // wavefront without a task
 template <class L, typename T>
@@ -101,7 +144,8 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     constexpr uint32_t SM = sol_mask<L, RED>();   // the solute set (D2Q5 / D3Q7 when RED)
     constexpr int QS = __builtin_popcount(SM);
     constexpr int LCAP = 256;   // links of a task staged in LDS (more: read in place)
-    __shared__ T sb[BLK / 64][LCAP], ss[BLK / 64][LCAP];
+    constexpr int NW = (int)(sizeof(T) / 4);
+    __shared__ uint32_t sb[BLK / 64][NW][LCAP], ss[BLK / 64][NW][LCAP];
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c)) return;
     const bool act = c.active;
@@ -123,24 +167,15 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
         nlt += __popcll(bal);
     }
     const bool staged = nlt <= LCAP;
-    if (staged) {
-        T vb[LCAP / 64];
-#pragma unroll
-        for (int r = 0; r < LCAP / 64; r++)
-            if (r * 64 + lane < nlt) vb[r] = a.lbeta[lt + r * 64 + lane];
-#pragma unroll
-        for (int r = 0; r < LCAP / 64; r++)
-            if (r * 64 + lane < nlt) sb[wv][r * 64 + lane] = vb[r];
-    }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
+    if (staged) lds_fetch<T, LCAP>(a.lbeta + lt, sb[wv], nlt, lane);
     if (act) {
+        const long ob = blk0(c.k, QS);
         T gv[Q];
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             if (!((SM >> i) & 1u)) continue;
-            gv[i] = c.kk[i] >= 0 ? a.gin[pidx(sol_slot(SM, i), c.kk[i], QS)]
-                                 : a.gin[pidx(sol_slot(SM, L::opp[i]), c.k, QS)];
+            gv[i] = c.kk[i] >= 0 ? a.gin[blk0(c.kk[i], QS) + 64 * sol_slot(SM, i)]
+                                 : a.gin[ob + 64 * sol_slot(SM, L::opp[i])];
         }
         // a pulled source is a direction without a link, which this loop
         // leaves unchanged
@@ -151,8 +186,8 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
             const int pos = lpos[i];
             const R own = (R)gv[i];
             const R srcv = (D.mech == LBM_PRECOLL && !(rbc & (1u << o))) ? (R)gv[o] : own;
-            const R beta = (R)(staged ? sb[wv][pos] : a.lbeta[lt + pos]);
-            if (staged) ss[wv][pos] = (T)srcv;
+            const R beta = (R)(staged ? lds_get<T, LCAP>(sb[wv], pos) : a.lbeta[lt + pos]);
+            if (staged) lds_put<T, LCAP>(ss[wv], pos, (T)srcv);
             else a.lsrc[lt + pos] = (T)srcv;
             gv[i] = (T)((R(1) - beta) * (sol_w<L>(D, i) * D.ceq_dev) + beta * srcv);
         }
@@ -165,7 +200,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
                 // TRT at rest: even parts relax with omega_gs toward w C, odd
                 // parts with omega_g toward 0 (as the fused step with u = 0)
                 const R oms = D.omega_gs, oma = D.omega_g;
-                a.gout[pidx(0, c.k, QS)] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
+                a.gout[ob] = (T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC);
 #pragma unroll
                 for (int i = 1; i < Q; i++) {
                     if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
@@ -173,8 +208,8 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
                     const R gi = (R)gv[i], go = (R)gv[o];
                     const R As = oms * sol_w<L>(D, i) * dC;
                     const R hs = R(0.5) * oms * (gi + go), ha = R(0.5) * oma * (gi - go);
-                    a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi - hs - ha + As);
-                    a.gout[pidx(sol_slot(SM, o), c.k, QS)] = (T)(go - hs + ha + As);
+                    a.gout[ob + 64 * sol_slot(SM, i)] = (T)(gi - hs - ha + As);
+                    a.gout[ob + 64 * sol_slot(SM, o)] = (T)(go - hs + ha + As);
                 }
             } else {
 #pragma unroll
@@ -182,7 +217,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
                     if (!((SM >> i) & 1u)) continue;
                     const R gi = (R)gv[i];
                     const R geq = sol_w<L>(D, i) * dC;
-                    a.gout[pidx(sol_slot(SM, i), c.k, QS)] = (T)(gi + D.omega_g * (geq - gi));
+                    a.gout[ob + 64 * sol_slot(SM, i)] = (T)(gi + D.omega_g * (geq - gi));
                 }
             }
         }
@@ -192,7 +227,7 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     if (staged) {
 #pragma unroll
         for (int r = 0; r < LCAP / 64; r++)
-            if (r * 64 + lane < nlt) a.lsrc[lt + r * 64 + lane] = ss[wv][r * 64 + lane];
+            if (r * 64 + lane < nlt) a.lsrc[lt + r * 64 + lane] = lds_get<T, LCAP>(ss[wv], r * 64 + lane);
     }
 }
 
@@ -219,8 +254,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     constexpr uint32_t SM = sol_mask<L, RED>();
     constexpr int QS = __builtin_popcount(SM);
     constexpr int LCAP = 256;   // links of a task staged in LDS (more: read in place)
-    __shared__ T sb[BLK / 64][LCAP], ss[BLK / 64][LCAP];
-    __shared__ double sg[BLK / 64][LCAP];
+    constexpr int NW = (int)(sizeof(T) / 4);
+    __shared__ uint32_t sb[BLK / 64][NW][LCAP], ss[BLK / 64][NW][LCAP], sg[BLK / 64][2][LCAP];
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c)) return;
     const bool act = c.active;
@@ -241,37 +276,19 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     }
     const bool staged = nlt <= LCAP;
     if (staged) {
-        T vb[LCAP / 64], vs[LCAP / 64];
-        double vg[LCAP / 64];
-#pragma unroll
-        for (int r = 0; r < LCAP / 64; r++) {
-            const int j = r * 64 + lane;
-            if (j < nlt) {
-                vb[r] = a.lbeta[lt + j];
-                vs[r] = a.lsrc[lt + j];
-                vg[r] = a.gbeta[lt + j];
-            }
-        }
-#pragma unroll
-        for (int r = 0; r < LCAP / 64; r++) {
-            const int j = r * 64 + lane;
-            if (j < nlt) {
-                sb[wv][j] = vb[r];
-                ss[wv][j] = vs[r];
-                sg[wv][j] = vg[r];
-            }
-        }
+        lds_fetch<T, LCAP>(a.lbeta + lt, sb[wv], nlt, lane);
+        lds_fetch<T, LCAP>(a.lsrc + lt, ss[wv], nlt, lane);
+        lds_fetch<double, LCAP>(a.gbeta + lt, sg[wv], nlt, lane);
     }
-    __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
-    __builtin_amdgcn_wave_barrier();
     if (act) {
+        const long ob = blk0(c.k, QS);
         // lambda(t+1) at this node: the forward pull with directions reversed
         T mu[Q];
 #pragma unroll
         for (int d = 0; d < Q; d++) {
             if (!((SM >> d) & 1u)) continue;
             const int kd = c.kk[L::opp[d]];
-            mu[d] = kd >= 0 ? a.pin[pidx(sol_slot(SM, d), kd, QS)] : a.pin[pidx(sol_slot(SM, L::opp[d]), c.k, QS)];
+            mu[d] = kd >= 0 ? a.pin[blk0(kd, QS) + 64 * sol_slot(SM, d)] : a.pin[ob + 64 * sol_slot(SM, L::opp[d])];
         }
         R m = R(0);
 #pragma unroll
@@ -279,13 +296,13 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             if ((SM >> i) & 1u) m += sol_w<L>(D, i) * (R)mu[i];
         const R om = D.omega_g, om1 = R(1) - om, oms = D.omega_gs;
         const R ta = R(1) - R(0.5) * (oms + om), tb = R(0.5) * (om - oms);
-        a.pout[pidx(0, c.k, QS)] = (T)(TRT ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
+        a.pout[ob] = (T)(TRT ? (R(1) - oms) * (R)mu[0] + oms * m : om1 * (R)mu[0] + om * m);
         auto link = [&](int d, R nu, R *out_d, R *out_other, bool pulled) {
             const int pos = lpos[d];
-            const R beta = (R)(staged ? sb[wv][pos] : a.lbeta[lt + pos]);
-            const R src = (R)(staged ? ss[wv][pos] : a.lsrc[lt + pos]);
+            const R beta = (R)(staged ? lds_get<T, LCAP>(sb[wv], pos) : a.lbeta[lt + pos]);
+            const R src = (R)(staged ? lds_get<T, LCAP>(ss[wv], pos) : a.lsrc[lt + pos]);
             const R add = nu * (src - sol_w<L>(D, d) * D.ceq_dev);
-            if (staged) sg[wv][pos] += add;
+            if (staged) lds_put<double, LCAP>(sg[wv], pos, lds_get<double, LCAP>(sg[wv], pos) + add);
             else a.gbeta[lt + pos] += add;
             if (pulled) {
                 *out_other += beta * nu;
@@ -311,8 +328,8 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const bool li = (rbc >> i) & 1u, lo = (rbc >> o) & 1u;
             if (li) link(i, nui, &outi, &outo, D.mech == LBM_PRECOLL && !lo);
             if (lo) link(o, nuo, &outo, &outi, D.mech == LBM_PRECOLL && !li);
-            a.pout[pidx(si, c.k, QS)] = (T)outi;
-            a.pout[pidx(so, c.k, QS)] = (T)outo;
+            a.pout[ob + 64 * si] = (T)outi;
+            a.pout[ob + 64 * so] = (T)outo;
         }
     }
     __builtin_amdgcn_fence(__ATOMIC_SEQ_CST, "wavefront");
@@ -321,7 +338,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < LCAP / 64; r++) {
             const int j = r * 64 + lane;
-            if (j < nlt) a.gbeta[lt + j] = sg[wv][j];
+            if (j < nlt) a.gbeta[lt + j] = lds_get<double, LCAP>(sg[wv], j);
         }
     }
 }
