@@ -302,8 +302,10 @@ lbm_status lbm_autotune(lbm_ctx *ctx, int32_t trial_steps, lbm_launch_config *be
  *   steps with a solute checkpoint every ckpt_every steps (1 <= ckpt_every <=
  *   nsteps) on the current geometry: ceil(nsteps/ckpt_every) + 4 solute
  *   states, ckpt_every per-link source values (one storage element per
- *   reactive link and step of a segment) and 8 B per reactive link of
- *   capacity.
+ *   reactive link and step of a segment; twice that when the run has more
+ *   than one segment, so that lbm_adjoint recomputes the next segment on a
+ *   second stream while it applies the transposed steps of the current one)
+ *   and 8 B per reactive link of capacity.
  * lbm_record: runs nsteps steps exactly as lbm_step does and keeps the
  *   checkpoints in dev_workspace (caller-owned, 256-byte aligned, untouched
  *   by anything else until lbm_adjoint has run).

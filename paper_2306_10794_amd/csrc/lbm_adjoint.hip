@@ -462,7 +462,6 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double 
     T *P[2] = {(T *)r.p[0], (T *)r.p[1]};
     const T *ck = (const T *)r.ckpt;
     T *rs[2] = {(T *)r.rst[0], (T *)r.rst[1]};
-    T *src = (T *)r.lsrc;
     // dL/dbeta := 0, lambda(T) from dL/dC_T
     hipLaunchKernelGGL(k_adj_zero, dim3((c.n_links + BLK - 1) / BLK + 1), dim3(BLK), 0, c.stream,
                        r.gbeta, (long)c.n_links);
@@ -471,28 +470,37 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double 
     if (nb > 0) hipLaunchKernelGGL((k_adj_init<L, T, RED>), dim3(nb), dim3(BLK), 0, c.stream, a);
     int cur = 0;
     const int nseg = (int)((r.nsteps + r.ckpt_every - 1) / r.ckpt_every);
-    for (int sgi = nseg - 1; sgi >= 0; sgi--) {
+    auto seg_len = [&](int sgi) {
         const long t0 = (long)sgi * r.ckpt_every;
-        const int len = (int)((r.nsteps - t0) < r.ckpt_every ? (r.nsteps - t0) : r.ckpt_every);
-        // recomputation: state 0 of the segment is its checkpoint, state j > 0
-        // lives in rs[(j - 1) & 1]; stepping from state j records the links'
-        // source values of step j (the last state's successor is not needed)
+        return (int)((r.nsteps - t0) < r.ckpt_every ? (r.nsteps - t0) : r.ckpt_every);
+    };
+    // recomputation of segment sgi on stream st: state 0 of the segment is
+    // its checkpoint, state j > 0 lives in rs[(j - 1) & 1]; stepping from
+    // state j records the links' source values of step j into src (the last
+    // state's successor is not needed)
+    auto recompute = [&](int sgi, hipStream_t st, T *src) -> hipError_t {
+        AdjArgs<T> b = a;
+        const int len = seg_len(sgi);
         for (int j = 0; j < len; j++) {
-            a.gin = j == 0 ? (T *)(ck + (size_t)sgi * slot) : rs[(j - 1) & 1];
-            a.gout = j + 1 < len ? rs[j & 1] : nullptr;
-            a.lsrc = src + (size_t)j * r.src_stride;
-            if (ms) (void)hipEventRecord(c.ev[0], c.stream);
-            if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T, RED, TRT>), dim3(nb), dim3(BLK), 0, c.stream, a);
+            b.gin = j == 0 ? (T *)(ck + (size_t)sgi * slot) : rs[(j - 1) & 1];
+            b.gout = j + 1 < len ? rs[j & 1] : nullptr;
+            b.lsrc = src + (size_t)j * r.src_stride;
+            if (ms) (void)hipEventRecord(c.ev[0], st);
+            if (nb > 0) hipLaunchKernelGGL((k_sol_step<L, T, RED, TRT>), dim3(nb), dim3(BLK), 0, st, b);
             if (ms) {
-                (void)hipEventRecord(c.ev[1], c.stream);
+                (void)hipEventRecord(c.ev[1], st);
                 hipError_t e = add_elapsed(c, &ms[0]);
                 if (e != hipSuccess) return e;
             }
         }
+        return hipGetLastError();
+    };
+    // the transposed steps of segment sgi, last step first, on the context stream
+    auto transpose = [&](int sgi, const T *src) -> hipError_t {
         a.gin = nullptr;
         a.gout = nullptr;
-        for (int j = len - 1; j >= 0; j--) {
-            a.lsrc = src + (size_t)j * r.src_stride;
+        for (int j = seg_len(sgi) - 1; j >= 0; j--) {
+            a.lsrc = (T *)src + (size_t)j * r.src_stride;
             a.pin = P[cur];
             a.pout = P[1 - cur];
             if (ms) (void)hipEventRecord(c.ev[0], c.stream);
@@ -504,9 +512,41 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double 
             }
             cur = 1 - cur;
         }
-        hipError_t e = hipGetLastError();
-        if (e != hipSuccess) return e;
+        return hipGetLastError();
+    };
+    // With a second source buffer the recomputation of segment sgi - 1 runs
+    // on the side stream while the transposed steps of segment sgi run on
+    // the context stream: they share no array (the transposed steps read no
+    // state), and both kernels are bound by latency rather than bandwidth at
+    // the sizes the adjoint is run at.  The timed variant, and a stream under
+    // capture, keep everything on the context stream.
+    hipStreamCaptureStatus cap = hipStreamCaptureStatusNone;
+    if (hipStreamIsCapturing(c.stream, &cap) != hipSuccess) cap = hipStreamCaptureStatusActive;
+    const bool ovl = !ms && r.lsrc2 && c.have_side && nseg > 1 && cap == hipStreamCaptureStatusNone;
+    T *buf[2] = {(T *)r.lsrc, ovl ? (T *)r.lsrc2 : (T *)r.lsrc};
+    hipError_t e = hipSuccess;
+    if (ovl) e = recompute(nseg - 1, c.stream, buf[(nseg - 1) & 1]);
+    for (int sgi = nseg - 1; sgi >= 0 && e == hipSuccess; sgi--) {
+        T *src = buf[sgi & 1];
+        if (!ovl) {
+            e = recompute(sgi, c.stream, src);
+            if (e == hipSuccess) e = transpose(sgi, src);
+            continue;
+        }
+        if (sgi > 0) {
+            // after all work so far on the context stream: the recomputation
+            // of segment sgi (whose states it reuses) and the transposed steps
+            // of segment sgi + 1 (which read the buffer it fills)
+            if ((e = hipEventRecord(c.ev_adj[0], c.stream)) != hipSuccess) break;
+            if ((e = hipStreamWaitEvent(c.side, c.ev_adj[0], 0)) != hipSuccess) break;
+            if ((e = recompute(sgi - 1, c.side, buf[(sgi - 1) & 1])) != hipSuccess) break;
+            if ((e = hipEventRecord(c.ev_adj[1], c.side)) != hipSuccess) break;
+        }
+        if ((e = transpose(sgi, src)) != hipSuccess) break;
+        // the next segment's transposed steps wait for its recomputation
+        if (sgi > 0) e = hipStreamWaitEvent(c.stream, c.ev_adj[1], 0);
     }
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(k_adj_zero, dim3((c.N + BLK - 1) / BLK), dim3(BLK), 0, c.stream, grad, c.N);
     if (c.n_sif > 0)
         hipLaunchKernelGGL((k_adj_grad<L>), dim3((c.n_sif + BLK - 1) / BLK), dim3(BLK), 0, c.stream,

@@ -401,13 +401,16 @@ static lbm_status create_common(const lbm_params *params, int nd, void *dev_work
             if (ok) made++;
             ok = ok && hipEventCreateWithFlags(&c->ev_phi[b], hipEventDisableTiming) == hipSuccess;
             if (ok) made++;
+            ok = ok && hipEventCreateWithFlags(&c->ev_adj[b], hipEventDisableTiming) == hipSuccess;
+            if (ok) made++;
         }
         if (!ok) {   // run without the overlap
             (void)hipGetLastError();
             if (es == hipSuccess) (void)hipStreamDestroy(c->side);
             for (int b = 0; b < 2; b++) {
-                if (made > 2 * b) (void)hipEventDestroy(c->ev_stp[b]);
-                if (made > 2 * b + 1) (void)hipEventDestroy(c->ev_phi[b]);
+                if (made > 3 * b) (void)hipEventDestroy(c->ev_stp[b]);
+                if (made > 3 * b + 1) (void)hipEventDestroy(c->ev_phi[b]);
+                if (made > 3 * b + 2) (void)hipEventDestroy(c->ev_adj[b]);
             }
         }
         c->have_side = ok;
@@ -640,6 +643,7 @@ void lbm_destroy(lbm_ctx *ctx) {
         for (int b = 0; b < 2; b++) {
             (void)hipEventDestroy(c->ev_stp[b]);
             (void)hipEventDestroy(c->ev_phi[b]);
+            (void)hipEventDestroy(c->ev_adj[b]);
         }
         (void)hipStreamDestroy(c->side);
     }
@@ -917,6 +921,7 @@ static size_t adj_layout(const Ctx *c, int64_t nsteps, int64_t ckpt, AdjState *s
     char *ck = take(ncp * slot);
     char *r0 = take(slot), *r1 = take(slot);
     char *ls = take((size_t)ckpt * stride * ts);
+    char *ls2 = ncp > 1 ? take((size_t)ckpt * stride * ts) : nullptr;
     char *p0 = take(slot), *p1 = take(slot);
     char *gb = take(sizeof(double) * (size_t)(c->max_links + 1));
     if (st) {
@@ -924,6 +929,7 @@ static size_t adj_layout(const Ctx *c, int64_t nsteps, int64_t ckpt, AdjState *s
         st->rst[0] = r0;
         st->rst[1] = r1;
         st->lsrc = ls;
+        st->lsrc2 = ls2;
         st->src_stride = (int64_t)stride;
         st->p[0] = p0;
         st->p[1] = p1;

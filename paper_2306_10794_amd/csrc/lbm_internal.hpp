@@ -61,6 +61,9 @@ struct AdjState {
     void *rst[2];            // [Q][S] recomputed states (alternating)
     void *lsrc;              // [ckpt_every][n_links + 1] per step and reactive link: the
                              // source value of its rate condition (recomputed)
+    void *lsrc2;             // a second such buffer (runs of more than one segment,
+                             // else null): the next segment is recomputed into it
+                             // while the transposed steps read the first
     int64_t src_stride;      // elements between two steps of lsrc
     void *p[2];              // [Q][S] adjoint arrays
     double *gbeta;           // [max_links] dL/dbeta
@@ -121,6 +124,7 @@ struct Ctx {
     // step t + 1 (second stream; default priority)
     hipStream_t side;
     hipEvent_t ev_stp[2], ev_phi[2];
+    hipEvent_t ev_adj[2];    // the adjoint's recomputation on the side stream
     bool have_side;
     bool phi_pending[2];     // ev_phi[b] marks a solid-side kernel still to be waited for
     int last_phi;            // buffer of the last overlapped solid-side kernel, -1 none
