@@ -89,13 +89,6 @@ __device__ __forceinline__ void lds_put(uint32_t (&dst)[sizeof(V) / 4][CAP], int
     }
 }
 
-// Element index of slot 0 of node k in a blocked population array (slot s
-// is 64 s further): pidx() with one 32 x 32 -> 64-bit multiply, for a compact
-// index k >= 0.  The node's own base is formed once and reused by every slot.
-__device__ __forceinline__ long blk0(int k, int nq) {
-    return (long)((unsigned long long)((unsigned)k >> 6) * (unsigned)(nq * 64)) + (k & 63);
-}
-
 // per-wavefront task setup shared by the three kernels; returns false for a
 // wavefront without a task
 template <class L, typename T>
@@ -168,15 +161,18 @@ __global__ __launch_bounds__(BLK) void k_sol_step(AdjArgs<T> a) {
     }
     const bool staged = nlt <= LCAP;
     if (staged) lds_fetch<T, LCAP>(a.lbeta + lt, sb[wv], nlt, lane);
+    const long ob = blk0(c.k, QS);
+    T gv[Q];
     if (act) {
-        const long ob = blk0(c.k, QS);
-        T gv[Q];
 #pragma unroll
         for (int i = 0; i < Q; i++) {
             if (!((SM >> i) & 1u)) continue;
-            gv[i] = c.kk[i] >= 0 ? a.gin[blk0(c.kk[i], QS) + 64 * sol_slot(SM, i)]
-                                 : a.gin[ob + 64 * sol_slot(SM, L::opp[i])];
+            gv[i] = a.gin[c.kk[i] >= 0 ? pidx(sol_slot(SM, i), c.kk[i], QS) : ob + 64 * sol_slot(SM, L::opp[i])];
         }
+    }
+    // the coefficients in LDS, on every path (the loads above are needed now too)
+    if (staged) lds_dma_wait();
+    if (act) {
         // a pulled source is a direction without a link, which this loop
         // leaves unchanged
 #pragma unroll
@@ -280,16 +276,20 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
         lds_fetch<T, LCAP>(a.lsrc + lt, ss[wv], nlt, lane);
         lds_fetch<double, LCAP>(a.gbeta + lt, sg[wv], nlt, lane);
     }
+    const long ob = blk0(c.k, QS);
+    // lambda(t+1) at this node: the forward pull with directions reversed
+    T mu[Q];
     if (act) {
-        const long ob = blk0(c.k, QS);
-        // lambda(t+1) at this node: the forward pull with directions reversed
-        T mu[Q];
 #pragma unroll
         for (int d = 0; d < Q; d++) {
             if (!((SM >> d) & 1u)) continue;
             const int kd = c.kk[L::opp[d]];
-            mu[d] = kd >= 0 ? a.pin[blk0(kd, QS) + 64 * sol_slot(SM, d)] : a.pin[ob + 64 * sol_slot(SM, L::opp[d])];
+            mu[d] = a.pin[kd >= 0 ? pidx(sol_slot(SM, d), kd, QS) : ob + 64 * sol_slot(SM, L::opp[d])];
         }
+    }
+    // the link values in LDS, on every path (the loads above are needed now too)
+    if (staged) lds_dma_wait();
+    if (act) {
         R m = R(0);
 #pragma unroll
         for (int i = 0; i < Q; i++)

@@ -92,6 +92,22 @@ __host__ __device__ __forceinline__ long pidx(int slot, long k, int nq) {
     return ((k >> 6) * nq + slot) * 64 + (k & 63);
 }
 
+// Wait for every outstanding vector memory operation of the wavefront,
+// global-to-LDS loads included.  The compiler does not order an LDS read after
+// the global-to-LDS load that fills its location (it may issue the read right
+// behind it), so a kernel that stages data that way calls this before its
+// first read of the staged data, at a point where it waits for its own loads
+// anyway.  The asm is a wait instruction, with a memory clobber so that no
+// LDS read is moved above it.
+__device__ __forceinline__ void lds_dma_wait() { asm volatile("s_waitcnt vmcnt(0)" ::: "memory"); }
+
+// Element index of slot 0 of node k (slot s is 64 s further): pidx() with one
+// 32 x 32 -> 64-bit multiply, for a compact index k >= 0.  Kernels form a
+// node's own base once and reuse it for every slot.
+__device__ __forceinline__ long blk0(int k, int nq) {
+    return (long)((unsigned long long)((unsigned)k >> 6) * (unsigned)(nq * 64)) + (k & 63);
+}
+
 // Node flags of the geometry pass (dense, uint32 per node; not read per step)
 //   bits 0..Q-1 : fluid view, upstream site x - e_i is solid or outside a
 //                 non-periodic face

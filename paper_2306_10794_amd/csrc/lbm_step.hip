@@ -227,11 +227,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const double phi_in = rbc ? a.phif[k] : 0.0;
 
     // ---- loads: Q fluid + QS solute values per node ----
+    const long obf = blk0(k, Q), obg = blk0(k, QS);   // the node's own slot 0
     T fv[Q], gv[Q];
 #pragma unroll
     for (int i = 0; i < Q; i++) {
         // fluid neighbour: pull along i; solid or box face: own value along opp(i)
-        fv[i] = kk[i] >= 0 ? a.fin[pidx(i, kk[i], Q)] : a.fin[pidx(L::opp[i], k, Q)];
+        fv[i] = a.fin[kk[i] >= 0 ? pidx(i, kk[i], Q) : obf + 64 * L::opp[i]];
     }
 #pragma unroll
     for (int i = 0; i < Q; i++) {
@@ -249,7 +250,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             }
         }
         // fluid neighbour: pull; solid or box face: own value along opp(i)
-        gv[i] = e >= 0 ? a.gin[pidx(sol_slot(SM, i), e, QS)] : a.gin[pidx(sol_slot(SM, L::opp[i]), k, QS)];
+        gv[i] = a.gin[e >= 0 ? pidx(sol_slot(SM, i), e, QS) : obg + 64 * sol_slot(SM, L::opp[i])];
     }
 
     // ---- fluid: moments and Guo-forced BGK ----
@@ -295,7 +296,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const R om = D.omega_f, ff = D.force_fac, om1 = R(1) - om;
     const R base = om * (drho - R(1.5) * rho * uu) - R(3) * ff * uF;
     const R c45 = R(4.5) * om * rho;
-    __builtin_nontemporal_store((T)(om1 * fp[0] + R(L::w[0]) * base), &a.fout[pidx(0, k, Q)]);
+    __builtin_nontemporal_store((T)(om1 * fp[0] + R(L::w[0]) * base), &a.fout[obf]);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i) continue;
@@ -310,12 +311,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             // second rate, the even ones with om
             const R B = R(3) * wi * (D.omega_fm * em + D.force_fac_m * eF);
             const R hp = R(0.5) * om * (fp[i] + fp[o]), hm = R(0.5) * D.omega_fm * (fp[i] - fp[o]);
-            __builtin_nontemporal_store((T)(fp[i] - hp - hm + (A + B)), &a.fout[pidx(i, k, Q)]);
-            __builtin_nontemporal_store((T)(fp[o] - hp + hm + (A - B)), &a.fout[pidx(o, k, Q)]);
+            __builtin_nontemporal_store((T)(fp[i] - hp - hm + (A + B)), &a.fout[obf + 64 * i]);
+            __builtin_nontemporal_store((T)(fp[o] - hp + hm + (A - B)), &a.fout[obf + 64 * o]);
         } else {
             const R B = R(3) * wi * (om * em + ff * eF);
-            __builtin_nontemporal_store((T)(om1 * fp[i] + (A + B)), &a.fout[pidx(i, k, Q)]);
-            __builtin_nontemporal_store((T)(om1 * fp[o] + (A - B)), &a.fout[pidx(o, k, Q)]);
+            __builtin_nontemporal_store((T)(om1 * fp[i] + (A + B)), &a.fout[obf + 64 * i]);
+            __builtin_nontemporal_store((T)(om1 * fp[o] + (A - B)), &a.fout[obf + 64 * o]);
         }
     }
 
@@ -333,7 +334,7 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
             for (int i = 1; i < Q; i++) {
                 if (!((SM >> i) & 1u) || !(cross & (1u << i))) continue;
                 if (cross_hi & (1u << i)) {
-                    xout += (R)gv[i] - (R)a.gin[pidx(sol_slot(SM, L::opp[i]), k, QS)];
+                    xout += (R)gv[i] - (R)a.gin[obg + 64 * sol_slot(SM, L::opp[i])];
                 } else {
                     const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
                     const R gin = sol_w<L>(D, i) * (D.c_in - D.c_ref) + sol_w<L>(D, i) * D.c_in * eu * D.inv_cs2s;
@@ -425,12 +426,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     const R omg = D.omega_g, omg1 = R(1) - omg, oms = D.omega_gs;
     const R Cw = omg * C * D.inv_cs2s * D.wsc;
     const R Aw = (TRT ? oms : omg) * D.wsc * dC;
-    __builtin_nontemporal_store((T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC), &a.gout[pidx(0, k, QS)]);
+    __builtin_nontemporal_store((T)((R(1) - oms) * (R)gv[0] + oms * sol_w<L>(D, 0) * dC), &a.gout[obg]);
 #pragma unroll
     for (int i = 1; i < Q; i++) {
         if (L::opp[i] < i || !((SM >> i) & 1u)) continue;
         const int o = L::opp[i];
-        const long si = pidx(sol_slot(SM, i), k, QS), so = pidx(sol_slot(SM, o), k, QS);
+        const long si = obg + 64 * sol_slot(SM, i), so = obg + 64 * sol_slot(SM, o);
         const R eu = R(L::ex[i]) * ux + R(L::ey[i]) * uy + R(L::ez[i]) * uz;
         const R wi = R(L::w[i]);
         const R Bs = (wi * Cw) * eu;
