@@ -320,6 +320,14 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
         }
     }
 
+    // The task's coefficients were fetched into LDS by global-to-LDS loads,
+    // which the compiler does not order before LDS reads.  They were issued
+    // before the fluid loads, and the fluid stores above consumed every fluid
+    // load: vector memory operations complete in order, so those loads' waits
+    // cover the coefficients.  This barrier keeps the compiler from moving an
+    // LDS read of them above the fluid stores (an explicit wait for all vector
+    // memory operations here would also wait for the stores: 8 us slower).
+    asm volatile("" ::: "memory");
     // ---- solute: plane faces, reactive links, collision ----
     // Inlet: the equilibrium at C_in for the populations entering across the
     // plane.  The mass a plane link brings in is the incoming value minus the
