@@ -371,6 +371,10 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
     if (rbc) {
         double sneg = 0.0;
         int off = 0;
+        // w_i C_eq = L::w[i] (wsc C_eq) with a uniform C_eq: one value held in
+        // registers of the wavefront (the loop's blocks otherwise reload the
+        // two factors from spilled scalar registers in every direction)
+        const R wceq = D.wsc * D.ceq_dev;
 #pragma unroll
         for (int i = 1; i < Q; i++) {
             if (!((SM >> i) & 1u)) continue;
@@ -389,11 +393,12 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
                     bt = __builtin_bit_cast(T, lo | (hi << 32));
                 }
                 const R beta = (R)bt;
-                // the link's C_eq: per solid node (a separate instantiation), or uniform
-                R ceqd = D.ceq_dev;
-                if constexpr (CEQ) ceqd = (R)a.lceq[lt + pos];
+                // w_i C_eq with the link's C_eq: per solid node (a separate
+                // instantiation), or uniform
+                R wc = R(L::w[i]) * wceq;
+                if constexpr (CEQ) wc = sol_w<L>(D, i) * (R)a.lceq[lt + pos];
                 // (1 - beta) w C_eq + beta g_src: exactly g_src at beta = 1
-                const R g = (R(1) - beta) * (sol_w<L>(D, i) * ceqd) + beta * srcv;
+                const R g = (R(1) - beta) * wc + beta * srcv;
                 const T qv = (T)(g - own);
                 if constexpr (NW == 1) {
                     slink[wv][0][pos] = __builtin_bit_cast(uint32_t, qv);
