@@ -99,18 +99,21 @@ def kernel_bytes(q, ts, n_fluid, n_links, n_fluid_iface, qs=None, n_tasks=0, n_r
             n_tasks * 32 + n_row_words * 16)
 
 
-def adjoint_kernel_bytes(q, ts, n_fluid, n_links, qs=None):
-    """Algorithmic HBM bytes of one launch of the adjoint's two kernels.
+def adjoint_kernel_bytes(q, ts, n_fluid, n_links, qs=None, seg=100):
+    """Algorithmic HBM bytes of one launch of each of the adjoint's kernels.
 
     Recomputation (one solute-only step at rest): per fluid node QS values
     read and QS written; per reactive link its coefficient read and the
     source value of its rate condition written.  Transposed step: per fluid
     node QS adjoint values read and QS written; per reactive link its
-    coefficient and that source value read (ts each) and its FP64 dL/dbeta
-    read and written (16 B)."""
+    coefficient and that source value read and the step's dL/dbeta term
+    written over the source value (ts each).  Fold (once per segment of seg
+    steps): per reactive link the segment's seg terms read (ts each) and its
+    FP64 dL/dbeta read and written (16 B)."""
     qs = q if qs is None else qs
     return (n_fluid * qs * ts * 2 + n_links * 2 * ts,
-            n_fluid * qs * ts * 2 + n_links * (2 * ts + 16))
+            n_fluid * qs * ts * 2 + n_links * 3 * ts,
+            n_links * (seg * ts + 16))
 
 
 def phi_kernel_bytes(ts, n_links, n_solid_iface):
@@ -124,6 +127,7 @@ def phi_kernel_bytes(ts, n_links, n_solid_iface):
 # kernel names as the profiler reports them, for the per-kernel byte counts
 SOL_KERNEL = "lbm::k_sol_step<lbm::D3Q19, float, false, false>"
 ADJ_KERNEL = "lbm::k_adj_step<lbm::D3Q19, float, false, false>"
+FOLD_KERNEL = "lbm::k_adj_fold<float>"
 ALGO_BYTES = {}   # kernel -> algorithmic bytes per launch, filled by the legs that run
 
 
@@ -281,18 +285,20 @@ def adjoint_ratio(steps, ckpt):
     ok = bool(torch.isfinite(g).all())
     # the backward pass's kernels timed one by one (same gradient)
     grad_t = torch.empty_like(g)
-    sol_ms, adj_ms = lbm_adjoint_timed(sim.ctx, dl, grad_t)
+    sol_ms, adj_ms, fold_ms = lbm_adjoint_timed(sim.ctx, dl, grad_t)
     torch.cuda.synchronize()
     same = bool(torch.equal(grad_t, g))
     sim.close()
     nseg = (steps + ckpt - 1) // ckpt
     # one recomputation launch per step (the last of a segment records the
-    # source values only) and one transposed step per step
+    # source values only), one transposed step per step, one fold per segment
     sol_us = sol_ms / steps * 1e3
     adj_us = adj_ms / steps * 1e3
-    sol_b, adj_b = adjoint_kernel_bytes(case.q, 4, nf, nl)
+    fold_us = fold_ms / nseg * 1e3
+    sol_b, adj_b, fold_b = adjoint_kernel_bytes(case.q, 4, nf, nl, seg=ckpt)
     ALGO_BYTES[SOL_KERNEL] = sol_b
     ALGO_BYTES[ADJ_KERNEL] = adj_b
+    ALGO_BYTES[FOLD_KERNEL] = fold_b
     del sim
     torch.cuda.empty_cache()
     return {
@@ -315,6 +321,9 @@ def adjoint_ratio(steps, ckpt):
         "transposed_kernel": {"kernel": "k_adj_step", "avg_us": round(adj_us, 2), "bytes_per_launch": int(adj_b),
                               "achieved_gbs": round(adj_b / adj_us / 1e3, 1),
                               "frac": round(adj_b / adj_us / 1e3 / HBM_PEAK_GBS, 4)},
+        "fold_kernel": {"kernel": "k_adj_fold", "launches": nseg, "avg_us": round(fold_us, 2),
+                        "bytes_per_launch": int(fold_b), "achieved_gbs": round(fold_b / fold_us / 1e3, 1),
+                        "frac": round(fold_b / fold_us / 1e3 / HBM_PEAK_GBS, 4)},
         "timed_gradient_identical": same,
     }
 
@@ -616,7 +625,7 @@ def summarize_counters(prof_dir, runs):
             k = (name.split("(")[0].replace("void ", ""), int(grid))
             table.setdefault(k, {}).setdefault(cname, []).append(float(val))
     # the kernels the bench legs time
-    timed = (STEP_KERNEL, PHI_KERNEL, RED_STEP_KERNEL, RED_PHI_KERNEL, SOL_KERNEL, ADJ_KERNEL)
+    timed = (STEP_KERNEL, PHI_KERNEL, RED_STEP_KERNEL, RED_PHI_KERNEL, SOL_KERNEL, ADJ_KERNEL, FOLD_KERNEL)
     keep = [k for k in table if k[0] in timed]
     cnames = sorted({c for k in keep for c in table[k]})
     lines = ["# SQ counters per dispatch (rocprofv3 --pmc, one pass per counter group)", "",

@@ -323,9 +323,10 @@ lbm_status lbm_adjoint(lbm_ctx *ctx, const double *dL_dC, double *grad_k);
 
 /* lbm_adjoint with per-kernel timing, for measurement: the same gradient
  * (bit for bit), with a HIP event pair around every kernel launch of the
- * backward pass; synchronises after each.  ms (host array of 2) receives the
+ * backward pass; synchronises after each.  ms (host array of 3) receives the
  * summed durations in milliseconds of the segment recomputation (solute-only
- * forward steps) and of the transposed steps. */
+ * forward steps), of the transposed steps, and of the per-segment folds of
+ * the transposed steps' dL/dbeta terms into the FP64 totals. */
 lbm_status lbm_adjoint_timed(lbm_ctx *ctx, const double *dL_dC, double *grad_k, double *ms);
 
 /* lbm_record without a workspace, for callers that cannot allocate device

@@ -249,10 +249,11 @@ def lbm_adjoint(ctx, dL_dC, grad_k):
 
 def lbm_adjoint_timed(ctx, dL_dC, grad_k):
     """lbm_adjoint; returns (ms of the recomputation kernels, ms of the
-    transposed-step kernels), summed over the backward pass."""
-    ms = (C.c_double * 2)()
+    transposed-step kernels, ms of the per-segment dL/dbeta folds), summed
+    over the backward pass."""
+    ms = (C.c_double * 3)()
     _check(lib.lbm_adjoint_timed(ctx, _ptr(dL_dC), _ptr(grad_k), ms), "lbm_adjoint_timed", ctx)
-    return ms[0], ms[1]
+    return ms[0], ms[1], ms[2]
 
 
 def lbm_get_fields(ctx, rho=None, u=None, c=None, phi=None, type=None):

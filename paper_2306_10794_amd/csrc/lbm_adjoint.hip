@@ -25,10 +25,12 @@
 //                             g*_o (else 0), the node's own lambda_o.
 // so that lambda_d(x, t) = P[d][kk[opp d]] if x + e_d is fluid, else
 // P[opp d][x]: the same gather as the forward pull, directions reversed.
-// dL/dbeta of each link accumulates nu_i (src_i - w_i C_eq) over the steps
-// (FP64, one lane per link); a last kernel turns it into dL/dk_r per solid
-// node through dbeta/dk_r of the link's scheme, summing its links in
-// direction order.
+// dL/dbeta of each link accumulates nu_i (src_i - w_i C_eq) over the steps:
+// each transposed step writes its term over the link's source value (storage
+// precision), and after a segment one kernel adds the segment's terms to the
+// FP64 total, one lane per link, in the order the steps ran; a last kernel
+// turns it into dL/dk_r per solid node through dbeta/dk_r of the link's
+// scheme, summing its links in direction order.
 #include "lbm_internal.hpp"
 #include "lbm_task.hpp"
 
@@ -251,7 +253,7 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     constexpr int QS = __builtin_popcount(SM);
     constexpr int LCAP = 256;   // links of a task staged in LDS (more: read in place)
     constexpr int NW = (int)(sizeof(T) / 4);
-    __shared__ uint32_t sb[BLK / 64][NW][LCAP], ss[BLK / 64][NW][LCAP], sg[BLK / 64][2][LCAP];
+    __shared__ uint32_t sb[BLK / 64][NW][LCAP], ss[BLK / 64][NW][LCAP];
     TaskCtx<L, T> c;
     if (!task_setup<L, T>(a, c)) return;
     const bool act = c.active;
@@ -274,7 +276,6 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
     if (staged) {
         lds_fetch<T, LCAP>(a.lbeta + lt, sb[wv], nlt, lane);
         lds_fetch<T, LCAP>(a.lsrc + lt, ss[wv], nlt, lane);
-        lds_fetch<double, LCAP>(a.gbeta + lt, sg[wv], nlt, lane);
     }
     const long ob = blk0(c.k, QS);
     // lambda(t+1) at this node: the forward pull with directions reversed
@@ -301,9 +302,11 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
             const int pos = lpos[d];
             const R beta = (R)(staged ? lds_get<T, LCAP>(sb[wv], pos) : a.lbeta[lt + pos]);
             const R src = (R)(staged ? lds_get<T, LCAP>(ss[wv], pos) : a.lsrc[lt + pos]);
-            const R add = nu * (src - sol_w<L>(D, d) * D.ceq_dev);
-            if (staged) lds_put<double, LCAP>(sg[wv], pos, lds_get<double, LCAP>(sg[wv], pos) + add);
-            else a.gbeta[lt + pos] += add;
+            // this step's term of dL/dbeta replaces the source value (read
+            // once, just above); the segment's terms are summed by k_adj_fold
+            const T add = (T)(nu * (src - sol_w<L>(D, d) * D.ceq_dev));
+            if (staged) lds_put<T, LCAP>(ss[wv], pos, add);
+            else a.lsrc[lt + pos] = add;
             if (pulled) {
                 *out_other += beta * nu;
                 *out_d = R(0);
@@ -338,9 +341,31 @@ __global__ __launch_bounds__(BLK) void k_adj_step(AdjArgs<T> a) {
 #pragma unroll
         for (int r = 0; r < LCAP / 64; r++) {
             const int j = r * 64 + lane;
-            if (j < nlt) a.gbeta[lt + j] = lds_get<double, LCAP>(sg[wv], j);
+            if (j < nlt) a.lsrc[lt + j] = lds_get<T, LCAP>(ss[wv], j);
         }
     }
+}
+
+// dL/dbeta of every link += the terms its segment's transposed steps wrote
+// over the source values, in the order those steps ran (last step first), in
+// FP64: the same sums as adding each step's term as it is formed.
+template <typename T>
+__global__ __launch_bounds__(BLK) void k_adj_fold(const T *__restrict__ terms, long stride, int len,
+                                                 double *__restrict__ gbeta, long nlinks) {
+    const long l = (long)blockIdx.x * BLK + threadIdx.x;
+    if (l >= nlinks) return;
+    double g = gbeta[l];
+    constexpr int U = 8;   // terms loaded ahead of the ordered sum
+    int j = len - 1;
+    for (; j >= U - 1; j -= U) {
+        T v[U];
+#pragma unroll
+        for (int u = 0; u < U; u++) v[u] = terms[(long)(j - u) * stride + l];
+#pragma unroll
+        for (int u = 0; u < U; u++) g += (double)v[u];
+    }
+    for (; j >= 0; j--) g += (double)terms[(long)j * stride + l];
+    gbeta[l] = g;
 }
 
 // dL/dk_r per solid interface node from dL/dbeta of its links (direction
@@ -511,6 +536,16 @@ static hipError_t adjoint_impl(Ctx &c, const double *dldc, double *grad, double 
                 if (e != hipSuccess) return e;
             }
             cur = 1 - cur;
+        }
+        if (c.n_links > 0) {
+            if (ms) (void)hipEventRecord(c.ev[0], c.stream);
+            hipLaunchKernelGGL((k_adj_fold<T>), dim3((c.n_links + BLK - 1) / BLK), dim3(BLK), 0, c.stream, src,
+                               (long)r.src_stride, seg_len(sgi), r.gbeta, (long)c.n_links);
+            if (ms) {
+                (void)hipEventRecord(c.ev[1], c.stream);
+                hipError_t e = add_elapsed(c, &ms[2]);
+                if (e != hipSuccess) return e;
+            }
         }
         return hipGetLastError();
     };

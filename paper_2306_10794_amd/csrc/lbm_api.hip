@@ -1101,7 +1101,7 @@ lbm_status lbm_adjoint_timed(lbm_ctx *ctx, const double *dL_dC, double *grad_k, 
         }
         c->have_events = true;
     }
-    ms[0] = ms[1] = 0.0;
+    ms[0] = ms[1] = ms[2] = 0.0;
     return adjoint_common(c, dL_dC, grad_k, ms);
 }
 

@@ -42,10 +42,12 @@ def test_adjoint_bytes_per_launch():
     import bench
     # recomputation: QS read + QS written per node, beta read and the source
     # value written per link; transposed step: the same per node, beta +
-    # source read and FP64 dL/dbeta read and written per link
-    sol, adj = bench.adjoint_kernel_bytes(19, 4, 939_011, 1_000_000)
+    # source read and the step's dL/dbeta term written per link; fold: per
+    # link a segment's terms read and the FP64 dL/dbeta read and written
+    sol, adj, fold = bench.adjoint_kernel_bytes(19, 4, 939_011, 1_000_000, seg=100)
     assert sol == 939_011 * 19 * 8 + 1_000_000 * 8
-    assert adj == 939_011 * 19 * 8 + 1_000_000 * (8 + 16)
+    assert adj == 939_011 * 19 * 8 + 1_000_000 * 12
+    assert fold == 1_000_000 * (100 * 4 + 16)
 
 
 if __name__ == "__main__":
