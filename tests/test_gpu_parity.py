@@ -153,6 +153,24 @@ def test_random_solid_gaps_and_fd_normals():
     _assert_parity(case, FP64, 100)
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_isolated_solid_voxels_many_links(precision):
+    """Single solid voxels on every third site, each with 18 reactive links:
+    the solid-side kernel gathers more than its 512-link round per wavefront
+    of 64 solid nodes (1,152 links: three rounds), and every node's sum
+    straddles a round boundary somewhere; dissolution lowers each voxel's
+    phi every step."""
+    n = 24
+    solid = np.zeros((n, n, n), np.uint8)
+    solid[1::3, 1::3, 1::3] = 1
+    rng = np.random.default_rng(14)
+    case = Case(name="voxels", dim=3, nx=n, ny=n, nz=n, q=19, solid=solid, normals=None,
+                tau_ns=0.9, tau_ad=0.7, j0=0.5, c_eq=1.0, k_r=0.05, v_m=1.0,
+                c_init=rng.uniform(0.0, 0.5, solid.size))
+    log(f"[parity] isolated voxels precision={precision} solid={int(solid.sum())}")
+    _assert_parity(case, precision, 60)
+
+
 def test_open_box_walls_fp64():
     """Non-periodic box faces act as plain bounce-back walls for both lattices."""
     rng = np.random.default_rng(10)
