@@ -99,6 +99,39 @@ def test_adjoint_matches_oracle(precision, name):
     assert err <= (1e-11 if precision == FP64 else 1e-5)
 
 
+@pytest.mark.parametrize("precision", [FP64, FP32])
+def test_adjoint_dense_links_read_in_place(precision):
+    """A 3D medium that is 60 % solid: a 64-node task of fluid nodes carries
+    several hundred reactive links, more than the 256 that the recomputation
+    and the transposed step stage in LDS, so they read (and write) the link
+    values in place; against the oracle as above."""
+    rng = np.random.default_rng(31)
+    n = 16
+    solid = (rng.uniform(size=(n, n, n)) < 0.6).astype(np.uint8)
+    k = configs.lognormal_rate_field(solid, 32, mu=math.log(2e-2), sigma=0.4)
+    case = Case(name="adj_dense", dim=3, nx=n, ny=n, nz=n, q=19, solid=solid, normals=None,
+                tau_ns=0.9, tau_ad=0.8, j0=-1.0, c_eq=1.0, k_r=2e-2, k_r_field=k, v_m=0.0,
+                periodic=(1, 1, 1), c0=0.2, mechanics=MECH_PRE, scheme=SCHEME_SNEW)
+    steps, ckpt = 40, 15
+    target = _target(case)
+    from paper_2306_10794_amd import Simulation
+    sim = Simulation(case, precision=precision)
+    d = sim.diag()
+    sim.close()
+    log(f"[adjoint] dense links precision={precision} solid={int(solid.sum())} steps={steps} ckpt={ckpt} "
+        f"links={d['n_links']} tasks={d['n_tasks']}")
+    # some task holds more links than the kernels stage
+    assert d["n_links"] / d["n_tasks"] > 256
+    g, _ = _gpu_grad(case, precision, steps, ckpt, target)
+    go = _oracle_grad(case, steps, target)
+    scale = np.abs(go).max()
+    err = np.abs(g - go).max() / scale
+    log(f"[adjoint] max |grad| {scale:.3e}, rel err {err:.3e}")
+    assert scale > 0
+    assert np.array_equal(g != 0, go != 0)
+    assert err <= (1e-11 if precision == FP64 else 1e-5)
+
+
 def test_adjoint_matches_central_differences_fp64():
     import torch
     from paper_2306_10794_amd import Simulation
