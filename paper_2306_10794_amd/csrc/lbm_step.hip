@@ -464,11 +464,14 @@ __global__ __launch_bounds__(64 * WV, sizeof(T) == 4 ? 4 : 1) void k_step(StepAr
 // dissolution side of the solid fraction, per solid interface node, links in
 // ascending direction order; also the step's total exchange, added to this
 // workgroup's own slot xpart[tile] (no atomics: the slots are folded
-// into the running total when it is read).  A wavefront takes 64 consecutive
-// solid nodes, whose links are one contiguous range of the solid-side list:
-// it reads that range coalesced and gathers the exchanges of up to PCH * 64
-// links at a time into LDS (every lane loading one link per round), and each
-// lane then sums its own node's links from there in order.
+// into the running total when it is read).  With up to 8 links per node a
+// thread takes a node and loads its link ids, then its exchanges.  With the
+// 18 of D3Q19 (4.7 on average in a packing) most of those loads would run
+// with few lanes active, so a wavefront takes 64 consecutive solid nodes,
+// whose links are one contiguous range of the solid-side list: it reads that
+// range coalesced and gathers the exchanges of up to PCH * 64 links at a time
+// into LDS (every lane loading one link per round), and each lane then sums
+// its own node's links from there in order.  Both sum in the same order.
 template <class L, typename T, bool RED>
 __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ soff,
                                                    const int32_t *__restrict__ slinks,
@@ -479,8 +482,6 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
                                                    unsigned long long *evflag, int evbatch, int evidx,
                                                    int remap) {
     constexpr int M = __builtin_popcount(sol_mask<L, RED>()) - 1;
-    constexpr int PCH = 8;
-    __shared__ T sq[BLK / 64][64 * PCH];
     if (evflag) {   // as in the fused kernel (the value is the same for every thread)
         const unsigned long long w = *evflag;
         if ((int)(w >> 32) == evbatch && (int)(unsigned)w < evidx) return;
@@ -490,55 +491,84 @@ __global__ __launch_bounds__(BLK) void k_phi_solid(const int32_t *__restrict__ s
     // planes) gather stay in that XCD's L2, which cuts the kernel's HBM reads
     // to about its algorithmic bytes
     const long tile = remap ? xcd_tile(blockIdx.x, gridDim.x) : (long)blockIdx.x;
-    const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
-    const long j0 = tile * BLK + wv * 64, j = j0 + lane;
     double tot = 0.0;
-    if (j0 < nsif) {
-        const bool act = j < nsif;
-        // lanes past the end read the last node's entries (no branches around
-        // the loads: the solid fraction's latency then hides behind the gathers)
-        const long jc = act ? j : nsif - 1;
-        const int kb0 = soff[jc], ke0 = soff[jc + 1];
-        const double ph = phis[jc];
-        const int kb = act ? kb0 : 0, ke = act ? ke0 : 0;
-        const int last = (int)(nsif - j0 < 64 ? nsif - j0 : 64) - 1;
-        const int s0 = __builtin_amdgcn_readfirstlane(kb);
-        const int ns = __builtin_amdgcn_readlane(ke, last) - s0;   // links of the wavefront's nodes
-        const int mb = kb - s0, me = ke - s0;                       // this lane's node, in that range
-        double pos = 0.0;
-        for (int c0 = 0; c0 < ns; c0 += 64 * PCH) {
-            int li[PCH];
+    if constexpr (M <= 8) {
+        // few links per node (D2Q9, D2Q5, D3Q7): one thread per node loads
+        // all its link ids, then all its exchanges, before the ordered sum
+        const long j = tile * BLK + threadIdx.x;
+        if (j < nsif) {
+            const int k0 = soff[j], nk = soff[j + 1] - k0;
+            const double ph = phis[j];   // read now: its latency hides behind the gathers
+            int li[M];
 #pragma unroll
-            for (int r = 0; r < PCH; r++) {
-                const int p = c0 + r * 64 + lane;
-                li[r] = p < ns ? slinks[s0 + p] : -1;
-            }
-            T qv[PCH];
+            for (int m = 0; m < M; m++) li[m] = m < nk ? slinks[k0 + m] : -1;
+            T qv[M];
 #pragma unroll
-            for (int r = 0; r < PCH; r++) qv[r] = li[r] >= 0 ? lq[li[r]] : T(0);
-            // reads of the previous round are done (LDS operations of one
-            // wavefront complete in order)
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-#pragma unroll
-            for (int r = 0; r < PCH; r++) sq[wv][r * 64 + lane] = qv[r];
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-            __builtin_amdgcn_wave_barrier();
-            const int lo = mb > c0 ? mb : c0, hi = me < c0 + 64 * PCH ? me : c0 + 64 * PCH;
+            for (int m = 0; m < M; m++) qv[m] = li[m] >= 0 ? lq[li[m]] : T(0);
+            double pos = 0.0;
 #pragma unroll
             for (int m = 0; m < M; m++) {
-                if (lo + m < hi) {
-                    const double v = (double)sq[wv][lo + m - c0];
-                    tot += v;
-                    if (v > 0.0) pos += v;
-                }
+                const double v = (double)qv[m];
+                tot += v;
+                if (v > 0.0) pos += v;
             }
-        }
-        if (act) {
             const double pn = ph - doms[ndom > 1 ? sdom[j] : 0].vma * pos;
             phis[j] = pn;
             // phase change: at or past the dissolution threshold
             if (evflag && pn <= 0.0) *evflag = ((unsigned long long)(unsigned)evbatch << 32) | (unsigned)evidx;
+        }
+    } else {
+        constexpr int PCH = 8;
+        __shared__ T sq[BLK / 64][64 * PCH];
+        const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+        const long j0 = tile * BLK + wv * 64, j = j0 + lane;
+        if (j0 < nsif) {
+            const bool act = j < nsif;
+            // lanes past the end read the last node's entries (no branches around
+            // the loads: the solid fraction's latency then hides behind the gathers)
+            const long jc = act ? j : nsif - 1;
+            const int kb0 = soff[jc], ke0 = soff[jc + 1];
+            const double ph = phis[jc];
+            const int kb = act ? kb0 : 0, ke = act ? ke0 : 0;
+            const int last = (int)(nsif - j0 < 64 ? nsif - j0 : 64) - 1;
+            const int s0 = __builtin_amdgcn_readfirstlane(kb);
+            const int ns = __builtin_amdgcn_readlane(ke, last) - s0;   // links of the wavefront's nodes
+            const int mb = kb - s0, me = ke - s0;                       // this lane's node, in that range
+            double pos = 0.0;
+            for (int c0 = 0; c0 < ns; c0 += 64 * PCH) {
+                int li[PCH];
+#pragma unroll
+                for (int r = 0; r < PCH; r++) {
+                    const int p = c0 + r * 64 + lane;
+                    li[r] = p < ns ? slinks[s0 + p] : -1;
+                }
+                T qv[PCH];
+#pragma unroll
+                for (int r = 0; r < PCH; r++) qv[r] = li[r] >= 0 ? lq[li[r]] : T(0);
+                // reads of the previous round are done (LDS operations of one
+                // wavefront complete in order)
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+#pragma unroll
+                for (int r = 0; r < PCH; r++) sq[wv][r * 64 + lane] = qv[r];
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+                __builtin_amdgcn_wave_barrier();
+                const int lo = mb > c0 ? mb : c0, hi = me < c0 + 64 * PCH ? me : c0 + 64 * PCH;
+#pragma unroll
+                for (int m = 0; m < M; m++) {
+                    if (lo + m < hi) {
+                        const double v = (double)sq[wv][lo + m - c0];
+                        tot += v;
+                        if (v > 0.0) pos += v;
+                    }
+                }
+            }
+            if (act) {
+                const double pn = ph - doms[ndom > 1 ? sdom[j] : 0].vma * pos;
+                phis[j] = pn;
+                // phase change: at or past the dissolution threshold
+                if (evflag && pn <= 0.0) *evflag = ((unsigned long long)(unsigned)evbatch << 32) | (unsigned)evidx;
+            }
         }
     }
     tot = block_sum(tot);
